@@ -1,0 +1,21 @@
+"""CPU oracle for the dense Kohn-Sham path -- TEST INFRASTRUCTURE ONLY.
+
+Plain FP64 C (``elsi_oracle.c``) behind ctypes.  Only the test-suite, the smoke
+check and the benchmark's CPU-baseline leg may import this package; the GPU
+library never does, and it shares no code with it.
+"""
+from .oracle import (  # noqa: F401
+    backsub,
+    band_energy,
+    build,
+    density,
+    dm,
+    gevp,
+    occupations,
+    potrf,
+    reduce_standard,
+    residual_norms,
+    tred,
+    tridiag_eig,
+    tridiag_eigvals,
+)

@@ -1,0 +1,211 @@
+"""ctypes wrapper of the plain-C FP64 oracle (test infrastructure only).
+
+Every function copies its inputs into Fortran-ordered float64 arrays, calls the
+C routine and returns fresh NumPy arrays; nothing here does any arithmetic of
+the method itself.  The sections and equations each routine follows are cited
+in ``elsi_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "elsi_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no GPU code involved)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        i, d = ctypes.c_int, ctypes.c_double
+        lib.orc_potrf.argtypes = [i, _dp, i]
+        lib.orc_reduce.argtypes = [i, _dp, i, _dp, i]
+        lib.orc_tred.argtypes = [i, _dp, i, _dp, _dp, _dp, i]
+        lib.orc_tql.argtypes = [i, _dp, _dp, _dp, i]
+        lib.orc_backsub.argtypes = [i, i, _dp, i, _dp, i]
+        lib.orc_gevp.argtypes = [i, i, _dp, i, _dp, i, _dp, _dp, _ip]
+        lib.orc_tridiag_eigvals.argtypes = [i, _dp, _dp, _dp]
+        lib.orc_tridiag_eig.argtypes = [i, _dp, _dp, _dp, _dp]
+        lib.orc_occupations.argtypes = [i, _dp, d, d, d, d, i, _dp, _dp]
+        lib.orc_density.argtypes = [i, i, _dp, i, _dp, _dp, i]
+        lib.orc_band_energy.argtypes = [i, _dp, _dp]
+        lib.orc_band_energy.restype = d
+        lib.orc_dm.argtypes = [i, _dp, i, _dp, i, d, d, d, d, i, _dp, i, _dp, _dp, _dp, _dp, _ip]
+        lib.orc_residual_norms.argtypes = [i, i, _dp, i, _dp, i, _dp, i, _dp, _dp]
+        _lib = lib
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.array(a, dtype=np.float64, order="F", copy=True)
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"oracle status {status}: {msg}")
+        self.status = status
+
+
+def potrf(S):
+    """Lower Cholesky factor L with S = L L^T (Eq. (10)); raises on a non-positive pivot."""
+    A = _f64(S)
+    n = A.shape[0]
+    info = _load().orc_potrf(n, _p(A), n)
+    if info:
+        raise OracleError(1, f"S not positive definite at column {info - 1}")
+    return A
+
+
+def reduce_standard(H, L):
+    """H~ = L^-1 H L^-T (Eq. (11)), full symmetric."""
+    A = _f64(H)
+    Lf = _f64(L)
+    n = A.shape[0]
+    _load().orc_reduce(n, _p(A), n, _p(Lf), n)
+    return A
+
+
+def tred(A):
+    """Householder tridiagonalization (Eq. (12)): returns d, e, Q with A = Q T Q^T."""
+    W = _f64(A)
+    n = W.shape[0]
+    d = np.zeros(n)
+    e = np.zeros(max(n - 1, 1))
+    Q = np.zeros((n, n), order="F")
+    _load().orc_tred(n, _p(W), n, _p(d), _p(e), _p(Q), n)
+    return d, e[: max(n - 1, 0)], Q
+
+
+def tridiag_eigvals(d, e):
+    """Eigenvalues (ascending) of the symmetric tridiagonal (d, e) by implicit QL."""
+    d = _f64(d)
+    n = d.shape[0]
+    ee = np.zeros(max(n, 1))
+    ee[: n - 1] = e
+    w = np.zeros(n)
+    st = _load().orc_tridiag_eigvals(n, _p(d), _p(ee), _p(w))
+    if st:
+        raise OracleError(st, "QL did not converge")
+    return w
+
+
+def tridiag_eig(d, e):
+    """Eigenpairs of the symmetric tridiagonal (d, e): (w ascending, Z column-major)."""
+    d = _f64(d)
+    n = d.shape[0]
+    ee = np.zeros(max(n, 1))
+    ee[: n - 1] = e
+    w = np.zeros(n)
+    Z = np.zeros((n, n), order="F")
+    st = _load().orc_tridiag_eig(n, _p(d), _p(ee), _p(w), _p(Z))
+    if st:
+        raise OracleError(st, "QL did not converge")
+    return w, Z
+
+
+def backsub(L, Z):
+    """C = L^-T Z."""
+    Lf = _f64(L)
+    C = _f64(Z)
+    n, k = C.shape
+    _load().orc_backsub(n, k, _p(Lf), n, _p(C), n)
+    return C
+
+
+def gevp(H, S, n_state=None):
+    """Generalized eigenpairs of Eq. (6): (eval ascending (n), evec n x n_state, L)."""
+    Hf = _f64(H)
+    Sf = _f64(S)
+    n = Hf.shape[0]
+    k = n if n_state is None else int(n_state)
+    ev = np.zeros(n)
+    C = np.zeros((n, max(k, 1)), order="F")
+    fail = ctypes.c_int(0)
+    st = _load().orc_gevp(n, k, _p(Hf), n, _p(Sf), n, _p(ev), _p(C), ctypes.byref(fail))
+    if st == 1:
+        raise OracleError(1, f"S not positive definite at column {fail.value - 1}")
+    if st:
+        raise OracleError(st, "eigensolver failed")
+    return ev, C[:, :k], Sf
+
+
+def occupations(eps, n_electron, kT, spin=1.0, occ_accuracy=1e-13, max_steps=100):
+    """Fermi-Dirac occupations (Eq. (17)) with mu from Eq. (18); returns (f, mu, status)."""
+    e = _f64(eps)
+    n = e.shape[0]
+    f = np.zeros(n)
+    mu = ctypes.c_double(0.0)
+    st = _load().orc_occupations(n, _p(e), float(n_electron), float(kT), float(spin),
+                                 float(occ_accuracy), int(max_steps), _p(f), ctypes.byref(mu))
+    return f, mu.value, st
+
+
+def density(C, f):
+    """D = sum_l f_l c_l c_l^T over f_l > 0 (Eq. (9))."""
+    Cf = _f64(C)
+    ff = _f64(f)
+    n, k = Cf.shape
+    D = np.zeros((n, n), order="F")
+    _load().orc_density(n, k, _p(Cf), n, _p(ff), _p(D), n)
+    return D
+
+
+def band_energy(f, eps):
+    ff = _f64(f)
+    e = _f64(eps)
+    return float(_load().orc_band_energy(ff.shape[0], _p(ff), _p(e)))
+
+
+def dm(H, S, n_electron, kT, spin=1.0, occ_accuracy=1e-13, max_steps=100):
+    """Density-matrix driver: returns dict(D, eval, occ, energy, mu, status)."""
+    Hf = _f64(H)
+    Sf = _f64(S)
+    n = Hf.shape[0]
+    D = np.zeros((n, n), order="F")
+    ev = np.zeros(n)
+    occ = np.zeros(n)
+    energy = ctypes.c_double(0.0)
+    mu = ctypes.c_double(0.0)
+    fail = ctypes.c_int(0)
+    st = _load().orc_dm(n, _p(Hf), n, _p(Sf), n, float(n_electron), float(kT), float(spin),
+                        float(occ_accuracy), int(max_steps), _p(D), n, _p(ev), _p(occ),
+                        ctypes.byref(energy), ctypes.byref(mu), ctypes.byref(fail))
+    if st in (1, 2):
+        raise OracleError(st, "eigensolve failed")
+    return dict(D=D, eval=ev, occ=occ, energy=energy.value, mu=mu.value, status=st, L=Sf)
+
+
+def residual_norms(H, S, X, lam):
+    """||H x_j - lam_j S x_j||_2 per column, accumulated in long double."""
+    Hf = _f64(H)
+    Sf = _f64(S)
+    Xf = _f64(X)
+    lf = _f64(lam)
+    n, k = Xf.shape
+    res = np.zeros(k)
+    _load().orc_residual_norms(n, k, _p(Hf), n, _p(Sf), n, _p(Xf), n, _p(lf), _p(res))
+    return res

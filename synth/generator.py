@@ -1,0 +1,197 @@
+"""Synthetic localized-basis H/S pairs standing in for the paper's KS-DFT matrices.
+
+The paper benchmarks on Hamiltonian and overlap matrices produced by FHI-aims
+and DGDFT graphene runs (Sec. 5, Table 1); those matrices are not available,
+so seeded synthetic matrices of the same kind stand in for them:
+
+* basis functions are normalized s-type Gaussians centred on atoms, so the
+  overlap is the integral of Eq. (5) evaluated analytically with the Gaussian
+  product theorem:  S_ab = (2 sqrt(a b) / (a + b))^{3/2} exp(-a b / (a + b) |A - B|^2);
+* the Hamiltonian is extended-Hueckel-like:  H_ii = h_i,
+  H_ij = 1.75 * S_ij * (h_i + h_j) / 2  (i != j), h_i ~ U(-15, -5) eV;
+* S is shifted by sigma * I, sigma = lambda_max(S_lit) / kappa, which fixes its
+  condition number at about kappa (the literal draw of many same-centre
+  exponents is numerically singular).  H is left unchanged because its
+  off-diagonal entries use S_ij, i != j, which the shift does not touch.
+
+Random numbers come from ``numpy.random.default_rng(seed)`` in a fixed order:
+atom jitter (atoms x 3), exponents (atoms x orbitals), on-site energies (N).
+Lengths are in bohr, energies in Hartree (eV are converted on the way in).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HARTREE_PER_EV = 1.0 / 27.211386245988  # CODATA 2018
+WH_K = 1.75                             # Wolfsberg-Helmholz constant
+DEFAULT_KAPPA = 1.0e6
+DEFAULT_KT = 0.01                       # Fermi-Dirac width in Hartree
+
+
+@dataclass
+class SystemSpec:
+    """A generated pencil plus the metadata needed to solve and report it."""
+
+    H: np.ndarray
+    S: np.ndarray
+    n_occ: float
+    kT: float
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.H.shape[0]
+
+
+# ----------------------------------------------------------------------------
+# geometry
+# ----------------------------------------------------------------------------
+def chain_positions(n_atoms: int, spacing: float, jitter: np.ndarray) -> np.ndarray:
+    """Atoms on a line: x_a = spacing * a + jitter_a (only the x jitter is used)."""
+    pos = np.zeros((n_atoms, 3))
+    pos[:, 0] = spacing * np.arange(n_atoms) + jitter[:, 0]
+    return pos
+
+
+def lattice_positions(n_atoms: int, spacing: float, jitter: np.ndarray) -> np.ndarray:
+    """First ``n_atoms`` sites of an m x m x m cubic lattice, x fastest, plus jitter."""
+    m = 1
+    while m ** 3 < n_atoms:
+        m += 1
+    idx = np.arange(n_atoms)
+    ix, iy, iz = idx % m, (idx // m) % m, idx // (m * m)
+    pos = spacing * np.stack([ix, iy, iz], axis=1).astype(np.float64)
+    return pos + jitter
+
+
+# ----------------------------------------------------------------------------
+# matrices
+# ----------------------------------------------------------------------------
+def s_gaussian_overlap(centers: np.ndarray, alphas: np.ndarray, block: int = 2048) -> np.ndarray:
+    """Overlap of normalized s-Gaussians (Gaussian product theorem), built in row blocks."""
+    n = alphas.shape[0]
+    S = np.empty((n, n))
+    for i0 in range(0, n, block):
+        i1 = min(n, i0 + block)
+        a = alphas[i0:i1, None]
+        b = alphas[None, :]
+        d2 = ((centers[i0:i1, None, :] - centers[None, :, :]) ** 2).sum(axis=2)
+        p = a + b
+        S[i0:i1] = (2.0 * np.sqrt(a * b) / p) ** 1.5 * np.exp(-(a * b / p) * d2)
+    return S
+
+
+def _lambda_max(S: np.ndarray) -> float:
+    """Largest eigenvalue of a symmetric matrix by Lanczos (deterministic start vector)."""
+    n = S.shape[0]
+    if n <= 64:
+        return float(np.linalg.eigvalsh(S)[-1])
+    from scipy.sparse.linalg import eigsh
+
+    v0 = np.ones(n) / math.sqrt(n)
+    val = eigsh(S, k=1, which="LA", v0=v0, tol=1e-10, return_eigenvectors=False)
+    return float(val[0])
+
+
+def build_system(centers_per_orbital: np.ndarray, alphas: np.ndarray, h: np.ndarray,
+                 kappa: float = DEFAULT_KAPPA, block: int = 2048):
+    """Return (H, S, sigma) for the given orbital centres, exponents and on-site energies."""
+    S = s_gaussian_overlap(centers_per_orbital, alphas, block=block)
+    n = S.shape[0]
+    sigma = 0.0
+    if kappa is not None and kappa > 0:
+        sigma = _lambda_max(S) / kappa
+    H = np.empty_like(S)
+    for i0 in range(0, n, block):
+        i1 = min(n, i0 + block)
+        H[i0:i1] = WH_K * 0.5 * S[i0:i1] * (h[i0:i1, None] + h[None, :])
+    di = np.arange(n)
+    H[di, di] = h
+    S[di, di] += sigma
+    return H, S, sigma
+
+
+def make_lattice_system(n: int, seed: int, kappa: float = DEFAULT_KAPPA,
+                        orbitals_per_atom: int = 15, spacing: float = 2.5,
+                        jitter_amp: float = 0.2, alpha_lo: float = 0.2,
+                        alpha_hi: float = 3.0) -> SystemSpec:
+    """3D jittered cubic lattice, ``orbitals_per_atom`` s-Gaussians per atom, first n orbitals kept."""
+    n_atoms = -(-n // orbitals_per_atom)
+    rng = np.random.default_rng(seed)
+    jitter = rng.uniform(-jitter_amp, jitter_amp, size=(n_atoms, 3))
+    alphas = rng.uniform(alpha_lo, alpha_hi, size=(n_atoms, orbitals_per_atom)).reshape(-1)[:n]
+    h = rng.uniform(-15.0, -5.0, size=n) * HARTREE_PER_EV
+    pos = lattice_positions(n_atoms, spacing, jitter)
+    centers = np.repeat(pos, orbitals_per_atom, axis=0)[:n]
+    H, S, sigma = build_system(centers, alphas, h, kappa)
+    return SystemSpec(H, S, n_occ=float(n // 4), kT=DEFAULT_KT,
+                      meta=dict(kind="lattice3d", n_atoms=n_atoms, seed=seed,
+                                kappa=kappa, sigma=sigma, orbitals_per_atom=orbitals_per_atom))
+
+
+def make_chain_system(seed: int = 0, kappa: float = DEFAULT_KAPPA, n_atoms: int = 128,
+                      orbitals_per_atom: int = 4) -> SystemSpec:
+    """1D chain: spacing 1.4 bohr, jitter U(+-0.1), 4 s-Gaussians per atom, alpha ~ U(0.3, 2.0)."""
+    rng = np.random.default_rng(seed)
+    jitter = rng.uniform(-0.1, 0.1, size=(n_atoms, 3))
+    alphas = rng.uniform(0.3, 2.0, size=(n_atoms, orbitals_per_atom)).reshape(-1)
+    n = n_atoms * orbitals_per_atom
+    h = rng.uniform(-15.0, -5.0, size=n) * HARTREE_PER_EV
+    pos = chain_positions(n_atoms, 1.4, jitter)
+    centers = np.repeat(pos, orbitals_per_atom, axis=0)
+    H, S, sigma = build_system(centers, alphas, h, kappa)
+    return SystemSpec(H, S, n_occ=float(n // 4), kT=DEFAULT_KT,
+                      meta=dict(kind="chain1d", n_atoms=n_atoms, seed=seed,
+                                kappa=kappa, sigma=sigma, orbitals_per_atom=orbitals_per_atom))
+
+
+def batch_sizes(count: int = 256, seed: int = 0, lo: int = 256, hi: int = 4096,
+                multiple: int = 15) -> np.ndarray:
+    """Problem sizes log-uniform in [lo, hi], rounded to a multiple of ``multiple``."""
+    rng = np.random.default_rng(seed)
+    raw = np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))
+    return (multiple * np.round(raw / multiple)).astype(np.int64)
+
+
+def make_config(cfg: int, seed: int = 0, kappa: float = DEFAULT_KAPPA) -> SystemSpec:
+    """The single-problem workloads: 0 = 512-orbital chain, 1 = N 8192 lattice, 2 = N 32768 lattice."""
+    if cfg == 0:
+        return make_chain_system(seed=seed, kappa=kappa)
+    if cfg == 1:
+        return make_lattice_system(8192, seed, kappa)
+    if cfg == 2:
+        return make_lattice_system(32768, seed, kappa)
+    raise ValueError(f"unknown single-problem config {cfg}")
+
+
+# ----------------------------------------------------------------------------
+# closed-form test pencils (inputs only; their exact spectra live in the tests)
+# ----------------------------------------------------------------------------
+def tight_binding_chain(n: int, eps0: float, t: float) -> np.ndarray:
+    """H = tridiag(t, eps0, t), the 1D nearest-neighbour tight-binding chain."""
+    H = np.zeros((n, n))
+    H[np.arange(n), np.arange(n)] = eps0
+    H[np.arange(n - 1), np.arange(1, n)] = t
+    H[np.arange(1, n), np.arange(n - 1)] = t
+    return H
+
+
+def toeplitz_pencil(n: int, alpha: float, beta: complex, sigma: complex):
+    """H = tridiag(conj(beta), alpha, beta), S = tridiag(conj(sigma), 1, sigma) (upper = beta)."""
+    cplx = np.iscomplexobj(beta) or np.iscomplexobj(sigma) or isinstance(beta, complex) \
+        or isinstance(sigma, complex)
+    dt = np.complex128 if cplx else np.float64
+    H = np.zeros((n, n), dtype=dt)
+    S = np.zeros((n, n), dtype=dt)
+    i = np.arange(n)
+    H[i, i] = alpha
+    S[i, i] = 1.0
+    # column-major reading: entry (row j, col j+1) is the upper one
+    H[i[:-1], i[1:]] = beta
+    H[i[1:], i[:-1]] = np.conj(beta)
+    S[i[:-1], i[1:]] = sigma
+    S[i[1:], i[:-1]] = np.conj(sigma)
+    return H, S
