@@ -1,0 +1,203 @@
+/*
+ * elsi_gpu.h -- C ABI of libelsi_gpu, a single-GPU (AMD Instinct MI355X,
+ * gfx950) solver for the dense Kohn-Sham generalized eigenproblem and the
+ * density matrix built from it.
+ *
+ * What is computed (ELSI paper, arXiv 1705.11191):
+ *   - H c = eps S c for real symmetric H and symmetric positive definite S,
+ *     Sec. 2, Eq. (6);
+ *   - by Cholesky S = L L^T, Eq. (10); reduction H~ = L^-1 H L^-T and
+ *     back substitution c = L^-T c~, Eq. (11); two-stage tridiagonalization
+ *     B = Q1 H~ Q1^T, T = Q2 B Q2^T, Eq. (13); divide and conquer on T and
+ *     back-transformation through Q2 and Q1 -- the five steps of Fig. 1
+ *     (Sec. 3.1);
+ *   - Fermi-Dirac occupations, Eq. (17), with the chemical potential fixed by
+ *     the electron count, Eq. (18), found by bisection and followed by the
+ *     exact charge fix-up described for elsi_dm_real (Sec. 4.5);
+ *   - the density matrix n_ij = sum_l f_l c_il c_jl, Eq. (9), and the band
+ *     energy sum_l f_l eps_l (Sec. 4.5).
+ *
+ * Conventions for every entry point:
+ *   - matrices are column-major; the leading dimension equals n_basis unless
+ *     an argument says otherwise; only the lower triangle of a symmetric
+ *     input is read;
+ *   - "device" pointers point to GPU memory on the current HIP device, "host"
+ *     pointers to CPU memory; the caller owns every buffer it passes; the
+ *     library keeps no caller pointer after a call returns, except a
+ *     workspace registered with elsi_gpu_set_workspace;
+ *   - calls are synchronous: they return after the handle's stream has
+ *     finished the work;
+ *   - return value: 0 success; -i the i-th argument is invalid (LAPACK style,
+ *     counted from 1, nothing was launched); a positive value is a numerical
+ *     or runtime failure (ELSI_GPU_ERR_*), see elsi_gpu_strerror.
+ *   - energies are in Hartree; the library does no unit conversion.
+ * One handle serves one host thread at a time; several handles may be used
+ * concurrently (the paper's opaque handle without globals, Sec. 4.3).
+ */
+#ifndef ELSI_GPU_H
+#define ELSI_GPU_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct elsi_gpu_handle_s *elsi_gpu_handle;
+
+/* scalar type of H, S, eigenvectors and D (Sec. 4.5: elsi_ev_real / _complex) */
+enum { ELSI_GPU_REAL64 = 0 };
+
+/* occupation scheme (Sec. 4.6, broadening_scheme): explicit values given by
+ * the caller, or Fermi-Dirac broadening, Eq. (17) */
+enum { ELSI_GPU_OCC_EXPLICIT = 0, ELSI_GPU_OCC_FERMI = 1 };
+
+/* failure codes (positive return values) */
+enum {
+    ELSI_GPU_ERR_NOT_PD = 1,      /* S not positive definite; info.fail_col = first bad pivot (1-based) */
+    ELSI_GPU_ERR_NO_CONV = 2,     /* tridiagonal eigensolver did not converge */
+    ELSI_GPU_ERR_REFINE = 3,      /* reserved: refinement tolerance not reached */
+    ELSI_GPU_ERR_MU = 4,          /* mu bisection ran out of steps (outputs still written) */
+    ELSI_GPU_ERR_HIP = 5,         /* HIP runtime error */
+    ELSI_GPU_ERR_OOM = 6,         /* device memory exhausted */
+    ELSI_GPU_ERR_NONFINITE = 7    /* H or S holds NaN or Inf */
+};
+
+/* stages timed in elsi_gpu_info.stage_ms (the five steps of Fig. 1 plus the
+ * transformations around them) */
+enum {
+    ELSI_GPU_ST_CHOLESKY = 0,   /* Eq. (10) */
+    ELSI_GPU_ST_REDUCE = 1,     /* Eq. (11), H~ = L^-1 H L^-T */
+    ELSI_GPU_ST_BAND = 2,       /* step (1): full -> band, Eq. (13) */
+    ELSI_GPU_ST_BULGE = 3,      /* step (2): band -> tridiagonal, Eq. (13) */
+    ELSI_GPU_ST_TRIDIAG = 4,    /* step (3): divide and conquer */
+    ELSI_GPU_ST_OCC = 5,        /* Eq. (17)-(18) */
+    ELSI_GPU_ST_BACK_Q2 = 6,    /* step (4) */
+    ELSI_GPU_ST_BACK_Q1 = 7,    /* step (5) */
+    ELSI_GPU_ST_BACKSUB = 8,    /* c = L^-T c~ */
+    ELSI_GPU_ST_DENSITY = 9,    /* Eq. (9) */
+    ELSI_GPU_NSTAGES = 10
+};
+
+typedef struct elsi_gpu_info {
+    double stage_ms[ELSI_GPU_NSTAGES]; /* device time per stage of the last call */
+    double total_ms;                   /* device time of the last call */
+    double mu;                         /* chemical potential of the last dm call (Ha) */
+    double energy;                     /* band energy of the last dm call (Ha) */
+    double charge_residual;            /* electron surplus left after the fix-up */
+    int k_s;                           /* eigenvectors that entered D (f_l > 1e-20) */
+    int fail_col;                      /* first non-positive pivot of S (1-based), else 0 */
+    int mu_steps;                      /* bisection steps taken */
+    int band_width;                    /* b of step (1) */
+    int n_basis;
+} elsi_gpu_info;
+
+/* Create a handle (elsi_init, Sec. 4.4).  n_state: eigenvectors returned by
+ * elsi_gpu_ev (1..n_basis); n_electron: electron count for elsi_gpu_dm;
+ * hip_stream: the hipStream_t every kernel is launched on (NULL = default
+ * stream).  Defaults: Fermi-Dirac, width 0.01 Ha, occ_accuracy 1e-13,
+ * mu_max_steps 100, spin factor 1, band width 64.
+ * Errors: -1 h NULL, -2 dtype, -3 n_basis < 1, -4 n_state outside 1..n_basis,
+ * -5 n_electron < 0 or above n_basis. */
+int elsi_gpu_init(elsi_gpu_handle *h, int dtype, int n_basis, int n_state,
+                  double n_electron, void *hip_stream);
+
+/* Device workspace the handle needs for elsi_gpu_ev / elsi_gpu_dm (bytes). */
+int elsi_gpu_workspace_size(elsi_gpu_handle h, size_t *bytes);
+
+/* Register a caller-owned device workspace of at least elsi_gpu_workspace_size
+ * bytes (e.g. a torch tensor); it must stay valid until elsi_gpu_finalize or
+ * the next call of this function.  Without it the library allocates its own
+ * workspace on first use and frees it in elsi_gpu_finalize.
+ * Errors: -2 NULL pointer, -3 too small. */
+int elsi_gpu_set_workspace(elsi_gpu_handle h, void *dev_ptr, size_t bytes);
+
+/* Occupation and chemical potential options (elsi_customize_mu, Sec. 4.6):
+ * scheme ELSI_GPU_OCC_*, width = k_B T in Ha (> 0), occ_accuracy (> 0),
+ * mu_max_steps (>= 1), spin_factor (> 0; f ranges over [0, spin_factor]). */
+int elsi_gpu_set_occupation(elsi_gpu_handle h, int scheme, double width,
+                            double occ_accuracy, int mu_max_steps, double spin_factor);
+
+/* overlap_is_unit (Sec. 4.6): S is the identity and is not read. */
+int elsi_gpu_set_overlap_is_unit(elsi_gpu_handle h, int flag);
+
+/* S already holds its Cholesky factor L from an earlier call on this handle
+ * (the reuse of L across the SCF cycle, Sec. 4.5); the factorization is skipped. */
+int elsi_gpu_set_overlap_factored(elsi_gpu_handle h, int flag);
+
+/* Band width b of step (1) (Eq. (13)); 8 <= b <= 64, multiple of 8. */
+int elsi_gpu_set_band_width(elsi_gpu_handle h, int b);
+
+/* Eigenvalues and eigenvectors (elsi_ev_real, Sec. 4.5).
+ *   H    device, n x n, in; destroyed on exit;
+ *   S    device, n x n, in (SPD); on exit holds L of Eq. (10) (lower, zero above);
+ *   eval device, n doubles, out: all eigenvalues, ascending;
+ *   evec device, n x n_state, out: S-orthonormal eigenvectors of the lowest
+ *        n_state eigenvalues (c^T S c = I).
+ * Errors: -1 handle, -2 H, -3 S, -4 eval, -5 evec; ELSI_GPU_ERR_NOT_PD, _NO_CONV,
+ * _HIP, _OOM, _NONFINITE. */
+int elsi_gpu_ev(elsi_gpu_handle h, double *H, double *S, double *eval, double *evec);
+
+/* Density matrix (elsi_dm_real, Sec. 4.5).
+ *   H, S    as for elsi_gpu_ev;
+ *   occ     device, n doubles: in for ELSI_GPU_OCC_EXPLICIT (f of the states in
+ *           ascending order), out (the Fermi-Dirac occupations) otherwise; may
+ *           be NULL in Fermi-Dirac mode;
+ *   D       device, n x n, out: both triangles;
+ *   eval    device, n doubles, out (may be NULL);
+ *   energy  host, out: sum_l f_l eps_l;   mu  host, out (may be NULL).
+ * Only the eigenvectors with f_l > 1e-20 are formed and used for D.
+ * Errors: -1 handle, -2 H, -3 S, -4 occ (NULL in explicit mode), -5 D, -7 energy;
+ * positive codes as for elsi_gpu_ev, plus ELSI_GPU_ERR_MU (outputs still written). */
+int elsi_gpu_dm(elsi_gpu_handle h, double *H, double *S, double *occ, double *D,
+                double *eval, double *energy, double *mu);
+
+/* Timings and diagnostics of the last ev/dm call. */
+int elsi_gpu_get_info(elsi_gpu_handle h, elsi_gpu_info *out);
+
+/* Destroy the handle and free what the library allocated (elsi_finalize,
+ * Sec. 4.7); *h is set to NULL. */
+int elsi_gpu_finalize(elsi_gpu_handle *h);
+
+/* Static text for a return code. */
+const char *elsi_gpu_strerror(int status);
+
+/* ------------------------------------------------------------------------
+ * Stage entry points: one step of the path each, on caller-owned device
+ * buffers, launched on hip_stream and synchronized before returning.  They
+ * allocate their own scratch.  Same return conventions as above.
+ * ------------------------------------------------------------------------ */
+
+/* C = alpha op(A) op(B) + beta C in FP64 on the matrix cores; ta, tb = 'N' or
+ * 'T'; C is m x n.  Errors: -1 ta, -2 tb, -3..-5 sizes < 0. */
+int elsi_gpu_x_dgemm(char ta, char tb, int m, int n, int k, double alpha, const double *A,
+                     int lda, const double *B, int ldb, double beta, double *C, int ldc,
+                     void *hip_stream);
+
+/* S <- L with S = L L^T, Eq. (10) (lower; strict upper set to zero).
+ * *fail_col (host, may be NULL) receives the 1-based first bad pivot. */
+int elsi_gpu_x_cholesky(int n, double *S, int lds, int *fail_col, void *hip_stream);
+
+/* H <- L^-1 H L^-T, Eq. (11); H full symmetric on exit; L from Eq. (10). */
+int elsi_gpu_x_reduce(int n, double *H, int ldh, const double *L, int ldl, void *hip_stream);
+
+/* X <- L^-T X (back substitution below Eq. (11)); X is n x k. */
+int elsi_gpu_x_backsub(int n, int k, const double *L, int ldl, double *X, int ldx,
+                       void *hip_stream);
+
+/* Occupations, Eq. (17), and mu, Eq. (18) (Sec. 4.5): eps device (n,
+ * ascending), f device out; mu, k_s (f > 1e-20 count) and status to host. */
+int elsi_gpu_x_occupations(int n, const double *eps, double n_electron, double kT,
+                           double spin, double occ_accuracy, int mu_max_steps, double *f,
+                           double *mu, int *k_s, void *hip_stream);
+
+/* D = sum_{l<k} f_l c_l c_l^T, Eq. (9): C device n x k (ldc), f device (k),
+ * D device n x n (ldd), both triangles written. */
+int elsi_gpu_x_density(int n, int k, const double *C, int ldc, const double *f, double *D,
+                       int ldd, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELSI_GPU_H */

@@ -1,0 +1,252 @@
+"""Thin ctypes binding of libelsi_gpu (argument marshalling only).
+
+Matrices cross the boundary column-major.  A torch tensor ``X`` of logical
+shape (rows, cols) is passed as-is when it is column-major contiguous
+(``X.stride() == (1, rows)``, e.g. made by :func:`fortran_empty` or a
+symmetric matrix's transpose view); otherwise a column-major copy is made.
+All compute happens in the HIP library: this module never computes any part
+of the method, and it raises when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libelsi_gpu.so")
+_lib = None
+
+REAL64 = 0
+OCC_EXPLICIT = 0
+OCC_FERMI = 1
+NSTAGES = 10
+STAGES = ["cholesky", "reduce", "band", "bulge", "tridiag", "occ", "back_q2", "back_q1",
+          "backsub", "density"]
+
+
+class ElsiGpuError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.elsi_gpu_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("stage_ms", ctypes.c_double * NSTAGES), ("total_ms", ctypes.c_double),
+                ("mu", ctypes.c_double), ("energy", ctypes.c_double),
+                ("charge_residual", ctypes.c_double), ("k_s", ctypes.c_int),
+                ("fail_col", ctypes.c_int), ("mu_steps", ctypes.c_int),
+                ("band_width", ctypes.c_int), ("n_basis", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "stage_ms"}
+        d["stage_ms"] = {s: self.stage_ms[i] for i, s in enumerate(STAGES)}
+        return d
+
+
+def lib():
+    """Load libelsi_gpu.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1705_11191_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d, c = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_char
+        sz = ctypes.c_size_t
+        L.elsi_gpu_strerror.restype = ctypes.c_char_p
+        L.elsi_gpu_strerror.argtypes = [i]
+        L.elsi_gpu_init.argtypes = [ctypes.POINTER(vp), i, i, i, d, vp]
+        L.elsi_gpu_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+        L.elsi_gpu_set_workspace.argtypes = [vp, vp, sz]
+        L.elsi_gpu_set_occupation.argtypes = [vp, i, d, d, i, d]
+        L.elsi_gpu_set_overlap_is_unit.argtypes = [vp, i]
+        L.elsi_gpu_set_overlap_factored.argtypes = [vp, i]
+        L.elsi_gpu_set_band_width.argtypes = [vp, i]
+        L.elsi_gpu_ev.argtypes = [vp, vp, vp, vp, vp]
+        L.elsi_gpu_dm.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d)]
+        L.elsi_gpu_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+        L.elsi_gpu_finalize.argtypes = [ctypes.POINTER(vp)]
+        L.elsi_gpu_x_dgemm.argtypes = [c, c, i, i, i, d, vp, i, vp, i, d, vp, i, vp]
+        L.elsi_gpu_x_cholesky.argtypes = [i, vp, i, ctypes.POINTER(i), vp]
+        L.elsi_gpu_x_reduce.argtypes = [i, vp, i, vp, i, vp]
+        L.elsi_gpu_x_backsub.argtypes = [i, i, vp, i, vp, i, vp]
+        L.elsi_gpu_x_occupations.argtypes = [i, vp, d, d, d, d, i, vp, ctypes.POINTER(d),
+                                             ctypes.POINTER(i), vp]
+        L.elsi_gpu_x_density.argtypes = [i, i, vp, i, vp, vp, i, vp]
+        _lib = L
+    return _lib
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def fortran_empty(rows: int, cols: int, device="cuda", dtype=torch.float64) -> torch.Tensor:
+    """Column-major (rows x cols) tensor: a transposed view of a (cols, rows) buffer."""
+    return torch.empty((cols, rows), device=device, dtype=dtype).t()
+
+
+def as_fortran(X: torch.Tensor) -> torch.Tensor:
+    """Column-major version of X (no copy when it already is one)."""
+    if X.dim() == 2 and X.stride(0) == 1 and (X.shape[1] <= 1 or X.stride(1) == X.shape[0]):
+        return X
+    Y = fortran_empty(X.shape[0], X.shape[1], device=X.device, dtype=X.dtype)
+    Y.copy_(X)
+    return Y
+
+
+def _check(rc: int, where: str, ok=(0,)):
+    if rc not in ok:
+        raise ElsiGpuError(rc, where)
+    return rc
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+# ---------------------------------------------------------------------------
+# stage entry points
+# ---------------------------------------------------------------------------
+def dgemm(ta: str, tb: str, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
+          alpha: float = 1.0, beta: float = 0.0) -> torch.Tensor:
+    """C = alpha op(A) op(B) + beta C on the matrix cores (column-major operands)."""
+    A, B = as_fortran(A), as_fortran(B)
+    m = A.shape[1] if ta == "T" else A.shape[0]
+    k = A.shape[0] if ta == "T" else A.shape[1]
+    n = B.shape[0] if tb == "T" else B.shape[1]
+    if C is None:
+        C = fortran_empty(m, n, device=A.device)
+        beta = 0.0
+    C2 = as_fortran(C)
+    rc = lib().elsi_gpu_x_dgemm(ta.encode(), tb.encode(), m, n, k, alpha, _ptr(A), max(1, A.shape[0]),
+                                _ptr(B), max(1, B.shape[0]), beta, _ptr(C2), max(1, m), _stream())
+    _check(rc, "elsi_gpu_x_dgemm")
+    if C2.data_ptr() != C.data_ptr():
+        C.copy_(C2)
+    return C
+
+
+def cholesky(S: torch.Tensor) -> int:
+    """S <- L in place (S symmetric, so either layout works); returns 0 or the failing pivot."""
+    n = S.shape[0]
+    fail = ctypes.c_int(0)
+    rc = lib().elsi_gpu_x_cholesky(n, _ptr(S), n, ctypes.byref(fail), _stream())
+    _check(rc, "elsi_gpu_x_cholesky", ok=(0, 1))
+    return fail.value
+
+
+def reduce_standard(H: torch.Tensor, L: torch.Tensor) -> None:
+    """H <- L^-1 H L^-T in place (H symmetric; L column-major lower)."""
+    n = H.shape[0]
+    rc = lib().elsi_gpu_x_reduce(n, _ptr(H), n, _ptr(L), n, _stream())
+    _check(rc, "elsi_gpu_x_reduce")
+
+
+def backsub(L: torch.Tensor, X: torch.Tensor) -> None:
+    """X <- L^-T X in place (X column-major n x k)."""
+    n, k = X.shape
+    rc = lib().elsi_gpu_x_backsub(n, k, _ptr(L), n, _ptr(X), n, _stream())
+    _check(rc, "elsi_gpu_x_backsub")
+
+
+def occupations(eps: torch.Tensor, n_electron: float, kT: float, spin: float = 1.0,
+                occ_accuracy: float = 1e-13, max_steps: int = 100):
+    """Fermi-Dirac occupations and mu on the device: returns (f, mu, k_s, status)."""
+    f = torch.empty_like(eps)
+    mu = ctypes.c_double(0.0)
+    ks = ctypes.c_int(0)
+    rc = lib().elsi_gpu_x_occupations(eps.shape[0], _ptr(eps), n_electron, kT, spin, occ_accuracy,
+                                      max_steps, _ptr(f), ctypes.byref(mu), ctypes.byref(ks), _stream())
+    _check(rc, "elsi_gpu_x_occupations", ok=(0, 4))
+    return f, mu.value, ks.value, rc
+
+
+def density(C: torch.Tensor, f: torch.Tensor) -> torch.Tensor:
+    """D = sum_l f_l c_l c_l^T from column-major C (n x k)."""
+    C = as_fortran(C)
+    n, k = C.shape
+    D = torch.empty((n, n), device=C.device, dtype=torch.float64)
+    rc = lib().elsi_gpu_x_density(n, k, _ptr(C), n, _ptr(f), _ptr(D), n, _stream())
+    _check(rc, "elsi_gpu_x_density")
+    return D
+
+
+# ---------------------------------------------------------------------------
+# handle API
+# ---------------------------------------------------------------------------
+class Handle:
+    """One elsi_gpu handle (elsi_init ... elsi_finalize)."""
+
+    def __init__(self, n_basis: int, n_state: int, n_electron: float, stream=None):
+        self._h = ctypes.c_void_p(0)
+        s = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        self.n = n_basis
+        self.n_state = n_state
+        _check(lib().elsi_gpu_init(ctypes.byref(self._h), REAL64, n_basis, n_state, n_electron,
+                                   ctypes.c_void_p(s)), "elsi_gpu_init")
+
+    def set_occupation(self, scheme=OCC_FERMI, width=0.01, occ_accuracy=1e-13, mu_max_steps=100,
+                       spin_factor=1.0):
+        _check(lib().elsi_gpu_set_occupation(self._h, scheme, width, occ_accuracy, mu_max_steps,
+                                             spin_factor), "elsi_gpu_set_occupation")
+
+    def set_overlap_is_unit(self, flag=True):
+        _check(lib().elsi_gpu_set_overlap_is_unit(self._h, int(flag)), "set_overlap_is_unit")
+
+    def set_overlap_factored(self, flag=True):
+        _check(lib().elsi_gpu_set_overlap_factored(self._h, int(flag)), "set_overlap_factored")
+
+    def set_band_width(self, b: int):
+        _check(lib().elsi_gpu_set_band_width(self._h, b), "set_band_width")
+
+    def workspace_size(self) -> int:
+        v = ctypes.c_size_t(0)
+        _check(lib().elsi_gpu_workspace_size(self._h, ctypes.byref(v)), "workspace_size")
+        return v.value
+
+    def set_workspace(self, buf: torch.Tensor):
+        self._ws = buf
+        _check(lib().elsi_gpu_set_workspace(self._h, _ptr(buf), buf.numel() * buf.element_size()),
+               "set_workspace")
+
+    def ev(self, H: torch.Tensor, S: torch.Tensor, eval_out=None, evec_out=None):
+        """Eigenpairs; H is destroyed and S receives L.  Returns (eval, evec column-major)."""
+        n = self.n
+        ev = eval_out if eval_out is not None else torch.empty(n, device=H.device, dtype=torch.float64)
+        C = evec_out if evec_out is not None else fortran_empty(n, self.n_state, device=H.device)
+        rc = lib().elsi_gpu_ev(self._h, _ptr(H), _ptr(S), _ptr(ev), _ptr(C))
+        _check(rc, "elsi_gpu_ev")
+        return ev, C
+
+    def dm(self, H: torch.Tensor, S: torch.Tensor, occ=None, D_out=None, eval_out=None,
+           ok=(0,)):
+        """Density matrix; returns (D, eval, occ, energy, mu, status)."""
+        n = self.n
+        D = D_out if D_out is not None else torch.empty((n, n), device=H.device, dtype=torch.float64)
+        ev = eval_out if eval_out is not None else torch.empty(n, device=H.device, dtype=torch.float64)
+        f = occ if occ is not None else torch.empty(n, device=H.device, dtype=torch.float64)
+        energy = ctypes.c_double(0.0)
+        mu = ctypes.c_double(0.0)
+        rc = lib().elsi_gpu_dm(self._h, _ptr(H), _ptr(S), _ptr(f), _ptr(D), _ptr(ev),
+                               ctypes.byref(energy), ctypes.byref(mu))
+        _check(rc, "elsi_gpu_dm", ok=ok)
+        return D, ev, f, energy.value, mu.value, rc
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(lib().elsi_gpu_get_info(self._h, ctypes.byref(inf)), "get_info")
+        return inf.as_dict()
+
+    def close(self):
+        if self._h:
+            lib().elsi_gpu_finalize(ctypes.byref(self._h))
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,245 @@
+// C ABI of libelsi_gpu: handle management, argument checking, workspace and
+// the stage entry points.  The solver drivers elsi_gpu_ev / elsi_gpu_dm live
+// in solver.hip.
+#include "api_internal.h"
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+using namespace eg;
+
+extern "C" {
+
+const char* elsi_gpu_strerror(int status)
+{
+    if (status == 0) return "success";
+    if (status < 0) return "invalid argument";
+    switch (status) {
+        case ELSI_GPU_ERR_NOT_PD: return "overlap matrix is not positive definite";
+        case ELSI_GPU_ERR_NO_CONV: return "tridiagonal eigensolver did not converge";
+        case ELSI_GPU_ERR_REFINE: return "refinement tolerance not reached";
+        case ELSI_GPU_ERR_MU: return "chemical potential bisection ran out of steps";
+        case ELSI_GPU_ERR_HIP: return "HIP runtime error";
+        case ELSI_GPU_ERR_OOM: return "out of device memory";
+        case ELSI_GPU_ERR_NONFINITE: return "input holds NaN or Inf";
+        default: return "unknown status";
+    }
+}
+
+int elsi_gpu_init(elsi_gpu_handle* h, int dtype, int n_basis, int n_state, double n_electron,
+                  void* hip_stream)
+{
+    if (!h) return -1;
+    *h = nullptr;
+    if (dtype != ELSI_GPU_REAL64) return -2;
+    if (n_basis < 1) return -3;
+    if (n_state < 1 || n_state > n_basis) return -4;
+    if (!(n_electron >= 0.0) || n_electron > (double)n_basis * 2.0) return -5;
+    elsi_gpu_handle_s* p = new (std::nothrow) elsi_gpu_handle_s();
+    if (!p) return ELSI_GPU_ERR_OOM;
+    p->dtype = dtype;
+    p->n = n_basis;
+    p->n_state = n_state;
+    p->n_electron = n_electron;
+    p->stream = (hipStream_t)hip_stream;
+    std::memset(&p->info, 0, sizeof(p->info));
+    p->info.n_basis = n_basis;
+    *h = p;
+    return 0;
+}
+
+int elsi_gpu_workspace_size(elsi_gpu_handle h, size_t* bytes)
+{
+    if (!h) return -1;
+    if (!bytes) return -2;
+    *bytes = workspace_bytes(h);
+    return 0;
+}
+
+int elsi_gpu_set_workspace(elsi_gpu_handle h, void* dev_ptr, size_t bytes)
+{
+    if (!h) return -1;
+    if (!dev_ptr) return -2;
+    if (bytes < workspace_bytes(h)) return -3;
+    release_workspace(h);
+    h->ws = dev_ptr;
+    h->ws_bytes = bytes;
+    h->ws_owned = 0;
+    return 0;
+}
+
+int elsi_gpu_set_occupation(elsi_gpu_handle h, int scheme, double width, double occ_accuracy,
+                            int mu_max_steps, double spin_factor)
+{
+    if (!h) return -1;
+    if (scheme != ELSI_GPU_OCC_EXPLICIT && scheme != ELSI_GPU_OCC_FERMI) return -2;
+    if (!(width > 0.0)) return -3;
+    if (!(occ_accuracy > 0.0)) return -4;
+    if (mu_max_steps < 1) return -5;
+    if (!(spin_factor > 0.0)) return -6;
+    h->occ_scheme = scheme;
+    h->kT = width;
+    h->occ_accuracy = occ_accuracy;
+    h->mu_max_steps = mu_max_steps;
+    h->spin = spin_factor;
+    return 0;
+}
+
+int elsi_gpu_set_overlap_is_unit(elsi_gpu_handle h, int flag)
+{
+    if (!h) return -1;
+    h->overlap_is_unit = flag ? 1 : 0;
+    return 0;
+}
+
+int elsi_gpu_set_overlap_factored(elsi_gpu_handle h, int flag)
+{
+    if (!h) return -1;
+    h->overlap_factored = flag ? 1 : 0;
+    return 0;
+}
+
+int elsi_gpu_set_band_width(elsi_gpu_handle h, int b)
+{
+    if (!h) return -1;
+    if (b < 8 || b > 64 || (b % 8) != 0) return -2;
+    h->band_width = b;
+    return 0;
+}
+
+int elsi_gpu_get_info(elsi_gpu_handle h, elsi_gpu_info* out)
+{
+    if (!h) return -1;
+    if (!out) return -2;
+    *out = h->info;
+    return 0;
+}
+
+int elsi_gpu_finalize(elsi_gpu_handle* h)
+{
+    if (!h || !*h) return -1;
+    release_workspace(*h);
+    delete *h;
+    *h = nullptr;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// stage entry points
+// ---------------------------------------------------------------------------
+int elsi_gpu_x_dgemm(char ta, char tb, int m, int n, int k, double alpha, const double* A, int lda,
+                     const double* B, int ldb, double beta, double* C, int ldc, void* hip_stream)
+{
+    if (ta != 'N' && ta != 'T') return -1;
+    if (tb != 'N' && tb != 'T') return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    if (m == 0 || n == 0) return 0;
+    if (!C) return -12;
+    if (k > 0 && (!A || !B)) return !A ? -7 : -9;
+    hipStream_t st = (hipStream_t)hip_stream;
+    dgemm(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 0);
+    return sync_status(st);
+}
+
+int elsi_gpu_x_cholesky(int n, double* S, int lds, int* fail_col, void* hip_stream)
+{
+    if (n < 0) return -1;
+    if (n == 0) return 0;
+    if (!S) return -2;
+    if (lds < n) return -3;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBuf<double> Linv;
+    DevBuf<int> info;
+    if (!Linv.alloc((size_t)ceil_div(n, 64) * 64 * 64) || !info.alloc(1)) return ELSI_GPU_ERR_OOM;
+    fill_i(st, info.p, 1, 0);
+    dpotrf(st, n, S, lds, Linv.p, info.p);
+    int hinfo = 0;
+    if (hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return ELSI_GPU_ERR_HIP;
+    int rc = sync_status(st);
+    if (rc) return rc;
+    if (fail_col) *fail_col = hinfo;
+    return hinfo ? ELSI_GPU_ERR_NOT_PD : 0;
+}
+
+int elsi_gpu_x_reduce(int n, double* H, int ldh, const double* L, int ldl, void* hip_stream)
+{
+    if (n < 0) return -1;
+    if (n == 0) return 0;
+    if (!H) return -2;
+    if (ldh < n) return -3;
+    if (!L) return -4;
+    if (ldl < n) return -5;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBuf<double> Linv;
+    if (!Linv.alloc((size_t)ceil_div(n, 64) * 64 * 64)) return ELSI_GPU_ERR_OOM;
+    reduce_to_standard(st, n, H, ldh, L, ldl, Linv.p);
+    return sync_status(st);
+}
+
+int elsi_gpu_x_backsub(int n, int k, const double* L, int ldl, double* X, int ldx, void* hip_stream)
+{
+    if (n < 0) return -1;
+    if (k < 0) return -2;
+    if (n == 0 || k == 0) return 0;
+    if (!L) return -3;
+    if (ldl < n) return -4;
+    if (!X) return -5;
+    if (ldx < n) return -6;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBuf<double> Linv;
+    if (!Linv.alloc((size_t)ceil_div(n, 64) * 64 * 64)) return ELSI_GPU_ERR_OOM;
+    dtrtri_diag_blocks(st, n, L, ldl, Linv.p);
+    dtrsm_left_lower_t(st, n, k, L, ldl, Linv.p, X, ldx);
+    return sync_status(st);
+}
+
+int elsi_gpu_x_occupations(int n, const double* eps, double n_electron, double kT, double spin,
+                           double occ_accuracy, int mu_max_steps, double* f, double* mu, int* k_s,
+                           void* hip_stream)
+{
+    if (n < 1) return -1;
+    if (!eps) return -2;
+    if (!(n_electron >= 0.0) || n_electron > spin * n) return -3;
+    if (!(kT > 0.0)) return -4;
+    if (!(spin > 0.0)) return -5;
+    if (!(occ_accuracy > 0.0)) return -6;
+    if (mu_max_steps < 1) return -7;
+    if (!f) return -8;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBuf<double> scal;
+    if (!scal.alloc(8)) return ELSI_GPU_ERR_OOM;
+    fermi_occupations(st, n, eps, n_electron, kT, spin, occ_accuracy, mu_max_steps, kFCut, f, scal.p);
+    double hs[8];
+    if (hipMemcpyAsync(hs, scal.p, 6 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return ELSI_GPU_ERR_HIP;
+    int rc = sync_status(st);
+    if (rc) return rc;
+    if (mu) *mu = hs[0];
+    if (k_s) *k_s = (int)hs[2];
+    return (int)hs[1];
+}
+
+int elsi_gpu_x_density(int n, int k, const double* C, int ldc, const double* f, double* D, int ldd,
+                       void* hip_stream)
+{
+    if (n < 0) return -1;
+    if (k < 0) return -2;
+    if (n == 0) return 0;
+    if (k > 0 && !C) return -3;
+    if (ldc < n) return -4;
+    if (k > 0 && !f) return -5;
+    if (!D) return -6;
+    if (ldd < n) return -7;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBuf<double> W;
+    if (k > 0 && !W.alloc((size_t)n * k)) return ELSI_GPU_ERR_OOM;
+    density_matrix(st, n, k, C, ldc, f, W.p, D, ldd);
+    return sync_status(st);
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Handle layout and internal driver declarations shared by api.hip and solver.hip.
+#pragma once
+#include "../../include/elsi_gpu.h"
+#include "common.h"
+
+namespace eg {
+
+constexpr double kFCut = 1e-20;   // eigenvectors with f_l <= kFCut do not enter D
+
+// RAII device buffer for the stage entry points.
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    bool alloc(size_t count) {
+        if (count == 0) count = 1;
+        return hipMalloc((void**)&p, count * sizeof(T)) == hipSuccess;
+    }
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+inline int sync_status(hipStream_t st)
+{
+    hipError_t e = hipGetLastError();
+    if (e == hipErrorOutOfMemory) return kStatusOom;
+    if (e != hipSuccess) return kStatusHip;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return kStatusHip;
+    return 0;
+}
+
+// H <- L^-1 H L^-T (full symmetric on exit); Linv receives the 64 x 64 block inverses.
+void reduce_to_standard(hipStream_t st, int n, double* H, int ldh, const double* L, int ldl, double* Linv);
+
+// D = (C sqrt(f)) (C sqrt(f))^T, both triangles; W is n x k scratch.
+void density_matrix(hipStream_t st, int n, int k, const double* C, int ldc, const double* f, double* W,
+                    double* D, int ldd);
+
+}  // namespace eg
+
+struct elsi_gpu_handle_s {
+    int dtype = 0;
+    int n = 0;
+    int n_state = 0;
+    double n_electron = 0.0;
+    hipStream_t stream = nullptr;
+    int occ_scheme = ELSI_GPU_OCC_FERMI;
+    double kT = 0.01;
+    double occ_accuracy = 1e-13;
+    int mu_max_steps = 100;
+    double spin = 1.0;
+    int overlap_is_unit = 0;
+    int overlap_factored = 0;
+    int band_width = 64;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int ws_owned = 0;
+    elsi_gpu_info info;
+};
+
+namespace eg {
+size_t workspace_bytes(const elsi_gpu_handle_s* h);
+void release_workspace(elsi_gpu_handle_s* h);
+}  // namespace eg

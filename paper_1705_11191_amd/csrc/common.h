@@ -1,0 +1,92 @@
+// Internal helpers shared by the HIP translation units of libelsi_gpu.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace eg {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kStatusOk = 0;
+constexpr int kStatusNotPD = 1;
+constexpr int kStatusNoConv = 2;
+constexpr int kStatusRefine = 3;
+constexpr int kStatusMu = 4;
+constexpr int kStatusHip = 5;
+constexpr int kStatusOom = 6;
+
+// Record the first HIP error; launchers return it as status 5.
+struct HipCheck {
+    hipError_t err = hipSuccess;
+    inline bool ok(hipError_t e) {
+        if (e != hipSuccess && err == hipSuccess) err = e;
+        return e == hipSuccess;
+    }
+};
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Column-major element address.
+__host__ __device__ inline size_t cm(int i, int j, int ld) {
+    return (size_t)j * (size_t)ld + (size_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers implemented in the .hip files
+// ---------------------------------------------------------------------------
+
+// C = alpha * op(A) op(B) + beta * C (FP64 MFMA).  op = 'N' or 'T'.
+// uplo: 0 = all tiles, 1 = only tiles that touch the lower triangle (i >= j).
+// C may alias A only when n <= 64 (each workgroup then reads exactly the A rows
+// it writes) and beta == 0; C may alias B only when m <= 64 and beta == 0.
+void dgemm(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha,
+           const double* A, int lda, const double* B, int ldb, double beta,
+           double* C, int ldc, int uplo = 0);
+
+// Deterministic split-K product W = A^T B for tall A (k x m), B (k x n),
+// m, n <= 64: partial products over row chunks are summed in a fixed order.
+// `part` needs ceil(k / chunk) * m * n doubles.
+void dgemm_tn_small(hipStream_t st, int m, int n, int k, double alpha, const double* A, int lda,
+                    const double* B, int ldb, double beta, double* C, int ldc, double* part,
+                    int chunk = 2048);
+
+// Cholesky S = L L^T in place (lower).  Linv receives the inverses of the
+// nb x nb diagonal blocks (nb = 64), laid out block after block (64 x 64 each).
+// info (device int) is set to j+1 for the first non-positive pivot j, else left 0.
+void dpotrf(hipStream_t st, int n, double* A, int lda, double* Linv, int* info);
+
+// Inverses of the 64 x 64 diagonal blocks of a lower triangular L.
+void dtrtri_diag_blocks(hipStream_t st, int n, const double* L, int ldl, double* Linv);
+
+// Triangular solves with the lower Cholesky factor, using the block inverses.
+//   left_lower_n : B <- L^-1 B     (n x ncol)
+//   right_lower_t: B <- B L^-T     (nrow x n)
+//   left_lower_t : B <- L^-T B     (n x ncol)
+void dtrsm_left_lower_n(hipStream_t st, int n, int ncol, const double* L, int ldl,
+                        const double* Linv, double* B, int ldb);
+void dtrsm_right_lower_t(hipStream_t st, int nrow, int n, const double* L, int ldl,
+                         const double* Linv, double* B, int ldb);
+void dtrsm_left_lower_t(hipStream_t st, int n, int ncol, const double* L, int ldl,
+                        const double* Linv, double* B, int ldb);
+
+// Utility kernels.
+void fill_d(hipStream_t st, double* p, size_t count, double v);
+void fill_i(hipStream_t st, int* p, size_t count, int v);
+void copy_matrix(hipStream_t st, int m, int n, const double* A, int lda, double* B, int ldb);
+void mirror_lower_to_upper(hipStream_t st, int n, double* A, int lda);
+void symmetrize_average(hipStream_t st, int n, double* A, int lda);
+void set_identity(hipStream_t st, int n, double* A, int lda);
+void scale_columns_sqrt(hipStream_t st, int n, int k, const double* C, int ldc, const double* f,
+                        double* out, int ldo);
+void check_finite(hipStream_t st, int m, int n, const double* A, int lda, int* flag);
+
+// Occupations and chemical potential on the device (one workgroup).
+//   eps ascending (n); f (n) out; scal (device, 4 doubles) out: mu, status, k_s, energy.
+void fermi_occupations(hipStream_t st, int n, const double* eps, double n_electron, double kT,
+                       double spin, double occ_accuracy, int max_steps, double f_cut,
+                       double* f, double* scal);
+
+}  // namespace eg

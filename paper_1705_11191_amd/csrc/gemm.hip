@@ -1,0 +1,238 @@
+// FP64 matrix products on the CDNA4 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// One workgroup of 256 threads (4 wave64s arranged 2 x 2) computes a BM x BN
+// tile of C; each wave owns a (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA
+// blocks kept in accumulator registers.  K advances in steps of 16: the next
+// A and B slices are fetched from HBM into registers while the current ones
+// are multiplied out of LDS.  Workgroups are renumbered so that each of the
+// eight XCDs walks a contiguous range of tiles (its L2 then holds the shared
+// operand panels).
+#include "common.h"
+
+namespace eg {
+namespace {
+
+constexpr int kBK = 16;
+
+template <int BM, int BN, bool TA, bool TB>
+__global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double alpha,
+                                                    const double* __restrict__ A, int lda,
+                                                    const double* __restrict__ B, int ldb,
+                                                    double beta, double* C, int ldc, int uplo,
+                                                    int tiles_m, int tiles_per_xcd)
+{
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr int A_PER = BM * kBK / 256;   // elements of the A slice per thread
+    constexpr int B_PER = BN * kBK / 256;
+    __shared__ double As[kBK][BM + 1];
+    __shared__ double Bs[kBK][BN + 1];
+
+    const int bid = blockIdx.x;
+    const int tile = (bid % 8) * tiles_per_xcd + bid / 8;
+    const int ntiles = tiles_m * ((n + BN - 1) / BN);
+    if (tile >= ntiles) return;
+    const int tm = tile % tiles_m, tn = tile / tiles_m;
+    const int row0 = tm * BM, col0 = tn * BN;
+    if (uplo && col0 > row0 + BM - 1) return;   // tile strictly above the diagonal
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+
+    double4_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+    double ra[A_PER], rb[B_PER];
+
+    auto load_slice = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < A_PER; ++r) {
+            int i, kk;
+            if (!TA) { i = tid % BM; kk = tid / BM + r * (256 / BM); }
+            else     { kk = tid % kBK; i = tid / kBK + r * (256 / kBK); }
+            int gi = row0 + i, gk = k0 + kk;
+            double v = 0.0;
+            if (gi < m && gk < k) v = TA ? A[cm(gk, gi, lda)] : A[cm(gi, gk, lda)];
+            ra[r] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < B_PER; ++r) {
+            int j, kk;
+            if (TB) { j = tid % BN; kk = tid / BN + r * (256 / BN); }
+            else    { kk = tid % kBK; j = tid / kBK + r * (256 / kBK); }
+            int gj = col0 + j, gk = k0 + kk;
+            double v = 0.0;
+            if (gj < n && gk < k) v = TB ? B[cm(gj, gk, ldb)] : B[cm(gk, gj, ldb)];
+            rb[r] = v;
+        }
+    };
+    auto store_slice = [&]() {
+#pragma unroll
+        for (int r = 0; r < A_PER; ++r) {
+            int i, kk;
+            if (!TA) { i = tid % BM; kk = tid / BM + r * (256 / BM); }
+            else     { kk = tid % kBK; i = tid / kBK + r * (256 / kBK); }
+            As[kk][i] = ra[r];
+        }
+#pragma unroll
+        for (int r = 0; r < B_PER; ++r) {
+            int j, kk;
+            if (TB) { j = tid % BN; kk = tid / BN + r * (256 / BN); }
+            else    { kk = tid % kBK; j = tid / kBK + r * (256 / kBK); }
+            Bs[kk][j] = rb[r];
+        }
+    };
+
+    const int nk = (k + kBK - 1) / kBK;
+    if (nk > 0) load_slice(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        store_slice();
+        __syncthreads();
+        if (kt + 1 < nk) load_slice((kt + 1) * kBK);
+#pragma unroll
+        for (int kk = 0; kk < kBK; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            double a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) a[i] = As[kr][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) b[j] = Bs[kr][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // D layout of the 16x16 f64 MFMA: lane l, element r holds row 4*r + l/16, column l%16
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int gc = col0 + wn * WN + j * 16 + (lane & 15);
+            if (gc >= n) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gr = row0 + wm * WM + i * 16 + r * 4 + (lane >> 4);
+                if (gr >= m) continue;
+                if (uplo && gr < gc) continue;
+                double v = alpha * acc[i][j][r];
+                double* p = C + cm(gr, gc, ldc);
+                if (beta != 0.0) v += beta * (*p);
+                *p = v;
+            }
+        }
+}
+
+template <int BM, int BN, bool TA, bool TB>
+void launch_gemm(hipStream_t st, int m, int n, int k, double alpha, const double* A, int lda,
+                 const double* B, int ldb, double beta, double* C, int ldc, int uplo)
+{
+    int tiles_m = (m + BM - 1) / BM;
+    int tiles_n = (n + BN - 1) / BN;
+    int ntiles = tiles_m * tiles_n;
+    int per = (ntiles + 7) / 8;
+    dim3 grid(per * 8), block(256);
+    hipLaunchKernelGGL((dgemm_kernel<BM, BN, TA, TB>), grid, block, 0, st, m, n, k, alpha, A, lda,
+                       B, ldb, beta, C, ldc, uplo, tiles_m, per);
+}
+
+template <int BM, int BN>
+void dispatch_t(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha,
+                const double* A, int lda, const double* B, int ldb, double beta, double* C,
+                int ldc, int uplo)
+{
+    bool TA = (ta == 'T' || ta == 't'), TB = (tb == 'T' || tb == 't');
+    if (!TA && !TB) launch_gemm<BM, BN, false, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
+    else if (!TA && TB) launch_gemm<BM, BN, false, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
+    else if (TA && !TB) launch_gemm<BM, BN, true, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
+    else launch_gemm<BM, BN, true, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
+}
+
+// ---------------------------------------------------------------------------
+// W = alpha A^T B + beta W for tall operands (k rows) and small m, n <= 64:
+// each workgroup forms the product over one chunk of rows; a second kernel
+// sums the chunk partials in chunk order (no atomics, bitwise reproducible).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void tn_small_partial(int m, int n, int k, const double* __restrict__ A,
+                                                        int lda, const double* __restrict__ B, int ldb,
+                                                        double* __restrict__ part, int chunk)
+{
+    __shared__ double As[32][65];
+    __shared__ double Bs[32][65];
+    const int r0 = blockIdx.x * chunk;
+    const int r1 = min(k, r0 + chunk);
+    const int tid = threadIdx.x;
+    // each thread accumulates 16 entries of the m x n (<= 64 x 64) result
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    for (int rr = r0; rr < r1; rr += 32) {
+        for (int e = tid; e < 32 * 64; e += 256) {
+            int kk = e % 32, c = e / 32;
+            int gk = rr + kk;
+            As[kk][c] = (gk < r1 && c < m) ? A[cm(gk, c, lda)] : 0.0;
+            Bs[kk][c] = (gk < r1 && c < n) ? B[cm(gk, c, ldb)] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            int e = tid + q * 256;
+            int i = e % 64, j = e / 64;
+            double s = acc[q];
+#pragma unroll 8
+            for (int kk = 0; kk < 32; ++kk) s += As[kk][i] * Bs[kk][j];
+            acc[q] = s;
+        }
+        __syncthreads();
+    }
+    double* P = part + (size_t)blockIdx.x * 64 * 64;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) P[tid + q * 256] = acc[q];
+}
+
+__global__ void tn_small_reduce(int m, int n, int nchunks, double alpha, const double* __restrict__ part,
+                                double beta, double* C, int ldc)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 64 * 64) return;
+    int i = e % 64, j = e / 64;
+    if (i >= m || j >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * 4096 + e];
+    double* p = C + cm(i, j, ldc);
+    double v = alpha * s;
+    if (beta != 0.0) v += beta * (*p);
+    *p = v;
+}
+
+}  // namespace
+
+void dgemm(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha, const double* A,
+           int lda, const double* B, int ldb, double beta, double* C, int ldc, int uplo)
+{
+    if (m <= 0 || n <= 0) return;
+    if (n <= 64)
+        dispatch_t<128, 64>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
+    else if (m <= 64)
+        dispatch_t<64, 128>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
+    else
+        dispatch_t<128, 128>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
+}
+
+void dgemm_tn_small(hipStream_t st, int m, int n, int k, double alpha, const double* A, int lda,
+                    const double* B, int ldb, double beta, double* C, int ldc, double* part, int chunk)
+{
+    if (m <= 0 || n <= 0) return;
+    int nchunks = k > 0 ? (k + chunk - 1) / chunk : 1;
+    hipLaunchKernelGGL(tn_small_partial, dim3(nchunks), dim3(256), 0, st, m, n, k, A, lda, B, ldb, part, chunk);
+    hipLaunchKernelGGL(tn_small_reduce, dim3(16), dim3(256), 0, st, m, n, nchunks, alpha, part, beta, C, ldc);
+}
+
+}  // namespace eg

@@ -1,0 +1,220 @@
+// Cholesky factorization S = L L^T (ELSI paper, Sec. 3.1, Eq. (10)) and the
+// triangular solves that use L (Eq. (11) and the back substitution c = L^-T c~).
+//
+// Blocking: 64 x 64 diagonal blocks are factored (and inverted) by one
+// workgroup entirely in LDS; inside a 256-wide outer panel the 64-column
+// steps update only the panel, and the trailing matrix receives one K = 256
+// update per outer panel on the matrix cores.  Triangular solves multiply by
+// the inverted 64 x 64 diagonal blocks and update with the same two-level
+// scheme.
+#include "common.h"
+
+namespace eg {
+namespace {
+
+constexpr int NB = 64;     // diagonal block
+constexpr int NBO = 256;   // outer panel
+
+// Factor the jb x jb diagonal block at (j0, j0) in LDS and write L and L^-1.
+__global__ __launch_bounds__(256) void potf2_inv_kernel(int jb, int j0, double* A, int lda,
+                                                        double* Linv, int* info)
+{
+    __shared__ double L[NB][NB + 1];
+    __shared__ double X[NB][NB + 1];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = (*info != 0);
+    for (int e = tid; e < NB * NB; e += 256) {
+        int i = e % NB, c = e / NB;
+        L[i][c] = (i < jb && c < jb && i >= c) ? A[cm(j0 + i, j0 + c, lda)] : 0.0;
+    }
+    __syncthreads();
+    if (bad) return;
+    for (int c = 0; c < jb; ++c) {
+        double s = L[c][c];
+        __syncthreads();
+        if (!(s > 0.0) || !isfinite(s)) {
+            if (tid == 0) { atomicCAS(info, 0, j0 + c + 1); bad = 1; }
+            __syncthreads();
+            break;
+        }
+        double d = sqrt(s);
+        if (tid == 0) L[c][c] = d;
+        for (int i = c + 1 + tid; i < jb; i += 256) L[i][c] /= d;
+        __syncthreads();
+        const int w = jb - c - 1;
+        for (int e = tid; e < w * w; e += 256) {
+            int i = c + 1 + e % w, c2 = c + 1 + e / w;
+            if (c2 <= i) L[i][c2] -= L[i][c] * L[c2][c];
+        }
+        __syncthreads();
+    }
+    if (bad) return;
+    // X = L^-1, column j solved by thread j (forward substitution)
+    if (tid < NB) {
+        const int j = tid;
+        for (int i = 0; i < NB; ++i) X[i][j] = 0.0;
+        if (j < jb) {
+            for (int i = j; i < jb; ++i) {
+                double t = (i == j) ? 1.0 : 0.0;
+                for (int q = j; q < i; ++q) t -= L[i][q] * X[q][j];
+                X[i][j] = t / L[i][i];
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += 256) {
+        int i = e % NB, c = e / NB;
+        if (i < jb && c < jb && i >= c) A[cm(j0 + i, j0 + c, lda)] = L[i][c];
+        Linv[e] = X[i][c];
+    }
+}
+
+// Inverse of each 64 x 64 diagonal block of an already factored L.
+__global__ __launch_bounds__(256) void trtri_blocks_kernel(int n, const double* L, int ldl, double* Linv)
+{
+    __shared__ double Ls[NB][NB + 1];
+    __shared__ double X[NB][NB + 1];
+    const int blk = blockIdx.x;
+    const int j0 = blk * NB;
+    const int jb = min(NB, n - j0);
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NB * NB; e += 256) {
+        int i = e % NB, c = e / NB;
+        Ls[i][c] = (i < jb && c < jb && i >= c) ? L[cm(j0 + i, j0 + c, ldl)] : 0.0;
+    }
+    __syncthreads();
+    if (tid < NB) {
+        const int j = tid;
+        for (int i = 0; i < NB; ++i) X[i][j] = 0.0;
+        if (j < jb) {
+            for (int i = j; i < jb; ++i) {
+                double t = (i == j) ? 1.0 : 0.0;
+                for (int q = j; q < i; ++q) t -= Ls[i][q] * X[q][j];
+                X[i][j] = t / Ls[i][i];
+            }
+        }
+    }
+    __syncthreads();
+    double* out = Linv + (size_t)blk * NB * NB;
+    for (int e = tid; e < NB * NB; e += 256) out[e] = X[e % NB][e / NB];
+}
+
+__global__ void zero_strict_upper_kernel(int n, double* A, int lda)
+{
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t total = (size_t)n * n;
+    if (e >= total) return;
+    int i = (int)(e % n), j = (int)(e / n);
+    if (i < j) A[cm(i, j, lda)] = 0.0;
+}
+
+}  // namespace
+
+void dtrtri_diag_blocks(hipStream_t st, int n, const double* L, int ldl, double* Linv)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(trtri_blocks_kernel, dim3(ceil_div(n, NB)), dim3(256), 0, st, n, L, ldl, Linv);
+}
+
+void dpotrf(hipStream_t st, int n, double* A, int lda, double* Linv, int* info)
+{
+    for (int J0 = 0; J0 < n; J0 += NBO) {
+        const int JB = std::min(NBO, n - J0);
+        for (int j0 = J0; j0 < J0 + JB; j0 += NB) {
+            const int jb = std::min(NB, J0 + JB - j0);
+            double* Lj = Linv + (size_t)(j0 / NB) * NB * NB;
+            hipLaunchKernelGGL(potf2_inv_kernel, dim3(1), dim3(256), 0, st, jb, j0, A, lda, Lj, info);
+            const int r0 = j0 + jb;
+            if (r0 >= n) break;
+            double* P = A + cm(r0, j0, lda);
+            // panel rows below the block: P <- P L_jj^-T
+            dgemm(st, 'N', 'T', n - r0, jb, jb, 1.0, P, lda, Lj, NB, 0.0, P, lda);
+            // update the rest of this outer panel (columns r0 .. J0+JB-1)
+            const int wc = J0 + JB - r0;
+            if (wc > 0)
+                dgemm(st, 'N', 'T', n - r0, wc, jb, -1.0, P, lda, A + cm(r0, j0, lda), lda, 1.0,
+                      A + cm(r0, r0, lda), lda, 1);
+        }
+        const int t0 = J0 + JB;
+        if (t0 < n) {
+            // trailing matrix: A22 -= P P^T (lower tiles), K = outer panel width
+            const double* P = A + cm(t0, J0, lda);
+            dgemm(st, 'N', 'T', n - t0, n - t0, JB, -1.0, P, lda, P, lda, 1.0, A + cm(t0, t0, lda), lda, 1);
+        }
+    }
+    size_t total = (size_t)n * n;
+    hipLaunchKernelGGL(zero_strict_upper_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       n, A, lda);
+}
+
+// B <- L^-1 B, L lower (n x n), B n x ncol.
+void dtrsm_left_lower_n(hipStream_t st, int n, int ncol, const double* L, int ldl,
+                        const double* Linv, double* B, int ldb)
+{
+    for (int I0 = 0; I0 < n; I0 += NBO) {
+        const int IB = std::min(NBO, n - I0);
+        for (int i0 = I0; i0 < I0 + IB; i0 += NB) {
+            const int ib = std::min(NB, I0 + IB - i0);
+            const double* Li = Linv + (size_t)(i0 / NB) * NB * NB;
+            dgemm(st, 'N', 'N', ib, ncol, ib, 1.0, Li, NB, B + i0, ldb, 0.0, B + i0, ldb);
+            const int r0 = i0 + ib, rn = I0 + IB - r0;
+            if (rn > 0)
+                dgemm(st, 'N', 'N', rn, ncol, ib, -1.0, L + cm(r0, i0, ldl), ldl, B + i0, ldb, 1.0,
+                      B + r0, ldb);
+        }
+        const int t0 = I0 + IB;
+        if (t0 < n)
+            dgemm(st, 'N', 'N', n - t0, ncol, IB, -1.0, L + cm(t0, I0, ldl), ldl, B + I0, ldb, 1.0,
+                  B + t0, ldb);
+    }
+}
+
+// B <- B L^-T, B nrow x n: solve X L^T = B column block by column block.
+void dtrsm_right_lower_t(hipStream_t st, int nrow, int n, const double* L, int ldl,
+                         const double* Linv, double* B, int ldb)
+{
+    for (int J0 = 0; J0 < n; J0 += NBO) {
+        const int JB = std::min(NBO, n - J0);
+        for (int j0 = J0; j0 < J0 + JB; j0 += NB) {
+            const int jb = std::min(NB, J0 + JB - j0);
+            const double* Lj = Linv + (size_t)(j0 / NB) * NB * NB;
+            double* Bj = B + cm(0, j0, ldb);
+            dgemm(st, 'N', 'T', nrow, jb, jb, 1.0, Bj, ldb, Lj, NB, 0.0, Bj, ldb);
+            const int c0 = j0 + jb, cn = J0 + JB - c0;
+            if (cn > 0)
+                dgemm(st, 'N', 'T', nrow, cn, jb, -1.0, Bj, ldb, L + cm(c0, j0, ldl), ldl, 1.0,
+                      B + cm(0, c0, ldb), ldb);
+        }
+        const int t0 = J0 + JB;
+        if (t0 < n)
+            dgemm(st, 'N', 'T', nrow, n - t0, JB, -1.0, B + cm(0, J0, ldb), ldb, L + cm(t0, J0, ldl), ldl,
+                  1.0, B + cm(0, t0, ldb), ldb);
+    }
+}
+
+// B <- L^-T B, B n x ncol: solve L^T X = B from the bottom block upward.
+void dtrsm_left_lower_t(hipStream_t st, int n, int ncol, const double* L, int ldl,
+                        const double* Linv, double* B, int ldb)
+{
+    const int nouter = ceil_div(n, NBO);
+    for (int ob = nouter - 1; ob >= 0; --ob) {
+        const int I0 = ob * NBO;
+        const int IB = std::min(NBO, n - I0);
+        const int ninner = ceil_div(IB, NB);
+        for (int q = ninner - 1; q >= 0; --q) {
+            const int i0 = I0 + q * NB;
+            const int ib = std::min(NB, I0 + IB - i0);
+            const double* Li = Linv + (size_t)(i0 / NB) * NB * NB;
+            dgemm(st, 'T', 'N', ib, ncol, ib, 1.0, Li, NB, B + i0, ldb, 0.0, B + i0, ldb);
+            const int rn = i0 - I0;   // rows of this outer block above the inner block
+            if (rn > 0)
+                dgemm(st, 'T', 'N', rn, ncol, ib, -1.0, L + cm(i0, I0, ldl), ldl, B + i0, ldb, 1.0,
+                      B + I0, ldb);
+        }
+        if (I0 > 0)
+            dgemm(st, 'T', 'N', I0, ncol, IB, -1.0, L + cm(I0, 0, ldl), ldl, B + I0, ldb, 1.0, B, ldb);
+    }
+}
+
+}  // namespace eg

@@ -1,0 +1,285 @@
+// Element-wise helpers, the density-matrix column scaling and the chemical
+// potential / occupation kernel.
+#include "common.h"
+
+namespace eg {
+namespace {
+
+__global__ void fill_d_kernel(double* p, size_t count, double v)
+{
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; e < count; e += stride) p[e] = v;
+}
+
+__global__ void fill_i_kernel(int* p, size_t count, int v)
+{
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; e < count; e += stride) p[e] = v;
+}
+
+__global__ void copy_matrix_kernel(int m, int n, const double* A, int lda, double* B, int ldb)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    for (; j < n; j += gridDim.y)
+        if (i < m) B[cm(i, j, ldb)] = A[cm(i, j, lda)];
+}
+
+// Copy the lower triangle onto the upper one through a 32 x 32 LDS tile so
+// that both the reads and the writes are coalesced.
+__global__ void mirror_kernel(int n, double* A, int lda)
+{
+    __shared__ double t[32][33];
+    int bi = blockIdx.x, bj = blockIdx.y;   // source tile (bi, bj) with bi >= bj
+    if (bi < bj) return;
+    int tx = threadIdx.x, ty = threadIdx.y; // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        int gi = bi * 32 + tx, gj = bj * 32 + r;
+        t[r][tx] = (gi < n && gj < n) ? A[cm(gi, gj, lda)] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        // destination (row = bj*32 + tx, col = bi*32 + r) = source (bi*32 + r, bj*32 + tx)
+        int di = bj * 32 + tx, dj = bi * 32 + r;
+        if (di < n && dj < n && di < dj) A[cm(di, dj, lda)] = t[tx][r];
+    }
+}
+
+// A <- (A + A^T) / 2 for one pair of 32 x 32 tiles (bi, bj), bi >= bj.
+__global__ void symmetrize_kernel(int n, double* A, int lda)
+{
+    __shared__ double lo[32][33];
+    __shared__ double up[32][33];
+    int bi = blockIdx.x, bj = blockIdx.y;
+    if (bi < bj) return;
+    int tx = threadIdx.x, ty = threadIdx.y;
+    for (int r = ty; r < 32; r += 8) {
+        int gi = bi * 32 + tx, gj = bj * 32 + r;          // lower tile element (gi, gj)
+        lo[r][tx] = (gi < n && gj < n) ? A[cm(gi, gj, lda)] : 0.0;
+        int ui = bj * 32 + tx, uj = bi * 32 + r;          // upper tile element (ui, uj)
+        up[r][tx] = (ui < n && uj < n) ? A[cm(ui, uj, lda)] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        // lower (bi*32+tx, bj*32+r) pairs with upper (bj*32+r, bi*32+tx) = up[tx][r]
+        int gi = bi * 32 + tx, gj = bj * 32 + r;
+        if (gi < n && gj < n && gi > gj) {
+            double v = 0.5 * (lo[r][tx] + up[tx][r]);
+            A[cm(gi, gj, lda)] = v;
+        }
+        int ui = bj * 32 + tx, uj = bi * 32 + r;           // upper (ui, uj) pairs with lo[tx][r]
+        if (ui < n && uj < n && ui < uj) {
+            double v = 0.5 * (up[r][tx] + lo[tx][r]);
+            A[cm(ui, uj, lda)] = v;
+        }
+    }
+}
+
+__global__ void identity_kernel(int n, double* A, int lda)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    for (; j < n; j += gridDim.y)
+        if (i < n) A[cm(i, j, lda)] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ void scale_sqrt_kernel(int n, int k, const double* C, int ldc, const double* f, double* out,
+                                  int ldo)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    for (; j < k; j += gridDim.y) {
+        double s = sqrt(fmax(f[j], 0.0));
+        if (i < n) out[cm(i, j, ldo)] = s * C[cm(i, j, ldc)];
+    }
+}
+
+__global__ void finite_kernel(int m, int n, const double* A, int lda, int* flag)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    for (; j < n; j += gridDim.y)
+        if (i < m && !isfinite(A[cm(i, j, lda)])) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Occupations (Eq. (17)) and chemical potential (Eq. (18)) by bisection, as
+// described for elsi_dm_real (Sec. 4.5): start from [eps_min - 10 kT,
+// eps_max + 10 kT], widen each side (doubling the step) until the electron
+// count brackets N_e, halve keeping a surplus at the upper bound until that
+// surplus is within occ_accuracy or the midpoint stops moving, take mu at the
+// upper bound and strip the remaining surplus from the highest occupied
+// states downward.  One workgroup; electron counts are block reductions in a
+// fixed order, so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+constexpr int FD_THREADS = 1024;
+
+__device__ inline double fd_occ(double eps, double mu, double kT, double spin)
+{
+    double x = (eps - mu) / kT;
+    if (x >= 0.0) {
+        double t = exp(-x);
+        return spin * t / (1.0 + t);
+    }
+    return spin / (1.0 + exp(x));
+}
+
+__device__ double block_sum(double v, double* red)
+{
+    const int tid = threadIdx.x;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (tid == 0) {
+        for (int w = 0; w < FD_THREADS / 64; ++w) s += red[w];
+        red[FD_THREADS / 64] = s;
+    }
+    __syncthreads();
+    return red[FD_THREADS / 64];
+}
+
+__device__ double count_electrons(int n, const double* eps, double mu, double kT, double spin, double* red)
+{
+    double s = 0.0;
+    for (int l = threadIdx.x; l < n; l += FD_THREADS) s += fd_occ(eps[l], mu, kT, spin);
+    return block_sum(s, red);
+}
+
+__global__ __launch_bounds__(FD_THREADS) void fermi_kernel(int n, const double* eps, double ne, double kT,
+                                                          double spin, double acc, int max_steps,
+                                                          double f_cut, double* f, double* scal)
+{
+    __shared__ double red[FD_THREADS / 64 + 1];
+    __shared__ double sh_surplus;
+    double lo = eps[0] - 10.0 * kT, hi = eps[n - 1] + 10.0 * kT;
+    double step = hi - lo;
+    for (int w = 0; w < 64 && count_electrons(n, eps, lo, kT, spin, red) - ne > 0.0; ++w) {
+        lo -= step;
+        step *= 2.0;
+    }
+    step = hi - lo;
+    for (int w = 0; w < 64 && count_electrons(n, eps, hi, kT, spin, red) - ne < 0.0; ++w) {
+        hi += step;
+        step *= 2.0;
+    }
+    int status = 0, steps = 0;
+    for (;;) {
+        double mid = 0.5 * (lo + hi);
+        if (!(lo < mid && mid < hi)) break;
+        if (steps >= max_steps) { status = kStatusMu; break; }
+        ++steps;
+        double g = count_electrons(n, eps, mid, kT, spin, red) - ne;
+        if (g >= 0.0) {
+            hi = mid;
+            if (g <= acc) break;
+        } else {
+            lo = mid;
+        }
+    }
+    const double mu = hi;
+    for (int l = threadIdx.x; l < n; l += FD_THREADS) f[l] = fd_occ(eps[l], mu, kT, spin);
+    double total = count_electrons(n, eps, mu, kT, spin, red);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double surplus = total - ne;
+        for (int l = n - 1; l >= 0 && surplus > 0.0; --l) {
+            double fl = f[l];
+            if (fl <= 0.0) continue;
+            double take = fl < surplus ? fl : surplus;
+            f[l] = fl - take;
+            surplus -= take;
+        }
+        sh_surplus = surplus;
+    }
+    __syncthreads();
+    // k_s: number of leading states with f > f_cut (f is non-increasing in l)
+    double cnt = 0.0, en = 0.0;
+    for (int l = threadIdx.x; l < n; l += FD_THREADS) {
+        double fl = f[l];
+        cnt += (fl > f_cut) ? 1.0 : 0.0;
+        en += fl * eps[l];
+    }
+    double ks = block_sum(cnt, red);
+    double energy = block_sum(en, red);
+    if (threadIdx.x == 0) {
+        scal[0] = mu;
+        scal[1] = (double)status;
+        scal[2] = ks;
+        scal[3] = energy;
+        scal[4] = (double)steps;
+        scal[5] = sh_surplus;
+    }
+}
+
+}  // namespace
+
+void fill_d(hipStream_t st, double* p, size_t count, double v)
+{
+    if (!count) return;
+    unsigned g = (unsigned)std::min<size_t>((count + 255) / 256, 65535);
+    hipLaunchKernelGGL(fill_d_kernel, dim3(g), dim3(256), 0, st, p, count, v);
+}
+
+void fill_i(hipStream_t st, int* p, size_t count, int v)
+{
+    if (!count) return;
+    unsigned g = (unsigned)std::min<size_t>((count + 255) / 256, 65535);
+    hipLaunchKernelGGL(fill_i_kernel, dim3(g), dim3(256), 0, st, p, count, v);
+}
+
+void copy_matrix(hipStream_t st, int m, int n, const double* A, int lda, double* B, int ldb)
+{
+    if (m <= 0 || n <= 0) return;
+    dim3 grid(ceil_div(m, 256), std::min(n, 65535));
+    hipLaunchKernelGGL(copy_matrix_kernel, grid, dim3(256), 0, st, m, n, A, lda, B, ldb);
+}
+
+void mirror_lower_to_upper(hipStream_t st, int n, double* A, int lda)
+{
+    if (n <= 1) return;
+    int t = ceil_div(n, 32);
+    hipLaunchKernelGGL(mirror_kernel, dim3(t, t), dim3(32, 8), 0, st, n, A, lda);
+}
+
+void symmetrize_average(hipStream_t st, int n, double* A, int lda)
+{
+    if (n <= 1) return;
+    int t = ceil_div(n, 32);
+    hipLaunchKernelGGL(symmetrize_kernel, dim3(t, t), dim3(32, 8), 0, st, n, A, lda);
+}
+
+void set_identity(hipStream_t st, int n, double* A, int lda)
+{
+    if (n <= 0) return;
+    dim3 grid(ceil_div(n, 256), std::min(n, 65535));
+    hipLaunchKernelGGL(identity_kernel, grid, dim3(256), 0, st, n, A, lda);
+}
+
+void scale_columns_sqrt(hipStream_t st, int n, int k, const double* C, int ldc, const double* f,
+                        double* out, int ldo)
+{
+    if (n <= 0 || k <= 0) return;
+    dim3 grid(ceil_div(n, 256), std::min(k, 65535));
+    hipLaunchKernelGGL(scale_sqrt_kernel, grid, dim3(256), 0, st, n, k, C, ldc, f, out, ldo);
+}
+
+void check_finite(hipStream_t st, int m, int n, const double* A, int lda, int* flag)
+{
+    if (m <= 0 || n <= 0) return;
+    dim3 grid(ceil_div(m, 256), std::min(n, 65535));
+    hipLaunchKernelGGL(finite_kernel, grid, dim3(256), 0, st, m, n, A, lda, flag);
+}
+
+void fermi_occupations(hipStream_t st, int n, const double* eps, double n_electron, double kT,
+                       double spin, double occ_accuracy, int max_steps, double f_cut, double* f,
+                       double* scal)
+{
+    hipLaunchKernelGGL(fermi_kernel, dim3(1), dim3(FD_THREADS), 0, st, n, eps, n_electron, kT, spin,
+                       occ_accuracy, max_steps, f_cut, f, scal);
+}
+
+}  // namespace eg

@@ -1,0 +1,65 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no compute calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "elsi_gpu.h")
+LIB = os.path.join(ROOT, "paper_1705_11191_amd", "libelsi_gpu.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(elsi_gpu_\w+)\s*\(", text)))
+
+
+def test_header_declares_core_api():
+    names = declared_functions()
+    for core in ["elsi_gpu_init", "elsi_gpu_ev", "elsi_gpu_dm", "elsi_gpu_finalize",
+                 "elsi_gpu_get_info", "elsi_gpu_workspace_size", "elsi_gpu_set_workspace"]:
+        assert core in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libelsi_gpu.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libelsi_gpu.so not built")
+def test_strerror_and_argument_checks_without_gpu():
+    lib = ctypes.CDLL(LIB)
+    lib.elsi_gpu_strerror.restype = ctypes.c_char_p
+    assert lib.elsi_gpu_strerror(0) == b"success"
+    assert b"positive definite" in lib.elsi_gpu_strerror(1)
+    h = ctypes.c_void_p(0)
+    lib.elsi_gpu_init.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int, ctypes.c_double, ctypes.c_void_p]
+    assert lib.elsi_gpu_init(None, 0, 10, 10, 5.0, None) == -1
+    assert lib.elsi_gpu_init(ctypes.byref(h), 3, 10, 10, 5.0, None) == -2
+    assert lib.elsi_gpu_init(ctypes.byref(h), 0, 0, 1, 5.0, None) == -3
+    assert lib.elsi_gpu_init(ctypes.byref(h), 0, 10, 11, 5.0, None) == -4
+    assert lib.elsi_gpu_init(ctypes.byref(h), 0, 10, 10, -1.0, None) == -5
+    assert lib.elsi_gpu_init(ctypes.byref(h), 0, 10, 10, 5.0, None) == 0
+    lib.elsi_gpu_set_band_width.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    assert lib.elsi_gpu_set_band_width(h, 12) == -2
+    assert lib.elsi_gpu_set_band_width(h, 32) == 0
+    lib.elsi_gpu_finalize.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    assert lib.elsi_gpu_finalize(ctypes.byref(h)) == 0
+    assert h.value is None
+
+
+def test_product_path_does_not_import_oracle():
+    # the GPU package and binding must not reach into the CPU oracle
+    pkg = os.path.join(ROOT, "paper_1705_11191_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+                assert "elsi_oracle" not in src and "liborc" not in src, f
