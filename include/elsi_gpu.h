@@ -196,6 +196,22 @@ int elsi_gpu_x_occupations(int n, const double *eps, double n_electron, double k
 int elsi_gpu_x_density(int n, int k, const double *C, int ldc, const double *f, double *D,
                        int ldd, void *hip_stream);
 
+/* Step (1), Eq. (13): band B = Q1^T A Q1 of the symmetric A (lower triangle
+ * read, A unchanged) with bandwidth b (1..64); band receives LAPACK lower band
+ * storage, band[r + c*ldband] = B(c + r, c) for 0 <= r <= b (ldband >= b+1). */
+int elsi_gpu_x_band_reduce(int n, int b, double *A, int lda, double *band, int ldband,
+                           void *hip_stream);
+
+/* Steps (1)+(2), Eq. (13): T = Q^T A Q tridiagonal (A unchanged); d (n) and
+ * e (n-1) device out, e[i] = T(i+1, i). */
+int elsi_gpu_x_tridiagonalize(int n, int b, double *A, int lda, double *d, double *e,
+                              void *hip_stream);
+
+/* Step (3): eigenvalues w (ascending) and eigenvectors Z (n x n, ldz) of the
+ * symmetric tridiagonal (d, e) by divide and conquer. */
+int elsi_gpu_x_tridiag_eig(int n, const double *d, const double *e, double *w, double *Z, int ldz,
+                           void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,9 @@ def lib():
         L.elsi_gpu_x_occupations.argtypes = [i, vp, d, d, d, d, i, vp, ctypes.POINTER(d),
                                              ctypes.POINTER(i), vp]
         L.elsi_gpu_x_density.argtypes = [i, i, vp, i, vp, vp, i, vp]
+        L.elsi_gpu_x_band_reduce.argtypes = [i, i, vp, i, vp, i, vp]
+        L.elsi_gpu_x_tridiagonalize.argtypes = [i, i, vp, i, vp, vp, vp]
+        L.elsi_gpu_x_tridiag_eig.argtypes = [i, vp, vp, vp, vp, i, vp]
         _lib = L
     return _lib
 
@@ -172,6 +175,36 @@ def density(C: torch.Tensor, f: torch.Tensor) -> torch.Tensor:
     rc = lib().elsi_gpu_x_density(n, k, _ptr(C), n, _ptr(f), _ptr(D), n, _stream())
     _check(rc, "elsi_gpu_x_density")
     return D
+
+
+def band_reduce(A: torch.Tensor, b: int) -> torch.Tensor:
+    """Band form (LAPACK lower band storage, (b+1) x n column-major) of symmetric A."""
+    n = A.shape[0]
+    band = fortran_empty(b + 1, n, device=A.device)
+    rc = lib().elsi_gpu_x_band_reduce(n, b, _ptr(A), n, _ptr(band), b + 1, _stream())
+    _check(rc, "elsi_gpu_x_band_reduce")
+    return band
+
+
+def tridiagonalize(A: torch.Tensor, b: int):
+    """(d, e) of the two-stage tridiagonal form of symmetric A."""
+    n = A.shape[0]
+    d = torch.empty(n, device=A.device, dtype=torch.float64)
+    e = torch.empty(max(n - 1, 1), device=A.device, dtype=torch.float64)
+    rc = lib().elsi_gpu_x_tridiagonalize(n, b, _ptr(A), n, _ptr(d), _ptr(e), _stream())
+    _check(rc, "elsi_gpu_x_tridiagonalize")
+    return d, e[: n - 1]
+
+
+def tridiag_eig(d: torch.Tensor, e: torch.Tensor):
+    """Eigenvalues (ascending) and eigenvectors (column-major) of tridiagonal (d, e)."""
+    n = d.shape[0]
+    w = torch.empty(n, device=d.device, dtype=torch.float64)
+    Z = fortran_empty(n, n, device=d.device)
+    ee = e if e.numel() > 0 else torch.zeros(1, device=d.device, dtype=torch.float64)
+    rc = lib().elsi_gpu_x_tridiag_eig(n, _ptr(d), _ptr(ee), _ptr(w), _ptr(Z), n, _stream())
+    _check(rc, "elsi_gpu_x_tridiag_eig")
+    return w, Z
 
 
 # ---------------------------------------------------------------------------

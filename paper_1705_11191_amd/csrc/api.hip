@@ -242,4 +242,85 @@ int elsi_gpu_x_density(int n, int k, const double* C, int ldc, const double* f, 
     return sync_status(st);
 }
 
+int elsi_gpu_x_band_reduce(int n, int b, double* A, int lda, double* band, int ldband, void* hip_stream)
+{
+    if (n < 1) return -1;
+    if (b < 1 || b > 64) return -2;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (!band) return -5;
+    if (ldband < b + 1) return -6;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int bb = std::min(b, std::max(1, n - 1));
+    DevBuf<double> Vall, Tall, Bd, work, Acopy;
+    if (!Vall.alloc((size_t)n * n) || !Tall.alloc((size_t)ceil_div(n, bb) * bb * bb) ||
+        !Bd.alloc((size_t)2 * bb * n) || !work.alloc(sy2sb_workspace_doubles(n, bb)) || !Acopy.alloc((size_t)n * n))
+        return ELSI_GPU_ERR_OOM;
+    copy_matrix(st, n, n, A, lda, Acopy.p, n);
+    mirror_lower_to_upper(st, n, Acopy.p, n);
+    sy2sb(st, n, bb, Acopy.p, n, Vall.p, Tall.p, Bd.p, 2 * bb, work.p);
+    for (int c = 0; c < n; ++c) fill_d(st, band + (size_t)c * ldband, (size_t)(b + 1), 0.0);
+    copy_matrix(st, bb + 1, n, Bd.p, 2 * bb, band, ldband);
+    return sync_status(st);
+}
+
+int elsi_gpu_x_tridiagonalize(int n, int b, double* A, int lda, double* d, double* e, void* hip_stream)
+{
+    if (n < 1) return -1;
+    if (b < 1 || b > 64) return -2;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (!d) return -5;
+    if (!e && n > 1) return -6;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int bb = std::min(b, std::max(1, n - 1));
+    DevBuf<double> Vall, Tall, Bd, work, Acopy, V2, tau2, ee;
+    DevBuf<int> ints;
+    if (!Vall.alloc((size_t)n * n) || !Tall.alloc((size_t)ceil_div(n, bb) * bb * bb) ||
+        !Bd.alloc((size_t)2 * bb * n) || !work.alloc(sy2sb_workspace_doubles(n, bb)) ||
+        !Acopy.alloc((size_t)n * n) || !V2.alloc((size_t)n * n) ||
+        !tau2.alloc((size_t)std::max(n - 2, 1) * sb2st_kmax(n, bb)) || !ee.alloc((size_t)n) ||
+        !ints.alloc((size_t)n + 64))
+        return ELSI_GPU_ERR_OOM;
+    copy_matrix(st, n, n, A, lda, Acopy.p, n);
+    mirror_lower_to_upper(st, n, Acopy.p, n);
+    sy2sb(st, n, bb, Acopy.p, n, Vall.p, Tall.p, Bd.p, 2 * bb, work.p);
+    int rc = sb2st(st, n, bb, Bd.p, 2 * bb, d, ee.p, V2.p, tau2.p, ints.p + 64, ints.p);
+    if (rc) return rc;
+    if (n > 1) (void)hipMemcpyAsync(e, ee.p, sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, st);
+    int herr = 0;
+    (void)hipMemcpyAsync(&herr, ints.p, sizeof(int), hipMemcpyDeviceToHost, st);
+    rc = sync_status(st);
+    if (rc) return rc;
+    return herr ? ELSI_GPU_ERR_NO_CONV : 0;
+}
+
+int elsi_gpu_x_tridiag_eig(int n, const double* d, const double* e, double* w, double* Z, int ldz,
+                           void* hip_stream)
+{
+    if (n < 1) return -1;
+    if (!d) return -2;
+    if (!e && n > 1) return -3;
+    if (!w) return -4;
+    if (!Z) return -5;
+    if (ldz < n) return -6;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBuf<double> Z1, Z2, U, ee;
+    DevBuf<char> work;
+    DevBuf<int> err;
+    if (!Z1.alloc((size_t)n * n) || !Z2.alloc((size_t)n * n) || !U.alloc((size_t)n * n) ||
+        !work.alloc(stedc_workspace_bytes(n)) || !err.alloc(4) || !ee.alloc((size_t)n))
+        return ELSI_GPU_ERR_OOM;
+    fill_d(st, ee.p, (size_t)n, 0.0);
+    if (n > 1) (void)hipMemcpyAsync(ee.p, e, sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, st);
+    int rc = stedc(st, n, d, ee.p, w, Z1.p, Z2.p, U.p, n, n, work.p, err.p, nullptr);
+    if (rc) return rc;
+    copy_matrix(st, n, n, Z1.p, n, Z, ldz);
+    int herr = 0;
+    (void)hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, st);
+    rc = sync_status(st);
+    if (rc) return rc;
+    return herr ? ELSI_GPU_ERR_NO_CONV : 0;
+}
+
 }  // extern "C"

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
+#include <algorithm>
 #include <cstdint>
 
 namespace eg {
@@ -26,7 +27,7 @@ struct HipCheck {
     }
 };
 
-inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Column-major element address.
@@ -88,5 +89,32 @@ void check_finite(hipStream_t st, int m, int n, const double* A, int lda, int* f
 void fermi_occupations(hipStream_t st, int n, const double* eps, double n_electron, double kT,
                        double spin, double occ_accuracy, int max_steps, double f_cut,
                        double* f, double* scal);
+
+// Explicit occupations: f given for all n states; scal: mu (0), status (0),
+// k_s (1 + last index with f > f_cut), energy (sum f eps).
+void explicit_occupations(hipStream_t st, int n, int n_state, const double* eps, const double* f,
+                          double f_cut, double* scal);
+
+// Step (1): full (n x n, full symmetric) -> band; see sy2sb.hip.
+size_t sy2sb_workspace_doubles(int n, int b);
+void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, double* Tall, double* Bd,
+           int ldbd, double* work);
+
+// Step (2): band -> tridiagonal; see sb2st.hip.
+int sb2st_kmax(int n, int b);
+int sb2st(hipStream_t st, int n, int b, double* Bd, int ldb, double* d, double* e, double* V2, double* tau2,
+          int* progress, int* err);
+
+// Step (3): tridiagonal divide and conquer; see stedc.hip.
+size_t stedc_workspace_bytes(int n);
+int stedc(hipStream_t st, int n, const double* d, const double* e, double* w, double* Z, double* Z2,
+          double* U, int ldz, int ncol_final, void* work, int* err, int* err_host_copy);
+
+// Steps (4) and (5): back-transformations; see backtx.hip.
+void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const double* tau2, int kmax,
+              double* X, int ldx);
+size_t apply_q1_workspace_doubles(int n, int ncol);
+void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const double* Tall, double* X,
+              int ldx, double* work);
 
 }  // namespace eg

@@ -3,6 +3,7 @@
 #include "api_internal.h"
 
 #include <algorithm>
+#include <cstring>
 
 namespace eg {
 
@@ -30,10 +31,45 @@ void density_matrix(hipStream_t st, int n, int k, const double* C, int ldc, cons
     mirror_lower_to_upper(st, n, D, ldd);
 }
 
+// ---------------------------------------------------------------------------
+// workspace layout (all sub-buffers 256-byte aligned)
+// ---------------------------------------------------------------------------
+struct Layout {
+    size_t linv, bd, vall, tall, v2, tau2, d, e, w, z, z2, u, sywork, dcwork, q1work, f, scal, ints;
+    size_t total;
+};
+
+static Layout make_layout(int n, int b, int ncol)
+{
+    Layout L{};
+    size_t off = 0;
+    auto put = [&](size_t bytes) { size_t r = off; off += align_up(std::max<size_t>(bytes, 8), 256); return r; };
+    const size_t nn = (size_t)n * n;
+    L.linv = put(sizeof(double) * (size_t)ceil_div(n, 64) * 4096);
+    L.bd = put(sizeof(double) * (size_t)2 * b * n);
+    L.vall = put(sizeof(double) * nn);
+    L.tall = put(sizeof(double) * (size_t)ceil_div(n, b) * b * b);
+    L.v2 = put(sizeof(double) * nn);
+    L.tau2 = put(sizeof(double) * (size_t)std::max(n - 2, 1) * sb2st_kmax(n, b));
+    L.d = put(sizeof(double) * n);
+    L.e = put(sizeof(double) * n);
+    L.w = put(sizeof(double) * n);
+    L.z = put(sizeof(double) * nn);
+    L.z2 = put(sizeof(double) * nn);
+    L.u = put(sizeof(double) * nn);
+    L.sywork = put(sizeof(double) * sy2sb_workspace_doubles(n, b));
+    L.dcwork = put(stedc_workspace_bytes(n));
+    L.q1work = put(sizeof(double) * apply_q1_workspace_doubles(n, ncol));
+    L.f = put(sizeof(double) * n);
+    L.scal = put(sizeof(double) * 16);
+    L.ints = put(sizeof(int) * ((size_t)n + 64));
+    L.total = off;
+    return L;
+}
+
 size_t workspace_bytes(const elsi_gpu_handle_s* h)
 {
-    (void)h;
-    return 0;
+    return make_layout(h->n, h->band_width, h->n).total;
 }
 
 void release_workspace(elsi_gpu_handle_s* h)
@@ -44,23 +80,234 @@ void release_workspace(elsi_gpu_handle_s* h)
     h->ws_owned = 0;
 }
 
+static int ensure_workspace(elsi_gpu_handle_s* h)
+{
+    size_t need = workspace_bytes(h);
+    if (h->ws && h->ws_bytes >= need) return 0;
+    if (h->ws && !h->ws_owned) return -1;   // caller-provided buffer became too small
+    release_workspace(h);
+    void* p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return kStatusOom;
+    }
+    h->ws = p;
+    h->ws_bytes = need;
+    h->ws_owned = 1;
+    return 0;
+}
+
+struct Timer {
+    hipEvent_t ev[ELSI_GPU_NSTAGES + 1];
+    int have[ELSI_GPU_NSTAGES + 1];
+    hipEvent_t start, stop;
+    hipStream_t st;
+    explicit Timer(hipStream_t s) : st(s) {
+        for (int i = 0; i <= ELSI_GPU_NSTAGES; ++i) { (void)hipEventCreate(&ev[i]); have[i] = 0; }
+        (void)hipEventCreate(&start);
+        (void)hipEventCreate(&stop);
+        (void)hipEventRecord(start, st);
+    }
+    // mark the end of stage `stage`
+    void mark(int stage) { (void)hipEventRecord(ev[stage], st); have[stage] = 1; }
+    void finish(elsi_gpu_info* info) {
+        (void)hipEventRecord(stop, st);
+        (void)hipEventSynchronize(stop);
+        hipEvent_t prev = start;
+        for (int i = 0; i < ELSI_GPU_NSTAGES; ++i) {
+            info->stage_ms[i] = 0.0;
+            if (!have[i]) continue;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, prev, ev[i]);
+            info->stage_ms[i] = ms;
+            prev = ev[i];
+        }
+        float tot = 0.f;
+        (void)hipEventElapsedTime(&tot, start, stop);
+        info->total_ms = tot;
+    }
+    ~Timer() {
+        for (int i = 0; i <= ELSI_GPU_NSTAGES; ++i) (void)hipEventDestroy(ev[i]);
+        (void)hipEventDestroy(start);
+        (void)hipEventDestroy(stop);
+    }
+};
+
+// Steps common to ev and dm: finiteness check, Cholesky (Eq. (10)),
+// reduction (Eq. (11)), full -> band and band -> tridiagonal (Eq. (13)), and
+// the tridiagonal eigenpairs (divide and conquer).  On success w holds all
+// eigenvalues ascending and Z the eigenvectors of T (first ncol columns).
+static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, const Layout& L, Timer& tm, int ncol)
+{
+    hipStream_t st = h->stream;
+    const int n = h->n, b = std::min(h->band_width, std::max(1, n - 1));
+    int* ints = (int*)(ws + L.ints);
+    int* info = ints;        // Cholesky pivot
+    int* flag = ints + 1;    // non-finite input
+    int* err = ints + 2;     // sb2st / stedc failure flags
+    int* err2 = ints + 3;
+    int* progress = ints + 64;
+    double* Linv = (double*)(ws + L.linv);
+    fill_i(st, ints, 64, 0);
+    check_finite(st, n, n, H, n, flag);
+    if (!h->overlap_is_unit) check_finite(st, n, n, S, n, flag);
+    int hflags[2] = {0, 0};
+    if (hipMemcpyAsync(hflags, ints, 2 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return kStatusHip;
+    if (hipStreamSynchronize(st) != hipSuccess) return kStatusHip;
+    if (hflags[1]) return 7;
+    if (!h->overlap_is_unit) {
+        if (!h->overlap_factored) {
+            dpotrf(st, n, S, n, Linv, info);
+            if (hipMemcpyAsync(hflags, info, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return kStatusHip;
+            if (hipStreamSynchronize(st) != hipSuccess) return kStatusHip;
+            if (hflags[0]) {
+                h->info.fail_col = hflags[0];
+                return kStatusNotPD;
+            }
+        }
+        tm.mark(ELSI_GPU_ST_CHOLESKY);
+        reduce_to_standard(st, n, H, n, S, n, Linv);
+    } else {
+        tm.mark(ELSI_GPU_ST_CHOLESKY);
+        mirror_lower_to_upper(st, n, H, n);
+    }
+    tm.mark(ELSI_GPU_ST_REDUCE);
+    double* Bd = (double*)(ws + L.bd);
+    double* Vall = (double*)(ws + L.vall);
+    double* Tall = (double*)(ws + L.tall);
+    sy2sb(st, n, b, H, n, Vall, Tall, Bd, 2 * b, (double*)(ws + L.sywork));
+    tm.mark(ELSI_GPU_ST_BAND);
+    double* d = (double*)(ws + L.d);
+    double* e = (double*)(ws + L.e);
+    int rc = sb2st(st, n, b, Bd, 2 * b, d, e, (double*)(ws + L.v2), (double*)(ws + L.tau2), progress, err);
+    if (rc) return rc;
+    tm.mark(ELSI_GPU_ST_BULGE);
+    double* w = (double*)(ws + L.w);
+    rc = stedc(st, n, d, e, w, (double*)(ws + L.z), (double*)(ws + L.z2), (double*)(ws + L.u), n, ncol,
+               ws + L.dcwork, err2, nullptr);
+    if (rc) return rc;
+    tm.mark(ELSI_GPU_ST_TRIDIAG);
+    return 0;
+}
+
+// X (n x k, in Z) <- L^-T Q1 Q2 X: steps (4), (5) and the back substitution.
+static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L, Timer& tm, int k)
+{
+    hipStream_t st = h->stream;
+    const int n = h->n, b = std::min(h->band_width, std::max(1, n - 1));
+    double* X = (double*)(ws + L.z);
+    apply_q2(st, n, b, k, (double*)(ws + L.v2), (double*)(ws + L.tau2), sb2st_kmax(n, b), X, n);
+    tm.mark(ELSI_GPU_ST_BACK_Q2);
+    apply_q1(st, n, b, k, (double*)(ws + L.vall), (double*)(ws + L.tall), X, n, (double*)(ws + L.q1work));
+    tm.mark(ELSI_GPU_ST_BACK_Q1);
+    if (!h->overlap_is_unit) {
+        double* Linv = (double*)(ws + L.linv);
+        dtrtri_diag_blocks(st, n, S, n, Linv);
+        dtrsm_left_lower_t(st, n, k, S, n, Linv, X, n);
+    }
+    tm.mark(ELSI_GPU_ST_BACKSUB);
+}
+
+static int read_flags(hipStream_t st, char* ws, const Layout& L)
+{
+    int f[4] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(f, ws + L.ints, 4 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return kStatusHip;
+    if (hipStreamSynchronize(st) != hipSuccess) return kStatusHip;
+    if (f[2] || f[3]) return kStatusNoConv;
+    return 0;
+}
+
 }  // namespace eg
+
+using namespace eg;
 
 extern "C" {
 
 int elsi_gpu_ev(elsi_gpu_handle h, double* H, double* S, double* eval, double* evec)
 {
-    (void)H; (void)S; (void)eval; (void)evec;
     if (!h) return -1;
-    return ELSI_GPU_ERR_HIP;
+    if (!H) return -2;
+    if (!S && !h->overlap_is_unit) return -3;
+    if (!eval) return -4;
+    if (!evec) return -5;
+    int rc = ensure_workspace(h);
+    if (rc) return rc < 0 ? -1 : rc;
+    hipStream_t st = h->stream;
+    const int n = h->n, k = h->n_state;
+    char* ws = (char*)h->ws;
+    const Layout L = make_layout(n, h->band_width, n);
+    std::memset(h->info.stage_ms, 0, sizeof(h->info.stage_ms));
+    h->info.fail_col = 0;
+    h->info.band_width = std::min(h->band_width, std::max(1, n - 1));
+    Timer tm(st);
+    rc = front_half(h, H, S, ws, L, tm, k);
+    if (rc) { tm.finish(&h->info); return rc; }
+    back_half(h, S, ws, L, tm, k);
+    copy_matrix(st, n, k, (double*)(ws + L.z), n, evec, n);
+    (void)hipMemcpyAsync(eval, ws + L.w, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    rc = sync_status(st);
+    if (rc) return rc;
+    tm.finish(&h->info);
+    return read_flags(st, ws, L);
 }
 
-int elsi_gpu_dm(elsi_gpu_handle h, double* H, double* S, double* occ, double* D, double* eval,
-                double* energy, double* mu)
+int elsi_gpu_dm(elsi_gpu_handle h, double* H, double* S, double* occ, double* D, double* eval, double* energy,
+                double* mu)
 {
-    (void)H; (void)S; (void)occ; (void)D; (void)eval; (void)energy; (void)mu;
     if (!h) return -1;
-    return ELSI_GPU_ERR_HIP;
+    if (!H) return -2;
+    if (!S && !h->overlap_is_unit) return -3;
+    if (!occ && h->occ_scheme == ELSI_GPU_OCC_EXPLICIT) return -4;
+    if (!D) return -5;
+    if (!energy) return -7;
+    int rc = ensure_workspace(h);
+    if (rc) return rc < 0 ? -1 : rc;
+    hipStream_t st = h->stream;
+    const int n = h->n;
+    char* ws = (char*)h->ws;
+    const Layout L = make_layout(n, h->band_width, n);
+    std::memset(h->info.stage_ms, 0, sizeof(h->info.stage_ms));
+    h->info.fail_col = 0;
+    h->info.band_width = std::min(h->band_width, std::max(1, n - 1));
+    Timer tm(st);
+    rc = front_half(h, H, S, ws, L, tm, n);
+    if (rc) { tm.finish(&h->info); return rc; }
+    double* w = (double*)(ws + L.w);
+    double* f = occ ? occ : (double*)(ws + L.f);
+    double* scal = (double*)(ws + L.scal);
+    int status = 0;
+    int ks = 0;
+    double hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (h->occ_scheme == ELSI_GPU_OCC_FERMI) {
+        fermi_occupations(st, n, w, h->n_electron, h->kT, h->spin, h->occ_accuracy, h->mu_max_steps, kFCut, f, scal);
+        if (hipMemcpyAsync(hs, scal, 6 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return kStatusHip;
+        if (hipStreamSynchronize(st) != hipSuccess) return kStatusHip;
+        status = (int)hs[1];
+        ks = (int)hs[2];
+    } else {
+        explicit_occupations(st, n, h->n_state, w, f, kFCut, scal);
+        if (hipMemcpyAsync(hs, scal, 6 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return kStatusHip;
+        if (hipStreamSynchronize(st) != hipSuccess) return kStatusHip;
+        ks = (int)hs[2];
+    }
+    tm.mark(ELSI_GPU_ST_OCC);
+    back_half(h, S, ws, L, tm, ks);
+    density_matrix(st, n, ks, (double*)(ws + L.z), n, f, (double*)(ws + L.z2), D, n);
+    tm.mark(ELSI_GPU_ST_DENSITY);
+    if (eval) (void)hipMemcpyAsync(eval, w, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    rc = sync_status(st);
+    if (rc) return rc;
+    tm.finish(&h->info);
+    *energy = hs[3];
+    if (mu) *mu = hs[0];
+    h->info.mu = hs[0];
+    h->info.energy = hs[3];
+    h->info.k_s = ks;
+    h->info.mu_steps = (int)hs[4];
+    h->info.charge_residual = hs[5];
+    rc = read_flags(st, ws, L);
+    if (rc) return rc;
+    return status;
 }
 
 }  // extern "C"

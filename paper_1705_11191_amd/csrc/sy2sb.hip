@@ -1,0 +1,264 @@
+// Step (1) of the two-stage tridiagonalization (ELSI paper, Sec. 3.1,
+// Eq. (13) and Fig. 1): B = Q1^T H~ Q1 with bandwidth b.
+//
+// Panel p covers columns j .. j+b-1.  Its sub-band block P = A(j+b:n, j:j+b)
+// (m x b) is reduced to upper triangular form by b Householder reflectors
+// H_c = I - tau_c v_c v_c^T, and the trailing matrix A22 = A(j+b:n, j+b:n)
+// receives the two-sided block update Q^T A22 Q with Q = I - V T V^T:
+//     Y = A22 V,  X = Y T,  W = X - 1/2 V (T^T (V^T X)),
+//     A22 <- A22 - V W^T - W V^T,
+// all as FP64 matrix-core products (A22 is kept full symmetric).
+//
+// The panel QR uses one kernel launch per column.  A reflector for column c
+// needs x = P(c:m, c) only through x^T P(c:m, r) (r >= c), so each launch
+// (1) reduces the per-workgroup partial Gram row of column c left by the
+// previous launch, (2) applies reflector c to its rows, and (3) forms the
+// partial Gram row of column c+1 -- one grid-wide reduction per column.
+#include "common.h"
+
+namespace eg {
+namespace {
+
+constexpr int PR = 256;    // panel rows per workgroup (one row per thread)
+constexpr int BMAX = 64;
+constexpr int GS = BMAX + 2;   // per-block partial record: Gram row (64), tail, spare
+
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// c >= 0: apply reflector c (its Gram row is in gin, row c in rin) and form the
+// Gram record of column c+1.  c == -1: only form the record of column 0.
+__global__ __launch_bounds__(PR) void panel_step_kernel(int m, int bw, int c, double* P, int ldp,
+                                                        const double* __restrict__ gin, double* gout,
+                                                        const double* __restrict__ rin, double* rout,
+                                                        double* tau, int nblk)
+{
+    __shared__ double G[BMAX + 1];
+    __shared__ double scoef[BMAX];
+    __shared__ double red[PR / 64][BMAX + 1];
+    __shared__ double sh[4];
+    const int tid = threadIdx.x;
+    const int blk = blockIdx.x;
+    const int i = blk * PR + tid;
+    const int lane = tid & 63, wave = tid >> 6;
+
+    double rowv[BMAX];
+    const bool have_row = (i < m) && (i >= (c < 0 ? 0 : c));
+#pragma unroll
+    for (int r = 0; r < BMAX; ++r) {
+        rowv[r] = 0.0;
+        if (r < bw && r >= (c < 0 ? 0 : c) && have_row) rowv[r] = P[cm(i, r, ldp)];
+    }
+
+    if (c >= 0) {
+        // (1) Gram row of column c over rows >= c, and the squared tail over rows > c
+        for (int r = tid; r <= BMAX; r += PR) {
+            if ((r >= c && r < bw) || r == BMAX) {
+                double s = 0.0;
+                for (int b = 0; b < nblk; ++b) s += gin[(size_t)b * GS + r];
+                G[r] = s;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double x0 = rin[c];
+            double tail = G[BMAX];
+            double t = 0.0, alpha = x0, den = 1.0;
+            if (tail > 0.0) {
+                double nrm = sqrt(x0 * x0 + tail);
+                alpha = (x0 >= 0.0) ? -nrm : nrm;
+                t = (alpha - x0) / alpha;
+                den = x0 - alpha;
+            }
+            sh[0] = t; sh[1] = alpha; sh[2] = den;
+            if (blk == 0) tau[c] = t;
+        }
+        __syncthreads();
+        const double t = sh[0], alpha = sh[1], den = sh[2];
+        for (int r = tid; r < bw; r += PR)
+            if (r > c) scoef[r] = (t != 0.0) ? (G[r] - alpha * rin[r]) / den : 0.0;
+        __syncthreads();
+        // (2) apply H_c = I - t v v^T to this block's rows (v_c = 1, v_i = x_i / den)
+        if (have_row) {
+            double xc = 0.0;
+#pragma unroll
+            for (int r = 0; r < BMAX; ++r) if (r == c) xc = rowv[r];
+            double vi = (i == c) ? 1.0 : ((t != 0.0) ? xc / den : 0.0);
+#pragma unroll
+            for (int r = 0; r < BMAX; ++r) {
+                if (r > c && r < bw) {
+                    rowv[r] -= t * vi * scoef[r];
+                    P[cm(i, r, ldp)] = rowv[r];
+                }
+            }
+            if (i == c) P[cm(i, c, ldp)] = alpha;
+            else P[cm(i, c, ldp)] = vi;
+        }
+    }
+
+    // (3) record of column cn = c+1: Gram row over rows >= cn, tail over rows > cn
+    const int cn = c + 1;
+    if (cn >= bw) return;
+    double xn = 0.0;
+#pragma unroll
+    for (int r = 0; r < BMAX; ++r) if (r == cn) xn = rowv[r];
+    if (!(i < m && i >= cn)) xn = 0.0;
+#pragma unroll
+    for (int r = 0; r < BMAX; ++r) {
+        if (r >= cn && r < bw) {
+            double s = wave_sum(xn * rowv[r]);
+            if (lane == 0) red[wave][r] = s;
+        }
+    }
+    {
+        double tl = (i > cn && i < m) ? xn * xn : 0.0;
+        double s = wave_sum(tl);
+        if (lane == 0) red[wave][BMAX] = s;
+    }
+    __syncthreads();
+    for (int r = tid; r <= BMAX; r += PR) {
+        if ((r >= cn && r < bw) || r == BMAX) {
+            double s = 0.0;
+            for (int w = 0; w < PR / 64; ++w) s += red[w][r];
+            gout[(size_t)blk * GS + r] = s;
+        }
+    }
+    if (i == cn && i < m) {
+#pragma unroll
+        for (int r = 0; r < BMAX; ++r)
+            if (r >= cn && r < bw) rout[r] = rowv[r];
+    }
+}
+
+// Explicit V (m x bw, unit lower trapezoidal) of the panel into V (ld ldv).
+__global__ void panel_store_v_kernel(int m, int bw, int nr, const double* P, int ldp, double* V, int ldv)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int c = blockIdx.y;
+    if (i >= m || c >= bw) return;
+    double v = 0.0;
+    if (c < nr) v = (i == c) ? 1.0 : (i > c ? P[cm(i, c, ldp)] : 0.0);
+    V[cm(i, c, ldv)] = v;
+}
+
+// T (upper triangular, bw x bw, ld ldt) of Q = H_0 ... H_{bw-1} = I - V T V^T
+// from G = V^T V and tau: T_cc = tau_c, T(0:c, c) = -tau_c T(0:c, 0:c) G(0:c, c).
+__global__ __launch_bounds__(64) void build_t_kernel(int bw, const double* G, int ldg, const double* tau,
+                                                      double* T, int ldt)
+{
+    __shared__ double Ts[BMAX][BMAX + 1];
+    __shared__ double g[BMAX];
+    const int q = threadIdx.x;
+    for (int c = 0; c < BMAX; ++c) Ts[q][c] = 0.0;
+    __syncthreads();
+    for (int c = 0; c < bw; ++c) {
+        if (q < c) g[q] = G[cm(q, c, ldg)];
+        __syncthreads();
+        double tc = tau[c];
+        if (q < c) {
+            double s = 0.0;
+            for (int j = q; j < c; ++j) s += Ts[q][j] * g[j];
+            Ts[q][c] = -tc * s;
+        }
+        if (q == c) Ts[c][c] = tc;
+        __syncthreads();
+    }
+    if (q < bw)
+        for (int c = 0; c < bw; ++c) T[cm(q, c, ldt)] = Ts[q][c];
+}
+
+// Band of the reduced matrix: Bd(r, c) = A(c + r, c) for 0 <= r <= b, zero for b < r < ldb.
+__global__ void extract_band_kernel(int n, int b, const double* A, int lda, double* Bd, int ldb)
+{
+    int r = threadIdx.x;   // blockDim.x == ldb
+    int c = blockIdx.x;
+    if (c >= n || r >= ldb) return;
+    double v = 0.0;
+    if (r <= b && c + r < n) v = A[cm(c + r, c, lda)];
+    Bd[cm(r, c, ldb)] = v;
+}
+
+}  // namespace
+
+size_t sy2sb_workspace_doubles(int n, int b)
+{
+    size_t nblk = (size_t)ceil_div(n, PR);
+    size_t w = 0;
+    w += (size_t)n * b * 2;          // Y, X
+    w += (size_t)n * 2 * b * 2;      // VW, WV
+    w += 2 * nblk * GS;              // Gram records (ping-pong)
+    w += 2 * 64 + 64;                // pivot rows, tau
+    w += 3 * 64 * 64;                // G, Z, U
+    w += (size_t)ceil_div(n, 2048) * 4096;  // split-K partials
+    return w;
+}
+
+// A (n x n, full symmetric) -> band in Bd (ldbd = 2b rows), reflectors in
+// Vall (n x n, ld n: panel p occupies rows j+b.., columns j..j+b-1) and
+// T factors in Tall (b x b per panel).
+void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, double* Tall, double* Bd,
+           int ldbd, double* work)
+{
+    const int nblk_max = ceil_div(n, PR);
+    double* Y = work;
+    double* X = Y + (size_t)n * b;
+    double* VW = X + (size_t)n * b;
+    double* WV = VW + (size_t)n * 2 * b;
+    double* gbuf0 = WV + (size_t)n * 2 * b;
+    double* gbuf1 = gbuf0 + (size_t)nblk_max * GS;
+    double* rbuf0 = gbuf1 + (size_t)nblk_max * GS;
+    double* rbuf1 = rbuf0 + 64;
+    double* tau = rbuf1 + 64;
+    double* Gv = tau + 64;
+    double* Z = Gv + 64 * 64;
+    double* U = Z + 64 * 64;
+    double* part = U + 64 * 64;
+
+    const int npanel = ceil_div(n, b);
+    for (int p = 0; p < npanel; ++p) {
+        const int j = p * b;
+        const int r0 = j + b;
+        const int m = n - r0;
+        const int bw = std::min(b, n - j);
+        if (m < 2) break;
+        const int nr = std::min(bw, m - 1);
+        double* P = A + cm(r0, j, lda);
+        const int nblk = ceil_div(m, PR);
+        double* gi = gbuf0; double* go = gbuf1;
+        double* ri = rbuf0; double* ro = rbuf1;
+        hipLaunchKernelGGL(panel_step_kernel, dim3(nblk), dim3(PR), 0, st, m, bw, -1, P, lda, gi, go, ri, ro,
+                           tau, nblk);
+        for (int c = 0; c < nr; ++c) {
+            std::swap(gi, go);
+            std::swap(ri, ro);
+            hipLaunchKernelGGL(panel_step_kernel, dim3(nblk), dim3(PR), 0, st, m, bw, c, P, lda, gi, go, ri,
+                               ro, tau, nblk);
+        }
+        if (nr < bw) fill_d(st, tau + nr, (size_t)(bw - nr), 0.0);
+        double* V = Vall + cm(r0, j, n);
+        hipLaunchKernelGGL(panel_store_v_kernel, dim3(ceil_div(m, 256), bw), dim3(256), 0, st, m, bw, nr, P,
+                           lda, V, n);
+        double* T = Tall + (size_t)p * b * b;
+        dgemm_tn_small(st, bw, bw, m, 1.0, V, n, V, n, 0.0, Gv, 64, part);
+        hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(64), 0, st, bw, Gv, 64, tau, T, b);
+
+        // two-sided update of A22 (full symmetric)
+        double* A22 = A + cm(r0, r0, lda);
+        dgemm(st, 'N', 'N', m, bw, m, 1.0, A22, lda, V, n, 0.0, Y, m);
+        dgemm(st, 'N', 'N', m, bw, bw, 1.0, Y, m, T, b, 0.0, X, m);
+        dgemm_tn_small(st, bw, bw, m, 1.0, V, n, X, m, 0.0, Z, 64, part);
+        dgemm(st, 'T', 'N', bw, bw, bw, 1.0, T, b, Z, 64, 0.0, U, 64);
+        dgemm(st, 'N', 'N', m, bw, bw, -0.5, V, n, U, 64, 1.0, X, m);   // X <- W
+        copy_matrix(st, m, bw, V, n, VW, m);
+        copy_matrix(st, m, bw, X, m, VW + (size_t)m * bw, m);
+        copy_matrix(st, m, bw, X, m, WV, m);
+        copy_matrix(st, m, bw, V, n, WV + (size_t)m * bw, m);
+        dgemm(st, 'N', 'T', m, m, 2 * bw, -1.0, VW, m, WV, m, 1.0, A22, lda);
+    }
+    hipLaunchKernelGGL(extract_band_kernel, dim3(n), dim3(ldbd), 0, st, n, b, A, lda, Bd, ldbd);
+}
+
+}  // namespace eg

@@ -215,7 +215,41 @@ __global__ __launch_bounds__(FD_THREADS) void fermi_kernel(int n, const double* 
     }
 }
 
+__global__ __launch_bounds__(FD_THREADS) void explicit_occ_kernel(int n, const double* eps, const double* f,
+                                                                  double f_cut, double* scal)
+{
+    __shared__ double red[FD_THREADS / 64 + 1];
+    double en = 0.0, last = -1.0;
+    for (int l = threadIdx.x; l < n; l += FD_THREADS) {
+        en += f[l] * eps[l];
+        if (f[l] > f_cut) last = fmax(last, (double)l);
+    }
+    double energy = block_sum(en, red);
+    // maximum of `last` through the same reduction shape
+    for (int off = 32; off > 0; off >>= 1) last = fmax(last, __shfl_down(last, off, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = -1.0;
+        for (int w = 0; w < FD_THREADS / 64; ++w) m = fmax(m, red[w]);
+        scal[0] = 0.0;
+        scal[1] = 0.0;
+        scal[2] = m + 1.0;
+        scal[3] = energy;
+        scal[4] = 0.0;
+        scal[5] = 0.0;
+    }
+}
+
 }  // namespace
+
+void explicit_occupations(hipStream_t st, int n, int n_state, const double* eps, const double* f,
+                          double f_cut, double* scal)
+{
+    (void)n_state;
+    hipLaunchKernelGGL(explicit_occ_kernel, dim3(1), dim3(FD_THREADS), 0, st, n, eps, f, f_cut, scal);
+}
 
 void fill_d(hipStream_t st, double* p, size_t count, double v)
 {

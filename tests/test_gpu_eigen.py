@@ -1,0 +1,210 @@
+"""Parity of the eigen stages and of the whole ev / dm path against the CPU oracle.
+
+Tolerances follow from backward stability: an orthogonal-transform method
+perturbs a symmetric T (or A) by about c n eps ||A||, which moves each
+eigenvalue by at most that much; eigenvector residuals are of the same order,
+and orthogonality loss is about c n eps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import generator as G
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), device="cuda", dtype=torch.float64)
+
+
+def _sym(n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    return (A + A.T) / 2
+
+
+def _band_dense(band, b, n):
+    B = np.zeros((n, n))
+    for r in range(b + 1):
+        for c in range(n - r):
+            B[c + r, c] = band[r, c]
+            B[c, c + r] = band[r, c]
+    return B
+
+
+@pytest.mark.parametrize("n,b", [(10, 8), (64, 16), (65, 32), (130, 64), (300, 64), (513, 32)])
+def test_band_reduce_keeps_spectrum(n, b):
+    from paper_1705_11191_amd import binding as B
+
+    A = _sym(n, n + b)
+    band = B.band_reduce(_dev(A), b).cpu().numpy()   # (b+1) x n
+    Bm = _band_dense(band, min(b, n - 1), n)
+    ev_ref = np.linalg.eigvalsh(A)
+    d, e, _ = O.tred(Bm)
+    ev = O.tridiag_eigvals(d, e)
+    assert np.abs(ev - ev_ref).max() <= 64 * n * EPS * np.abs(ev_ref).max()
+
+
+@pytest.mark.parametrize("n,b", [(2, 8), (3, 8), (17, 8), (64, 64), (100, 32), (257, 64), (600, 64)])
+def test_tridiagonalize_keeps_spectrum(n, b):
+    from paper_1705_11191_amd import binding as B
+
+    A = _sym(n, 7 * n + b)
+    d, e = B.tridiagonalize(_dev(A), b)
+    w = O.tridiag_eigvals(d.cpu().numpy(), e.cpu().numpy())
+    ref = O.tridiag_eigvals(*O.tred(A)[:2])
+    assert np.abs(w - ref).max() <= 64 * n * EPS * np.abs(ref).max()
+
+
+def _tridiag_cases():
+    rng = np.random.default_rng(11)
+    cases = []
+    for n in [1, 2, 3, 63, 64, 65, 100, 200, 513, 1000]:
+        cases.append((f"rand{n}", rng.standard_normal(n), rng.standard_normal(max(n - 1, 0))))
+    n = 300   # chain: many close eigenvalue pairs after tearing
+    cases.append(("chain300", np.zeros(n), -np.ones(n - 1)))
+    e = rng.standard_normal(399)
+    e[::7] = 0.0   # exact splits -> deflation
+    cases.append(("split400", rng.standard_normal(400), e))
+    d = np.repeat([1.0, 2.0, 3.0], 100)   # clusters of equal diagonal entries
+    cases.append(("cluster300", d, 1e-9 * rng.standard_normal(299)))
+    k = np.arange(257)
+    cases.append(("wilk257", np.abs(k - 128.0), np.ones(256)))   # Wilkinson-like, close pairs
+    return cases
+
+
+@pytest.mark.parametrize("name,d,e", _tridiag_cases(), ids=lambda x: x if isinstance(x, str) else "")
+def test_tridiag_divide_and_conquer(name, d, e):
+    from paper_1705_11191_amd import binding as B
+
+    n = d.shape[0]
+    w, Z = B.tridiag_eig(_dev(d), _dev(e))
+    w = w.cpu().numpy()
+    Z = Z.cpu().numpy()
+    ref = O.tridiag_eigvals(d, e)
+    nrm = max(np.abs(d).max() + 2 * (np.abs(e).max() if e.size else 0.0), 1e-300)
+    assert np.all(np.diff(w) >= 0)
+    assert np.abs(w - ref).max() <= 32 * n * EPS * nrm
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    assert np.abs(T @ Z - Z * w).max() <= 32 * n * EPS * nrm
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 32 * n * EPS
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 129, 300])
+def test_standard_ev_overlap_is_unit(n):
+    from paper_1705_11191_amd import binding as B
+
+    A = _sym(n, 3 * n)
+    h = B.Handle(n, n, n / 4)
+    h.set_overlap_is_unit(True)
+    ev, C = h.ev(_dev(A), None)
+    h.close()
+    ev = ev.cpu().numpy()
+    C = C.cpu().numpy()
+    ref = np.linalg.eigvalsh(A)
+    assert np.abs(ev - ref).max() <= 64 * n * EPS * np.abs(ref).max()
+    assert np.abs(A @ C - C * ev).max() <= 64 * n * EPS * np.abs(ref).max()
+    assert np.abs(C.T @ C - np.eye(n)).max() <= 64 * n * EPS
+
+
+def _gate_eigs(ev, ref):
+    """|eps - eps_ref| <= 1e-10 Ha max(1, |eps|)."""
+    return (np.abs(ev - ref) / np.maximum(1.0, np.abs(ref))).max()
+
+
+@pytest.mark.parametrize("b", [64, 32])
+def test_ev_config0_vs_oracle(b):
+    from paper_1705_11191_amd import binding as B
+
+    sp = G.make_config(0)
+    ev_ref, C_ref, _ = O.gevp(sp.H, sp.S)
+    h = B.Handle(sp.n, sp.n, sp.n_occ)
+    h.set_band_width(b)
+    S = _dev(sp.S)
+    ev, C = h.ev(_dev(sp.H), S)
+    h.close()
+    ev = ev.cpu().numpy()
+    C = C.cpu().numpy()
+    assert _gate_eigs(ev, ev_ref) <= 1e-10
+    # S-orthonormality, and subspace agreement of the occupied block with the oracle
+    assert np.abs(C.T @ sp.S @ C - np.eye(sp.n)).max() <= 1e-8
+    k = int(sp.n_occ)
+    P = C[:, :k] @ C[:, :k].T
+    P_ref = C_ref[:, :k] @ C_ref[:, :k].T
+    assert np.abs(P - P_ref).max() <= 1e-8
+    # L was written into S (lower, zero above)
+    L = S.cpu().numpy().T
+    assert np.abs(np.triu(L, 1)).max() == 0.0
+    assert np.abs(L @ L.T - sp.S).max() <= 1e-12 * np.abs(sp.S).max() * sp.n
+
+
+def test_dm_config0_vs_oracle():
+    from paper_1705_11191_amd import binding as B
+
+    sp = G.make_config(0)
+    ref = O.dm(sp.H, sp.S, sp.n_occ, sp.kT)
+    h = B.Handle(sp.n, sp.n, sp.n_occ)
+    D, ev, f, energy, mu, st = h.dm(_dev(sp.H), _dev(sp.S))
+    info = h.info()
+    h.close()
+    D = D.cpu().numpy()
+    ev = ev.cpu().numpy()
+    assert st == 0
+    assert _gate_eigs(ev, ref["eval"]) <= 1e-10
+    assert np.abs(D - ref["D"]).max() <= 1e-9
+    assert np.abs(D - D.T).max() == 0.0
+    assert abs(mu - ref["mu"]) <= 1e-9
+    assert abs(energy - ref["energy"]) <= 1e-9
+    assert abs(np.trace(D @ sp.S) - sp.n_occ) <= 1e-10
+    assert info["k_s"] == int(np.sum(ref["occ"] > 1e-20))
+
+
+def test_dm_explicit_integer_occupations_idempotent():
+    from paper_1705_11191_amd import binding as B
+
+    sp = G.make_config(0)
+    n, k = sp.n, int(sp.n_occ)
+    f = np.zeros(n)
+    f[:k] = 1.0
+    h = B.Handle(n, n, float(k))
+    h.set_occupation(scheme=B.OCC_EXPLICIT)
+    D, ev, _, energy, mu, st = h.dm(_dev(sp.H), _dev(sp.S), occ=_dev(f))
+    h.close()
+    D = D.cpu().numpy()
+    assert st == 0
+    assert np.abs(D @ sp.S @ D - D).max() <= 1e-9
+    assert abs(np.trace(D @ sp.S) - k) <= 1e-10
+    assert abs(energy - ev.cpu().numpy()[:k].sum()) <= 1e-10
+
+
+def test_dm_not_positive_definite_reports_status():
+    from paper_1705_11191_amd import binding as B
+
+    sp = G.make_config(0)
+    S = sp.S.copy()
+    S[100, 100] = -1.0
+    h = B.Handle(sp.n, sp.n, sp.n_occ)
+    with pytest.raises(B.ElsiGpuError) as ei:
+        h.dm(_dev(sp.H), _dev(S))
+    assert ei.value.status == 1
+    assert h.info()["fail_col"] == 101
+    h.close()
+
+
+def test_dm_nonfinite_input_reports_status():
+    from paper_1705_11191_amd import binding as B
+
+    sp = G.make_config(0)
+    H = sp.H.copy()
+    H[5, 3] = np.nan
+    h = B.Handle(sp.n, sp.n, sp.n_occ)
+    with pytest.raises(B.ElsiGpuError) as ei:
+        h.dm(_dev(H), _dev(sp.S))
+    assert ei.value.status == 7
+    h.close()
