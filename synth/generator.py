@@ -114,11 +114,7 @@ def build_system(centers_per_orbital: np.ndarray, alphas: np.ndarray, h: np.ndar
     return H, S, sigma
 
 
-def make_lattice_system(n: int, seed: int, kappa: float = DEFAULT_KAPPA,
-                        orbitals_per_atom: int = 15, spacing: float = 2.5,
-                        jitter_amp: float = 0.2, alpha_lo: float = 0.2,
-                        alpha_hi: float = 3.0) -> SystemSpec:
-    """3D jittered cubic lattice, ``orbitals_per_atom`` s-Gaussians per atom, first n orbitals kept."""
+def _draw_lattice(n, seed, orbitals_per_atom, spacing, jitter_amp, alpha_lo, alpha_hi):
     n_atoms = -(-n // orbitals_per_atom)
     rng = np.random.default_rng(seed)
     jitter = rng.uniform(-jitter_amp, jitter_amp, size=(n_atoms, 3))
@@ -126,7 +122,77 @@ def make_lattice_system(n: int, seed: int, kappa: float = DEFAULT_KAPPA,
     h = rng.uniform(-15.0, -5.0, size=n) * HARTREE_PER_EV
     pos = lattice_positions(n_atoms, spacing, jitter)
     centers = np.repeat(pos, orbitals_per_atom, axis=0)[:n]
-    H, S, sigma = build_system(centers, alphas, h, kappa)
+    return n_atoms, centers, alphas, h
+
+
+def build_system_torch(centers, alphas, h, kappa=DEFAULT_KAPPA, device="cuda", block=4096,
+                       lanczos_steps=80):
+    """Same matrices as :func:`build_system`, assembled with torch on ``device``.
+
+    Returns (H, S, sigma) as float64 torch tensors.  lambda_max(S_lit) comes
+    from a Lanczos run with full reorthogonalization (deterministic start).
+    """
+    import torch
+
+    c = torch.as_tensor(centers, dtype=torch.float64, device=device)
+    a = torch.as_tensor(alphas, dtype=torch.float64, device=device)
+    hh = torch.as_tensor(h, dtype=torch.float64, device=device)
+    n = a.shape[0]
+    S = torch.empty((n, n), dtype=torch.float64, device=device)
+    H = torch.empty((n, n), dtype=torch.float64, device=device)
+    for i0 in range(0, n, block):
+        i1 = min(n, i0 + block)
+        ai = a[i0:i1, None]
+        p = ai + a[None, :]
+        d2 = torch.zeros((i1 - i0, n), dtype=torch.float64, device=device)
+        for ax in range(3):
+            d2 += (c[i0:i1, ax, None] - c[None, :, ax]) ** 2
+        Sb = (2.0 * torch.sqrt(ai * a[None, :]) / p) ** 1.5 * torch.exp(-(ai * a[None, :] / p) * d2)
+        S[i0:i1] = Sb
+        H[i0:i1] = WH_K * 0.5 * Sb * (hh[i0:i1, None] + hh[None, :])
+        del ai, p, d2, Sb
+    sigma = 0.0
+    if kappa is not None and kappa > 0:
+        k = min(lanczos_steps, n)
+        Q = torch.zeros((k + 1, n), dtype=torch.float64, device=device)
+        alpha = torch.zeros(k, dtype=torch.float64)
+        beta = torch.zeros(k, dtype=torch.float64)
+        Q[0] = 1.0 / math.sqrt(n)
+        m = k
+        for j in range(k):
+            w = S @ Q[j]
+            alpha[j] = torch.dot(w, Q[j]).item()
+            w = w - Q[: j + 1].T @ (Q[: j + 1] @ w)
+            w = w - Q[: j + 1].T @ (Q[: j + 1] @ w)
+            bj = torch.linalg.norm(w).item()
+            beta[j] = bj
+            if bj < 1e-14:
+                m = j + 1
+                break
+            Q[j + 1] = w / bj
+        T = np.diag(alpha[:m].numpy()) + np.diag(beta[: m - 1].numpy(), 1) + np.diag(beta[: m - 1].numpy(), -1)
+        sigma = float(np.linalg.eigvalsh(T)[-1]) / kappa
+        del Q
+    di = torch.arange(n, device=device)
+    H[di, di] = hh
+    S[di, di] += sigma
+    return H, S, sigma
+
+
+def make_lattice_system(n: int, seed: int, kappa: float = DEFAULT_KAPPA,
+                        orbitals_per_atom: int = 15, spacing: float = 2.5,
+                        jitter_amp: float = 0.2, alpha_lo: float = 0.2,
+                        alpha_hi: float = 3.0, device=None) -> SystemSpec:
+    """3D jittered cubic lattice, ``orbitals_per_atom`` s-Gaussians per atom, first n orbitals kept.
+
+    With ``device`` set (a torch device) H and S are torch tensors built there.
+    """
+    n_atoms, centers, alphas, h = _draw_lattice(n, seed, orbitals_per_atom, spacing, jitter_amp,
+                                                alpha_lo, alpha_hi)
+    if device is not None:
+        H, S, sigma = build_system_torch(centers, alphas, h, kappa, device=device)
+    else:
+        H, S, sigma = build_system(centers, alphas, h, kappa)
     return SystemSpec(H, S, n_occ=float(n // 4), kT=DEFAULT_KT,
                       meta=dict(kind="lattice3d", n_atoms=n_atoms, seed=seed,
                                 kappa=kappa, sigma=sigma, orbitals_per_atom=orbitals_per_atom))
@@ -156,14 +222,14 @@ def batch_sizes(count: int = 256, seed: int = 0, lo: int = 256, hi: int = 4096,
     return (multiple * np.round(raw / multiple)).astype(np.int64)
 
 
-def make_config(cfg: int, seed: int = 0, kappa: float = DEFAULT_KAPPA) -> SystemSpec:
+def make_config(cfg: int, seed: int = 0, kappa: float = DEFAULT_KAPPA, device=None) -> SystemSpec:
     """The single-problem workloads: 0 = 512-orbital chain, 1 = N 8192 lattice, 2 = N 32768 lattice."""
     if cfg == 0:
         return make_chain_system(seed=seed, kappa=kappa)
     if cfg == 1:
-        return make_lattice_system(8192, seed, kappa)
+        return make_lattice_system(8192, seed, kappa, device=device)
     if cfg == 2:
-        return make_lattice_system(32768, seed, kappa)
+        return make_lattice_system(32768, seed, kappa, device=device)
     raise ValueError(f"unknown single-problem config {cfg}")
 
 
