@@ -9,8 +9,11 @@
 // Grouping b consecutive sweeps g, the order "groups descending, inside a
 // group k ascending, inside (g, k) sweeps descending" keeps every overlapping
 // pair in its reverse-execution order, and the reflectors of one (g, k) all
-// live in a window of 2b-1 rows.  One workgroup owns a slab of columns of X,
-// stages each window in LDS and applies the reflectors there.
+// live in a window of 2b-1 rows.  The b reflectors of (g, k), applied sweeps
+// descending, form one block reflector H_{s_lo} ... H_{s_hi} = I - V T V^T
+// (T formed once per (g, k) by a separate kernel); one workgroup owns a slab
+// of 32 columns of X and applies each block as three FP64 matrix-core
+// products (V^T X_W, T W, X_W - V W2) on the window staged in LDS.
 //
 // Step (5).  Q1 = Q_0 Q_1 ... with Q_p = I - V_p T_p V_p^T from the panels of
 // step (1); X <- Q1 X applies the panels last to first as three FP64
@@ -21,123 +24,195 @@ namespace eg {
 namespace {
 
 constexpr int NB2 = 64;     // maximum band width
-constexpr int NC = 64;      // columns of X per workgroup
+constexpr int NCB = 32;     // columns of X per workgroup in the blocked Q2 application
 
-__global__ __launch_bounds__(256) void apply_q2_kernel(int n, int b, int ncol, const double* __restrict__ V2,
-                                                       const double* __restrict__ tau2, int kmax, double* X,
-                                                       int ldx)
+__device__ inline int q2_ntasks(int n, int b, int s) { return (n - 2 - s) / b + 1; }
+
+// Stage the reflectors of group (g, k) in LDS: column i is the reflector of
+// sweep s_lo + i at rows [i, i + L_i) of the window that starts at base.
+__device__ void q2_load_v(int n, int b, int g, int k, const double* __restrict__ V2, double (*Vs)[NB2 + 1])
 {
-    __shared__ double W[2 * NB2][NC + 1];
-    __shared__ double vs[NB2];
-    __shared__ double red[4][NC + 1];
+    const int nsweeps = n - 2;
+    const int s_lo = g * b;
+    const int base = s_lo + 1 + k * b;
+    for (int e = threadIdx.x; e < 2 * NB2 * NB2; e += blockDim.x) {
+        const int r = e % (2 * NB2), i = e / (2 * NB2);
+        double v = 0.0;
+        const int s = s_lo + i;
+        if (i < b && s < nsweeps && k < q2_ntasks(n, b, s)) {
+            const int r0 = s + 1 + k * b;
+            const int L = min(b, n - r0);
+            const int q = r - i;
+            if (q >= 0 && q < L) v = V2[cm(base + r, s, n)];
+        }
+        Vs[r][i] = v;
+    }
+}
+
+// T of P = H_{s_lo} H_{s_lo+1} ... H_{s_hi} = I - V T V^T for every (g, k)
+// (forward accumulation from G = V^T V and the tau's).
+__global__ __launch_bounds__(256) void q2_build_t_kernel(int n, int b, const double* __restrict__ V2,
+                                                         const double* __restrict__ tau2, int kmax, double* Tq)
+{
+    __shared__ double Vs[2 * NB2][NB2 + 1];
+    __shared__ double Gs[NB2][NB2 + 1];
+    __shared__ double Ts[NB2][NB2 + 1];
+    __shared__ double tau[NB2];
+    const int g = blockIdx.x, k = blockIdx.y;
+    const int nsweeps = n - 2;
+    const int s_lo = g * b;
+    if (k >= q2_ntasks(n, b, s_lo)) return;
     const int tid = threadIdx.x;
-    const int c = tid & 63, part = tid >> 6;
-    const int col0 = blockIdx.x * NC;
-    const int gc = col0 + c;
+    q2_load_v(n, b, g, k, V2, Vs);
+    if (tid < NB2) {
+        const int s = s_lo + tid;
+        tau[tid] = (tid < b && s < nsweeps && k < q2_ntasks(n, b, s)) ? tau2[(size_t)s * kmax + k] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < NB2 * NB2; e += 256) {
+        const int i = e % NB2, j = e / NB2;
+        double acc = 0.0;
+        if (i < j) {
+            for (int r = 0; r < 2 * NB2; ++r) acc += Vs[r][i] * Vs[r][j];
+        }
+        Gs[i][j] = acc;
+        Ts[i][j] = 0.0;
+    }
+    __syncthreads();
+    for (int c = 0; c < b; ++c) {
+        if (tid < c) {
+            double acc = 0.0;
+            for (int j = tid; j < c; ++j) acc += Ts[tid][j] * Gs[j][c];
+            Ts[tid][c] = -tau[c] * acc;
+        }
+        if (tid == c) Ts[c][c] = tau[c];
+        __syncthreads();
+    }
+    double* T = Tq + ((size_t)g * kmax + k) * NB2 * NB2;
+    for (int e = tid; e < NB2 * NB2; e += 256) T[e] = Ts[e % NB2][e / NB2];   // column-major, ld 64
+}
+
+// acc (16 x 16 block) += A (16 x 4K) B (4K x 16) with A(i, kk) = fa(i, kk), B(kk, j) = fb(kk, j)
+// D layout: lane l, element r -> row 4 r + l / 16, column l % 16.
+
+__global__ __launch_bounds__(256) void q2_apply_blocked_kernel(int n, int b, int ncol, const double* __restrict__ V2,
+                                                               const double* __restrict__ Tq, int kmax, double* X,
+                                                               int ldx)
+{
+    __shared__ double Vs[2 * NB2][NB2 + 1];
+    __shared__ double Xs[2 * NB2][NCB + 1];
+    __shared__ double Ws[NB2][NCB + 1];
+    __shared__ double W2s[NB2][NCB + 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int col0 = blockIdx.x * NCB;
     const int nsweeps = n - 2;
     if (nsweeps <= 0) return;
     const int ngroups = ceil_div(nsweeps, b);
+    const int li = lane & 15, lk = lane >> 4;
     for (int g = ngroups - 1; g >= 0; --g) {
         const int s_lo = g * b;
-        const int s_hi = min(nsweeps - 1, s_lo + b - 1);
-        const int nt_max = (n - 2 - s_lo) / b + 1;
-        for (int k = 0; k < nt_max; ++k) {
+        const int ntk = q2_ntasks(n, b, s_lo);
+        for (int k = 0; k < ntk; ++k) {
             const int base = s_lo + 1 + k * b;
-            if (base >= n) break;
             const int wrows = min(2 * b - 1, n - base);
-            // stage the window
-            for (int r = part; r < wrows; r += 4)
-                W[r][c] = (gc < ncol) ? X[cm(base + r, gc, ldx)] : 0.0;
-            __syncthreads();
-            for (int s = s_hi; s >= s_lo; --s) {
-                if (k > (n - 2 - s) / b) continue;   // sweep s has no task k
-                const double t = tau2[(size_t)s * kmax + k];
-                if (t == 0.0) continue;
-                const int r0 = s + 1 + k * b;
-                const int L = min(b, n - r0);
-                const int off = r0 - base;
-                if (tid < L) vs[tid] = V2[cm(r0 + tid, s, n)];
-                __syncthreads();
-                double acc = 0.0;
-                for (int i = part; i < L; i += 4) acc += vs[i] * W[off + i][c];
-                red[part][c] = acc;
-                __syncthreads();
-                const double u = t * (red[0][c] + red[1][c] + red[2][c] + red[3][c]);
-                for (int i = part; i < L; i += 4) W[off + i][c] -= vs[i] * u;
-                __syncthreads();
+            q2_load_v(n, b, g, k, V2, Vs);
+            for (int e = tid; e < 2 * NB2 * NCB; e += 256) {
+                const int r = e % (2 * NB2), c = e / (2 * NB2);
+                const int gc = col0 + c;
+                Xs[r][c] = (r < wrows && gc < ncol) ? X[cm(base + r, gc, ldx)] : 0.0;
             }
-            for (int r = part; r < wrows; r += 4)
-                if (gc < ncol) X[cm(base + r, gc, ldx)] = W[r][c];
+            __syncthreads();
+            // W = V^T X_W (64 x 32): wave w owns rows 16w .. 16w+15, both column blocks
+            {
+                double4_t a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+                const int i0 = wave * 16;
+                for (int kk = 0; kk < 2 * NB2; kk += 4) {
+                    const double av = Vs[kk + lk][i0 + li];
+                    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xs[kk + lk][li], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xs[kk + lk][16 + li], a1, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    Ws[i0 + 4 * r + lk][li] = a0[r];
+                    Ws[i0 + 4 * r + lk][16 + li] = a1[r];
+                }
+            }
+            __syncthreads();
+            // W2 = T W (64 x 32), T from global (column-major, ld 64)
+            {
+                const double* T = Tq + ((size_t)g * kmax + k) * NB2 * NB2;
+                double4_t a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+                const int i0 = wave * 16;
+                for (int kk = 0; kk < NB2; kk += 4) {
+                    const double av = T[(i0 + li) + (size_t)(kk + lk) * NB2];
+                    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ws[kk + lk][li], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ws[kk + lk][16 + li], a1, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    W2s[i0 + 4 * r + lk][li] = a0[r];
+                    W2s[i0 + 4 * r + lk][16 + li] = a1[r];
+                }
+            }
+            __syncthreads();
+            // X_W -= V W2 (128 x 32): wave w owns rows 32w .. 32w+31
+            {
+                double4_t acc[2][2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) acc[a][c] = (double4_t){0, 0, 0, 0};
+                const int i0 = wave * 32;
+                for (int kk = 0; kk < NB2; kk += 4) {
+                    const double b0 = W2s[kk + lk][li], b1 = W2s[kk + lk][16 + li];
+                    const double v0 = Vs[i0 + li][kk + lk], v1 = Vs[i0 + 16 + li][kk + lk];
+                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, b0, acc[0][0], 0, 0, 0);
+                    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, b1, acc[0][1], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(v1, b0, acc[1][0], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(v1, b1, acc[1][1], 0, 0, 0);
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) Xs[i0 + 16 * a + 4 * r + lk][16 * c + li] -= acc[a][c][r];
+            }
+            __syncthreads();
+            for (int e = tid; e < 2 * NB2 * NCB; e += 256) {
+                const int r = e % (2 * NB2), c = e / (2 * NB2);
+                const int gc = col0 + c;
+                if (r < wrows && gc < ncol) X[cm(base + r, gc, ldx)] = Xs[r][c];
+            }
             __syncthreads();
         }
     }
-}
-
-// partial W = A^T B over one chunk of rows for a 64-column tile of B (A has m <= 64 columns)
-__global__ __launch_bounds__(256) void tn_tile_partial(int m, int ncol, int k, const double* __restrict__ A,
-                                                       int lda, const double* __restrict__ B, int ldb,
-                                                       double* __restrict__ part, int chunk)
-{
-    __shared__ double As[32][65];
-    __shared__ double Bs[32][65];
-    const int r0 = blockIdx.x * chunk;
-    const int r1 = min(k, r0 + chunk);
-    const int c0 = blockIdx.y * 64;
-    const int tid = threadIdx.x;
-    double acc[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    for (int rr = r0; rr < r1; rr += 32) {
-        for (int e = tid; e < 32 * 64; e += 256) {
-            int kk = e % 32, cc = e / 32;
-            int gk = rr + kk;
-            As[kk][cc] = (gk < r1 && cc < m) ? A[cm(gk, cc, lda)] : 0.0;
-            Bs[kk][cc] = (gk < r1 && c0 + cc < ncol) ? B[cm(gk, c0 + cc, ldb)] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            int e = tid + q * 256;
-            int i = e % 64, j = e / 64;
-            double s = acc[q];
-#pragma unroll 8
-            for (int kk = 0; kk < 32; ++kk) s += As[kk][i] * Bs[kk][j];
-            acc[q] = s;
-        }
-        __syncthreads();
-    }
-    double* P = part + ((size_t)blockIdx.x * gridDim.y + blockIdx.y) * 4096;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) P[tid + q * 256] = acc[q];
-}
-
-__global__ void tn_tile_reduce(int m, int ncol, int nchunks, int ntiles, const double* __restrict__ part,
-                               double* C, int ldc)
-{
-    const int tile = blockIdx.y;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 4096) return;
-    const int i = e % 64, j = tile * 64 + e / 64;
-    if (i >= m || j >= ncol) return;
-    double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += part[((size_t)c * ntiles + tile) * 4096 + e];
-    C[cm(i, j, ldc)] = s;
 }
 
 }  // namespace
 
+size_t apply_q2_workspace_doubles(int n, int b)
+{
+    const int ngroups = std::max(1, ceil_div(std::max(n - 2, 1), b));
+    const int kmax = n >= 2 ? (n - 2) / b + 1 : 1;
+    return (size_t)ngroups * kmax * NB2 * NB2;
+}
+
+// X (n x ncol) <- Q2 X; Tq: apply_q2_workspace_doubles(n, b) doubles.
 void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const double* tau2, int kmax, double* X,
-              int ldx)
+              int ldx, double* Tq)
 {
     if (n <= 2 || ncol <= 0) return;
-    hipLaunchKernelGGL(apply_q2_kernel, dim3(ceil_div(ncol, NC)), dim3(256), 0, st, n, b, ncol, V2, tau2, kmax,
-                       X, ldx);
+    const int ngroups = ceil_div(n - 2, b);
+    hipLaunchKernelGGL(q2_build_t_kernel, dim3(ngroups, kmax), dim3(256), 0, st, n, b, V2, tau2, kmax, Tq);
+    hipLaunchKernelGGL(q2_apply_blocked_kernel, dim3(ceil_div(ncol, NCB)), dim3(256), 0, st, n, b, ncol, V2, Tq,
+                       kmax, X, ldx);
 }
 
 size_t apply_q1_workspace_doubles(int n, int ncol)
 {
-    const int chunk = 1024;
-    return (size_t)ceil_div(n, chunk) * ceil_div(std::max(ncol, 1), 64) * 4096 + (size_t)2 * 64 * std::max(ncol, 1);
+    return (size_t)8 * 64 * std::max(ncol, 1) + (size_t)2 * 64 * std::max(ncol, 1);
 }
 
 // X (n x ncol) <- Q1 X with the panel reflectors of step (1).
@@ -145,12 +220,11 @@ void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const 
               double* work)
 {
     if (ncol <= 0) return;
-    const int chunk = 1024;
     const int npanel = ceil_div(n, b);
     double* W = work;                        // 64 x ncol
     double* W2 = W + (size_t)64 * ncol;      // 64 x ncol
     double* part = W2 + (size_t)64 * ncol;
-    const int ntiles = ceil_div(ncol, 64);
+    const size_t npart = apply_q1_workspace_doubles(n, ncol) - (size_t)2 * 64 * ncol;
     for (int p = npanel - 1; p >= 0; --p) {
         const int j = p * b;
         const int r0 = j + b;
@@ -159,11 +233,7 @@ void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const 
         const int bw = std::min(b, n - j);
         const double* V = Vall + cm(r0, j, n);
         const double* T = Tall + (size_t)p * b * b;
-        const int nchunks = ceil_div(m, chunk);
-        hipLaunchKernelGGL(tn_tile_partial, dim3(nchunks, ntiles), dim3(256), 0, st, bw, ncol, m, V, n,
-                           X + r0, ldx, part, chunk);
-        hipLaunchKernelGGL(tn_tile_reduce, dim3(16, ntiles), dim3(256), 0, st, bw, ncol, nchunks, ntiles, part, W,
-                           64);
+        dgemm_splitk(st, 'T', 'N', bw, ncol, m, 1.0, V, n, X + r0, ldx, 0.0, W, 64, part, npart);
         dgemm(st, 'N', 'N', bw, ncol, bw, 1.0, T, b, W, 64, 0.0, W2, 64);
         dgemm(st, 'N', 'N', m, ncol, bw, -1.0, V, n, W2, 64, 1.0, X + r0, ldx);
     }

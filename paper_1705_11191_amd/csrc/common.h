@@ -47,6 +47,12 @@ void dgemm(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha,
            const double* A, int lda, const double* B, int ldb, double beta,
            double* C, int ldc, int uplo = 0);
 
+// As dgemm, split over K into partial products (summed in a fixed order) when
+// the output has too few tiles to fill the GPU; `work` holds the partials.
+void dgemm_splitk(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha,
+                  const double* A, int lda, const double* B, int ldb, double beta, double* C,
+                  int ldc, double* work, size_t work_doubles);
+
 // Deterministic split-K product W = A^T B for tall A (k x m), B (k x n),
 // m, n <= 64: partial products over row chunks are summed in a fixed order.
 // `part` needs ceil(k / chunk) * m * n doubles.
@@ -111,8 +117,9 @@ int stedc(hipStream_t st, int n, const double* d, const double* e, double* w, do
           double* U, int ldz, int ncol_final, void* work, int* err, int* err_host_copy);
 
 // Steps (4) and (5): back-transformations; see backtx.hip.
+size_t apply_q2_workspace_doubles(int n, int b);
 void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const double* tau2, int kmax,
-              double* X, int ldx);
+              double* X, int ldx, double* Tq);
 size_t apply_q1_workspace_doubles(int n, int ncol);
 void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const double* Tall, double* X,
               int ldx, double* work);

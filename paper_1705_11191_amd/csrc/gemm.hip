@@ -14,13 +14,23 @@ namespace {
 
 constexpr int kBK = 16;
 
+// blockIdx.y selects a K range of length kper when the product is split over
+// K: that slice's partial product goes to C + blockIdx.y * cstride.
 template <int BM, int BN, bool TA, bool TB>
 __global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double alpha,
                                                     const double* __restrict__ A, int lda,
                                                     const double* __restrict__ B, int ldb,
                                                     double beta, double* C, int ldc, int uplo,
-                                                    int tiles_m, int tiles_per_xcd)
+                                                    int tiles_m, int tiles_per_xcd, int kper,
+                                                    size_t cstride)
 {
+    {
+        const int k0 = blockIdx.y * kper;
+        k = min(kper, k - k0);
+        A += TA ? (size_t)k0 : (size_t)k0 * lda;
+        B += TB ? (size_t)k0 * ldb : (size_t)k0;
+        C += (size_t)blockIdx.y * cstride;
+    }
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int A_PER = BM * kBK / 256;   // elements of the A slice per thread
@@ -132,27 +142,72 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double 
 
 template <int BM, int BN, bool TA, bool TB>
 void launch_gemm(hipStream_t st, int m, int n, int k, double alpha, const double* A, int lda,
-                 const double* B, int ldb, double beta, double* C, int ldc, int uplo)
+                 const double* B, int ldb, double beta, double* C, int ldc, int uplo, int nsplit,
+                 int kper, size_t cstride)
 {
     int tiles_m = (m + BM - 1) / BM;
     int tiles_n = (n + BN - 1) / BN;
     int ntiles = tiles_m * tiles_n;
     int per = (ntiles + 7) / 8;
-    dim3 grid(per * 8), block(256);
+    dim3 grid(per * 8, nsplit), block(256);
     hipLaunchKernelGGL((dgemm_kernel<BM, BN, TA, TB>), grid, block, 0, st, m, n, k, alpha, A, lda,
-                       B, ldb, beta, C, ldc, uplo, tiles_m, per);
+                       B, ldb, beta, C, ldc, uplo, tiles_m, per, kper, cstride);
 }
 
 template <int BM, int BN>
 void dispatch_t(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha,
                 const double* A, int lda, const double* B, int ldb, double beta, double* C,
-                int ldc, int uplo)
+                int ldc, int uplo, int nsplit = 1, int kper = 0, size_t cstride = 0)
 {
+    if (nsplit <= 1) { nsplit = 1; kper = k; cstride = 0; }
     bool TA = (ta == 'T' || ta == 't'), TB = (tb == 'T' || tb == 't');
-    if (!TA && !TB) launch_gemm<BM, BN, false, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
-    else if (!TA && TB) launch_gemm<BM, BN, false, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
-    else if (TA && !TB) launch_gemm<BM, BN, true, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
-    else launch_gemm<BM, BN, true, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
+    if (!TA && !TB)
+        launch_gemm<BM, BN, false, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+    else if (!TA && TB)
+        launch_gemm<BM, BN, false, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+    else if (TA && !TB)
+        launch_gemm<BM, BN, true, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+    else
+        launch_gemm<BM, BN, true, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+}
+
+// C = alpha * sum_s P_s + beta * C, partials summed in split order.
+__global__ void splitk_reduce_kernel(int m, int n, int nsplit, double alpha, const double* __restrict__ part,
+                                     double beta, double* C, int ldc)
+{
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t mn = (size_t)m * n;
+    if (e >= mn) return;
+    int i = (int)(e % m), j = (int)(e / m);
+    double s = 0.0;
+    for (int q = 0; q < nsplit; ++q) s += part[(size_t)q * mn + e];
+    double* p = C + cm(i, j, ldc);
+    double v = alpha * s;
+    if (beta != 0.0) v += beta * (*p);
+    *p = v;
+}
+
+void tile_shape(int m, int n, int& BM, int& BN)
+{
+    if (n <= 64) { BN = 64; BM = (m >= 16384) ? 128 : 64; }
+    else if (m <= 64) { BM = 64; BN = 128; }
+    else { BM = 128; BN = 128; }
+}
+
+void dispatch_shape(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha, const double* A, int lda,
+                    const double* B, int ldb, double beta, double* C, int ldc, int uplo, int nsplit, int kper,
+                    size_t cstride)
+{
+    int BM, BN;
+    tile_shape(m, n, BM, BN);
+    if (BM == 128 && BN == 64)
+        dispatch_t<128, 64>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+    else if (BM == 64 && BN == 64)
+        dispatch_t<64, 64>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+    else if (BM == 64)
+        dispatch_t<64, 128>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+    else
+        dispatch_t<128, 128>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
 }
 
 // ---------------------------------------------------------------------------
@@ -218,12 +273,29 @@ void dgemm(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha, 
            int lda, const double* B, int ldb, double beta, double* C, int ldc, int uplo)
 {
     if (m <= 0 || n <= 0) return;
-    if (n <= 64)
-        dispatch_t<128, 64>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
-    else if (m <= 64)
-        dispatch_t<64, 128>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
-    else
-        dispatch_t<128, 128>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
+    dispatch_shape(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, 1, k, 0);
+}
+
+void dgemm_splitk(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha, const double* A,
+                  int lda, const double* B, int ldb, double beta, double* C, int ldc, double* work,
+                  size_t work_doubles)
+{
+    if (m <= 0 || n <= 0) return;
+    int BM, BN;
+    tile_shape(m, n, BM, BN);
+    const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
+    int nsplit = std::max(1, std::min(512 / std::max(tiles, 1), k / 256));
+    while (nsplit > 1 && (size_t)nsplit * m * n > work_doubles) --nsplit;
+    if (nsplit <= 1) {
+        dgemm(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 0);
+        return;
+    }
+    const int kper = (k + nsplit - 1) / nsplit;
+    nsplit = (k + kper - 1) / kper;
+    dispatch_shape(st, ta, tb, m, n, k, 1.0, A, lda, B, ldb, 0.0, work, m, 0, nsplit, kper, (size_t)m * n);
+    const size_t mn = (size_t)m * n;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, m, n, nsplit,
+                       alpha, work, beta, C, ldc);
 }
 
 void dgemm_tn_small(hipStream_t st, int m, int n, int k, double alpha, const double* A, int lda,

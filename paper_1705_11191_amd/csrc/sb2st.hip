@@ -15,9 +15,15 @@
 // Parallel schedule: one workgroup per sweep, sweeps dealt round-robin to a
 // grid that is entirely resident (cooperative launch).  Task k of sweep s
 // touches only rows J_k(s); it overlaps task k+1 of sweep s-1 and nothing
-// later, so it starts once sweep s-1 reports k+2 finished tasks.  Progress
-// counters are published with agent-scope release and read with acquire; every
-// wait is bounded and an expired wait aborts the whole grid with an error flag.
+// later, so it starts once sweep s-1 reports k+2 finished tasks.
+//
+// Hand-off between workgroups: the band is only ever read and written with
+// device-scope (agent) relaxed atomic accesses, which are coherent across the
+// XCDs without writing back or invalidating their L2 caches.  A task's stores
+// complete (s_waitcnt) before the workgroup barrier, after which one lane
+// publishes the progress counter; waiting lanes poll the counter with the same
+// kind of access.  Every wait is bounded and an expired wait aborts the whole
+// grid with an error flag.
 #include "common.h"
 
 namespace eg {
@@ -39,77 +45,64 @@ struct SbArgs {
 
 __device__ inline int ntasks(int n, int b, int s) { return (n - 2 - s) / b + 1; }
 
-__device__ inline int load_acquire(int* p)
+__device__ inline int ld_flag(int* p)
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline void store_release(int* p, int v)
+__device__ inline void st_flag(int* p, int v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Householder vector of x (length L in xs[0..L)): on exit v in vs (v0 = 1),
-// returns tau, writes alpha.  tail == 0 gives tau = 0, v = e0.
-__device__ void house(int L, const double* xs, double* vs, double* sh, int tid)
+// coherent (device-scope) band accesses
+__device__ inline double ldc(const double* p)
 {
-    if (tid == 0) {
-        double x0 = xs[0], tail = 0.0;
-        for (int i = 1; i < L; ++i) tail += xs[i] * xs[i];
-        double t = 0.0, alpha = x0, den = 1.0;
-        if (tail > 0.0) {
-            double nrm = sqrt(x0 * x0 + tail);
-            alpha = (x0 >= 0.0) ? -nrm : nrm;
-            t = (alpha - x0) / alpha;
-            den = x0 - alpha;
-        }
-        sh[0] = t;
-        sh[1] = alpha;
-        sh[2] = (tail > 0.0) ? 1.0 / den : 0.0;
-    }
-    __syncthreads();
-    double inv = sh[2];
-    for (int i = tid; i < SB; i += SBT) vs[i] = (i == 0) ? 1.0 : ((i < L) ? xs[i] * inv : 0.0);
-    __syncthreads();
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// DG <- H DG H for the symmetric L x L block in LDS, H = I - t v v^T.
-__device__ void two_sided(int L, double (*DG)[SB + 1], const double* v, double t, double* p, double* sh,
-                          int tid)
+__device__ inline void stc(double* p, double v)
 {
-    if (t == 0.0) return;
-    if (tid < L) {
-        double s = 0.0;
-        for (int j = 0; j < L; ++j) s += DG[tid][j] * v[j];
-        p[tid] = t * s;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double s = 0.0;
-        for (int i = 0; i < L; ++i) s += p[i] * v[i];
-        sh[3] = 0.5 * t * s;
-    }
-    __syncthreads();
-    double beta = sh[3];
-    if (tid < L) p[tid] -= beta * v[tid];   // p is now w
-    __syncthreads();
-    for (int e = tid; e < L * L; e += SBT) {
-        int i = e % L, j = e / L;
-        DG[i][j] -= v[i] * p[j] + p[i] * v[j];
-    }
-    __syncthreads();
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double wave_sum64(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One task runs in a workgroup of 256 threads: thread (i, q) = (tid % 64,
+// tid / 64) keeps entries (i, 16q .. 16q+15) of both blocks in registers.
+// Band traffic uses pipelined buffer loads and stores with device-scope
+// coherence (sc1), so no cache writeback or invalidate is needed at the
+// hand-off; dot products along a row are 16-long register chains combined
+// through LDS, and column sums are wave reductions inside each wave.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kSc1 = 16;   // cache-policy bit: device-scope coherence
+
+__device__ inline double bld(__amdgpu_buffer_rsrc_t r, int elem)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, elem * 8, 0, kSc1));
+}
+
+__device__ inline void bst(__amdgpu_buffer_rsrc_t r, int elem, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, elem * 8, 0, kSc1);
 }
 
 __global__ __launch_bounds__(SBT) void sb2st_kernel(SbArgs a)
 {
-    __shared__ double DG[SB][SB + 1];
-    __shared__ double OB[SB][SB + 1];
-    __shared__ double v[SB], vp[SB], xs[SB], p[SB], u[SB];
-    __shared__ double sh[8];
+    __shared__ double LW[SB][SB + 1];      // lower triangle of the diagonal block
+    __shared__ double red[4][SB];
+    __shared__ double vs[SB], vps[SB], ws[SB];
+    __shared__ double sh[4];
     __shared__ int abort_flag;
     const int tid = threadIdx.x;
+    const int i = tid & 63, q = tid >> 6;
     const int n = a.n, b = a.b, ldb = a.ldb;
-    double* Bd = a.Bd;
+    const __amdgpu_buffer_rsrc_t band =
+        __builtin_amdgcn_make_buffer_rsrc(a.Bd, (short)0, (int)((size_t)ldb * n * 8), 0x00020000);
 
     for (int s = blockIdx.x; s < a.nsweeps; s += gridDim.x) {
         const int nt = ntasks(n, b, s);
@@ -122,109 +115,121 @@ __global__ __launch_bounds__(SBT) void sb2st_kernel(SbArgs a)
                     const int need = min(k + 2, ntasks(n, b, s - 1));
                     long long spins = 0;
                     for (;;) {
-                        int pr = load_acquire(&a.progress[s - 1]);
-                        if (pr >= need) break;
-                        if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                            abort_flag = 1;
-                            break;
-                        }
+                        if (ld_flag(&a.progress[s - 1]) >= need) break;
+                        if (ld_flag(a.err)) { abort_flag = 1; break; }
                         if (++spins > a.spin_limit) {
-                            __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            st_flag(a.err, 1);
                             abort_flag = 1;
                             break;
                         }
-                        __builtin_amdgcn_s_sleep(2);
+                        __builtin_amdgcn_s_sleep(1);
                     }
                 }
             }
             __syncthreads();
             if (abort_flag) return;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
             const int rk = s + 1 + k * b;                 // first row of J_k
             const int Lk = min(b, n - rk);
-            double t = 0.0;
-            if (k == 0) {
-                // column s, rows J0
-                for (int i = tid; i < Lk; i += SBT) xs[i] = Bd[cm(1 + i, s, ldb)];
-                for (int e = tid; e < SB * SB; e += SBT) {
-                    int i = e % SB, c = e / SB;
-                    if (i < Lk && c < Lk && i >= c) {
-                        double val = Bd[cm(i - c, rk + c, ldb)];
-                        DG[i][c] = val;
-                        DG[c][i] = val;
-                    }
-                }
-                __syncthreads();
-                house(Lk, xs, v, sh, tid);
-                t = sh[0];
-                const double alpha = sh[1];
-                for (int i = tid; i < Lk; i += SBT) Bd[cm(1 + i, s, ldb)] = (i == 0) ? alpha : 0.0;
-                two_sided(Lk, DG, v, t, p, sh, tid);
-            } else {
-                // block A(J_k, J_{k-1}): rows rk + i, columns rk - b + c
-                for (int e = tid; e < SB * SB; e += SBT) {
-                    int i = e % SB, c = e / SB;
-                    if (i < Lk && c < b) OB[i][c] = Bd[cm(b + i - c, rk - b + c, ldb)];
-                    if (i < Lk && c < Lk && i >= c) {
-                        double val = Bd[cm(i - c, rk + c, ldb)];
-                        DG[i][c] = val;
-                        DG[c][i] = val;
-                    }
-                }
-                __syncthreads();
-                // right application of the previous reflector: OB <- OB (I - tp vp vp^T)
-                if (tp != 0.0) {
-                    if (tid < Lk) {
-                        double s2 = 0.0;
-                        for (int c = 0; c < b; ++c) s2 += OB[tid][c] * vp[c];
-                        p[tid] = tp * s2;
-                    }
-                    __syncthreads();
-                    for (int e = tid; e < Lk * b; e += SBT) {
-                        int i = e % Lk, c = e / Lk;
-                        OB[i][c] -= p[i] * vp[c];
-                    }
-                    __syncthreads();
-                }
-                // new reflector from the block's first column
-                for (int i = tid; i < Lk; i += SBT) xs[i] = OB[i][0];
-                __syncthreads();
-                house(Lk, xs, v, sh, tid);
-                t = sh[0];
-                const double alpha = sh[1];
-                if (t != 0.0) {
-                    if (tid < b && tid > 0) {
-                        double s2 = 0.0;
-                        for (int i = 0; i < Lk; ++i) s2 += v[i] * OB[i][tid];
-                        u[tid] = t * s2;
-                    }
-                    __syncthreads();
-                    for (int e = tid; e < Lk * b; e += SBT) {
-                        int i = e % Lk, c = e / Lk;
-                        if (c == 0) OB[i][0] = (i == 0) ? alpha : 0.0;
-                        else OB[i][c] -= v[i] * u[c];
-                    }
-                    __syncthreads();
-                }
-                two_sided(Lk, DG, v, t, p, sh, tid);
-                for (int e = tid; e < SB * SB; e += SBT) {
-                    int i = e % SB, c = e / SB;
-                    if (i < Lk && c < b) Bd[cm(b + i - c, rk - b + c, ldb)] = OB[i][c];
-                }
+            // ---- loads: off-diagonal block row (k >= 1) and the diagonal block's lower triangle
+            double ob[16], dg[16];
+#pragma unroll
+            for (int cq = 0; cq < 16; ++cq) {
+                const int c = 16 * q + cq;
+                ob[cq] = (k > 0 && i < Lk && c < b) ? bld(band, cm(b + i - c, rk - b + c, ldb)) : 0.0;
+                dg[cq] = (i < Lk && c <= i) ? bld(band, cm(i - c, rk + c, ldb)) : 0.0;
             }
-            // write back the diagonal block and the reflector
-            for (int e = tid; e < SB * SB; e += SBT) {
-                int i = e % SB, c = e / SB;
-                if (i < Lk && c < Lk && i >= c) Bd[cm(i - c, rk + c, ldb)] = DG[i][c];
-            }
-            for (int i = tid; i < Lk; i += SBT) a.V2[cm(rk + i, s, n)] = v[i];
-            if (tid == 0) a.tau2[(size_t)s * a.kmax + k] = t;
-            for (int i = tid; i < SB; i += SBT) vp[i] = v[i];
-            tp = t;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            double xi = 0.0;
+            if (k == 0 && q == 0) xi = (i < Lk) ? bld(band, cm(1 + i, s, ldb)) : 0.0;
+#pragma unroll
+            for (int cq = 0; cq < 16; ++cq) LW[i][16 * q + cq] = dg[cq];
             __syncthreads();
-            if (tid == 0) store_release(&a.progress[s], (k + 1 == nt) ? kDone : k + 1);
+            // full rows of the symmetric diagonal block
+#pragma unroll
+            for (int cq = 0; cq < 16; ++cq) {
+                const int c = 16 * q + cq;
+                dg[cq] = (c <= i) ? LW[i][c] : LW[c][i];
+                if (c >= Lk || i >= Lk) dg[cq] = 0.0;
+            }
+            if (k > 0) {
+                // ---- right application of the previous reflector: ob <- ob (I - tp vp vp^T)
+                if (tp != 0.0) {
+                    double part = 0.0;
+#pragma unroll
+                    for (int cq = 0; cq < 16; ++cq) part += ob[cq] * vps[16 * q + cq];
+                    red[q][i] = part;
+                    __syncthreads();
+                    const double wr = tp * (red[0][i] + red[1][i] + red[2][i] + red[3][i]);
+#pragma unroll
+                    for (int cq = 0; cq < 16; ++cq) ob[cq] -= wr * vps[16 * q + cq];
+                }
+                if (q == 0) xi = ob[0];
+            }
+            // ---- Householder vector of column 0 (k >= 1) or of column s (k == 0), wave 0
+            if (q == 0) {
+                const double tail = wave_sum64((i >= 1 && i < Lk) ? xi * xi : 0.0);
+                const double x0 = __shfl(xi, 0, 64);
+                double t = 0.0, den = 1.0, alpha = x0;
+                if (tail > 0.0) {
+                    const double nrm = sqrt(x0 * x0 + tail);
+                    alpha = (x0 >= 0.0) ? -nrm : nrm;
+                    t = (alpha - x0) / alpha;
+                    den = x0 - alpha;
+                }
+                vs[i] = (i == 0) ? 1.0 : ((i < Lk && tail > 0.0) ? xi / den : 0.0);
+                if (i == 0) { sh[0] = t; sh[1] = alpha; }
+            }
+            __syncthreads();
+            const double t = sh[0], alpha = sh[1];
+            const double vi = vs[i];
+            if (k == 0) {
+                if (q == 0 && i < Lk) bst(band, cm(1 + i, s, ldb), (i == 0) ? alpha : 0.0);
+            } else {
+                // ---- left application: ob <- (I - t v v^T) ob, column sums inside each wave
+                if (t != 0.0) {
+#pragma unroll
+                    for (int cq = 0; cq < 16; ++cq) {
+                        const double uc = t * wave_sum64(vi * ob[cq]);
+                        ob[cq] -= vi * uc;
+                    }
+                    if (q == 0) ob[0] = (i == 0) ? alpha : 0.0;
+                }
+#pragma unroll
+                for (int cq = 0; cq < 16; ++cq) {
+                    const int c = 16 * q + cq;
+                    if (i < Lk && c < b) bst(band, cm(b + i - c, rk - b + c, ldb), ob[cq]);
+                }
+            }
+            // ---- two-sided update of the diagonal block: dg <- H dg H
+            if (t != 0.0) {
+                double part = 0.0;
+#pragma unroll
+                for (int cq = 0; cq < 16; ++cq) part += dg[cq] * vs[16 * q + cq];
+                red[q][i] = part;
+                __syncthreads();
+                const double pi = t * (red[0][i] + red[1][i] + red[2][i] + red[3][i]);
+                const double beta = 0.5 * t * wave_sum64(pi * vi);
+                const double wi = pi - beta * vi;
+                if (q == 0) ws[i] = wi;
+                __syncthreads();
+#pragma unroll
+                for (int cq = 0; cq < 16; ++cq) {
+                    const int c = 16 * q + cq;
+                    dg[cq] -= vi * ws[c] + wi * vs[c];
+                }
+            }
+#pragma unroll
+            for (int cq = 0; cq < 16; ++cq) {
+                const int c = 16 * q + cq;
+                if (i < Lk && c <= i) bst(band, cm(i - c, rk + c, ldb), dg[cq]);
+            }
+            if (q == 0 && i < Lk) a.V2[cm(rk + i, s, n)] = vi;
+            if (tid == 0) a.tau2[(size_t)s * a.kmax + k] = t;
+            if (q == 0) vps[i] = vi;
+            tp = t;
+            __builtin_amdgcn_s_waitcnt(0);   // this thread's band stores have completed
+            __syncthreads();
+            if (tid == 0) st_flag(&a.progress[s], (k + 1 == nt) ? kDone : k + 1);
         }
     }
 }

@@ -35,7 +35,7 @@ void density_matrix(hipStream_t st, int n, int k, const double* C, int ldc, cons
 // workspace layout (all sub-buffers 256-byte aligned)
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t linv, bd, vall, tall, v2, tau2, d, e, w, z, z2, u, sywork, dcwork, q1work, f, scal, ints;
+    size_t linv, bd, vall, tall, v2, tau2, tq2, d, e, w, z, z2, u, sywork, dcwork, q1work, f, scal, ints;
     size_t total;
 };
 
@@ -51,6 +51,7 @@ static Layout make_layout(int n, int b, int ncol)
     L.tall = put(sizeof(double) * (size_t)ceil_div(n, b) * b * b);
     L.v2 = put(sizeof(double) * nn);
     L.tau2 = put(sizeof(double) * (size_t)std::max(n - 2, 1) * sb2st_kmax(n, b));
+    L.tq2 = put(sizeof(double) * apply_q2_workspace_doubles(n, b));
     L.d = put(sizeof(double) * n);
     L.e = put(sizeof(double) * n);
     L.w = put(sizeof(double) * n);
@@ -196,7 +197,8 @@ static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L
     hipStream_t st = h->stream;
     const int n = h->n, b = std::min(h->band_width, std::max(1, n - 1));
     double* X = (double*)(ws + L.z);
-    apply_q2(st, n, b, k, (double*)(ws + L.v2), (double*)(ws + L.tau2), sb2st_kmax(n, b), X, n);
+    apply_q2(st, n, b, k, (double*)(ws + L.v2), (double*)(ws + L.tau2), sb2st_kmax(n, b), X, n,
+             (double*)(ws + L.tq2));
     tm.mark(ELSI_GPU_ST_BACK_Q2);
     apply_q1(st, n, b, k, (double*)(ws + L.vall), (double*)(ws + L.tall), X, n, (double*)(ws + L.q1work));
     tm.mark(ELSI_GPU_ST_BACK_Q1);

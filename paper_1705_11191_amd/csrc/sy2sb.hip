@@ -133,6 +133,145 @@ __global__ __launch_bounds__(PR) void panel_step_kernel(int m, int bw, int c, do
     }
 }
 
+__device__ inline double ldc(const double* p)
+{
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void stc(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Whole panel QR in one cooperative launch: every workgroup keeps its PR
+// panel rows in registers across all columns; the per-column Gram records and
+// the pivot row cross workgroups through device-coherent accesses, separated
+// by a grid barrier (a monotonic arrival counter with a bounded wait).
+__global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr, double* P, int ldp,
+                                                           double* gbuf, double* rbuf, double* tau,
+                                                           int* counter, int* err, int nblk)
+{
+    __shared__ double G[BMAX + 1];
+    __shared__ double scoef[BMAX];
+    __shared__ double red[PR / 64][BMAX + 1];
+    __shared__ double sh[4];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int blk = blockIdx.x;
+    const int i = blk * PR + tid;
+    const int lane = tid & 63, wave = tid >> 6;
+
+    double rowv[BMAX];
+#pragma unroll
+    for (int r = 0; r < BMAX; ++r) rowv[r] = (r < bw && i < m) ? P[cm(i, r, ldp)] : 0.0;
+    int arrive = 0;
+
+    for (int c = -1; c < nr; ++c) {
+        const double* gin = gbuf + (size_t)((c + 2) & 1) * nblk * GS;
+        double* gout = gbuf + (size_t)((c + 1) & 1) * nblk * GS;
+        const double* rin = rbuf + ((c + 2) & 1) * 64;
+        double* rout = rbuf + ((c + 1) & 1) * 64;
+        if (c >= 0) {
+            for (int r = tid; r <= BMAX; r += PR) {
+                if ((r >= c && r < bw) || r == BMAX) {
+                    double s = 0.0;
+                    for (int b = 0; b < nblk; ++b) s += ldc(&gin[(size_t)b * GS + r]);
+                    G[r] = s;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double x0 = ldc(&rin[c]);
+                double tail = G[BMAX];
+                double t = 0.0, alpha = x0, den = 1.0;
+                if (tail > 0.0) {
+                    double nrm = sqrt(x0 * x0 + tail);
+                    alpha = (x0 >= 0.0) ? -nrm : nrm;
+                    t = (alpha - x0) / alpha;
+                    den = x0 - alpha;
+                }
+                sh[0] = t; sh[1] = alpha; sh[2] = den;
+                if (blk == 0) tau[c] = t;
+            }
+            __syncthreads();
+            const double t = sh[0], alpha = sh[1], den = sh[2];
+            for (int r = tid; r < bw; r += PR)
+                if (r > c) scoef[r] = (t != 0.0) ? (G[r] - alpha * ldc(&rin[r])) / den : 0.0;
+            __syncthreads();
+            if (i < m && i >= c) {
+                double xc = 0.0;
+#pragma unroll
+                for (int r = 0; r < BMAX; ++r) if (r == c) xc = rowv[r];
+                const double vi = (i == c) ? 1.0 : ((t != 0.0) ? xc / den : 0.0);
+#pragma unroll
+                for (int r = 0; r < BMAX; ++r)
+                    if (r > c && r < bw) rowv[r] -= t * vi * scoef[r];
+                // column c is final for this row: alpha on the diagonal, v below it
+                P[cm(i, c, ldp)] = (i == c) ? alpha : vi;
+            }
+        }
+        const int cn = c + 1;
+        if (cn < nr) {
+            double xn = 0.0;
+#pragma unroll
+            for (int r = 0; r < BMAX; ++r) if (r == cn) xn = rowv[r];
+            if (!(i < m && i >= cn)) xn = 0.0;
+#pragma unroll
+            for (int r = 0; r < BMAX; ++r) {
+                if (r >= cn && r < bw) {
+                    double s = wave_sum(xn * rowv[r]);
+                    if (lane == 0) red[wave][r] = s;
+                }
+            }
+            {
+                double tl = (i > cn && i < m) ? xn * xn : 0.0;
+                double s = wave_sum(tl);
+                if (lane == 0) red[wave][BMAX] = s;
+            }
+            __syncthreads();
+            for (int r = tid; r <= BMAX; r += PR) {
+                if ((r >= cn && r < bw) || r == BMAX) {
+                    double s = 0.0;
+                    for (int w = 0; w < PR / 64; ++w) s += red[w][r];
+                    stc(&gout[(size_t)blk * GS + r], s);
+                }
+            }
+            if (i == cn && i < m) {
+#pragma unroll
+                for (int r = 0; r < BMAX; ++r)
+                    if (r >= cn && r < bw) stc(&rout[r], rowv[r]);
+            }
+            // grid barrier
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            arrive += nblk;
+            if (tid == 0) {
+                bad = 0;
+                __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                long long spins = 0;
+                while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < arrive) {
+                    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { bad = 1; break; }
+                    if (++spins > (1LL << 22)) {
+                        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        bad = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __syncthreads();
+            if (bad) return;
+        }
+    }
+    // write back the entries not yet final in P: R above the diagonal and the
+    // columns that needed no reflector
+    if (i < m) {
+#pragma unroll
+        for (int r = 0; r < BMAX; ++r)
+            if (r < bw && !(r < nr && i >= r)) P[cm(i, r, ldp)] = rowv[r];
+    }
+}
+
 // Explicit V (m x bw, unit lower trapezoidal) of the panel into V (ld ldv).
 __global__ void panel_store_v_kernel(int m, int bw, int nr, const double* P, int ldp, double* V, int ldv)
 {
@@ -181,6 +320,19 @@ __global__ void extract_band_kernel(int n, int b, const double* A, int lda, doub
     Bd[cm(r, c, ldb)] = v;
 }
 
+int coop_max_blocks()
+{
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, panel_qr_coop_kernel, PR, 0);
+        cached = std::max(0, cus * per_cu);
+    }
+    return cached;
+}
+
 }  // namespace
 
 size_t sy2sb_workspace_doubles(int n, int b)
@@ -192,7 +344,8 @@ size_t sy2sb_workspace_doubles(int n, int b)
     w += 2 * nblk * GS;              // Gram records (ping-pong)
     w += 2 * 64 + 64;                // pivot rows, tau
     w += 3 * 64 * 64;                // G, Z, U
-    w += (size_t)ceil_div(n, 2048) * 4096;  // split-K partials
+    w += (size_t)8 * n * 64;                 // split-K partials
+    w += 64;                                 // barrier counter and error flag
     return w;
 }
 
@@ -216,6 +369,7 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
     double* Z = Gv + 64 * 64;
     double* U = Z + 64 * 64;
     double* part = U + 64 * 64;
+    int* ibuf = (int*)(part + (size_t)8 * n * 64);
 
     const int npanel = ceil_div(n, b);
     for (int p = 0; p < npanel; ++p) {
@@ -227,29 +381,47 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
         const int nr = std::min(bw, m - 1);
         double* P = A + cm(r0, j, lda);
         const int nblk = ceil_div(m, PR);
-        double* gi = gbuf0; double* go = gbuf1;
-        double* ri = rbuf0; double* ro = rbuf1;
-        hipLaunchKernelGGL(panel_step_kernel, dim3(nblk), dim3(PR), 0, st, m, bw, -1, P, lda, gi, go, ri, ro,
-                           tau, nblk);
-        for (int c = 0; c < nr; ++c) {
-            std::swap(gi, go);
-            std::swap(ri, ro);
-            hipLaunchKernelGGL(panel_step_kernel, dim3(nblk), dim3(PR), 0, st, m, bw, c, P, lda, gi, go, ri,
-                               ro, tau, nblk);
+        bool coop_done = false;
+        if (nblk <= coop_max_blocks()) {
+            fill_i(st, ibuf, 2, 0);
+            int mm = m, bww = bw, nrr = nr, ld = lda, nb = nblk;
+            double* Pp = P;
+            double* gb = gbuf0;
+            double* rb = rbuf0;
+            double* tp = tau;
+            int* cnt = ibuf;
+            int* er = ibuf + 1;
+            void* args[] = {&mm, &bww, &nrr, &Pp, &ld, &gb, &rb, &tp, &cnt, &er, &nb};
+            coop_done = hipLaunchCooperativeKernel((const void*)panel_qr_coop_kernel, dim3(nblk), dim3(PR), args, 0,
+                                                   st) == hipSuccess;
+            if (!coop_done) (void)hipGetLastError();
+        }
+        if (!coop_done) {
+            double* gi = gbuf0; double* go = gbuf1;
+            double* ri = rbuf0; double* ro = rbuf1;
+            hipLaunchKernelGGL(panel_step_kernel, dim3(nblk), dim3(PR), 0, st, m, bw, -1, P, lda, gi, go, ri, ro,
+                               tau, nblk);
+            for (int c = 0; c < nr; ++c) {
+                std::swap(gi, go);
+                std::swap(ri, ro);
+                hipLaunchKernelGGL(panel_step_kernel, dim3(nblk), dim3(PR), 0, st, m, bw, c, P, lda, gi, go, ri,
+                                   ro, tau, nblk);
+            }
         }
         if (nr < bw) fill_d(st, tau + nr, (size_t)(bw - nr), 0.0);
         double* V = Vall + cm(r0, j, n);
         hipLaunchKernelGGL(panel_store_v_kernel, dim3(ceil_div(m, 256), bw), dim3(256), 0, st, m, bw, nr, P,
                            lda, V, n);
         double* T = Tall + (size_t)p * b * b;
-        dgemm_tn_small(st, bw, bw, m, 1.0, V, n, V, n, 0.0, Gv, 64, part);
+        const size_t npart = (size_t)8 * n * 64;
+        dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, V, n, 0.0, Gv, 64, part, npart);
         hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(64), 0, st, bw, Gv, 64, tau, T, b);
 
         // two-sided update of A22 (full symmetric)
         double* A22 = A + cm(r0, r0, lda);
-        dgemm(st, 'N', 'N', m, bw, m, 1.0, A22, lda, V, n, 0.0, Y, m);
+        dgemm_splitk(st, 'N', 'N', m, bw, m, 1.0, A22, lda, V, n, 0.0, Y, m, part, npart);
         dgemm(st, 'N', 'N', m, bw, bw, 1.0, Y, m, T, b, 0.0, X, m);
-        dgemm_tn_small(st, bw, bw, m, 1.0, V, n, X, m, 0.0, Z, 64, part);
+        dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, X, m, 0.0, Z, 64, part, npart);
         dgemm(st, 'T', 'N', bw, bw, bw, 1.0, T, b, Z, 64, 0.0, U, 64);
         dgemm(st, 'N', 'N', m, bw, bw, -0.5, V, n, U, 64, 1.0, X, m);   // X <- W
         copy_matrix(st, m, bw, V, n, VW, m);
