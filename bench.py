@@ -71,7 +71,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
     ap.add_argument("--band", type=int, default=64)
-    ap.add_argument("--cpu-sample-n", type=int, default=2048)
+    ap.add_argument("--cpu-sample-n", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

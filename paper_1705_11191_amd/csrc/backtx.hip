@@ -30,23 +30,29 @@ __device__ inline int q2_ntasks(int n, int b, int s) { return (n - 2 - s) / b + 
 
 // Stage the reflectors of group (g, k) in LDS: column i is the reflector of
 // sweep s_lo + i at rows [i, i + L_i) of the window that starts at base.
+// Thread t always handles window row t % 128 and columns t / 128 + 2 j; all of
+// its loads are issued before any LDS store so that their latencies overlap.
 __device__ void q2_load_v(int n, int b, int g, int k, const double* __restrict__ V2, double (*Vs)[NB2 + 1])
 {
     const int nsweeps = n - 2;
     const int s_lo = g * b;
     const int base = s_lo + 1 + k * b;
-    for (int e = threadIdx.x; e < 2 * NB2 * NB2; e += blockDim.x) {
-        const int r = e % (2 * NB2), i = e / (2 * NB2);
-        double v = 0.0;
+    const int r = threadIdx.x & 127, i0 = threadIdx.x >> 7;
+    double v[NB2 / 2];
+#pragma unroll
+    for (int j = 0; j < NB2 / 2; ++j) {
+        const int i = i0 + 2 * j;
         const int s = s_lo + i;
-        if (i < b && s < nsweeps && k < q2_ntasks(n, b, s)) {
-            const int r0 = s + 1 + k * b;
+        v[j] = 0.0;
+        if (i < b && s < nsweeps) {
+            const int r0 = s + 1 + k * b;          // first row of this reflector
             const int L = min(b, n - r0);
-            const int q = r - i;
-            if (q >= 0 && q < L) v = V2[cm(base + r, s, n)];
+            const int qq = r - i;
+            if (r0 < n && qq >= 0 && qq < L) v[j] = V2[cm(base + r, s, n)];
         }
-        Vs[r][i] = v;
     }
+#pragma unroll
+    for (int j = 0; j < NB2 / 2; ++j) Vs[r][i0 + 2 * j] = v[j];
 }
 
 // T of P = H_{s_lo} H_{s_lo+1} ... H_{s_hi} = I - V T V^T for every (g, k)
@@ -116,11 +122,22 @@ __global__ __launch_bounds__(256) void q2_apply_blocked_kernel(int n, int b, int
         for (int k = 0; k < ntk; ++k) {
             const int base = s_lo + 1 + k * b;
             const int wrows = min(2 * b - 1, n - base);
-            q2_load_v(n, b, g, k, V2, Vs);
-            for (int e = tid; e < 2 * NB2 * NCB; e += 256) {
-                const int r = e % (2 * NB2), c = e / (2 * NB2);
-                const int gc = col0 + c;
-                Xs[r][c] = (r < wrows && gc < ncol) ? X[cm(base + r, gc, ldx)] : 0.0;
+            // this lane's operands of T (rows 16 wave + li, columns kk + lk), fetched early
+            const double* T = Tq + ((size_t)g * kmax + k) * NB2 * NB2;
+            double treg[NB2 / 4];
+#pragma unroll
+            for (int q4 = 0; q4 < NB2 / 4; ++q4) treg[q4] = T[(wave * 16 + li) + (size_t)(4 * q4 + lk) * NB2];
+            {
+                const int r = tid & 127, c0 = tid >> 7;
+                double xv[NCB / 2];
+#pragma unroll
+                for (int j = 0; j < NCB / 2; ++j) {
+                    const int gc = col0 + c0 + 2 * j;
+                    xv[j] = (r < wrows && gc < ncol) ? X[cm(base + r, gc, ldx)] : 0.0;
+                }
+                q2_load_v(n, b, g, k, V2, Vs);
+#pragma unroll
+                for (int j = 0; j < NCB / 2; ++j) Xs[r][c0 + 2 * j] = xv[j];
             }
             __syncthreads();
             // W = V^T X_W (64 x 32): wave w owns rows 16w .. 16w+15, both column blocks
@@ -139,13 +156,14 @@ __global__ __launch_bounds__(256) void q2_apply_blocked_kernel(int n, int b, int
                 }
             }
             __syncthreads();
-            // W2 = T W (64 x 32), T from global (column-major, ld 64)
+            // W2 = T W (64 x 32), T operands from registers
             {
-                const double* T = Tq + ((size_t)g * kmax + k) * NB2 * NB2;
                 double4_t a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
                 const int i0 = wave * 16;
-                for (int kk = 0; kk < NB2; kk += 4) {
-                    const double av = T[(i0 + li) + (size_t)(kk + lk) * NB2];
+#pragma unroll
+                for (int q4 = 0; q4 < NB2 / 4; ++q4) {
+                    const int kk = 4 * q4;
+                    const double av = treg[q4];
                     a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ws[kk + lk][li], a0, 0, 0, 0);
                     a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ws[kk + lk][16 + li], a1, 0, 0, 0);
                 }
@@ -180,10 +198,13 @@ __global__ __launch_bounds__(256) void q2_apply_blocked_kernel(int n, int b, int
                         for (int r = 0; r < 4; ++r) Xs[i0 + 16 * a + 4 * r + lk][16 * c + li] -= acc[a][c][r];
             }
             __syncthreads();
-            for (int e = tid; e < 2 * NB2 * NCB; e += 256) {
-                const int r = e % (2 * NB2), c = e / (2 * NB2);
-                const int gc = col0 + c;
-                if (r < wrows && gc < ncol) X[cm(base + r, gc, ldx)] = Xs[r][c];
+            {
+                const int r = tid & 127, c0 = tid >> 7;
+#pragma unroll
+                for (int j = 0; j < NCB / 2; ++j) {
+                    const int gc = col0 + c0 + 2 * j;
+                    if (r < wrows && gc < ncol) X[cm(base + r, gc, ldx)] = Xs[r][c0 + 2 * j];
+                }
             }
             __syncthreads();
         }

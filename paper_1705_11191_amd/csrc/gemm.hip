@@ -12,7 +12,7 @@
 namespace eg {
 namespace {
 
-constexpr int kBK = 16;
+constexpr int kBK = 32;
 
 // blockIdx.y selects a K range of length kper when the product is split over
 // K: that slice's partial product goes to C + blockIdx.y * cstride.
@@ -111,33 +111,57 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double 
             for (int i = 0; i < FM; ++i) a[i] = As[kr][wm * WM + i * 16 + (lane & 15)];
 #pragma unroll
             for (int j = 0; j < FN; ++j) b[j] = Bs[kr][wn * WN + j * 16 + (lane & 15)];
+            // operands swapped: the MFMA forms the transposed 16 x 16 block of C,
+            // so that a lane's results run down one column of C
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
 
-    // D layout of the 16x16 f64 MFMA: lane l, element r holds row 4*r + l/16, column l%16
+    // D layout of the 16x16 f64 MFMA: lane l, element r holds D(4r + l/16, l%16);
+    // D is the transposed block, so that is C(row l%16, column 4r + l/16).
+    // All C loads of a lane are issued before any store so that they overlap.
+    const int rbase = row0 + wm * WM + (lane & 15);
+    const int cbase = col0 + wn * WN + (lane >> 4);
+    const bool interior = (row0 + BM <= m) && (col0 + BN <= n) && !(uplo && col0 + BN - 1 > row0);
+    auto valid = [&](int gr, int gc) {
+        return interior || (gr < m && gc < n && !(uplo && gr < gc));
+    };
+    if (beta != 0.0) {
+        double cv[FM][FN][4];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int gc = col0 + wn * WN + j * 16 + (lane & 15);
-            if (gc >= n) continue;
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gr = row0 + wm * WM + i * 16 + r * 4 + (lane >> 4);
-                if (gr >= m) continue;
-                if (uplo && gr < gc) continue;
-                double v = alpha * acc[i][j][r];
-                double* p = C + cm(gr, gc, ldc);
-                if (beta != 0.0) v += beta * (*p);
-                *p = v;
-            }
-        }
+                for (int r = 0; r < 4; ++r) {
+                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * 4;
+                    cv[i][j][r] = valid(gr, gc) ? C[cm(gr, gc, ldc)] : 0.0;
+                }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * 4;
+                    if (valid(gr, gc)) C[cm(gr, gc, ldc)] = alpha * acc[i][j][r] + beta * cv[i][j][r];
+                }
+    } else {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * 4;
+                    if (valid(gr, gc)) C[cm(gr, gc, ldc)] = alpha * acc[i][j][r];
+                }
+    }
 }
 
 template <int BM, int BN, bool TA, bool TB>

@@ -133,14 +133,19 @@ __global__ __launch_bounds__(PR) void panel_step_kernel(int m, int bw, int c, do
     }
 }
 
-__device__ inline double ldc(const double* p)
+// Pipelined buffer loads and stores with device-scope coherence (sc1): the
+// cross-workgroup records need no cache writeback or invalidate.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kSc1 = 16;
+
+__device__ inline double bld(__amdgpu_buffer_rsrc_t r, int elem)
 {
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, elem * 8, 0, kSc1));
 }
 
-__device__ inline void stc(double* p, double v)
+__device__ inline void bst(__amdgpu_buffer_rsrc_t r, int elem, double v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, elem * 8, 0, kSc1);
 }
 
 // Whole panel QR in one cooperative launch: every workgroup keeps its PR
@@ -160,6 +165,9 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
     const int blk = blockIdx.x;
     const int i = blk * PR + tid;
     const int lane = tid & 63, wave = tid >> 6;
+    const __amdgpu_buffer_rsrc_t grs =
+        __builtin_amdgcn_make_buffer_rsrc(gbuf, (short)0, (int)((size_t)2 * nblk * GS * 8), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rrs = __builtin_amdgcn_make_buffer_rsrc(rbuf, (short)0, 2 * 64 * 8, 0x00020000);
 
     double rowv[BMAX];
 #pragma unroll
@@ -167,21 +175,22 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
     int arrive = 0;
 
     for (int c = -1; c < nr; ++c) {
-        const double* gin = gbuf + (size_t)((c + 2) & 1) * nblk * GS;
-        double* gout = gbuf + (size_t)((c + 1) & 1) * nblk * GS;
-        const double* rin = rbuf + ((c + 2) & 1) * 64;
-        double* rout = rbuf + ((c + 1) & 1) * 64;
+        const int gin = ((c + 2) & 1) * nblk * GS;    // element offsets into gbuf / rbuf
+        const int gout = ((c + 1) & 1) * nblk * GS;
+        const int rin = ((c + 2) & 1) * 64;
+        const int rout = ((c + 1) & 1) * 64;
         if (c >= 0) {
             for (int r = tid; r <= BMAX; r += PR) {
                 if ((r >= c && r < bw) || r == BMAX) {
                     double s = 0.0;
-                    for (int b = 0; b < nblk; ++b) s += ldc(&gin[(size_t)b * GS + r]);
+#pragma unroll 8
+                    for (int b = 0; b < nblk; ++b) s += bld(grs, gin + b * GS + r);
                     G[r] = s;
                 }
             }
             __syncthreads();
             if (tid == 0) {
-                double x0 = ldc(&rin[c]);
+                double x0 = bld(rrs, rin + c);
                 double tail = G[BMAX];
                 double t = 0.0, alpha = x0, den = 1.0;
                 if (tail > 0.0) {
@@ -196,7 +205,7 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
             __syncthreads();
             const double t = sh[0], alpha = sh[1], den = sh[2];
             for (int r = tid; r < bw; r += PR)
-                if (r > c) scoef[r] = (t != 0.0) ? (G[r] - alpha * ldc(&rin[r])) / den : 0.0;
+                if (r > c) scoef[r] = (t != 0.0) ? (G[r] - alpha * bld(rrs, rin + r)) / den : 0.0;
             __syncthreads();
             if (i < m && i >= c) {
                 double xc = 0.0;
@@ -233,13 +242,13 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
                 if ((r >= cn && r < bw) || r == BMAX) {
                     double s = 0.0;
                     for (int w = 0; w < PR / 64; ++w) s += red[w][r];
-                    stc(&gout[(size_t)blk * GS + r], s);
+                    bst(grs, gout + blk * GS + r, s);
                 }
             }
             if (i == cn && i < m) {
 #pragma unroll
                 for (int r = 0; r < BMAX; ++r)
-                    if (r >= cn && r < bw) stc(&rout[r], rowv[r]);
+                    if (r >= cn && r < bw) bst(rrs, rout + r, rowv[r]);
             }
             // grid barrier
             __builtin_amdgcn_s_waitcnt(0);
