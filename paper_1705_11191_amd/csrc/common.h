@@ -4,6 +4,7 @@
 #include <cstddef>
 #include <algorithm>
 #include <cstdint>
+#include <vector>
 
 namespace eg {
 
@@ -78,6 +79,9 @@ void dtrsm_right_lower_t(hipStream_t st, int nrow, int n, const double* L, int l
                          const double* Linv, double* B, int ldb);
 void dtrsm_left_lower_t(hipStream_t st, int n, int ncol, const double* L, int ldl,
                         const double* Linv, double* B, int ldb);
+//   right_lower_t_lowerpart: lower triangle of B <- B L^-T (B n x n)
+void dtrsm_right_lower_t_lowerpart(hipStream_t st, int n, const double* L, int ldl,
+                                   const double* Linv, double* B, int ldb);
 
 // Utility kernels.
 void fill_d(hipStream_t st, double* p, size_t count, double v);
@@ -112,7 +116,22 @@ int sb2st(hipStream_t st, int n, int b, double* Bd, int ldb, double* d, double* 
           int* progress, int* err);
 
 // Step (3): tridiagonal divide and conquer; see stedc.hip.
+struct MergeDescH {
+    int o, n1, n2;
+};
+struct DcState {
+    int n = 0, ldz = 0;
+    double* Z = nullptr;      // where the eigenvectors end up
+    double* Zin = nullptr;    // solved halves of the last merge
+    double* Zout = nullptr;
+    double* U = nullptr;      // coefficient blocks of the last merge
+    bool have_last = false;
+    std::vector<MergeDescH> last;
+};
 size_t stedc_workspace_bytes(int n);
+int stedc_values(hipStream_t st, int n, const double* d, const double* e, double* w, double* Z, double* Z2,
+                 double* U, int ldz, void* work, int* err, DcState* state);
+void stedc_vectors(hipStream_t st, DcState& state, int ncol);
 int stedc(hipStream_t st, int n, const double* d, const double* e, double* w, double* Z, double* Z2,
           double* U, int ldz, int ncol_final, void* work, int* err, int* err_host_copy);
 

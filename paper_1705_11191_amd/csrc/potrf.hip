@@ -170,6 +170,32 @@ void dtrsm_left_lower_n(hipStream_t st, int n, int ncol, const double* L, int ld
     }
 }
 
+// Lower triangle only of X = B L^-T (n x n): column block j of X needs rows
+// >= j of B's column block j and of the earlier X blocks, so every product
+// is restricted to rows at or below its column block (upper entries of B are
+// left in an unspecified state).
+void dtrsm_right_lower_t_lowerpart(hipStream_t st, int n, const double* L, int ldl, const double* Linv,
+                                   double* B, int ldb)
+{
+    for (int J0 = 0; J0 < n; J0 += NBO) {
+        const int JB = std::min(NBO, n - J0);
+        for (int j0 = J0; j0 < J0 + JB; j0 += NB) {
+            const int jb = std::min(NB, J0 + JB - j0);
+            const double* Lj = Linv + (size_t)(j0 / NB) * NB * NB;
+            double* Bj = B + cm(j0, j0, ldb);
+            dgemm(st, 'N', 'T', n - j0, jb, jb, 1.0, Bj, ldb, Lj, NB, 0.0, Bj, ldb);
+            const int c0 = j0 + jb, cn = J0 + JB - c0;
+            if (cn > 0)
+                dgemm(st, 'N', 'T', n - c0, cn, jb, -1.0, B + cm(c0, j0, ldb), ldb, L + cm(c0, j0, ldl), ldl,
+                      1.0, B + cm(c0, c0, ldb), ldb, 1);
+        }
+        const int t0 = J0 + JB;
+        if (t0 < n)
+            dgemm(st, 'N', 'T', n - t0, n - t0, JB, -1.0, B + cm(t0, J0, ldb), ldb, L + cm(t0, J0, ldl), ldl,
+                  1.0, B + cm(t0, t0, ldb), ldb, 1);
+    }
+}
+
 // B <- B L^-T, B nrow x n: solve X L^T = B column block by column block.
 void dtrsm_right_lower_t(hipStream_t st, int nrow, int n, const double* L, int ldl,
                          const double* Linv, double* B, int ldb)

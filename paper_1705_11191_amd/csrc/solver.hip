@@ -7,14 +7,14 @@
 
 namespace eg {
 
-// Eq. (11): W = L^-1 H, then H~ = W L^-T, then H~ <- (H~ + H~^T)/2.
+// Eq. (11): W = L^-1 H, then the lower triangle of H~ = W L^-T, mirrored.
 void reduce_to_standard(hipStream_t st, int n, double* H, int ldh, const double* L, int ldl, double* Linv)
 {
     dtrtri_diag_blocks(st, n, L, ldl, Linv);
     mirror_lower_to_upper(st, n, H, ldh);   // only the lower triangle of H is read
     dtrsm_left_lower_n(st, n, n, L, ldl, Linv, H, ldh);
-    dtrsm_right_lower_t(st, n, n, L, ldl, Linv, H, ldh);
-    symmetrize_average(st, n, H, ldh);
+    dtrsm_right_lower_t_lowerpart(st, n, L, ldl, Linv, H, ldh);
+    mirror_lower_to_upper(st, n, H, ldh);
 }
 
 // Eq. (9): D = sum_l f_l c_l c_l^T = (C F^1/2)(C F^1/2)^T, lower tiles on the
@@ -98,29 +98,35 @@ static int ensure_workspace(elsi_gpu_handle_s* h)
     return 0;
 }
 
+// Per-stage device time: each mark() closes the interval since the previous
+// mark (or the start) and charges it to the given stage.
 struct Timer {
-    hipEvent_t ev[ELSI_GPU_NSTAGES + 1];
-    int have[ELSI_GPU_NSTAGES + 1];
+    static constexpr int kMax = 32;
     hipEvent_t start, stop;
+    hipEvent_t ev[kMax];
+    int stage[kMax];
+    int nmark = 0;
     hipStream_t st;
     explicit Timer(hipStream_t s) : st(s) {
-        for (int i = 0; i <= ELSI_GPU_NSTAGES; ++i) { (void)hipEventCreate(&ev[i]); have[i] = 0; }
         (void)hipEventCreate(&start);
         (void)hipEventCreate(&stop);
         (void)hipEventRecord(start, st);
     }
-    // mark the end of stage `stage`
-    void mark(int stage) { (void)hipEventRecord(ev[stage], st); have[stage] = 1; }
+    void mark(int stg) {
+        if (nmark >= kMax) return;
+        (void)hipEventCreate(&ev[nmark]);
+        (void)hipEventRecord(ev[nmark], st);
+        stage[nmark++] = stg;
+    }
     void finish(elsi_gpu_info* info) {
         (void)hipEventRecord(stop, st);
         (void)hipEventSynchronize(stop);
+        for (int i = 0; i < ELSI_GPU_NSTAGES; ++i) info->stage_ms[i] = 0.0;
         hipEvent_t prev = start;
-        for (int i = 0; i < ELSI_GPU_NSTAGES; ++i) {
-            info->stage_ms[i] = 0.0;
-            if (!have[i]) continue;
+        for (int i = 0; i < nmark; ++i) {
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, prev, ev[i]);
-            info->stage_ms[i] = ms;
+            info->stage_ms[stage[i]] += ms;
             prev = ev[i];
         }
         float tot = 0.f;
@@ -128,7 +134,7 @@ struct Timer {
         info->total_ms = tot;
     }
     ~Timer() {
-        for (int i = 0; i <= ELSI_GPU_NSTAGES; ++i) (void)hipEventDestroy(ev[i]);
+        for (int i = 0; i < nmark; ++i) (void)hipEventDestroy(ev[i]);
         (void)hipEventDestroy(start);
         (void)hipEventDestroy(stop);
     }
@@ -138,7 +144,8 @@ struct Timer {
 // reduction (Eq. (11)), full -> band and band -> tridiagonal (Eq. (13)), and
 // the tridiagonal eigenpairs (divide and conquer).  On success w holds all
 // eigenvalues ascending and Z the eigenvectors of T (first ncol columns).
-static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, const Layout& L, Timer& tm, int ncol)
+static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, const Layout& L, Timer& tm,
+                      DcState* dc)
 {
     hipStream_t st = h->stream;
     const int n = h->n, b = std::min(h->band_width, std::max(1, n - 1));
@@ -184,19 +191,21 @@ static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, cons
     if (rc) return rc;
     tm.mark(ELSI_GPU_ST_BULGE);
     double* w = (double*)(ws + L.w);
-    rc = stedc(st, n, d, e, w, (double*)(ws + L.z), (double*)(ws + L.z2), (double*)(ws + L.u), n, ncol,
-               ws + L.dcwork, err2, nullptr);
+    rc = stedc_values(st, n, d, e, w, (double*)(ws + L.z), (double*)(ws + L.z2), (double*)(ws + L.u), n,
+                      ws + L.dcwork, err2, dc);
     if (rc) return rc;
     tm.mark(ELSI_GPU_ST_TRIDIAG);
     return 0;
 }
 
 // X (n x k, in Z) <- L^-T Q1 Q2 X: steps (4), (5) and the back substitution.
-static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L, Timer& tm, int k)
+static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L, Timer& tm, int k, DcState* dc)
 {
     hipStream_t st = h->stream;
     const int n = h->n, b = std::min(h->band_width, std::max(1, n - 1));
     double* X = (double*)(ws + L.z);
+    stedc_vectors(st, *dc, k);   // top merge of step (3) restricted to the k wanted columns
+    tm.mark(ELSI_GPU_ST_TRIDIAG);
     apply_q2(st, n, b, k, (double*)(ws + L.v2), (double*)(ws + L.tau2), sb2st_kmax(n, b), X, n,
              (double*)(ws + L.tq2));
     tm.mark(ELSI_GPU_ST_BACK_Q2);
@@ -242,9 +251,10 @@ int elsi_gpu_ev(elsi_gpu_handle h, double* H, double* S, double* eval, double* e
     h->info.fail_col = 0;
     h->info.band_width = std::min(h->band_width, std::max(1, n - 1));
     Timer tm(st);
-    rc = front_half(h, H, S, ws, L, tm, k);
+    DcState dc;
+    rc = front_half(h, H, S, ws, L, tm, &dc);
     if (rc) { tm.finish(&h->info); return rc; }
-    back_half(h, S, ws, L, tm, k);
+    back_half(h, S, ws, L, tm, k, &dc);
     copy_matrix(st, n, k, (double*)(ws + L.z), n, evec, n);
     (void)hipMemcpyAsync(eval, ws + L.w, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
     rc = sync_status(st);
@@ -272,7 +282,8 @@ int elsi_gpu_dm(elsi_gpu_handle h, double* H, double* S, double* occ, double* D,
     h->info.fail_col = 0;
     h->info.band_width = std::min(h->band_width, std::max(1, n - 1));
     Timer tm(st);
-    rc = front_half(h, H, S, ws, L, tm, n);
+    DcState dc;
+    rc = front_half(h, H, S, ws, L, tm, &dc);
     if (rc) { tm.finish(&h->info); return rc; }
     double* w = (double*)(ws + L.w);
     double* f = occ ? occ : (double*)(ws + L.f);
@@ -293,7 +304,7 @@ int elsi_gpu_dm(elsi_gpu_handle h, double* H, double* S, double* occ, double* D,
         ks = (int)hs[2];
     }
     tm.mark(ELSI_GPU_ST_OCC);
-    back_half(h, S, ws, L, tm, ks);
+    back_half(h, S, ws, L, tm, ks, &dc);
     density_matrix(st, n, ks, (double*)(ws + L.z), n, f, (double*)(ws + L.z2), D, n);
     tm.mark(ELSI_GPU_ST_DENSITY);
     if (eval) (void)hipMemcpyAsync(eval, w, sizeof(double) * n, hipMemcpyDeviceToDevice, st);

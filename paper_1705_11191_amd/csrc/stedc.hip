@@ -157,9 +157,7 @@ struct MergeArrays {
     int* stag;
 };
 
-struct MergeDesc {
-    int o, n1, n2;
-};
+typedef MergeDescH MergeDesc;
 
 __device__ double block_reduce_sum(double v, double* red)
 {
@@ -521,13 +519,14 @@ size_t stedc_workspace_bytes(int n)
     return b + 4096;
 }
 
-// Eigenpairs of the tridiagonal (d, e): w (n) ascending, Z (n x ncol_final,
-// ld ldz) the eigenvectors of the lowest ncol_final eigenvalues.  Z and Z2
-// are n x n work areas (the result ends in Z); U is n x n.  Returns 0 or 2.
-int stedc(hipStream_t st, int n, const double* d, const double* e, double* w, double* Z, double* Z2,
-          double* U, int ldz, int ncol_final, void* work, int* err, int* err_host_copy)
+// Phase 1 of the tridiagonal solve: every eigenvalue (w, ascending) and every
+// merge level except the products of the last one, whose coefficient block U
+// is left ready.  Phase 2 (stedc_vectors) forms the eigenvectors of the
+// lowest ncol eigenvalues only -- the top merge dominates the cost, and the
+// density matrix needs only the states with non-negligible occupation.
+int stedc_values(hipStream_t st, int n, const double* d, const double* e, double* w, double* Z, double* Z2,
+                 double* U, int ldz, void* work, int* err, DcState* state)
 {
-    (void)err_host_copy;
     char* p = (char*)work;
     auto take = [&](size_t bytes) { void* r = p; p += align_up(bytes, 256); return r; };
     MergeArrays ma;
@@ -557,6 +556,13 @@ int stedc(hipStream_t st, int n, const double* d, const double* e, double* w, do
     ma.skey = (double*)take(sizeof(double) * 2 * n);
     MergeDesc* mdev = (MergeDesc*)take(sizeof(MergeDesc) * (n / LEAF + 2));
 
+    state->n = n;
+    state->ldz = ldz;
+    state->Z = Z;
+    state->Zin = Z;
+    state->Zout = Z2;
+    state->U = U;
+    state->have_last = false;
     fill_i(st, err, 1, 0);
     const int nleaf = ceil_div(n, LEAF);
     hipLaunchKernelGGL(dc_leaf_kernel, dim3(nleaf), dim3(64), 0, st, n, d, e, Z, ldz, w, err);
@@ -593,6 +599,13 @@ int stedc(hipStream_t st, int n, const double* d, const double* e, double* w, do
         hipLaunchKernelGGL(dc_order_kernel, dim3(nm), dim3(1024), 0, st, mdl, ma, w);
         hipLaunchKernelGGL(dc_vectors_kernel, dim3(maxns, nm), dim3(256), 0, st, mdl, ma, U, ldz);
         hipLaunchKernelGGL(dc_rot_kernel, dim3(ceil_div(maxns, 256), nm), dim3(256), 0, st, mdl, ma, U, ldz);
+        if (last) {
+            state->Zin = Zin;
+            state->Zout = Zout;
+            state->last = md;
+            state->have_last = true;
+            return 0;
+        }
         // blocks that pass through unchanged keep their columns: copy them across
         for (int o = 0; o < n; o += 2 * size) {
             int n1 = std::min(size, n - o);
@@ -600,15 +613,44 @@ int stedc(hipStream_t st, int n, const double* d, const double* e, double* w, do
         }
         for (const MergeDesc& m : md) {
             const int ns = m.n1 + m.n2;
-            const int nc = last ? std::min(ns, ncol_final) : ns;
-            dgemm(st, 'N', 'N', m.n1, nc, m.n1, 1.0, Zin + cm(m.o, m.o, ldz), ldz, U + cm(m.o, m.o, ldz), ldz,
+            dgemm(st, 'N', 'N', m.n1, ns, m.n1, 1.0, Zin + cm(m.o, m.o, ldz), ldz, U + cm(m.o, m.o, ldz), ldz,
                   0.0, Zout + cm(m.o, m.o, ldz), ldz, 0);
-            dgemm(st, 'N', 'N', m.n2, nc, m.n2, 1.0, Zin + cm(m.o + m.n1, m.o + m.n1, ldz), ldz,
+            dgemm(st, 'N', 'N', m.n2, ns, m.n2, 1.0, Zin + cm(m.o + m.n1, m.o + m.n1, ldz), ldz,
                   U + cm(m.o + m.n1, m.o, ldz), ldz, 0.0, Zout + cm(m.o + m.n1, m.o, ldz), ldz, 0);
         }
         std::swap(Zin, Zout);
     }
-    if (Zin != Z) copy_matrix(st, n, std::min(n, ncol_final), Zin, ldz, Z, ldz);
+    return 0;
+}
+
+// Phase 2: eigenvectors of the lowest ncol eigenvalues into state->Z (n x ncol).
+void stedc_vectors(hipStream_t st, DcState& state, int ncol)
+{
+    if (!state.have_last || ncol <= 0) return;
+    const int ldz = state.ldz;
+    double* Zin = state.Zin;
+    double* Zout = state.Zout;
+    double* U = state.U;
+    for (const MergeDesc& m : state.last) {
+        const int nc = std::min(m.n1 + m.n2, ncol);
+        dgemm(st, 'N', 'N', m.n1, nc, m.n1, 1.0, Zin + cm(m.o, m.o, ldz), ldz, U + cm(m.o, m.o, ldz), ldz, 0.0,
+              Zout + cm(m.o, m.o, ldz), ldz, 0);
+        dgemm(st, 'N', 'N', m.n2, nc, m.n2, 1.0, Zin + cm(m.o + m.n1, m.o + m.n1, ldz), ldz,
+              U + cm(m.o + m.n1, m.o, ldz), ldz, 0.0, Zout + cm(m.o + m.n1, m.o, ldz), ldz, 0);
+    }
+    if (Zout != state.Z) copy_matrix(st, state.n, std::min(state.n, ncol), Zout, ldz, state.Z, ldz);
+    state.have_last = false;
+}
+
+// Both phases: all n eigenvalues, eigenvectors of the lowest ncol_final.
+int stedc(hipStream_t st, int n, const double* d, const double* e, double* w, double* Z, double* Z2,
+          double* U, int ldz, int ncol_final, void* work, int* err, int* err_host_copy)
+{
+    (void)err_host_copy;
+    DcState state;
+    int rc = stedc_values(st, n, d, e, w, Z, Z2, U, ldz, work, err, &state);
+    if (rc) return rc;
+    stedc_vectors(st, state, ncol_final);
     return 0;
 }
 
