@@ -35,10 +35,104 @@ WORKLOADS = {
 }
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+GEMM_SRC = os.path.join(ROOT, "paper_1705_11191_amd", "csrc", "gemm.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+# plain copy kernel used to calibrate the HBM byte counters: y = -x over
+# COPY_ELEMS doubles reads and writes COPY_ELEMS * 8 bytes each
+COPY_ELEMS = 1 << 28
 
 
 def algorithmic_flops(n: int, ks: int) -> float:
     return (8.0 / 3.0) * n ** 3 + 6.0 * n * n * ks
+
+
+def _sha256(path: str) -> str:
+    import hashlib
+
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def _traffic_file(kernel: str, workload: str) -> str:
+    tag = kernel.replace("<", "_").replace(">", "").replace(",", "_")
+    return os.path.join(PROFILES, f"{tag}_{workload}_hbm_traffic.md")
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none or the GEMM source changed since it was taken."""
+    path = _traffic_file(kernel, workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic_json:"):
+                rec = json.loads(line.split(":", 1)[1])
+                if rec.get("kernel") == kernel and rec.get("gemm_src_sha256") == _sha256(GEMM_SRC):
+                    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return None
+
+
+def _pmc_rows(csv_path: str, counter: str):
+    """(kernel name, value in KiB) per dispatch from a rocprofv3 counter_collection.csv."""
+    import csv
+
+    rows = []
+    with open(csv_path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Counter_Name") == counter:
+                rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, kernel: str, workload: str, commands: list):
+    """Write the per-launch HBM traffic summary of `kernel` (bytes), each counter
+    scaled so that the calibration copy kernel reads/writes its known size."""
+    known_kib = COPY_ELEMS * 8 / 1024.0
+    out = {}
+    for which, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _pmc_rows(path, counter)
+        copies = [v for name, v in rows if "neg" in name.lower()]
+        if not copies:
+            raise SystemExit(f"{path}: no calibration copy dispatch found")
+        # the calibration copy is the largest dispatch of the negation kernel
+        factor = known_kib / max(copies)
+        vals = [v for name, v in rows if _kernel_matches(name, kernel)]
+        if not vals:
+            raise SystemExit(f"{path}: no dispatch of {kernel}")
+        out[which] = dict(factor=factor, launches=len(vals), kib_per_launch=sum(vals) / len(vals))
+    rec = {
+        "kernel": kernel,
+        "workload": workload,
+        "gemm_src_sha256": _sha256(GEMM_SRC),
+        "fetch_bytes_per_launch": out["fetch"]["kib_per_launch"] * 1024 * out["fetch"]["factor"],
+        "write_bytes_per_launch": out["write"]["kib_per_launch"] * 1024 * out["write"]["factor"],
+        "fetch_factor": out["fetch"]["factor"],
+        "write_factor": out["write"]["factor"],
+        "launches": out["fetch"]["launches"],
+    }
+    path = _traffic_file(kernel, workload)
+    with open(path, "w") as fh:
+        fh.write(f"# HBM traffic of {kernel}, workload {workload}\n\n")
+        fh.write("Counters: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), one rocprofv3 pass each.\n")
+        fh.write(f"Calibration: a plain copy kernel (y = -x over {COPY_ELEMS} doubles, "
+                 f"{COPY_ELEMS * 8} bytes each way) in the same run; factor = known size / counter.\n\n")
+        fh.write("Commands:\n\n")
+        for c in commands:
+            fh.write(f"    {c}\n")
+        fh.write("\n")
+        fh.write(f"| counter | launches | KiB/launch (raw) | factor | bytes/launch |\n|---|---|---|---|---|\n")
+        fh.write(f"| FETCH_SIZE | {out['fetch']['launches']} | {out['fetch']['kib_per_launch']:.1f} | "
+                 f"{out['fetch']['factor']:.4f} | {rec['fetch_bytes_per_launch']:.4g} |\n")
+        fh.write(f"| WRITE_SIZE | {out['write']['launches']} | {out['write']['kib_per_launch']:.1f} | "
+                 f"{out['write']['factor']:.4f} | {rec['write_bytes_per_launch']:.4g} |\n\n")
+        fh.write("traffic_json: " + json.dumps(rec) + "\n")
+    print(path)
+
+
+def _kernel_matches(full_name: str, short: str) -> bool:
+    """rocprofv3 prints e.g. 'void eg::(anonymous namespace)::dgemm_kernel<128, 128, false, true>(...)'."""
+    return full_name.replace(" ", "").find(short.replace(" ", "") + "(") >= 0
 
 
 def cpu_baseline(n_sample: int):
@@ -73,7 +167,17 @@ def main():
     ap.add_argument("--band", type=int, default=64)
     ap.add_argument("--cpu-sample-n", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain copy kernel of known size first (HBM counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic summary of --kernel from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--kernel", default="dgemm_kernel<128,128,0,true>")
+    ap.add_argument("--pmc-command", action="append", default=[])
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.kernel,
+                      WORKLOADS[args.config]["name"], args.pmc_command)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path has no multi-GPU mode); got --gpus {args.gpus}",
               file=sys.stderr)
@@ -103,6 +207,13 @@ def main():
     ws = torch.empty(h.workspace_size() // 8 + 1, device=dev, dtype=torch.float64)
     h.set_workspace(ws)
 
+    if args.calibrate_copy:
+        x = torch.ones(COPY_ELEMS, device=dev, dtype=torch.float64)
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
+
     def step():
         H.copy_(H0)
         S.copy_(S0)
@@ -112,6 +223,7 @@ def main():
         step()
         print(f"[bench] warmup {w} done: {h.info()['total_ms']:.1f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    h.set_launch_timing(True)   # HIP events around each GEMM launch, on the library's stream
     t0 = time.perf_counter()
     stage_ms = None
     for k in range(args.steps):
@@ -126,9 +238,25 @@ def main():
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
     info = h.info()
+    h.set_launch_timing(False)
     ks = info["k_s"]
     F = algorithmic_flops(n, ks)
     value = F / (ms / 1e3) / 1e12
+    kname = info["probe_kernel"]
+    launches = max(info["probe_launches"], 1)
+    achieved = info["probe_flops"] / (info["probe_ms"] * 1e-3) / 1e12 if info["probe_ms"] > 0 else 0.0
+    roofline = {
+        "bound": "mfma",
+        "achieved": achieved,
+        "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / FP64_PEAK_TFLOPS,
+        "traffic": load_traffic(kname, wl["name"]),
+        "kernel": kname,
+        "launches_per_step": info["probe_launches"] / args.steps,
+        "avg_launch_ms": info["probe_ms"] / launches,
+        "flops_per_launch": info["probe_flops"] / launches,
+    }
     # quick invariants on the last step: tr(D S) = N_e, ascending eigenvalues
     trace_ds = float((D * S0).sum().item())
     ascending = bool(torch.all(ev[1:] >= ev[:-1]).item())
@@ -149,6 +277,7 @@ def main():
         "config": {"workload": wl["name"], "n_basis": n, "n_occ": int(n_occ), "kT_Ha": spec.kT,
                    "kappa_S": spec.meta["kappa"], "band_width": info["band_width"], "k_s": ks,
                    "path": "plain_fp64"},
+        "roofline": roofline,
         "algorithmic_flops": F,
         "stage_ms": stage_ms,
         "checks": {"trace_DS_minus_Ne": trace_ds - n_occ, "eigenvalues_ascending": ascending,

@@ -90,6 +90,15 @@ typedef struct elsi_gpu_info {
     int mu_steps;                      /* bisection steps taken */
     int band_width;                    /* b of step (1) */
     int n_basis;
+    /* Launch timing (elsi_gpu_set_launch_timing): the GEMM kernel
+     * instantiation with the largest summed device time since timing was
+     * switched on, its launch count, summed device time and summed
+     * algorithmic flops (2mnk per product, lower-triangle entries only for the
+     * triangular updates).  Zero / empty while timing is off. */
+    int probe_launches;
+    double probe_ms;
+    double probe_flops;
+    char probe_kernel[48];
 } elsi_gpu_info;
 
 /* Create a handle (elsi_init, Sec. 4.4).  n_state: eigenvectors returned by
@@ -127,6 +136,14 @@ int elsi_gpu_set_overlap_factored(elsi_gpu_handle h, int flag);
 
 /* Band width b of step (1) (Eq. (13)); 8 <= b <= 64, multiple of 8. */
 int elsi_gpu_set_band_width(elsi_gpu_handle h, int b);
+
+/* Measurement aid, not part of the method: on = 1 brackets every GEMM launch
+ * with a pair of HIP events on the handle's stream and resets the totals
+ * reported in elsi_gpu_info.probe_*; on = 0 stops it.  The totals are
+ * harvested (the events synchronized) at the end of each elsi_gpu_ev /
+ * elsi_gpu_dm call.  The timing state is process-wide: it covers launches of
+ * every handle.  Errors: -1 null handle, -2 on not 0 or 1. */
+int elsi_gpu_set_launch_timing(elsi_gpu_handle h, int on);
 
 /* Eigenvalues and eigenvectors (elsi_ev_real, Sec. 4.5).
  *   H    device, n x n, in; destroyed on exit;
@@ -169,7 +186,9 @@ const char *elsi_gpu_strerror(int status);
  * ------------------------------------------------------------------------ */
 
 /* C = alpha op(A) op(B) + beta C in FP64 on the matrix cores; ta, tb = 'N' or
- * 'T'; C is m x n.  Errors: -1 ta, -2 tb, -3..-5 sizes < 0. */
+ * 'T'; C is m x n.  ta = 'S': A is symmetric with only its lower triangle
+ * read (the product Y = A22 V of step (1), Eq. (13)); then k == m and
+ * tb == 'N'.  Errors: -1 ta, -2 tb, -3..-5 sizes < 0 (-5 also k != m for 'S'). */
 int elsi_gpu_x_dgemm(char ta, char tb, int m, int n, int k, double alpha, const double *A,
                      int lda, const double *B, int ldb, double beta, double *C, int ldc,
                      void *hip_stream);

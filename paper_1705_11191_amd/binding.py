@@ -38,10 +38,13 @@ class Info(ctypes.Structure):
                 ("mu", ctypes.c_double), ("energy", ctypes.c_double),
                 ("charge_residual", ctypes.c_double), ("k_s", ctypes.c_int),
                 ("fail_col", ctypes.c_int), ("mu_steps", ctypes.c_int),
-                ("band_width", ctypes.c_int), ("n_basis", ctypes.c_int)]
+                ("band_width", ctypes.c_int), ("n_basis", ctypes.c_int),
+                ("probe_launches", ctypes.c_int), ("probe_ms", ctypes.c_double),
+                ("probe_flops", ctypes.c_double), ("probe_kernel", ctypes.c_char * 48)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "stage_ms"}
+        d["probe_kernel"] = self.probe_kernel.decode()
         d["stage_ms"] = {s: self.stage_ms[i] for i, s in enumerate(STAGES)}
         return d
 
@@ -64,6 +67,7 @@ def lib():
         L.elsi_gpu_set_overlap_is_unit.argtypes = [vp, i]
         L.elsi_gpu_set_overlap_factored.argtypes = [vp, i]
         L.elsi_gpu_set_band_width.argtypes = [vp, i]
+        L.elsi_gpu_set_launch_timing.argtypes = [vp, i]
         L.elsi_gpu_ev.argtypes = [vp, vp, vp, vp, vp]
         L.elsi_gpu_dm.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d)]
         L.elsi_gpu_get_info.argtypes = [vp, ctypes.POINTER(Info)]
@@ -234,6 +238,10 @@ class Handle:
 
     def set_band_width(self, b: int):
         _check(lib().elsi_gpu_set_band_width(self._h, b), "set_band_width")
+
+    def set_launch_timing(self, on: bool):
+        """Per-launch HIP-event timing of the GEMM kernels (measurement aid)."""
+        _check(lib().elsi_gpu_set_launch_timing(self._h, int(bool(on))), "set_launch_timing")
 
     def workspace_size(self) -> int:
         v = ctypes.c_size_t(0)

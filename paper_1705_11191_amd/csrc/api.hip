@@ -109,6 +109,19 @@ int elsi_gpu_set_band_width(elsi_gpu_handle h, int b)
     return 0;
 }
 
+int elsi_gpu_set_launch_timing(elsi_gpu_handle h, int on)
+{
+    if (!h) return -1;
+    if (on != 0 && on != 1) return -2;
+    launch_probe::enable(on != 0);
+    if (on) launch_probe::reset_totals();
+    h->info.probe_launches = 0;
+    h->info.probe_ms = 0.0;
+    h->info.probe_flops = 0.0;
+    h->info.probe_kernel[0] = '\0';
+    return 0;
+}
+
 int elsi_gpu_get_info(elsi_gpu_handle h, elsi_gpu_info* out)
 {
     if (!h) return -1;
@@ -132,11 +145,12 @@ int elsi_gpu_finalize(elsi_gpu_handle* h)
 int elsi_gpu_x_dgemm(char ta, char tb, int m, int n, int k, double alpha, const double* A, int lda,
                      const double* B, int ldb, double beta, double* C, int ldc, void* hip_stream)
 {
-    if (ta != 'N' && ta != 'T') return -1;
+    if (ta != 'N' && ta != 'T' && ta != 'S') return -1;
     if (tb != 'N' && tb != 'T') return -2;
+    if (ta == 'S' && tb != 'N') return -2;
     if (m < 0) return -3;
     if (n < 0) return -4;
-    if (k < 0) return -5;
+    if (k < 0 || (ta == 'S' && k != m)) return -5;
     if (m == 0 || n == 0) return 0;
     if (!C) return -12;
     if (k > 0 && (!A || !B)) return !A ? -7 : -9;

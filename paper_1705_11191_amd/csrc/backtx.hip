@@ -11,9 +11,8 @@
 // pair in its reverse-execution order, and the reflectors of one (g, k) all
 // live in a window of 2b-1 rows.  The b reflectors of (g, k), applied sweeps
 // descending, form one block reflector H_{s_lo} ... H_{s_hi} = I - V T V^T
-// (T formed once per (g, k) by a separate kernel), applied to a slab of 32
-// columns as three FP64 matrix-core products (V^T X_W, T W, X_W - V W2) on
-// the window staged in LDS.  Blocks run in anti-diagonal steps t = (G-1-g)+k:
+// (T formed once per (g, k) by a separate kernel), applied to a slab of X
+// columns as three FP64 matrix-core products (V^T X_W, T W, X_W - V W2).  Blocks run in anti-diagonal steps t = (G-1-g)+k:
 // the windows of (g, k) and (g', k') overlap only when |(g+k) - (g'+k')| <= 1,
 // so blocks of one step are independent and overlapping pairs keep their
 // order; each step is one launch over all of its blocks and column slabs.
@@ -101,117 +100,175 @@ __global__ __launch_bounds__(256) void q2_build_t_kernel(int n, int b, const dou
     for (int e = tid; e < NB2 * NB2; e += 256) T[e] = Ts[e % NB2][e / NB2];   // column-major, ld 64
 }
 
-// acc (16 x 16 block) += A (16 x 4K) B (4K x 16) with A(i, kk) = fa(i, kk), B(kk, j) = fb(kk, j)
-// D layout: lane l, element r -> row 4 r + l / 16, column l % 16.
+// One block reflector (g, k) applied to a slab of QW columns of X per
+// workgroup, 32 columns at a time; the launch covers every (g, k) on the
+// anti-diagonal step t = (G-1-g) + k.  Blocks on one step touch disjoint row
+// windows, and every pair of blocks whose windows overlap lands on different
+// steps in the reverse-execution order (windows overlap only when g + k
+// differ by at most one).
+//
+// Reflector i of the block is nonzero only in window rows i .. i+b-1, so V is
+// a 128 x 64 parallelogram: the products skip the 16 x 4 MFMA blocks that lie
+// outside it.  V and T sit in registers as MFMA operands for the whole slab;
+// LDS holds only the current 32-column chunk of X and the two 64 x 32
+// intermediates, which lets two workgroups share a CU.  Workgroups are
+// numbered so that all slabs of one block run on one XCD (one L2 copy of V).
+constexpr int QW = 128;   // columns of X per workgroup
 
-// One block reflector (g, k) on one 32-column slab of X per workgroup; the
-// launch covers every (g, k) on the anti-diagonal step t = (G-1-g) + k.
-// Blocks on one step touch disjoint row windows, and every pair of blocks
-// whose windows overlap lands on different steps in the reverse-execution
-// order (windows overlap only when g + k differ by at most one).
-__global__ __launch_bounds__(256) void q2_apply_step_kernel(int n, int b, int ncol, int t,
-                                                            const double* __restrict__ V2,
-                                                            const double* __restrict__ Tq, int kmax, double* X,
-                                                            int ldx)
+// Phase-3 row blocks of each wave (16-row blocks of the 128-row window with
+// their first nonzero 4-column step), balanced to 20 MFMA steps per wave.
+__device__ __forceinline__ void q2_rowblocks(int wave, int& rbA, int& kA0, int& nA, int& rbB, int& kB0)
 {
-    __shared__ double Vs[2 * NB2][NB2 + 1];
-    __shared__ double Xs[2 * NB2][NCB + 1];
-    __shared__ double Ws[NB2][NCB + 1];
-    __shared__ double W2s[NB2][NCB + 1];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    switch (wave) {
+    case 0: rbA = 3; kA0 = 0; nA = 16; rbB = 0; kB0 = 0; break;
+    case 1: rbA = 4; kA0 = 0; nA = 16; rbB = 7; kB0 = 48; break;
+    case 2: rbA = 2; kA0 = 0; nA = 12; rbB = 1; kB0 = 0; break;
+    default: rbA = 5; kA0 = 16; nA = 12; rbB = 6; kB0 = 32; break;
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void q2_apply_step_kernel(int n, int b, int ncol, int t, int nb, int nslab,
+                                                               const double* __restrict__ V2,
+                                                               const double* __restrict__ Tq, int kmax, double* X,
+                                                               int ldx)
+{
+    // phase 0: V (128 x 65); afterwards X chunk (128 x 33), W and W2 (64 x 33 each)
+    __shared__ double lds[2 * NB2 * (NCB + 1) + 2 * NB2 * (NCB + 1)];
+    double(*Vs)[NB2 + 1] = (double(*)[NB2 + 1])lds;
+    double(*Xs)[NCB + 1] = (double(*)[NCB + 1])lds;
+    double(*Ws)[NCB + 1] = (double(*)[NCB + 1])(lds + 2 * NB2 * (NCB + 1));
+    double(*W2s)[NCB + 1] = (double(*)[NCB + 1])(lds + 3 * NB2 * (NCB + 1));
+
+    const int bid = blockIdx.x;
+    const int q = bid >> 3;
+    const int slab = q % nslab;
+    const int blk = (q / nslab) * 8 + (bid & 7);
+    if (blk >= nb) return;
     const int nsweeps = n - 2;
     const int ngroups = ceil_div(nsweeps, b);
-    const int g = ngroups - 1 - (int)blockIdx.x;
-    const int k = t - (int)blockIdx.x;
+    const int g = ngroups - 1 - blk;
+    const int k = t - blk;
     if (g < 0 || k < 0 || k >= q2_ntasks(n, b, g * b)) return;
-    const int col0 = blockIdx.y * NCB;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int s_lo = g * b;
     const int base = s_lo + 1 + k * b;
     const int wrows = min(2 * b - 1, n - base);
-    const double* T = Tq + ((size_t)g * kmax + k) * NB2 * NB2;
+    const int cbeg = slab * QW, cend = min(ncol, cbeg + QW);
+
     double treg[NB2 / 4];
-#pragma unroll
-    for (int q4 = 0; q4 < NB2 / 4; ++q4) treg[q4] = T[(wave * 16 + li) + (size_t)(4 * q4 + lk) * NB2];
     {
-        const int r = tid & 127, c0 = tid >> 7;
-        double xv[NCB / 2];
+        const double* T = Tq + ((size_t)g * kmax + k) * NB2 * NB2;
+#pragma unroll
+        for (int q4 = 0; q4 < NB2 / 4; ++q4) treg[q4] = T[(wave * 16 + li) + (size_t)(4 * q4 + lk) * NB2];
+    }
+    const int xr = tid & 127, xc = tid >> 7;
+    double xv[NCB / 2];
+    auto load_x = [&](int c0) {
 #pragma unroll
         for (int j = 0; j < NCB / 2; ++j) {
-            const int gc = col0 + c0 + 2 * j;
-            xv[j] = (r < wrows && gc < ncol) ? X[cm(base + r, gc, ldx)] : 0.0;
+            const int gc = c0 + xc + 2 * j;
+            xv[j] = (xr < wrows && gc < cend) ? X[cm(base + xr, gc, ldx)] : 0.0;
         }
-        q2_load_v(n, b, g, k, V2, Vs);
-#pragma unroll
-        for (int j = 0; j < NCB / 2; ++j) Xs[r][c0 + 2 * j] = xv[j];
-    }
+    };
+    load_x(cbeg);
+    q2_load_v(n, b, g, k, V2, Vs);
     __syncthreads();
-    // W = V^T X_W (64 x 32): wave w owns rows 16w .. 16w+15, both column blocks
-    {
-        double4_t a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
-        const int i0 = wave * 16;
-        for (int kk = 0; kk < 2 * NB2; kk += 4) {
-            const double av = Vs[kk + lk][i0 + li];
-            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xs[kk + lk][li], a0, 0, 0, 0);
-            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xs[kk + lk][16 + li], a1, 0, 0, 0);
+
+    // phase-1 operand: V^T rows 16w.., window rows 16w .. 16w+79
+    double va1[20];
+#pragma unroll
+    for (int j = 0; j < 20; ++j) va1[j] = Vs[16 * wave + 4 * j + lk][16 * wave + li];
+    int rbA, kA0, nA, rbB, kB0;
+    q2_rowblocks(wave, rbA, kA0, nA, rbB, kB0);
+    double va3[20];
+#pragma unroll
+    for (int j = 0; j < 20; ++j)
+        va3[j] = (j < nA) ? Vs[16 * rbA + li][kA0 + 4 * j + lk] : Vs[16 * rbB + li][kB0 + 4 * (j - nA) + lk];
+    __syncthreads();   // the V area now holds X chunks
+
+    for (int c0 = cbeg; c0 < cend; c0 += NCB) {
+#pragma unroll
+        for (int j = 0; j < NCB / 2; ++j) Xs[xr][xc + 2 * j] = xv[j];
+        __syncthreads();
+        if (c0 + NCB < cend) load_x(c0 + NCB);
+        // W = V^T X (64 x 32): wave w owns rows 16w .. 16w+15
+        {
+            double4_t a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < 20; ++j) {
+                const int kk = 16 * wave + 4 * j + lk;
+                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(va1[j], Xs[kk][li], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(va1[j], Xs[kk][16 + li], a1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Ws[16 * wave + 4 * r + lk][li] = a0[r];
+                Ws[16 * wave + 4 * r + lk][16 + li] = a1[r];
+            }
         }
+        __syncthreads();
+        // W2 = T W (64 x 32)
+        {
+            double4_t a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            Ws[i0 + 4 * r + lk][li] = a0[r];
-            Ws[i0 + 4 * r + lk][16 + li] = a1[r];
+            for (int q4 = 0; q4 < NB2 / 4; ++q4) {
+                const int kk = 4 * q4 + lk;
+                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q4], Ws[kk][li], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q4], Ws[kk][16 + li], a1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                W2s[16 * wave + 4 * r + lk][li] = a0[r];
+                W2s[16 * wave + 4 * r + lk][16 + li] = a1[r];
+            }
         }
-    }
-    __syncthreads();
-    // W2 = T W (64 x 32), T operands from registers
-    {
-        double4_t a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
-        const int i0 = wave * 16;
+        __syncthreads();
+        // X -= V W2 on the wave's two row blocks; operands swapped so that a
+        // lane's results run down a column: lane l, element r holds
+        // (V W2)(16 rb + l % 16, 16 cb + 4 r + l / 16)
+        {
+            double4_t A0 = {0, 0, 0, 0}, A1 = {0, 0, 0, 0}, B0 = {0, 0, 0, 0}, B1 = {0, 0, 0, 0};
 #pragma unroll
-        for (int q4 = 0; q4 < NB2 / 4; ++q4) {
-            const int kk = 4 * q4;
-            const double av = treg[q4];
-            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ws[kk + lk][li], a0, 0, 0, 0);
-            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ws[kk + lk][16 + li], a1, 0, 0, 0);
+            for (int j = 0; j < 12; ++j) {
+                const int kk = kA0 + 4 * j + lk;
+                A0 = __builtin_amdgcn_mfma_f64_16x16x4f64(W2s[kk][li], va3[j], A0, 0, 0, 0);
+                A1 = __builtin_amdgcn_mfma_f64_16x16x4f64(W2s[kk][16 + li], va3[j], A1, 0, 0, 0);
+            }
+            if (nA == 16) {
+#pragma unroll
+                for (int j = 12; j < 16; ++j) {
+                    const int kk = kA0 + 4 * j + lk;
+                    A0 = __builtin_amdgcn_mfma_f64_16x16x4f64(W2s[kk][li], va3[j], A0, 0, 0, 0);
+                    A1 = __builtin_amdgcn_mfma_f64_16x16x4f64(W2s[kk][16 + li], va3[j], A1, 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int j = 12; j < 16; ++j) {
+                    const int kk = kB0 + 4 * (j - 12) + lk;
+                    B0 = __builtin_amdgcn_mfma_f64_16x16x4f64(W2s[kk][li], va3[j], B0, 0, 0, 0);
+                    B1 = __builtin_amdgcn_mfma_f64_16x16x4f64(W2s[kk][16 + li], va3[j], B1, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int j = 16; j < 20; ++j) {
+                const int kk = kB0 + 4 * (j - nA) + lk;
+                B0 = __builtin_amdgcn_mfma_f64_16x16x4f64(W2s[kk][li], va3[j], B0, 0, 0, 0);
+                B1 = __builtin_amdgcn_mfma_f64_16x16x4f64(W2s[kk][16 + li], va3[j], B1, 0, 0, 0);
+            }
+            const int ra = 16 * rbA + li, rb = 16 * rbB + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = 4 * r + lk;
+                if (ra < wrows && c0 + c < cend) X[cm(base + ra, c0 + c, ldx)] = Xs[ra][c] - A0[r];
+                if (ra < wrows && c0 + 16 + c < cend) X[cm(base + ra, c0 + 16 + c, ldx)] = Xs[ra][16 + c] - A1[r];
+                if (rb < wrows && c0 + c < cend) X[cm(base + rb, c0 + c, ldx)] = Xs[rb][c] - B0[r];
+                if (rb < wrows && c0 + 16 + c < cend) X[cm(base + rb, c0 + 16 + c, ldx)] = Xs[rb][16 + c] - B1[r];
+            }
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            W2s[i0 + 4 * r + lk][li] = a0[r];
-            W2s[i0 + 4 * r + lk][16 + li] = a1[r];
-        }
-    }
-    __syncthreads();
-    // X_W -= V W2 (128 x 32): wave w owns rows 32w .. 32w+31
-    {
-        double4_t acc[2][2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) acc[a][c] = (double4_t){0, 0, 0, 0};
-        const int i0 = wave * 32;
-        for (int kk = 0; kk < NB2; kk += 4) {
-            const double b0 = W2s[kk + lk][li], b1 = W2s[kk + lk][16 + li];
-            const double v0 = Vs[i0 + li][kk + lk], v1 = Vs[i0 + 16 + li][kk + lk];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(v1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(v1, b1, acc[1][1], 0, 0, 0);
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Xs[i0 + 16 * a + 4 * r + lk][16 * c + li] -= acc[a][c][r];
-    }
-    __syncthreads();
-    {
-        const int r = tid & 127, c0 = tid >> 7;
-#pragma unroll
-        for (int j = 0; j < NCB / 2; ++j) {
-            const int gc = col0 + c0 + 2 * j;
-            if (r < wrows && gc < ncol) X[cm(base + r, gc, ldx)] = Xs[r][c0 + 2 * j];
-        }
+        __syncthreads();   // Xs, W, W2 free for the next chunk
     }
 }
 
@@ -231,12 +288,13 @@ void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const do
     if (n <= 2 || ncol <= 0) return;
     const int ngroups = ceil_div(n - 2, b);
     hipLaunchKernelGGL(q2_build_t_kernel, dim3(ngroups, kmax), dim3(256), 0, st, n, b, V2, tau2, kmax, Tq);
-    const int nslab = ceil_div(ncol, NCB);
+    const int nslab = ceil_div(ncol, QW);
     const int tmax = (ngroups - 1) + kmax;   // last step: g = 0 with its last block
     for (int t = 0; t < tmax; ++t) {
-        const int nb = std::min(ngroups, t + 1);   // blockIdx.x = G-1-g ranges over 0 .. min(G-1, t)
-        hipLaunchKernelGGL(q2_apply_step_kernel, dim3(nb, nslab), dim3(256), 0, st, n, b, ncol, t, V2, Tq, kmax,
-                           X, ldx);
+        const int nb = std::min(ngroups, t + 1);   // block index G-1-g ranges over 0 .. min(G-1, t)
+        const int nwg = ceil_div(nb, 8) * 8 * nslab;
+        hipLaunchKernelGGL(q2_apply_step_kernel, dim3(nwg), dim3(256), 0, st, n, b, ncol, t, nb, nslab, V2, Tq,
+                           kmax, X, ldx);
     }
 }
 

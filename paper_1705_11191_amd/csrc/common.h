@@ -40,7 +40,25 @@ __host__ __device__ inline size_t cm(int i, int j, int ld) {
 // host-side launchers implemented in the .hip files
 // ---------------------------------------------------------------------------
 
-// C = alpha * op(A) op(B) + beta * C (FP64 MFMA).  op = 'N' or 'T'.
+// Optional device timing of individual launches (off by default).  While it is
+// enabled, the GEMM launchers bracket every launch with a pair of events on the
+// launch stream and record the launch's algorithmic flops under the id of the
+// kernel instantiation; harvest() waits for the events and folds them into
+// per-instantiation totals.
+namespace launch_probe {
+void enable(bool on);
+bool enabled();
+int begin(hipStream_t st);   // returns a slot (or -1 when disabled / pool exhausted)
+void end(hipStream_t st, int slot, int kernel_id, double flops);
+void harvest();              // synchronizes the recorded events
+void reset_totals();
+// instantiation with the largest summed device time since reset_totals()
+bool dominant(int* launches, double* ms, double* flops, const char** name);
+}  // namespace launch_probe
+
+// C = alpha * op(A) op(B) + beta * C (FP64 MFMA).  op = 'N' or 'T'; for A
+// also 'S': A is symmetric (m == k) and only its lower triangle is read
+// (op(B) must then be 'N').
 // uplo: 0 = all tiles, 1 = only tiles that touch the lower triangle (i >= j).
 // C may alias A only when n <= 64 (each workgroup then reads exactly the A rows
 // it writes) and beta == 0; C may alias B only when m <= 64 and beta == 0.

@@ -9,25 +9,35 @@
 // operand panels).
 #include "common.h"
 
+#include <cstdio>
+#include <vector>
+
 namespace eg {
 namespace {
 
 constexpr int kBK = 32;
 
+// Operand modes of A: op(A) = A, op(A) = A^T, or op(A) = the symmetric matrix
+// whose lower triangle A holds (m == k; the strict upper part of A is never read).
+constexpr int kOpN = 0, kOpT = 1, kOpSymLower = 2;
+
 // blockIdx.y selects a K range of length kper when the product is split over
 // K: that slice's partial product goes to C + blockIdx.y * cstride.
-template <int BM, int BN, bool TA, bool TB>
+template <int BM, int BN, int AM, bool TB>
 __global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double alpha,
                                                     const double* __restrict__ A, int lda,
                                                     const double* __restrict__ B, int ldb,
                                                     double beta, double* C, int ldc, int uplo,
-                                                    int tiles_m, int tiles_per_xcd, int kper,
+                                                    int tiles_m, int ntiles, int tiles_per_xcd, int kper,
                                                     size_t cstride)
 {
+    constexpr bool TA = (AM == kOpT);
+    int kofs = 0;   // first global column of A in this K range (symmetric mode)
     {
         const int k0 = blockIdx.y * kper;
         k = min(kper, k - k0);
-        A += TA ? (size_t)k0 : (size_t)k0 * lda;
+        if (AM == kOpSymLower) kofs = k0;
+        else A += TA ? (size_t)k0 : (size_t)k0 * lda;
         B += TB ? (size_t)k0 * ldb : (size_t)k0;
         C += (size_t)blockIdx.y * cstride;
     }
@@ -40,11 +50,25 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double 
 
     const int bid = blockIdx.x;
     const int tile = (bid % 8) * tiles_per_xcd + bid / 8;
-    const int ntiles = tiles_m * ((n + BN - 1) / BN);
     if (tile >= ntiles) return;
-    const int tm = tile % tiles_m, tn = tile / tiles_m;
+    int tm, tn;
+    if (!uplo) {
+        tm = tile % tiles_m;
+        tn = tile / tiles_m;
+    } else {
+        // only the tiles that touch the lower triangle are enumerated (column
+        // by column), so every XCD gets the same share of the work
+        int rem = tile;
+        tn = 0;
+        tm = 0;
+        for (;; ++tn) {
+            const int tmin = (tn * BN) / BM;   // first tile row with row0 + BM - 1 >= col0
+            const int cnt = max(0, tiles_m - tmin);
+            if (rem < cnt) { tm = tmin + rem; break; }
+            rem -= cnt;
+        }
+    }
     const int row0 = tm * BM, col0 = tn * BN;
-    if (uplo && col0 > row0 + BM - 1) return;   // tile strictly above the diagonal
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -57,17 +81,45 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double 
         for (int j = 0; j < FN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
     double ra[A_PER], rb[B_PER];
+    // symmetric mode: slices left of the tile's rows read A (coalesced down
+    // columns), slices right of them read the mirrored entries A^T (coalesced
+    // along K), and the slices that cross the diagonal select per element
+    bool at = TA;   // thread mapping of the slice held in ra
 
     auto load_slice = [&](int k0) {
+        if (AM == kOpSymLower) {
+            const int c0 = kofs + k0;
+            if (c0 >= row0 + BM) {
+                at = true;
 #pragma unroll
-        for (int r = 0; r < A_PER; ++r) {
-            int i, kk;
-            if (!TA) { i = tid % BM; kk = tid / BM + r * (256 / BM); }
-            else     { kk = tid % kBK; i = tid / kBK + r * (256 / kBK); }
-            int gi = row0 + i, gk = k0 + kk;
-            double v = 0.0;
-            if (gi < m && gk < k) v = TA ? A[cm(gk, gi, lda)] : A[cm(gi, gk, lda)];
-            ra[r] = v;
+                for (int r = 0; r < A_PER; ++r) {
+                    const int kk = tid % kBK, i = tid / kBK + r * (256 / kBK);
+                    const int gi = row0 + i, gk = k0 + kk;
+                    ra[r] = (gi < m && gk < k) ? A[cm(kofs + gk, gi, lda)] : 0.0;
+                }
+            } else {
+                at = false;
+                const bool cross = c0 + kBK > row0;
+#pragma unroll
+                for (int r = 0; r < A_PER; ++r) {
+                    const int i = tid % BM, kk = tid / BM + r * (256 / BM);
+                    const int gi = row0 + i, gk = k0 + kk, gc = kofs + gk;
+                    double v = 0.0;
+                    if (gi < m && gk < k) v = (!cross || gc <= gi) ? A[cm(gi, gc, lda)] : A[cm(gc, gi, lda)];
+                    ra[r] = v;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < A_PER; ++r) {
+                int i, kk;
+                if (!TA) { i = tid % BM; kk = tid / BM + r * (256 / BM); }
+                else     { kk = tid % kBK; i = tid / kBK + r * (256 / kBK); }
+                int gi = row0 + i, gk = k0 + kk;
+                double v = 0.0;
+                if (gi < m && gk < k) v = TA ? A[cm(gk, gi, lda)] : A[cm(gi, gk, lda)];
+                ra[r] = v;
+            }
         }
 #pragma unroll
         for (int r = 0; r < B_PER; ++r) {
@@ -81,12 +133,17 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double 
         }
     };
     auto store_slice = [&]() {
+        if (AM == kOpSymLower && at) {
 #pragma unroll
-        for (int r = 0; r < A_PER; ++r) {
-            int i, kk;
-            if (!TA) { i = tid % BM; kk = tid / BM + r * (256 / BM); }
-            else     { kk = tid % kBK; i = tid / kBK + r * (256 / kBK); }
-            As[kk][i] = ra[r];
+            for (int r = 0; r < A_PER; ++r) As[tid % kBK][tid / kBK + r * (256 / kBK)] = ra[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < A_PER; ++r) {
+                int i, kk;
+                if (!TA) { i = tid % BM; kk = tid / BM + r * (256 / BM); }
+                else     { kk = tid % kBK; i = tid / kBK + r * (256 / kBK); }
+                As[kk][i] = ra[r];
+            }
         }
 #pragma unroll
         for (int r = 0; r < B_PER; ++r) {
@@ -164,7 +221,24 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double 
     }
 }
 
-template <int BM, int BN, bool TA, bool TB>
+constexpr int shape_index(int BM, int BN)
+{
+    return BM == 128 ? (BN == 128 ? 0 : 1) : (BN == 64 ? 2 : 3);
+}
+
+// Algorithmic flops of one product: 2 m n k, restricted to the lower
+// triangle (i >= j) of C when uplo is set.
+double product_flops(int m, int n, int k, int uplo)
+{
+    double entries = (double)m * n;
+    if (uplo) {
+        const double nn = std::min(m, n);
+        entries = nn * (nn + 1) / 2 + (double)(m - nn) * nn;
+    }
+    return 2.0 * entries * k;
+}
+
+template <int BM, int BN, int AM, bool TB>
 void launch_gemm(hipStream_t st, int m, int n, int k, double alpha, const double* A, int lda,
                  const double* B, int ldb, double beta, double* C, int ldc, int uplo, int nsplit,
                  int kper, size_t cstride)
@@ -172,10 +246,19 @@ void launch_gemm(hipStream_t st, int m, int n, int k, double alpha, const double
     int tiles_m = (m + BM - 1) / BM;
     int tiles_n = (n + BN - 1) / BN;
     int ntiles = tiles_m * tiles_n;
+    if (uplo) {
+        ntiles = 0;
+        for (int tn = 0; tn < tiles_n; ++tn) ntiles += std::max(0, tiles_m - (tn * BN) / BM);
+        if (ntiles == 0) return;
+    }
     int per = (ntiles + 7) / 8;
     dim3 grid(per * 8, nsplit), block(256);
-    hipLaunchKernelGGL((dgemm_kernel<BM, BN, TA, TB>), grid, block, 0, st, m, n, k, alpha, A, lda,
-                       B, ldb, beta, C, ldc, uplo, tiles_m, per, kper, cstride);
+    const int slot = launch_probe::begin(st);
+    hipLaunchKernelGGL((dgemm_kernel<BM, BN, AM, TB>), grid, block, 0, st, m, n, k, alpha, A, lda,
+                       B, ldb, beta, C, ldc, uplo, tiles_m, ntiles, per, kper, cstride);
+    if (slot >= 0)
+        launch_probe::end(st, slot, shape_index(BM, BN) * 6 + AM * 2 + (TB ? 1 : 0),
+                          product_flops(m, n, k, uplo));
 }
 
 template <int BM, int BN>
@@ -184,15 +267,21 @@ void dispatch_t(hipStream_t st, char ta, char tb, int m, int n, int k, double al
                 int ldc, int uplo, int nsplit = 1, int kper = 0, size_t cstride = 0)
 {
     if (nsplit <= 1) { nsplit = 1; kper = k; cstride = 0; }
-    bool TA = (ta == 'T' || ta == 't'), TB = (tb == 'T' || tb == 't');
-    if (!TA && !TB)
-        launch_gemm<BM, BN, false, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+    const bool TA = (ta == 'T' || ta == 't'), SY = (ta == 'S' || ta == 's'), TB = (tb == 'T' || tb == 't');
+    if (SY && TB) {
+        std::fprintf(stderr, "dgemm: symmetric A needs op(B) = B\n");
+        return;
+    }
+    if (SY)
+        launch_gemm<BM, BN, kOpSymLower, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+    else if (!TA && !TB)
+        launch_gemm<BM, BN, kOpN, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
     else if (!TA && TB)
-        launch_gemm<BM, BN, false, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        launch_gemm<BM, BN, kOpN, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
     else if (TA && !TB)
-        launch_gemm<BM, BN, true, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        launch_gemm<BM, BN, kOpT, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
     else
-        launch_gemm<BM, BN, true, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        launch_gemm<BM, BN, kOpT, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
 }
 
 // C = alpha * sum_s P_s + beta * C, partials summed in split order.
@@ -292,6 +381,121 @@ __global__ void tn_small_reduce(int m, int n, int nchunks, double alpha, const d
 }
 
 }  // namespace
+
+namespace launch_probe {
+namespace {
+constexpr int kSlots = 16384;
+constexpr int kIds = 24;
+struct State {
+    bool on = false;
+    std::vector<hipEvent_t> ev;   // 2 per slot
+    std::vector<int> id;
+    std::vector<double> flops;
+    int used = 0;
+    int launches[kIds] = {};
+    double ms[kIds] = {};
+    double fl[kIds] = {};
+};
+State& state()
+{
+    static State s;
+    return s;
+}
+const char* kNames[kIds] = {
+    "dgemm_kernel<128,128,0,false>",
+    "dgemm_kernel<128,128,0,true>",
+    "dgemm_kernel<128,128,1,false>",
+    "dgemm_kernel<128,128,1,true>",
+    "dgemm_kernel<128,128,2,false>",
+    "dgemm_kernel<128,128,2,true>",
+    "dgemm_kernel<128,64,0,false>",
+    "dgemm_kernel<128,64,0,true>",
+    "dgemm_kernel<128,64,1,false>",
+    "dgemm_kernel<128,64,1,true>",
+    "dgemm_kernel<128,64,2,false>",
+    "dgemm_kernel<128,64,2,true>",
+    "dgemm_kernel<64,64,0,false>",
+    "dgemm_kernel<64,64,0,true>",
+    "dgemm_kernel<64,64,1,false>",
+    "dgemm_kernel<64,64,1,true>",
+    "dgemm_kernel<64,64,2,false>",
+    "dgemm_kernel<64,64,2,true>",
+    "dgemm_kernel<64,128,0,false>",
+    "dgemm_kernel<64,128,0,true>",
+    "dgemm_kernel<64,128,1,false>",
+    "dgemm_kernel<64,128,1,true>",
+    "dgemm_kernel<64,128,2,false>",
+    "dgemm_kernel<64,128,2,true>",
+};
+}  // namespace
+
+void enable(bool on)
+{
+    State& s = state();
+    if (on && s.ev.empty()) {
+        s.ev.resize(2 * kSlots, nullptr);
+        for (auto& e : s.ev)
+            if (hipEventCreate(&e) != hipSuccess) { e = nullptr; }
+        s.id.assign(kSlots, 0);
+        s.flops.assign(kSlots, 0.0);
+    }
+    s.on = on;
+}
+
+bool enabled() { return state().on; }
+
+int begin(hipStream_t st)
+{
+    State& s = state();
+    if (!s.on || s.used >= kSlots || !s.ev[2 * s.used] || !s.ev[2 * s.used + 1]) return -1;
+    const int slot = s.used++;
+    (void)hipEventRecord(s.ev[2 * slot], st);
+    return slot;
+}
+
+void end(hipStream_t st, int slot, int kernel_id, double flops)
+{
+    State& s = state();
+    (void)hipEventRecord(s.ev[2 * slot + 1], st);
+    s.id[slot] = kernel_id;
+    s.flops[slot] = flops;
+}
+
+void harvest()
+{
+    State& s = state();
+    for (int q = 0; q < s.used; ++q) {
+        float t = 0.f;
+        if (hipEventSynchronize(s.ev[2 * q + 1]) != hipSuccess) continue;
+        if (hipEventElapsedTime(&t, s.ev[2 * q], s.ev[2 * q + 1]) != hipSuccess) continue;
+        const int k = s.id[q];
+        s.launches[k] += 1;
+        s.ms[k] += t;
+        s.fl[k] += s.flops[q];
+    }
+    s.used = 0;
+}
+
+void reset_totals()
+{
+    State& s = state();
+    for (int k = 0; k < kIds; ++k) { s.launches[k] = 0; s.ms[k] = 0.0; s.fl[k] = 0.0; }
+}
+
+bool dominant(int* launches, double* ms, double* flops, const char** name)
+{
+    State& s = state();
+    int best = -1;
+    for (int k = 0; k < kIds; ++k)
+        if (s.launches[k] > 0 && (best < 0 || s.ms[k] > s.ms[best])) best = k;
+    if (best < 0) return false;
+    *launches = s.launches[best];
+    *ms = s.ms[best];
+    *flops = s.fl[best];
+    *name = kNames[best];
+    return true;
+}
+}  // namespace launch_probe
 
 void dgemm(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha, const double* A,
            int lda, const double* B, int ldb, double beta, double* C, int ldc, int uplo)

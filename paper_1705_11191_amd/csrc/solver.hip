@@ -2,6 +2,8 @@
 // (below) the eigensolver / density-matrix entry points.
 #include "api_internal.h"
 
+#include <cstdio>
+
 #include <algorithm>
 #include <cstring>
 
@@ -219,6 +221,22 @@ static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L
     tm.mark(ELSI_GPU_ST_BACKSUB);
 }
 
+// Fold the launch timings of the finished call into the info record.
+static void harvest_launch_probe(elsi_gpu_handle_s* h)
+{
+    if (!launch_probe::enabled()) return;
+    launch_probe::harvest();
+    int nl = 0;
+    double ms = 0.0, fl = 0.0;
+    const char* name = "";
+    if (launch_probe::dominant(&nl, &ms, &fl, &name)) {
+        h->info.probe_launches = nl;
+        h->info.probe_ms = ms;
+        h->info.probe_flops = fl;
+        std::snprintf(h->info.probe_kernel, sizeof(h->info.probe_kernel), "%s", name);
+    }
+}
+
 static int read_flags(hipStream_t st, char* ws, const Layout& L)
 {
     int f[4] = {0, 0, 0, 0};
@@ -260,6 +278,7 @@ int elsi_gpu_ev(elsi_gpu_handle h, double* H, double* S, double* eval, double* e
     rc = sync_status(st);
     if (rc) return rc;
     tm.finish(&h->info);
+    harvest_launch_probe(h);
     return read_flags(st, ws, L);
 }
 
@@ -311,6 +330,7 @@ int elsi_gpu_dm(elsi_gpu_handle h, double* H, double* S, double* occ, double* D,
     rc = sync_status(st);
     if (rc) return rc;
     tm.finish(&h->info);
+    harvest_launch_probe(h);
     *energy = hs[3];
     if (mu) *mu = hs[0];
     h->info.mu = hs[0];

@@ -7,7 +7,9 @@
 // receives the two-sided block update Q^T A22 Q with Q = I - V T V^T:
 //     Y = A22 V,  X = Y T,  W = X - 1/2 V (T^T (V^T X)),
 //     A22 <- A22 - V W^T - W V^T,
-// all as FP64 matrix-core products (A22 is kept full symmetric).
+// all as FP64 matrix-core products.  Only the lower triangle of A22 is read
+// (Y by a symmetric product) and updated (the rank-2b update skips tiles
+// above the diagonal).
 //
 // The panel QR uses one kernel launch per column.  A reflector for column c
 // needs x = P(c:m, c) only through x^T P(c:m, r) (r >= c), so each launch
@@ -358,7 +360,8 @@ size_t sy2sb_workspace_doubles(int n, int b)
     return w;
 }
 
-// A (n x n, full symmetric) -> band in Bd (ldbd = 2b rows), reflectors in
+// A (n x n symmetric, lower triangle read; the strict upper part is left
+// stale) -> band in Bd (ldbd = 2b rows), reflectors in
 // Vall (n x n, ld n: panel p occupies rows j+b.., columns j..j+b-1) and
 // T factors in Tall (b x b per panel).
 void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, double* Tall, double* Bd,
@@ -426,9 +429,9 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
         dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, V, n, 0.0, Gv, 64, part, npart);
         hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(64), 0, st, bw, Gv, 64, tau, T, b);
 
-        // two-sided update of A22 (full symmetric)
+        // two-sided update of A22; only its lower triangle is read and kept
         double* A22 = A + cm(r0, r0, lda);
-        dgemm_splitk(st, 'N', 'N', m, bw, m, 1.0, A22, lda, V, n, 0.0, Y, m, part, npart);
+        dgemm_splitk(st, 'S', 'N', m, bw, m, 1.0, A22, lda, V, n, 0.0, Y, m, part, npart);
         dgemm(st, 'N', 'N', m, bw, bw, 1.0, Y, m, T, b, 0.0, X, m);
         dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, X, m, 0.0, Z, 64, part, npart);
         dgemm(st, 'T', 'N', bw, bw, bw, 1.0, T, b, Z, 64, 0.0, U, 64);
@@ -437,7 +440,7 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
         copy_matrix(st, m, bw, X, m, VW + (size_t)m * bw, m);
         copy_matrix(st, m, bw, X, m, WV, m);
         copy_matrix(st, m, bw, V, n, WV + (size_t)m * bw, m);
-        dgemm(st, 'N', 'T', m, m, 2 * bw, -1.0, VW, m, WV, m, 1.0, A22, lda);
+        dgemm(st, 'N', 'T', m, m, 2 * bw, -1.0, VW, m, WV, m, 1.0, A22, lda, 1);
     }
     hipLaunchKernelGGL(extract_band_kernel, dim3(n), dim3(ldbd), 0, st, n, b, A, lda, Bd, ldbd);
 }

@@ -56,6 +56,27 @@ def test_dgemm_all_transposes(ta, tb, m, n, k):
     assert np.abs(got - ref).max() <= tol
 
 
+@pytest.mark.parametrize("m,n", [(1, 1), (63, 64), (130, 70), (300, 64), (517, 33), (1030, 64)])
+def test_dgemm_symmetric_lower(m, n):
+    """op(A) = the symmetric matrix held in A's lower triangle; the strict upper
+    triangle holds NaN and must never be read."""
+    from paper_1705_11191_amd import binding as B
+
+    rng = np.random.default_rng(m + 11 * n)
+    G = rng.standard_normal((m, m))
+    Asym = G + G.T
+    A = np.tril(Asym) + np.triu(np.full((m, m), np.nan), 1)
+    Bm = rng.standard_normal((m, n))
+    C0 = rng.standard_normal((m, n))
+    ref = 0.7 * Asym @ Bm - 1.3 * C0
+    C = _fortran(C0)
+    B.dgemm("S", "N", _fortran(A), _fortran(Bm), C, alpha=0.7, beta=-1.3)
+    got = C.cpu().numpy()
+    tol = 4 * m * EPS * (np.abs(Asym) @ np.abs(Bm)).max() + 8 * EPS * np.abs(C0).max()
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - ref).max() <= tol
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 130, 257, 300, 513])
 def test_cholesky_vs_oracle(n):
     from paper_1705_11191_amd import binding as B
