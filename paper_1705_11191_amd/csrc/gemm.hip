@@ -2,9 +2,12 @@
 //
 // One workgroup of 256 threads (4 wave64s arranged 2 x 2) computes a BM x BN
 // tile of C; each wave owns a (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA
-// blocks kept in accumulator registers.  K advances in steps of 16: the next
+// blocks kept in accumulator registers.  K advances in slices of 16: the next
 // A and B slices are fetched from HBM into registers while the current ones
-// are multiplied out of LDS.  Workgroups are renumbered so that each of the
+// are multiplied out of LDS.  The kernel is held to 256 VGPRs so that two
+// workgroups share a CU (one's barriers and LDS stores hide behind the
+// other's matrix-core work); the epilogue reads C one 16-row block at a time
+// for the same reason.  Workgroups are renumbered so that each of the
 // eight XCDs walks a contiguous range of tiles (its L2 then holds the shared
 // operand panels).
 #include "common.h"
@@ -15,7 +18,7 @@
 namespace eg {
 namespace {
 
-constexpr int kBK = 32;
+constexpr int kBK = 16;
 
 // Operand modes of A: op(A) = A, op(A) = A^T, or op(A) = the symmetric matrix
 // whose lower triangle A holds (m == k; the strict upper part of A is never read).
@@ -24,7 +27,7 @@ constexpr int kOpN = 0, kOpT = 1, kOpSymLower = 2;
 // blockIdx.y selects a K range of length kper when the product is split over
 // K: that slice's partial product goes to C + blockIdx.y * cstride.
 template <int BM, int BN, int AM, bool TB>
-__global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double alpha,
+__global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, double alpha,
                                                     const double* __restrict__ A, int lda,
                                                     const double* __restrict__ B, int ldb,
                                                     double beta, double* C, int ldc, int uplo,
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double 
 
     // D layout of the 16x16 f64 MFMA: lane l, element r holds D(4r + l/16, l%16);
     // D is the transposed block, so that is C(row l%16, column 4r + l/16).
-    // All C loads of a lane are issued before any store so that they overlap.
+    // The C loads of one 16-row block are all issued before its stores so that they overlap.
     const int rbase = row0 + wm * WM + (lane & 15);
     const int cbase = col0 + wn * WN + (lane >> 4);
     const bool interior = (row0 + BM <= m) && (col0 + BN <= n) && !(uplo && col0 + BN - 1 > row0);
@@ -189,25 +192,24 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int m, int n, int k, double 
         return interior || (gr < m && gc < n && !(uplo && gr < gc));
     };
     if (beta != 0.0) {
-        double cv[FM][FN][4];
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * 4;
-                    cv[i][j][r] = valid(gr, gc) ? C[cm(gr, gc, ldc)] : 0.0;
-                }
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i) {
+            double cv[FN][4];
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int gr = rbase + i * 16, gc = cbase + j * 16 + r * 4;
-                    if (valid(gr, gc)) C[cm(gr, gc, ldc)] = alpha * acc[i][j][r] + beta * cv[i][j][r];
+                    cv[j][r] = valid(gr, gc) ? C[cm(gr, gc, ldc)] : 0.0;
                 }
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * 4;
+                    if (valid(gr, gc)) C[cm(gr, gc, ldc)] = alpha * acc[i][j][r] + beta * cv[j][r];
+                }
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < FM; ++i)
