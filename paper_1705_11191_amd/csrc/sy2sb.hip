@@ -182,13 +182,23 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
         const int rin = ((c + 2) & 1) * 64;
         const int rout = ((c + 1) & 1) * 64;
         if (c >= 0) {
-            for (int r = tid; r <= BMAX; r += PR) {
-                if ((r >= c && r < bw) || r == BMAX) {
-                    double s = 0.0;
+            // sum the per-block records: wave w takes blocks w, w+4, ..., lane r entry r
+            {
+                double s = 0.0, st = 0.0;
+                const bool need = lane >= c && lane < bw;
 #pragma unroll 8
-                    for (int b = 0; b < nblk; ++b) s += bld(grs, gin + b * GS + r);
-                    G[r] = s;
+                for (int b = wave; b < nblk; b += PR / 64) {
+                    if (need) s += bld(grs, gin + b * GS + lane);
+                    if (lane == 0) st += bld(grs, gin + b * GS + BMAX);
                 }
+                red[wave][lane] = s;
+                if (lane == 0) red[wave][BMAX] = st;
+            }
+            __syncthreads();
+            if (tid <= BMAX) {
+                double s = 0.0;
+                for (int w = 0; w < PR / 64; ++w) s += red[w][tid];
+                G[tid] = s;
             }
             __syncthreads();
             if (tid == 0) {
@@ -227,14 +237,25 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
 #pragma unroll
             for (int r = 0; r < BMAX; ++r) if (r == cn) xn = rowv[r];
             if (!(i < m && i >= cn)) xn = 0.0;
-#pragma unroll
-            for (int r = 0; r < BMAX; ++r) {
-                if (r >= cn && r < bw) {
-                    double s = wave_sum(xn * rowv[r]);
-                    if (lane == 0) red[wave][r] = s;
-                }
-            }
+            // Gram row of column cn over the wave's rows by a butterfly
+            // transpose-reduction: after the step with offset h a lane keeps the
+            // half of its partial sums selected by lane bit h, so that at the end
+            // lane l holds the wave total of entry l
             {
+                double v[BMAX];
+#pragma unroll
+                for (int r = 0; r < BMAX; ++r) v[r] = (r >= cn && r < bw) ? xn * rowv[r] : 0.0;
+#pragma unroll
+                for (int h = BMAX / 2; h >= 1; h >>= 1) {
+                    const bool up = (lane & h) != 0;
+#pragma unroll
+                    for (int j = 0; j < h; ++j) {
+                        const double send = up ? v[j] : v[j + h];
+                        const double keep = up ? v[j + h] : v[j];
+                        v[j] = keep + __shfl_xor(send, h, 64);
+                    }
+                }
+                red[wave][lane] = v[0];
                 double tl = (i > cn && i < m) ? xn * xn : 0.0;
                 double s = wave_sum(tl);
                 if (lane == 0) red[wave][BMAX] = s;

@@ -155,6 +155,7 @@ def test_dm_config0_vs_oracle():
     h.close()
     D = D.cpu().numpy()
     ev = ev.cpu().numpy()
+    f = f.cpu().numpy()
     assert st == 0
     assert _gate_eigs(ev, ref["eval"]) <= 1e-10
     assert np.abs(D - ref["D"]).max() <= 1e-9
@@ -162,7 +163,17 @@ def test_dm_config0_vs_oracle():
     assert abs(mu - ref["mu"]) <= 1e-9
     assert abs(energy - ref["energy"]) <= 1e-9
     assert abs(np.trace(D @ sp.S) - sp.n_occ) <= 1e-10
-    assert info["k_s"] == int(np.sum(ref["occ"] > 1e-20))
+    assert np.abs(f - ref["occ"]).max() <= 1e-12
+    # k_s counts f > 1e-20 after the charge fix-up, which removes a surplus of
+    # order occ_accuracy from the top states down: states occupied below that
+    # level are kept or dropped by rounding, so k_s is bracketed by the states
+    # the fix-up cannot remove (f > occ_accuracy) and those with a Fermi-Dirac
+    # occupation above the cut before it
+    assert info["k_s"] == int(np.sum(f > 1e-20))
+    x = (ref["eval"] - ref["mu"]) / sp.kT
+    k_hi = int(np.sum(x < -math.log(1e-20)))
+    k_lo = int(np.sum(ref["occ"] > 1e-13))
+    assert k_lo <= info["k_s"] <= k_hi
 
 
 def test_dm_explicit_integer_occupations_idempotent():
