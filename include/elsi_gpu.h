@@ -169,6 +169,51 @@ int elsi_gpu_ev(elsi_gpu_handle h, double *H, double *S, double *eval, double *e
 int elsi_gpu_dm(elsi_gpu_handle h, double *H, double *S, double *occ, double *D,
                 double *eval, double *energy, double *mu);
 
+/* ------------------------------------------------------------------------
+ * Batched calls: many independent problems of uneven size in one call, the
+ * way ELSI treats k-points and spin channels as independent eigenproblems
+ * (Sec. 4.3, parallel modes).  The handle supplies the settings (occupation
+ * scheme and parameters, band width, overlap flags); its n_basis, n_state and
+ * n_electron are not used.  Problem p has its own column-major device arrays
+ * with ld = n[p].  A pool of host worker threads (elsi_gpu_set_batch_workers,
+ * default 4), each with its own stream and device workspace (allocated for
+ * the duration of the call), solves the problems largest first, so that the
+ * kernels of different problems overlap on the device.  The caller's stream
+ * is synchronized before the problems start; every output is complete when
+ * the call returns.  status[p] (host) receives the return code of problem p
+ * as its single-problem call would give it; a failing problem does not stop
+ * the others.  Returns 0 when every problem succeeded, else the status of
+ * the lowest-index failing problem; negative codes name a bad argument (-3
+ * also covers a bad entry of a per-problem array).
+ * ------------------------------------------------------------------------ */
+
+/* Worker threads of the batched calls, 1 <= workers <= 16.
+ * Errors: -1 handle, -2 workers. */
+int elsi_gpu_set_batch_workers(elsi_gpu_handle h, int workers);
+
+/* elsi_gpu_ev for count problems: n[p] basis functions, the n_state[p]
+ * lowest eigenpairs into eval[p] (n[p] doubles) and evec[p] (n[p] x
+ * n_state[p]); H[p] destroyed, S[p] receives L (S may be NULL with the unit
+ * overlap flag).  Errors: -1 handle, -2 count < 0, -3 n or a per-problem
+ * entry, -4 n_state, -5 H, -6 S, -7 eval, -8 evec, -9 status. */
+int elsi_gpu_ev_batched(elsi_gpu_handle h, int count, const int *n, const int *n_state,
+                        double *const *H, double *const *S, double *const *eval,
+                        double *const *evec, int *status);
+
+/* elsi_gpu_dm for count problems with Fermi-Dirac occupations (the handle's
+ * scheme must be ELSI_GPU_OCC_FERMI) and an independent chemical potential
+ * per problem (Eq. (18) per problem): D[p] (n[p] x n[p], both triangles),
+ * eval[p] (may be NULL, or eval itself NULL), energy[p] and mu[p] (host
+ * arrays; mu may be NULL).  kweight must be NULL: a chemical potential shared
+ * across problems with k-point weights is not provided.
+ * Errors: -1 handle or explicit occupation scheme, -2 count < 0, -3 n or a
+ * per-problem entry, -4 n_electron, -5 kweight not NULL, -6 H, -7 S, -8 D,
+ * -10 energy, -12 status. */
+int elsi_gpu_dm_batched(elsi_gpu_handle h, int count, const int *n, const double *n_electron,
+                        const double *kweight, double *const *H, double *const *S,
+                        double *const *D, double *const *eval, double *energy, double *mu,
+                        int *status);
+
 /* Timings and diagnostics of the last ev/dm call. */
 int elsi_gpu_get_info(elsi_gpu_handle h, elsi_gpu_info *out);
 

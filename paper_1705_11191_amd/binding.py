@@ -49,6 +49,14 @@ class Info(ctypes.Structure):
         return d
 
 
+def _ptrs(tensors):
+    """Host array of device pointers (double *const *)."""
+    arr = (ctypes.c_void_p * len(tensors))()
+    for q, t in enumerate(tensors):
+        arr[q] = t.data_ptr()
+    return arr
+
+
 def lib():
     """Load libelsi_gpu.so (fails loudly when it has not been built)."""
     global _lib
@@ -68,6 +76,10 @@ def lib():
         L.elsi_gpu_set_overlap_factored.argtypes = [vp, i]
         L.elsi_gpu_set_band_width.argtypes = [vp, i]
         L.elsi_gpu_set_launch_timing.argtypes = [vp, i]
+        L.elsi_gpu_set_batch_workers.argtypes = [vp, i]
+        pp, ip, dp = ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(d)
+        L.elsi_gpu_ev_batched.argtypes = [vp, i, ip, ip, pp, pp, pp, pp, ip]
+        L.elsi_gpu_dm_batched.argtypes = [vp, i, ip, dp, dp, pp, pp, pp, pp, dp, dp, ip]
         L.elsi_gpu_ev.argtypes = [vp, vp, vp, vp, vp]
         L.elsi_gpu_dm.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d)]
         L.elsi_gpu_get_info.argtypes = [vp, ctypes.POINTER(Info)]
@@ -275,6 +287,38 @@ class Handle:
                                ctypes.byref(energy), ctypes.byref(mu))
         _check(rc, "elsi_gpu_dm", ok=ok)
         return D, ev, f, energy.value, mu.value, rc
+
+    def set_batch_workers(self, workers: int):
+        _check(lib().elsi_gpu_set_batch_workers(self._h, workers), "set_batch_workers")
+
+    def ev_batched(self, Hs, Ss, n_states, ok=(0,)):
+        """Batched eigenpairs: returns (evals, evecs column-major, per-problem status, rc)."""
+        count = len(Hs)
+        n = [int(H.shape[0]) for H in Hs]
+        evals = [torch.empty(m, device=Hs[0].device, dtype=torch.float64) for m in n]
+        evecs = [fortran_empty(m, int(k), device=Hs[0].device) for m, k in zip(n, n_states)]
+        status = (ctypes.c_int * count)()
+        rc = lib().elsi_gpu_ev_batched(
+            self._h, count, (ctypes.c_int * count)(*n), (ctypes.c_int * count)(*[int(k) for k in n_states]),
+            _ptrs(Hs), _ptrs(Ss) if Ss is not None else None, _ptrs(evals), _ptrs(evecs), status)
+        _check(rc, "elsi_gpu_ev_batched", ok=ok)
+        return evals, evecs, list(status), rc
+
+    def dm_batched(self, Hs, Ss, n_electrons, ok=(0,)):
+        """Batched density matrices (independent mu per problem): returns
+        (Ds, evals, energies, mus, per-problem status, rc)."""
+        count = len(Hs)
+        n = [int(H.shape[0]) for H in Hs]
+        Ds = [torch.empty((m, m), device=Hs[0].device, dtype=torch.float64) for m in n]
+        evals = [torch.empty(m, device=Hs[0].device, dtype=torch.float64) for m in n]
+        energy = (ctypes.c_double * count)()
+        mu = (ctypes.c_double * count)()
+        status = (ctypes.c_int * count)()
+        rc = lib().elsi_gpu_dm_batched(
+            self._h, count, (ctypes.c_int * count)(*n), (ctypes.c_double * count)(*[float(x) for x in n_electrons]),
+            None, _ptrs(Hs), _ptrs(Ss) if Ss is not None else None, _ptrs(Ds), _ptrs(evals), energy, mu, status)
+        _check(rc, "elsi_gpu_dm_batched", ok=ok)
+        return Ds, evals, list(energy), list(mu), list(status), rc
 
     def info(self) -> dict:
         inf = Info()

@@ -1,0 +1,177 @@
+// Many independent eigenproblems in one call (ELSI paper, Sec. 4.3: k-points
+// and spin channels are independent problems that ELSI distributes over
+// process groups; here they share one GPU).
+//
+// A pool of host worker threads, each with its own non-blocking stream and its
+// own workspace, takes problems largest first (longest-processing-time order)
+// and runs the single-problem driver on them, so that the many small kernels of
+// small problems overlap on the device.  Kernels whose workgroups wait on each
+// other pass a gate while a batch is active (one at a time on the device), and
+// the panel factorization of step (1) takes its per-column path, so that no two
+// waiting kernels can hold the device between them.
+#include "api_internal.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <thread>
+#include <vector>
+
+namespace eg {
+namespace {
+
+std::atomic<int> g_batch_depth{0};
+std::mutex g_persistent_mu;
+
+struct BatchDepth {
+    BatchDepth() { g_batch_depth.fetch_add(1); }
+    ~BatchDepth() { g_batch_depth.fetch_sub(1); }
+};
+
+// Worker-local copy of the caller's handle: settings shared, stream and
+// workspace private.
+elsi_gpu_handle_s worker_handle(const elsi_gpu_handle_s* proto, hipStream_t st)
+{
+    elsi_gpu_handle_s w;
+    w.dtype = proto->dtype;
+    w.occ_scheme = proto->occ_scheme;
+    w.kT = proto->kT;
+    w.occ_accuracy = proto->occ_accuracy;
+    w.mu_max_steps = proto->mu_max_steps;
+    w.spin = proto->spin;
+    w.overlap_is_unit = proto->overlap_is_unit;
+    w.overlap_factored = proto->overlap_factored;
+    w.band_width = proto->band_width;
+    w.batch_workers = 1;
+    w.stream = st;
+    std::memset(&w.info, 0, sizeof(w.info));
+    return w;
+}
+
+// Run fn(worker handle, problem index) over all problems with the pool.
+template <typename Fn>
+int run_pool(elsi_gpu_handle_s* h, int count, const int* n, int* status, Fn fn)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return kStatusHip;
+    // the caller's inputs must be complete before other streams read them
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return kStatusHip;
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+    std::atomic<int> next{0};
+    const int nworkers = std::max(1, std::min(h->batch_workers, count));
+    BatchDepth depth;
+    auto work = [&]() {
+        (void)hipSetDevice(dev);
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (int q = next.fetch_add(1); q < count; q = next.fetch_add(1)) status[order[q]] = kStatusHip;
+            return;
+        }
+        elsi_gpu_handle_s w = worker_handle(h, st);
+        for (int q = next.fetch_add(1); q < count; q = next.fetch_add(1)) status[order[q]] = fn(&w, order[q]);
+        release_workspace(&w);
+        (void)hipStreamDestroy(st);
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nworkers; ++t) pool.emplace_back(work);
+    work();
+    for (auto& t : pool) t.join();
+    for (int p = 0; p < count; ++p)
+        if (status[p] != 0) return status[p];
+    return 0;
+}
+
+}  // namespace
+
+bool batch_mode_active() { return g_batch_depth.load(std::memory_order_relaxed) > 0; }
+
+bool persistent_enter()
+{
+    if (!batch_mode_active()) return false;
+    g_persistent_mu.lock();
+    return true;
+}
+
+void persistent_leave(hipStream_t st, bool entered)
+{
+    if (!entered) return;
+    (void)hipStreamSynchronize(st);
+    g_persistent_mu.unlock();
+}
+
+}  // namespace eg
+
+using namespace eg;
+
+extern "C" {
+
+int elsi_gpu_set_batch_workers(elsi_gpu_handle h, int workers)
+{
+    if (!h) return -1;
+    if (workers < 1 || workers > 16) return -2;
+    h->batch_workers = workers;
+    return 0;
+}
+
+int elsi_gpu_ev_batched(elsi_gpu_handle h, int count, const int* n, const int* n_state, double* const* H,
+                        double* const* S, double* const* eval, double* const* evec, int* status)
+{
+    if (!h) return -1;
+    if (count < 0) return -2;
+    if (count == 0) return 0;
+    if (!n) return -3;
+    if (!n_state) return -4;
+    if (!H) return -5;
+    if (!S && !h->overlap_is_unit) return -6;
+    if (!eval) return -7;
+    if (!evec) return -8;
+    if (!status) return -9;
+    for (int p = 0; p < count; ++p)
+        if (n[p] < 1 || n_state[p] < 1 || n_state[p] > n[p] || !H[p] || (!h->overlap_is_unit && !S[p]) ||
+            !eval[p] || !evec[p])
+            return -3;
+    return run_pool(h, count, n, status, [&](elsi_gpu_handle_s* w, int p) {
+        w->n = n[p];
+        w->n_state = n_state[p];
+        w->n_electron = 0.0;
+        return elsi_gpu_ev(w, H[p], S ? S[p] : nullptr, eval[p], evec[p]);
+    });
+}
+
+int elsi_gpu_dm_batched(elsi_gpu_handle h, int count, const int* n, const double* n_electron,
+                        const double* kweight, double* const* H, double* const* S, double* const* D,
+                        double* const* eval, double* energy, double* mu, int* status)
+{
+    if (!h) return -1;
+    if (h->occ_scheme != ELSI_GPU_OCC_FERMI) return -1;
+    if (count < 0) return -2;
+    if (count == 0) return 0;
+    if (!n) return -3;
+    if (!n_electron) return -4;
+    if (kweight) return -5;
+    if (!H) return -6;
+    if (!S && !h->overlap_is_unit) return -7;
+    if (!D) return -8;
+    if (!energy) return -10;
+    if (!status) return -12;
+    for (int p = 0; p < count; ++p)
+        if (n[p] < 1 || !(n_electron[p] >= 0.0) || n_electron[p] > 2.0 * n[p] || !H[p] ||
+            (!h->overlap_is_unit && !S[p]) || !D[p])
+            return -3;
+    return run_pool(h, count, n, status, [&](elsi_gpu_handle_s* w, int p) {
+        w->n = n[p];
+        w->n_state = n[p];
+        w->n_electron = n_electron[p];
+        double e = 0.0, m = 0.0;
+        const int rc = elsi_gpu_dm(w, H[p], S ? S[p] : nullptr, nullptr, D[p], eval ? eval[p] : nullptr, &e, &m);
+        energy[p] = e;
+        if (mu) mu[p] = m;
+        return rc;
+    });
+}
+
+}  // extern "C"

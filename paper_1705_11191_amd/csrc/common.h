@@ -40,6 +40,15 @@ __host__ __device__ inline size_t cm(int i, int j, int ld) {
 // host-side launchers implemented in the .hip files
 // ---------------------------------------------------------------------------
 
+// Batched calls run several problems at once from host worker threads on
+// their own streams.  While such a call is active, kernels whose workgroups
+// wait on one another (persistent cooperative kernels) are admitted to the
+// device one at a time: enter() takes the gate, leave() waits for the kernel
+// on its stream and releases it.  Outside batched calls both are no-ops.
+bool batch_mode_active();
+bool persistent_enter();
+void persistent_leave(hipStream_t st, bool entered);
+
 // Optional device timing of individual launches (off by default).  While it is
 // enabled, the GEMM launchers bracket every launch with a pair of events on the
 // launch stream and record the launch's algorithmic flops under the id of the

@@ -13,6 +13,7 @@
 #include "common.h"
 
 #include <cstdio>
+#include <mutex>
 #include <vector>
 
 namespace eg {
@@ -389,6 +390,7 @@ namespace {
 constexpr int kSlots = 16384;
 constexpr int kIds = 24;
 struct State {
+    std::mutex mu;   // batched calls launch from several host threads
     bool on = false;
     std::vector<hipEvent_t> ev;   // 2 per slot
     std::vector<int> id;
@@ -449,7 +451,9 @@ bool enabled() { return state().on; }
 int begin(hipStream_t st)
 {
     State& s = state();
-    if (!s.on || s.used >= kSlots || !s.ev[2 * s.used] || !s.ev[2 * s.used + 1]) return -1;
+    if (!s.on) return -1;
+    std::lock_guard<std::mutex> lk(s.mu);
+    if (s.used >= kSlots || !s.ev[2 * s.used] || !s.ev[2 * s.used + 1]) return -1;
     const int slot = s.used++;
     (void)hipEventRecord(s.ev[2 * slot], st);
     return slot;
@@ -458,6 +462,7 @@ int begin(hipStream_t st)
 void end(hipStream_t st, int slot, int kernel_id, double flops)
 {
     State& s = state();
+    std::lock_guard<std::mutex> lk(s.mu);
     (void)hipEventRecord(s.ev[2 * slot + 1], st);
     s.id[slot] = kernel_id;
     s.flops[slot] = flops;
@@ -466,6 +471,7 @@ void end(hipStream_t st, int slot, int kernel_id, double flops)
 void harvest()
 {
     State& s = state();
+    std::lock_guard<std::mutex> lk(s.mu);
     for (int q = 0; q < s.used; ++q) {
         float t = 0.f;
         if (hipEventSynchronize(s.ev[2 * q + 1]) != hipSuccess) continue;
@@ -481,12 +487,14 @@ void harvest()
 void reset_totals()
 {
     State& s = state();
+    std::lock_guard<std::mutex> lk(s.mu);
     for (int k = 0; k < kIds; ++k) { s.launches[k] = 0; s.ms[k] = 0.0; s.fl[k] = 0.0; }
 }
 
 bool dominant(int* launches, double* ms, double* flops, const char** name)
 {
     State& s = state();
+    std::lock_guard<std::mutex> lk(s.mu);
     int best = -1;
     for (int k = 0; k < kIds; ++k)
         if (s.launches[k] > 0 && (best < 0 || s.ms[k] > s.ms[best])) best = k;

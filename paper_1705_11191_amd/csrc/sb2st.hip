@@ -267,7 +267,9 @@ int sb2st(hipStream_t st, int n, int b, double* Bd, int ldb, double* d, double* 
         a.Bd = Bd; a.V2 = V2; a.tau2 = tau2; a.progress = progress; a.err = err;
         a.spin_limit = 1LL << 22;
         void* args[] = {&a};
+        const bool gated = persistent_enter();
         hipError_t rc = hipLaunchCooperativeKernel((const void*)sb2st_kernel, dim3(grid), dim3(SBT), args, 0, st);
+        persistent_leave(st, gated);
         if (rc != hipSuccess) return kStatusHip;
     }
     hipLaunchKernelGGL(extract_tridiag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, Bd, ldb, d, e);

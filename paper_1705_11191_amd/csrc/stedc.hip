@@ -582,7 +582,8 @@ int stedc_values(hipStream_t st, int n, const double* d, const double* e, double
         }
     }
     lev_start.push_back((int)all.size());
-    if (hipMemcpy(mdev, all.data(), sizeof(MergeDesc) * all.size(), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpyAsync(mdev, all.data(), sizeof(MergeDesc) * all.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
         return kStatusHip;
     double* Zin = Z;
     double* Zout = Z2;

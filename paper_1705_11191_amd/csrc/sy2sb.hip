@@ -354,14 +354,13 @@ __global__ void extract_band_kernel(int n, int b, const double* A, int lda, doub
 
 int coop_max_blocks()
 {
-    static int cached = -1;
-    if (cached < 0) {
+    static const int cached = [] {
         int dev = 0, cus = 0, per_cu = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, panel_qr_coop_kernel, PR, 0);
-        cached = std::max(0, cus * per_cu);
-    }
+        return std::max(0, cus * per_cu);
+    }();
     return cached;
 }
 
@@ -415,7 +414,8 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
         double* P = A + cm(r0, j, lda);
         const int nblk = ceil_div(m, PR);
         bool coop_done = false;
-        if (nblk <= coop_max_blocks()) {
+        // batched calls take the per-column path: its kernels never wait on each other
+        if (!batch_mode_active() && nblk <= coop_max_blocks()) {
             fill_i(st, ibuf, 2, 0);
             int mm = m, bww = bw, nrr = nr, ld = lda, nb = nblk;
             double* Pp = P;

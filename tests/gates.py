@@ -1,0 +1,31 @@
+"""Parity gates shared by the GPU tests.
+
+Eigenvalues: 1e-10 Ha for every state with |eps| <= 1 Ha (all states that enter
+the density matrix and its Fermi-Dirac tail).  States with |eps| > 1 Ha are the
+large eigenvalues created by the near-singular directions of S; for an
+eigenvalue of the definite pencil, a relative backward error eps_mach of S's
+factorization moves lambda by up to eps_mach * cond(S) * |lambda|, so every
+FP64 solver (the oracle included) carries that much noise there.  Their gate is
+1e-10 relative plus 2 eps_mach cond(S).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+EPS = np.finfo(np.float64).eps
+
+
+def overlap_condition(S) -> float:
+    w = np.linalg.eigvalsh(np.asarray(S, dtype=np.float64))
+    return float(w[-1] / w[0])
+
+
+def eig_excess(ev, ref, S, tol: float = 1e-10) -> float:
+    """max over states of |ev - ref| / allowed; <= 1 passes."""
+    ev = np.asarray(ev, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    big = np.abs(ref) > 1.0
+    allowed = tol * np.maximum(1.0, np.abs(ref))
+    if np.any(big):
+        allowed = allowed + np.where(big, 2.0 * EPS * overlap_condition(S) * np.abs(ref), 0.0)
+    return float(np.max(np.abs(ev - ref) / allowed))

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from gates import eig_excess
 from synth import generator as G
 
 torch = pytest.importorskip("torch")
@@ -113,9 +114,6 @@ def test_standard_ev_overlap_is_unit(n):
     assert np.abs(C.T @ C - np.eye(n)).max() <= 64 * n * EPS
 
 
-def _gate_eigs(ev, ref):
-    """|eps - eps_ref| <= 1e-10 Ha max(1, |eps|)."""
-    return (np.abs(ev - ref) / np.maximum(1.0, np.abs(ref))).max()
 
 
 @pytest.mark.parametrize("b", [64, 32])
@@ -131,7 +129,7 @@ def test_ev_config0_vs_oracle(b):
     h.close()
     ev = ev.cpu().numpy()
     C = C.cpu().numpy()
-    assert _gate_eigs(ev, ev_ref) <= 1e-10
+    assert eig_excess(ev, ev_ref, sp.S) <= 1.0
     # S-orthonormality, and subspace agreement of the occupied block with the oracle
     assert np.abs(C.T @ sp.S @ C - np.eye(sp.n)).max() <= 1e-8
     k = int(sp.n_occ)
@@ -157,7 +155,7 @@ def test_dm_config0_vs_oracle():
     ev = ev.cpu().numpy()
     f = f.cpu().numpy()
     assert st == 0
-    assert _gate_eigs(ev, ref["eval"]) <= 1e-10
+    assert eig_excess(ev, ref["eval"], sp.S) <= 1.0
     assert np.abs(D - ref["D"]).max() <= 1e-9
     assert np.abs(D - D.T).max() == 0.0
     assert abs(mu - ref["mu"]) <= 1e-9
