@@ -18,8 +18,8 @@
 // order; each step is one launch over all of its blocks and column slabs.
 //
 // Step (5).  Q1 = Q_0 Q_1 ... with Q_p = I - V_p T_p V_p^T from the panels of
-// step (1); X <- Q1 X applies the panels last to first as three FP64
-// matrix-core products (V^T X with a deterministic split over rows).
+// step (1); X <- Q1 X applies groups of panels last to first, each as three
+// FP64 matrix-core products (V^T X with a deterministic split over rows).
 #include "common.h"
 
 namespace eg {
@@ -298,9 +298,20 @@ void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const do
     }
 }
 
+// Q1 is applied in groups of Q1G consecutive panels: their product
+// Q_p ... Q_{p+Q1G-1} = I - V' T' V'^T with V' = [V_p ... V_{p+Q1G-1}] (the
+// later panels' columns are zero above their first row) and T' upper
+// triangular, built block column by block column from
+//   T'(0:c, block q) = -T'(0:c, 0:c) (V'(:, 0:c)^T V_q) T_q,
+// so that every application is a product with K = Q1G b.
+constexpr int Q1G = 4;
+
 size_t apply_q1_workspace_doubles(int n, int ncol)
 {
-    return (size_t)8 * 64 * std::max(ncol, 1) + (size_t)2 * 64 * std::max(ncol, 1);
+    const size_t w = (size_t)Q1G * 64;
+    const size_t c = (size_t)std::max(ncol, 1);
+    (void)n;
+    return 2 * w * c + 8 * w * c + 2 * w * w + w * 64;
 }
 
 // X (n x ncol) <- Q1 X with the panel reflectors of step (1).
@@ -308,22 +319,46 @@ void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const 
               double* work)
 {
     if (ncol <= 0) return;
-    const int npanel = ceil_div(n, b);
-    double* W = work;                        // 64 x ncol
-    double* W2 = W + (size_t)64 * ncol;      // 64 x ncol
-    double* part = W2 + (size_t)64 * ncol;
-    const size_t npart = apply_q1_workspace_doubles(n, ncol) - (size_t)2 * 64 * ncol;
-    for (int p = npanel - 1; p >= 0; --p) {
-        const int j = p * b;
-        const int r0 = j + b;
+    const int wmax = Q1G * 64;
+    double* W = work;                                // wmax x ncol
+    double* W2 = W + (size_t)wmax * ncol;            // wmax x ncol
+    double* part = W2 + (size_t)wmax * ncol;         // split-K partials
+    const size_t npart = (size_t)8 * wmax * ncol;
+    double* Tg = part + npart;                       // wmax x wmax
+    double* Gg = Tg + (size_t)wmax * wmax;           // wmax x wmax
+    double* tmp = Gg + (size_t)wmax * wmax;          // wmax x 64
+    // panels with at least two rows below them carry reflectors (full width b)
+    int nvalid = 0;
+    while (n - (nvalid + 1) * b >= 2) ++nvalid;
+    const int ngroups = ceil_div(nvalid, Q1G);
+    for (int g = ngroups - 1; g >= 0; --g) {
+        const int p0 = g * Q1G;
+        const int np = std::min(Q1G, nvalid - p0);
+        const int w = np * b;
+        const int j0 = p0 * b;
+        const int r0 = j0 + b;
         const int m = n - r0;
-        if (m < 2) continue;
-        const int bw = std::min(b, n - j);
-        const double* V = Vall + cm(r0, j, n);
-        const double* T = Tall + (size_t)p * b * b;
-        dgemm_splitk(st, 'T', 'N', bw, ncol, m, 1.0, V, n, X + r0, ldx, 0.0, W, 64, part, npart);
-        dgemm(st, 'N', 'N', bw, ncol, bw, 1.0, T, b, W, 64, 0.0, W2, 64);
-        dgemm(st, 'N', 'N', m, ncol, bw, -1.0, V, n, W2, 64, 1.0, X + r0, ldx);
+        const double* V = Vall + cm(r0, j0, n);
+        const double* T = Tall + (size_t)p0 * b * b;
+        if (np == 1) {
+            dgemm_splitk(st, 'T', 'N', b, ncol, m, 1.0, V, n, X + r0, ldx, 0.0, W, wmax, part, npart);
+            dgemm(st, 'N', 'N', b, ncol, b, 1.0, T, b, W, wmax, 0.0, W2, wmax);
+            dgemm(st, 'N', 'N', m, ncol, b, -1.0, V, n, W2, wmax, 1.0, X + r0, ldx);
+            continue;
+        }
+        // T' of the group
+        dgemm_splitk(st, 'T', 'N', w, w, m, 1.0, V, n, V, n, 0.0, Gg, wmax, part, npart);
+        fill_d(st, Tg, (size_t)wmax * w, 0.0);
+        for (int q = 0; q < np; ++q)
+            copy_matrix(st, b, b, T + (size_t)q * b * b, b, Tg + cm(q * b, q * b, wmax), wmax);
+        for (int q = 1; q < np; ++q) {
+            const int c = q * b;
+            dgemm(st, 'N', 'N', c, b, b, 1.0, Gg + cm(0, c, wmax), wmax, T + (size_t)q * b * b, b, 0.0, tmp, wmax);
+            dgemm(st, 'N', 'N', c, b, c, -1.0, Tg, wmax, tmp, wmax, 0.0, Tg + cm(0, c, wmax), wmax);
+        }
+        dgemm_splitk(st, 'T', 'N', w, ncol, m, 1.0, V, n, X + r0, ldx, 0.0, W, wmax, part, npart);
+        dgemm(st, 'N', 'N', w, ncol, w, 1.0, Tg, wmax, W, wmax, 0.0, W2, wmax);
+        dgemm(st, 'N', 'N', m, ncol, w, -1.0, V, n, W2, wmax, 1.0, X + r0, ldx);
     }
 }
 

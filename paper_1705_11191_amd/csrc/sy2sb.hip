@@ -304,15 +304,18 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
     }
 }
 
-// Explicit V (m x bw, unit lower trapezoidal) of the panel into V (ld ldv).
-__global__ void panel_store_v_kernel(int m, int bw, int nr, const double* P, int ldp, double* V, int ldv)
+// Explicit V (m x bw, unit lower trapezoidal) of the panel into V (ld ldv),
+// and zeros into the zpad rows above it (so that V of several consecutive
+// panels reads as one matrix with the later panels zero above their rows).
+__global__ void panel_store_v_kernel(int m, int bw, int nr, const double* P, int ldp, double* V, int ldv,
+                                     int zpad)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = (int)(blockIdx.x * blockDim.x + threadIdx.x) - zpad;
     int c = blockIdx.y;
     if (i >= m || c >= bw) return;
     double v = 0.0;
-    if (c < nr) v = (i == c) ? 1.0 : (i > c ? P[cm(i, c, ldp)] : 0.0);
-    V[cm(i, c, ldv)] = v;
+    if (i >= 0 && c < nr) v = (i == c) ? 1.0 : (i > c ? P[cm(i, c, ldp)] : 0.0);
+    V[(ptrdiff_t)c * ldv + i] = v;
 }
 
 // T (upper triangular, bw x bw, ld ldt) of Q = H_0 ... H_{bw-1} = I - V T V^T
@@ -370,13 +373,14 @@ size_t sy2sb_workspace_doubles(int n, int b)
 {
     size_t nblk = (size_t)ceil_div(n, PR);
     size_t w = 0;
-    w += (size_t)n * b * 2;          // Y, X
-    w += (size_t)n * 2 * b * 2;      // VW, WV
+    w += (size_t)n * b * 3;          // Y, W of the first and of the second panel of a pair
+    w += (size_t)n * 4 * b * 2;      // VW, WV (up to four b-wide blocks each)
     w += 2 * nblk * GS;              // Gram records (ping-pong)
     w += 2 * 64 + 64;                // pivot rows, tau
-    w += 3 * 64 * 64;                // G, Z, U
-    w += (size_t)8 * n * 64;                 // split-K partials
-    w += 64;                                 // barrier counter and error flag
+    w += 3 * 64 * 64;                // Gram of V, Z, U
+    w += 2 * 64 * 64;                // correction coefficients of a pair (2b x b)
+    w += (size_t)8 * n * 64;         // split-K partials
+    w += 64;                         // barrier counter and error flag
     return w;
 }
 
@@ -384,15 +388,27 @@ size_t sy2sb_workspace_doubles(int n, int b)
 // stale) -> band in Bd (ldbd = 2b rows), reflectors in
 // Vall (n x n, ld n: panel p occupies rows j+b.., columns j..j+b-1) and
 // T factors in Tall (b x b per panel).
+//
+// Panels are taken in pairs so that the trailing matrix receives one update
+// of rank 4b instead of two of rank 2b (the matrix cores run much closer to
+// peak at K = 4b).  With A1 = A - V1 W1^T - W1 V1^T the update of the first
+// panel, the second panel needs
+//   (a) its own columns of A1, formed directly: A(R1, J2) -= [V1 W1] [W1 V1]^T
+//       restricted to the rows of J2;
+//   (b) Y2 = A1(R2, R2) V2 = A(R2, R2) V2 - V1' (W1'^T V2) - W1' (V1'^T V2),
+//       with V1', W1' the rows of V1, W1 in R2, so A(R2, R2) is never formed
+//       in between;
+// and A(R2, R2) -= [V1' W1' V2 W2] [W1' V1' W2 V2]^T applies both panels.
 void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, double* Tall, double* Bd,
            int ldbd, double* work)
 {
     const int nblk_max = ceil_div(n, PR);
     double* Y = work;
-    double* X = Y + (size_t)n * b;
-    double* VW = X + (size_t)n * b;
-    double* WV = VW + (size_t)n * 2 * b;
-    double* gbuf0 = WV + (size_t)n * 2 * b;
+    double* W1 = Y + (size_t)n * b;
+    double* W2 = W1 + (size_t)n * b;
+    double* VW = W2 + (size_t)n * b;
+    double* WV = VW + (size_t)n * 4 * b;
+    double* gbuf0 = WV + (size_t)n * 4 * b;
     double* gbuf1 = gbuf0 + (size_t)nblk_max * GS;
     double* rbuf0 = gbuf1 + (size_t)nblk_max * GS;
     double* rbuf1 = rbuf0 + 64;
@@ -400,17 +416,15 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
     double* Gv = tau + 64;
     double* Z = Gv + 64 * 64;
     double* U = Z + 64 * 64;
-    double* part = U + 64 * 64;
+    double* Gc = U + 64 * 64;
+    double* part = Gc + 2 * 64 * 64;
     int* ibuf = (int*)(part + (size_t)8 * n * 64);
+    const size_t npart = (size_t)8 * n * 64;
 
-    const int npanel = ceil_div(n, b);
-    for (int p = 0; p < npanel; ++p) {
+    // QR of panel p (columns j .. j+bw-1, rows j+b ..): V into Vall, T into Tall.
+    auto factor_panel = [&](int p, int m, int bw, int nr) {
         const int j = p * b;
         const int r0 = j + b;
-        const int m = n - r0;
-        const int bw = std::min(b, n - j);
-        if (m < 2) break;
-        const int nr = std::min(bw, m - 1);
         double* P = A + cm(r0, j, lda);
         const int nblk = ceil_div(m, PR);
         bool coop_done = false;
@@ -443,25 +457,82 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
         }
         if (nr < bw) fill_d(st, tau + nr, (size_t)(bw - nr), 0.0);
         double* V = Vall + cm(r0, j, n);
-        hipLaunchKernelGGL(panel_store_v_kernel, dim3(ceil_div(m, 256), bw), dim3(256), 0, st, m, bw, nr, P,
-                           lda, V, n);
+        const int zpad = std::min(3 * b, r0);
+        hipLaunchKernelGGL(panel_store_v_kernel, dim3(ceil_div(m + zpad, 256), bw), dim3(256), 0, st, m, bw, nr, P,
+                           lda, V, n, zpad);
         double* T = Tall + (size_t)p * b * b;
-        const size_t npart = (size_t)8 * n * 64;
         dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, V, n, 0.0, Gv, 64, part, npart);
         hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(64), 0, st, bw, Gv, 64, tau, T, b);
-
-        // two-sided update of A22; only its lower triangle is read and kept
-        double* A22 = A + cm(r0, r0, lda);
-        dgemm_splitk(st, 'S', 'N', m, bw, m, 1.0, A22, lda, V, n, 0.0, Y, m, part, npart);
-        dgemm(st, 'N', 'N', m, bw, bw, 1.0, Y, m, T, b, 0.0, X, m);
-        dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, X, m, 0.0, Z, 64, part, npart);
+    };
+    // Y = A22 V (A22 = A(r0.., r0..), symmetric, lower triangle read)
+    auto form_y = [&](int r0, int m, int bw, const double* V) {
+        dgemm_splitk(st, 'S', 'N', m, bw, m, 1.0, A + cm(r0, r0, lda), lda, V, n, 0.0, Y, m, part, npart);
+    };
+    // W = X - 1/2 V (T^T (V^T X)) with X = Y T
+    auto finish_w = [&](int m, int bw, const double* V, const double* T, double* W) {
+        dgemm(st, 'N', 'N', m, bw, bw, 1.0, Y, m, T, b, 0.0, W, m);
+        dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, W, m, 0.0, Z, 64, part, npart);
         dgemm(st, 'T', 'N', bw, bw, bw, 1.0, T, b, Z, 64, 0.0, U, 64);
-        dgemm(st, 'N', 'N', m, bw, bw, -0.5, V, n, U, 64, 1.0, X, m);   // X <- W
-        copy_matrix(st, m, bw, V, n, VW, m);
-        copy_matrix(st, m, bw, X, m, VW + (size_t)m * bw, m);
-        copy_matrix(st, m, bw, X, m, WV, m);
-        copy_matrix(st, m, bw, V, n, WV + (size_t)m * bw, m);
-        dgemm(st, 'N', 'T', m, m, 2 * bw, -1.0, VW, m, WV, m, 1.0, A22, lda, 1);
+        dgemm(st, 'N', 'N', m, bw, bw, -0.5, V, n, U, 64, 1.0, W, m);
+    };
+
+    const int npanel = ceil_div(n, b);
+    int p = 0;
+    while (p < npanel) {
+        const int j = p * b;
+        const int r0 = j + b;
+        const int m = n - r0;
+        const int bw = std::min(b, n - j);
+        if (m < 2) break;
+        const int nr = std::min(bw, m - 1);
+        const int m2 = m - b;
+        const bool pair = (p + 1 < npanel) && bw == b && m2 > 2 * b;
+        factor_panel(p, m, bw, nr);
+        const double* V1 = Vall + cm(r0, j, n);
+        const double* T1 = Tall + (size_t)p * b * b;
+        form_y(r0, m, bw, V1);
+        finish_w(m, bw, V1, T1, W1);
+        if (!pair) {
+            // A22 -= [V W] [W V]^T, lower tiles
+            copy_matrix(st, m, bw, V1, n, VW, m);
+            copy_matrix(st, m, bw, W1, m, VW + (size_t)m * bw, m);
+            copy_matrix(st, m, bw, W1, m, WV, m);
+            copy_matrix(st, m, bw, V1, n, WV + (size_t)m * bw, m);
+            dgemm(st, 'N', 'T', m, m, 2 * bw, -1.0, VW, m, WV, m, 1.0, A + cm(r0, r0, lda), lda, 1);
+            ++p;
+            continue;
+        }
+        // (a) the second panel's columns J2 = [r0, r0+b) over rows r0..: -= [V1 W1] [W1 V1]^T
+        copy_matrix(st, m, b, V1, n, VW, m);
+        copy_matrix(st, m, b, W1, m, VW + (size_t)m * b, m);
+        copy_matrix(st, b, b, W1, m, WV, b);
+        copy_matrix(st, b, b, V1, n, WV + (size_t)b * b, b);
+        dgemm(st, 'N', 'T', m, b, 2 * b, -1.0, VW, m, WV, b, 1.0, A + cm(r0, r0, lda), lda);
+        // second panel
+        const int r2 = r0 + b;
+        const int nr2 = std::min(b, m2 - 1);
+        factor_panel(p + 1, m2, b, nr2);
+        const double* V2 = Vall + cm(r2, r0, n);
+        const double* T2 = Tall + (size_t)(p + 1) * b * b;
+        const double* V1s = V1 + b;          // rows of V1 in R2 (ld n)
+        const double* W1s = W1 + b;          // rows of W1 in R2 (ld m)
+        form_y(r2, m2, b, V2);
+        // (b) Y2 -= [V1' W1'] [W1'^T V2 ; V1'^T V2]
+        dgemm_splitk(st, 'T', 'N', b, b, m2, 1.0, W1s, m, V2, n, 0.0, Gc, 2 * b, part, npart);
+        dgemm_splitk(st, 'T', 'N', b, b, m2, 1.0, V1s, n, V2, n, 0.0, Gc + b, 2 * b, part, npart);
+        copy_matrix(st, m2, b, V1s, n, VW, m2);
+        copy_matrix(st, m2, b, W1s, m, VW + (size_t)m2 * b, m2);
+        dgemm(st, 'N', 'N', m2, b, 2 * b, -1.0, VW, m2, Gc, 2 * b, 1.0, Y, m2);
+        finish_w(m2, b, V2, T2, W2);
+        // A(R2, R2) -= [V1' W1' V2 W2] [W1' V1' W2 V2]^T, lower tiles
+        copy_matrix(st, m2, b, V2, n, VW + (size_t)2 * m2 * b, m2);
+        copy_matrix(st, m2, b, W2, m2, VW + (size_t)3 * m2 * b, m2);
+        copy_matrix(st, m2, b, W1s, m, WV, m2);
+        copy_matrix(st, m2, b, V1s, n, WV + (size_t)m2 * b, m2);
+        copy_matrix(st, m2, b, W2, m2, WV + (size_t)2 * m2 * b, m2);
+        copy_matrix(st, m2, b, V2, n, WV + (size_t)3 * m2 * b, m2);
+        dgemm(st, 'N', 'T', m2, m2, 4 * b, -1.0, VW, m2, WV, m2, 1.0, A + cm(r2, r2, lda), lda, 1);
+        p += 2;
     }
     hipLaunchKernelGGL(extract_band_kernel, dim3(n), dim3(ldbd), 0, st, n, b, A, lda, Bd, ldbd);
 }
