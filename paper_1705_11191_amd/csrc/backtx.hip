@@ -100,8 +100,8 @@ __global__ __launch_bounds__(256) void q2_build_t_kernel(int n, int b, const dou
     for (int e = tid; e < NB2 * NB2; e += 256) T[e] = Ts[e % NB2][e / NB2];   // column-major, ld 64
 }
 
-// One block reflector (g, k) applied to a slab of QW columns of X per
-// workgroup, 32 columns at a time; the launch covers every (g, k) on the
+// One block reflector (g, k) applied to a slab of X columns per workgroup,
+// 32 columns at a time; the launch covers every (g, k) on the
 // anti-diagonal step t = (G-1-g) + k.  Blocks on one step touch disjoint row
 // windows, and every pair of blocks whose windows overlap lands on different
 // steps in the reverse-execution order (windows overlap only when g + k
@@ -113,7 +113,9 @@ __global__ __launch_bounds__(256) void q2_build_t_kernel(int n, int b, const dou
 // LDS holds only the current 32-column chunk of X and the two 64 x 32
 // intermediates, which lets two workgroups share a CU.  Workgroups are
 // numbered so that all slabs of one block run on one XCD (one L2 copy of V).
-constexpr int QW = 128;   // columns of X per workgroup
+// columns of X per workgroup: wide slabs amortize the loads of V and T, narrow
+// ones keep enough workgroups in flight when X has few columns
+int q2_slab_width(int ncol) { return ncol >= 8192 ? 512 : (ncol >= 2048 ? 256 : 128); }
 
 // Phase-3 row blocks of each wave (16-row blocks of the 128-row window with
 // their first nonzero 4-column step), balanced to 20 MFMA steps per wave.
@@ -127,7 +129,7 @@ __device__ __forceinline__ void q2_rowblocks(int wave, int& rbA, int& kA0, int& 
     }
 }
 
-__global__ __launch_bounds__(256, 2) void q2_apply_step_kernel(int n, int b, int ncol, int t, int nb, int nslab,
+__global__ __launch_bounds__(256, 2) void q2_apply_step_kernel(int n, int b, int ncol, int qw, int t, int nb, int nslab,
                                                                const double* __restrict__ V2,
                                                                const double* __restrict__ Tq, int kmax, double* X,
                                                                int ldx)
@@ -156,13 +158,23 @@ __global__ __launch_bounds__(256, 2) void q2_apply_step_kernel(int n, int b, int
     const int s_lo = g * b;
     const int base = s_lo + 1 + k * b;
     const int wrows = min(2 * b - 1, n - base);
-    const int cbeg = slab * QW, cend = min(ncol, cbeg + QW);
+    const int cbeg = slab * qw, cend = min(ncol, cbeg + qw);
 
-    double treg[NB2 / 4];
+    // W2 = T W with T upper triangular: row block rb needs K from 16 rb.  Wave w
+    // forms column block w & 1 of two row blocks with complementary K ranges
+    // (rows 0 and 3, or 1 and 2): 20 MFMA steps each.
+    const int t_cb = wave & 1;
+    const int t_rb0 = (wave >> 1) ? 1 : 0, t_rb1 = 3 - t_rb0;
+    double treg[20];
     {
         const double* T = Tq + ((size_t)g * kmax + k) * NB2 * NB2;
+        const int n0 = 16 - 4 * t_rb0;   // steps of the first row block (16 or 12)
 #pragma unroll
-        for (int q4 = 0; q4 < NB2 / 4; ++q4) treg[q4] = T[(wave * 16 + li) + (size_t)(4 * q4 + lk) * NB2];
+        for (int q = 0; q < 20; ++q) {
+            const int rb = (q < n0) ? t_rb0 : t_rb1;
+            const int kq = (q < n0) ? 4 * t_rb0 + q : 4 * t_rb1 + (q - n0);
+            treg[q] = T[(rb * 16 + li) + (size_t)(4 * kq + lk) * NB2];
+        }
     }
     const int xr = tid & 127, xc = tid >> 7;
     double xv[NCB / 2];
@@ -213,16 +225,35 @@ __global__ __launch_bounds__(256, 2) void q2_apply_step_kernel(int n, int b, int
         // W2 = T W (64 x 32)
         {
             double4_t a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+            const int n0 = 16 - 4 * t_rb0;
+            const int cc = 16 * t_cb + li;
 #pragma unroll
-            for (int q4 = 0; q4 < NB2 / 4; ++q4) {
-                const int kk = 4 * q4 + lk;
-                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q4], Ws[kk][li], a0, 0, 0, 0);
-                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q4], Ws[kk][16 + li], a1, 0, 0, 0);
+            for (int q = 0; q < 12; ++q) {
+                const int kk = 4 * (4 * t_rb0 + q) + lk;
+                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q], Ws[kk][cc], a0, 0, 0, 0);
+            }
+            if (n0 == 16) {
+#pragma unroll
+                for (int q = 12; q < 16; ++q) {
+                    const int kk = 4 * q + lk;
+                    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q], Ws[kk][cc], a0, 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int q = 12; q < 16; ++q) {
+                    const int kk = 4 * (4 * t_rb1 + (q - 12)) + lk;
+                    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q], Ws[kk][cc], a1, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int q = 16; q < 20; ++q) {
+                const int kk = 4 * (4 * t_rb1 + (q - n0)) + lk;
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q], Ws[kk][cc], a1, 0, 0, 0);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                W2s[16 * wave + 4 * r + lk][li] = a0[r];
-                W2s[16 * wave + 4 * r + lk][16 + li] = a1[r];
+                W2s[16 * t_rb0 + 4 * r + lk][cc] = a0[r];
+                W2s[16 * t_rb1 + 4 * r + lk][cc] = a1[r];
             }
         }
         __syncthreads();
@@ -288,12 +319,13 @@ void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const do
     if (n <= 2 || ncol <= 0) return;
     const int ngroups = ceil_div(n - 2, b);
     hipLaunchKernelGGL(q2_build_t_kernel, dim3(ngroups, kmax), dim3(256), 0, st, n, b, V2, tau2, kmax, Tq);
-    const int nslab = ceil_div(ncol, QW);
+    const int qw = q2_slab_width(ncol);
+    const int nslab = ceil_div(ncol, qw);
     const int tmax = (ngroups - 1) + kmax;   // last step: g = 0 with its last block
     for (int t = 0; t < tmax; ++t) {
         const int nb = std::min(ngroups, t + 1);   // block index G-1-g ranges over 0 .. min(G-1, t)
         const int nwg = ceil_div(nb, 8) * 8 * nslab;
-        hipLaunchKernelGGL(q2_apply_step_kernel, dim3(nwg), dim3(256), 0, st, n, b, ncol, t, nb, nslab, V2, Tq,
+        hipLaunchKernelGGL(q2_apply_step_kernel, dim3(nwg), dim3(256), 0, st, n, b, ncol, qw, t, nb, nslab, V2, Tq,
                            kmax, X, ldx);
     }
 }
