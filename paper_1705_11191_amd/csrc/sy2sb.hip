@@ -162,6 +162,7 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
     __shared__ double scoef[BMAX];
     __shared__ double red[PR / 64][BMAX + 1];
     __shared__ double sh[4];
+    __shared__ double prow[BMAX];
     __shared__ int bad;
     const int tid = threadIdx.x;
     const int blk = blockIdx.x;
@@ -175,6 +176,7 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
 #pragma unroll
     for (int r = 0; r < BMAX; ++r) rowv[r] = (r < bw && i < m) ? P[cm(i, r, ldp)] : 0.0;
     int arrive = 0;
+    double xn = 0.0;   // this row's entry in the column the next step reflects
 
     for (int c = -1; c < nr; ++c) {
         const int gin = ((c + 2) & 1) * nblk * GS;    // element offsets into gbuf / rbuf
@@ -182,17 +184,40 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
         const int rin = ((c + 2) & 1) * 64;
         const int rout = ((c + 1) & 1) * 64;
         if (c >= 0) {
-            // sum the per-block records: wave w takes blocks w, w+4, ..., lane r entry r
+            // everything column c needs from other workgroups, loaded at once:
+            // the per-block records (wave w takes blocks w, w+4, ..., lane r
+            // entry r) and the pivot row (thread r entry r)
             {
+                // loads are unconditional and issued in batches of RU so that they
+                // are in flight together (a guarded load would wait by itself); the
+                // entries a lane does not need are dropped by a select
+                constexpr int RU = 16;
+                const double pv = bld(rrs, rin + lane);
                 double s = 0.0, st = 0.0;
                 const bool need = lane >= c && lane < bw;
-#pragma unroll 8
-                for (int b = wave; b < nblk; b += PR / 64) {
-                    if (need) s += bld(grs, gin + b * GS + lane);
-                    if (lane == 0) st += bld(grs, gin + b * GS + BMAX);
+                int b = wave;
+                for (; b + (RU - 1) * (PR / 64) < nblk; b += RU * (PR / 64)) {
+                    double v[RU], vt[RU];
+#pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+                        v[u] = bld(grs, gin + (b + u * (PR / 64)) * GS + lane);
+                        vt[u] = bld(grs, gin + (b + u * (PR / 64)) * GS + BMAX);
+                    }
+#pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+                        s += need ? v[u] : 0.0;
+                        st += vt[u];
+                    }
+                }
+                for (; b < nblk; b += PR / 64) {
+                    const double v = bld(grs, gin + b * GS + lane);
+                    const double vt = bld(grs, gin + b * GS + BMAX);
+                    s += need ? v : 0.0;
+                    st += vt;
                 }
                 red[wave][lane] = s;
                 if (lane == 0) red[wave][BMAX] = st;
+                if (tid < BMAX) prow[tid] = (lane < bw) ? pv : 0.0;
             }
             __syncthreads();
             if (tid <= BMAX) {
@@ -202,7 +227,7 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
             }
             __syncthreads();
             if (tid == 0) {
-                double x0 = bld(rrs, rin + c);
+                double x0 = prow[c];
                 double tail = G[BMAX];
                 double t = 0.0, alpha = x0, den = 1.0;
                 if (tail > 0.0) {
@@ -216,26 +241,42 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
             }
             __syncthreads();
             const double t = sh[0], alpha = sh[1], den = sh[2];
-            for (int r = tid; r < bw; r += PR)
-                if (r > c) scoef[r] = (t != 0.0) ? (G[r] - alpha * bld(rrs, rin + r)) / den : 0.0;
+            // coefficients of the update, zero outside columns c+1 .. bw-1 so that
+            // the update below needs no per-column condition
+            if (tid < BMAX)
+                scoef[tid] = (tid > c && tid < bw && t != 0.0) ? (G[tid] - alpha * prow[tid]) / den : 0.0;
             __syncthreads();
             if (i < m && i >= c) {
-                double xc = 0.0;
+                // xn of the previous step is this row's entry in column c
+                const double vi = (i == c) ? 1.0 : ((t != 0.0) ? xn / den : 0.0);
+                const double tv = t * vi;
 #pragma unroll
-                for (int r = 0; r < BMAX; ++r) if (r == c) xc = rowv[r];
-                const double vi = (i == c) ? 1.0 : ((t != 0.0) ? xc / den : 0.0);
-#pragma unroll
-                for (int r = 0; r < BMAX; ++r)
-                    if (r > c && r < bw) rowv[r] -= t * vi * scoef[r];
+                for (int r = 0; r < BMAX; ++r) rowv[r] -= tv * scoef[r];
                 // column c is final for this row: alpha on the diagonal, v below it
                 P[cm(i, c, ldp)] = (i == c) ? alpha : vi;
             }
         }
         const int cn = c + 1;
         if (cn < nr) {
-            double xn = 0.0;
+            {
+                // rowv[cn] for the uniform cn in two levels (eight group
+                // conditions, then eight entry conditions), so that rowv stays
+                // in registers and few condition masks are live
+                double g8[8];
 #pragma unroll
-            for (int r = 0; r < BMAX; ++r) if (r == cn) xn = rowv[r];
+                for (int q = 0; q < 8; ++q) g8[q] = 0.0;
+                const int hi = cn >> 3, lo = cn & 7;
+#pragma unroll
+                for (int g = 0; g < 8; ++g)
+                    if (g == hi) {
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) g8[q] = rowv[8 * g + q];
+                    }
+                xn = 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q == lo) xn = g8[q];
+            }
             if (!(i < m && i >= cn)) xn = 0.0;
             // Gram row of column cn over the wave's rows by a butterfly
             // transpose-reduction: after the step with offset h a lane keeps the
@@ -244,7 +285,7 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
             {
                 double v[BMAX];
 #pragma unroll
-                for (int r = 0; r < BMAX; ++r) v[r] = (r >= cn && r < bw) ? xn * rowv[r] : 0.0;
+                for (int r = 0; r < BMAX; ++r) v[r] = xn * rowv[r];   // entries r < cn are never read
 #pragma unroll
                 for (int h = BMAX / 2; h >= 1; h >>= 1) {
                     const bool up = (lane & h) != 0;
@@ -270,8 +311,7 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
             }
             if (i == cn && i < m) {
 #pragma unroll
-                for (int r = 0; r < BMAX; ++r)
-                    if (r >= cn && r < bw) bst(rrs, rout + r, rowv[r]);
+                for (int r = 0; r < BMAX; ++r) bst(rrs, rout + r, rowv[r]);   // entries r < cn are never read
             }
             // grid barrier
             __builtin_amdgcn_s_waitcnt(0);
