@@ -297,21 +297,36 @@ __global__ __launch_bounds__(256) void dc_prep_kernel(const MergeDesc* __restric
     ma.zs2[mi] = zs2;
 }
 
-// One root of 1 + rho sum_i z_i^2 / (d_i - lam) = 0 per thread.
+// Sum over the wave by an xor butterfly: every lane ends with the same bits
+// (each step adds two operands, and a + b == b + a exactly).
+__device__ __forceinline__ double wave_allsum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One root of 1 + rho sum_i z_i^2 / (d_i - lam) = 0 per wave: the lanes split
+// the sums over i, and the iteration (identical in every lane) follows the
+// two-pole rational model with a bisection safeguard.
+constexpr int kRootsPerBlock = 4;
 __global__ __launch_bounds__(256) void dc_secular_kernel(const MergeDesc* __restrict__ md, MergeArrays ma,
                                                          int* err)
 {
     const int mi = blockIdx.y;
     const int o = md[mi].o;
     const int K = ma.K[mi];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * kRootsPerBlock + (threadIdx.x >> 6);
     if (j >= K) return;
     const double* ds = ma.ds + o;
     const double* zs = ma.zs + o;
     const double rho = ma.rho[mi];
     if (K == 1) {
-        ma.org[o] = 0;
-        ma.tau[o] = rho * zs[0] * zs[0];
+        if (lane == 0) {
+            ma.org[o] = 0;
+            ma.tau[o] = rho * zs[0] * zs[0];
+        }
         return;
     }
     int org;
@@ -319,8 +334,9 @@ __global__ __launch_bounds__(256) void dc_secular_kernel(const MergeDesc* __rest
     if (j < K - 1) {
         const double gap = ds[j + 1] - ds[j];
         const double mid = 0.5 * gap;
-        double f = 1.0;
-        for (int i = 0; i < K; ++i) f += rho * zs[i] * zs[i] / ((ds[i] - ds[j]) - mid);
+        double f = 0.0;
+        for (int i = lane; i < K; i += 64) f += rho * zs[i] * zs[i] / ((ds[i] - ds[j]) - mid);
+        f = 1.0 + wave_allsum(f);
         if (f >= 0.0) { org = j; lo = 0.0; hi = mid; tau = 0.5 * mid; }
         else { org = j + 1; lo = -mid; hi = 0.0; tau = -0.5 * mid; }
     } else {
@@ -335,13 +351,18 @@ __global__ __launch_bounds__(256) void dc_secular_kernel(const MergeDesc* __rest
     bool done = false;
     for (int it = 0; it < 120; ++it) {
         double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, abs_sum = 0.0;
-        for (int i = 0; i < K; ++i) {
+        for (int i = lane; i < K; i += 64) {
             double t = zs[i] / ((ds[i] - dorg) - tau);
             double term = zs[i] * t;
             if (i <= j) { psi += term; dpsi += t * t; }
             else { phi += term; dphi += t * t; }
             abs_sum += fabs(term);
         }
+        psi = wave_allsum(psi);
+        dpsi = wave_allsum(dpsi);
+        phi = wave_allsum(phi);
+        dphi = wave_allsum(dphi);
+        abs_sum = wave_allsum(abs_sum);
         const double fr = 1.0 / rho + psi + phi;   // f / rho
         const double errb = kEps * (8.0 * (1.0 / rho + abs_sum) + fabs(tau) * (dpsi + dphi));
         if (fabs(fr) <= errb) { done = true; break; }
@@ -375,9 +396,11 @@ __global__ __launch_bounds__(256) void dc_secular_kernel(const MergeDesc* __rest
         tau = tn;
         if (hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi))) { done = true; break; }
     }
-    if (!done) atomicOr(err, 2);
-    ma.org[o + j] = org;
-    ma.tau[o + j] = tau;
+    if (lane == 0) {
+        if (!done) atomicOr(err, 2);
+        ma.org[o + j] = org;
+        ma.tau[o + j] = tau;
+    }
 }
 
 // Loewner weights: zhat_q^2 = prod_j (lam_j - d_q) / (rho prod_{j != q} (d_j - d_q)).
@@ -595,7 +618,8 @@ int stedc_values(hipStream_t st, int n, const double* d, const double* e, double
         const int maxns = 2 * size;
         const bool last = (2 * size >= n);
         hipLaunchKernelGGL(dc_prep_kernel, dim3(nm), dim3(256), 0, st, mdl, n, e, Zin, ldz, w, ma);
-        hipLaunchKernelGGL(dc_secular_kernel, dim3(ceil_div(maxns, 256), nm), dim3(256), 0, st, mdl, ma, err);
+        hipLaunchKernelGGL(dc_secular_kernel, dim3(ceil_div(maxns, kRootsPerBlock), nm), dim3(256), 0, st, mdl, ma,
+                           err);
         hipLaunchKernelGGL(dc_zhat_kernel, dim3(ceil_div(maxns, 256), nm), dim3(256), 0, st, mdl, ma);
         hipLaunchKernelGGL(dc_order_kernel, dim3(nm), dim3(1024), 0, st, mdl, ma, w);
         hipLaunchKernelGGL(dc_vectors_kernel, dim3(maxns, nm), dim3(256), 0, st, mdl, ma, U, ldz);
