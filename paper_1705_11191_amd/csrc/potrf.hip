@@ -42,23 +42,35 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(int jb, int j0, double* 
         if (tid == 0) L[c][c] = d;
         for (int i = c + 1 + tid; i < jb; i += 256) L[i][c] /= d;
         __syncthreads();
-        const int w = jb - c - 1;
-        for (int e = tid; e < w * w; e += 256) {
-            int i = c + 1 + e % w, c2 = c + 1 + e / w;
-            if (c2 <= i) L[i][c2] -= L[i][c] * L[c2][c];
+        // trailing update: thread (i, r) = (tid % 64, tid / 64) takes row i and
+        // every fourth column from c + 1 + r
+        {
+            const int i = tid & 63, r = tid >> 6;
+            if (i > c && i < jb) {
+                const double lic = L[i][c];
+                for (int c2 = c + 1 + r; c2 <= i; c2 += 4) L[i][c2] -= lic * L[c2][c];
+            }
         }
         __syncthreads();
     }
     if (bad) return;
-    // X = L^-1, column j solved by thread j (forward substitution)
+    // X = L^-1, column j solved by thread j (forward substitution), the dot
+    // products split over four accumulators
     if (tid < NB) {
         const int j = tid;
         for (int i = 0; i < NB; ++i) X[i][j] = 0.0;
         if (j < jb) {
             for (int i = j; i < jb; ++i) {
-                double t = (i == j) ? 1.0 : 0.0;
-                for (int q = j; q < i; ++q) t -= L[i][q] * X[q][j];
-                X[i][j] = t / L[i][i];
+                double t0 = (i == j) ? 1.0 : 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+                int q = j;
+                for (; q + 3 < i; q += 4) {
+                    t0 -= L[i][q] * X[q][j];
+                    t1 -= L[i][q + 1] * X[q + 1][j];
+                    t2 -= L[i][q + 2] * X[q + 2][j];
+                    t3 -= L[i][q + 3] * X[q + 3][j];
+                }
+                for (; q < i; ++q) t0 -= L[i][q] * X[q][j];
+                X[i][j] = ((t0 + t1) + (t2 + t3)) / L[i][i];
             }
         }
     }
@@ -89,9 +101,16 @@ __global__ __launch_bounds__(256) void trtri_blocks_kernel(int n, const double* 
         for (int i = 0; i < NB; ++i) X[i][j] = 0.0;
         if (j < jb) {
             for (int i = j; i < jb; ++i) {
-                double t = (i == j) ? 1.0 : 0.0;
-                for (int q = j; q < i; ++q) t -= Ls[i][q] * X[q][j];
-                X[i][j] = t / Ls[i][i];
+                double t0 = (i == j) ? 1.0 : 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+                int q = j;
+                for (; q + 3 < i; q += 4) {
+                    t0 -= Ls[i][q] * X[q][j];
+                    t1 -= Ls[i][q + 1] * X[q + 1][j];
+                    t2 -= Ls[i][q + 2] * X[q + 2][j];
+                    t3 -= Ls[i][q + 3] * X[q + 3][j];
+                }
+                for (; q < i; ++q) t0 -= Ls[i][q] * X[q][j];
+                X[i][j] = ((t0 + t1) + (t2 + t3)) / Ls[i][i];
             }
         }
     }

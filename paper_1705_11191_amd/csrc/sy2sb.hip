@@ -364,18 +364,27 @@ __global__ __launch_bounds__(64) void build_t_kernel(int bw, const double* G, in
                                                       double* T, int ldt)
 {
     __shared__ double Ts[BMAX][BMAX + 1];
-    __shared__ double g[BMAX];
+    __shared__ double Gs[BMAX][BMAX + 1];
+    __shared__ double ts[BMAX];
     const int q = threadIdx.x;
-    for (int c = 0; c < BMAX; ++c) Ts[q][c] = 0.0;
+    // G and tau are read once; the column recurrence then runs out of LDS
+    for (int c = 0; c < BMAX; ++c) {
+        Ts[q][c] = 0.0;
+        Gs[q][c] = (q < bw && c < bw) ? G[cm(q, c, ldg)] : 0.0;
+    }
+    ts[q] = (q < bw) ? tau[q] : 0.0;
     __syncthreads();
     for (int c = 0; c < bw; ++c) {
-        if (q < c) g[q] = G[cm(q, c, ldg)];
-        __syncthreads();
-        double tc = tau[c];
+        const double tc = ts[c];
         if (q < c) {
-            double s = 0.0;
-            for (int j = q; j < c; ++j) s += Ts[q][j] * g[j];
-            Ts[q][c] = -tc * s;
+            double s0 = 0.0, s1 = 0.0;
+            int j = q;
+            for (; j + 1 < c; j += 2) {
+                s0 += Ts[q][j] * Gs[j][c];
+                s1 += Ts[q][j + 1] * Gs[j + 1][c];
+            }
+            if (j < c) s0 += Ts[q][j] * Gs[j][c];
+            Ts[q][c] = -tc * (s0 + s1);
         }
         if (q == c) Ts[c][c] = tc;
         __syncthreads();
