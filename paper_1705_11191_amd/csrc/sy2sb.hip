@@ -359,38 +359,49 @@ __global__ void panel_store_v_kernel(int m, int bw, int nr, const double* P, int
 }
 
 // T (upper triangular, bw x bw, ld ldt) of Q = H_0 ... H_{bw-1} = I - V T V^T
-// from G = V^T V and tau: T_cc = tau_c, T(0:c, c) = -tau_c T(0:c, 0:c) G(0:c, c).
-__global__ __launch_bounds__(64) void build_t_kernel(int bw, const double* G, int ldg, const double* tau,
-                                                      double* T, int ldt)
+// from G = V^T V and tau.  T_cc = tau_c, and for two adjacent blocks of
+// reflectors A, B (A first) T_AB = -T_AA G_AB T_BB; the blocks double in size
+// from 1 to 32, each level two parallel small products over 256 threads.
+__global__ __launch_bounds__(256) void build_t_kernel(int bw, const double* G, int ldg, const double* tau,
+                                                       double* T, int ldt)
 {
     __shared__ double Ts[BMAX][BMAX + 1];
     __shared__ double Gs[BMAX][BMAX + 1];
-    __shared__ double ts[BMAX];
-    const int q = threadIdx.x;
-    // G and tau are read once; the column recurrence then runs out of LDS
-    for (int c = 0; c < BMAX; ++c) {
-        Ts[q][c] = 0.0;
-        Gs[q][c] = (q < bw && c < bw) ? G[cm(q, c, ldg)] : 0.0;
+    __shared__ double Ys[BMAX][BMAX + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < BMAX * BMAX; e += 256) {
+        const int r = e % BMAX, c = e / BMAX;
+        Gs[r][c] = (r < bw && c < bw) ? G[cm(r, c, ldg)] : 0.0;
+        Ts[r][c] = (r == c && r < bw) ? tau[r] : 0.0;
     }
-    ts[q] = (q < bw) ? tau[q] : 0.0;
     __syncthreads();
-    for (int c = 0; c < bw; ++c) {
-        const double tc = ts[c];
-        if (q < c) {
-            double s0 = 0.0, s1 = 0.0;
-            int j = q;
-            for (; j + 1 < c; j += 2) {
-                s0 += Ts[q][j] * Gs[j][c];
-                s1 += Ts[q][j + 1] * Gs[j + 1][c];
-            }
-            if (j < c) s0 += Ts[q][j] * Gs[j][c];
-            Ts[q][c] = -tc * (s0 + s1);
+    for (int sz = 1; sz < BMAX; sz *= 2) {
+        const int nout = (BMAX / (2 * sz)) * sz * sz;   // entries of all off-diagonal blocks
+        // Y = G_AB T_BB (row a of A, column b of B)
+        for (int e = tid; e < nout; e += 256) {
+            const int pr = e / (sz * sz), rem = e % (sz * sz);
+            const int a = rem % sz, bb = rem / sz;
+            const int p0 = pr * 2 * sz, pb = p0 + sz;
+            double y = 0.0;
+            for (int jj = 0; jj <= bb; ++jj) y += Gs[p0 + a][pb + jj] * Ts[pb + jj][pb + bb];
+            Ys[p0 + a][pb + bb] = y;
         }
-        if (q == c) Ts[c][c] = tc;
+        __syncthreads();
+        // T_AB = -T_AA Y
+        for (int e = tid; e < nout; e += 256) {
+            const int pr = e / (sz * sz), rem = e % (sz * sz);
+            const int a = rem % sz, bb = rem / sz;
+            const int p0 = pr * 2 * sz, pb = p0 + sz;
+            double t = 0.0;
+            for (int ii = a; ii < sz; ++ii) t += Ts[p0 + a][p0 + ii] * Ys[p0 + ii][pb + bb];
+            Ts[p0 + a][pb + bb] = -t;
+        }
         __syncthreads();
     }
-    if (q < bw)
-        for (int c = 0; c < bw; ++c) T[cm(q, c, ldt)] = Ts[q][c];
+    for (int e = tid; e < bw * bw; e += 256) {
+        const int r = e % bw, c = e / bw;
+        T[cm(r, c, ldt)] = Ts[r][c];
+    }
 }
 
 // Band of the reduced matrix: Bd(r, c) = A(c + r, c) for 0 <= r <= b, zero for b < r < ldb.
@@ -511,7 +522,7 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
                            lda, V, n, zpad);
         double* T = Tall + (size_t)p * b * b;
         dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, V, n, 0.0, Gv, 64, part, npart);
-        hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(64), 0, st, bw, Gv, 64, tau, T, b);
+        hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(256), 0, st, bw, Gv, 64, tau, T, b);
     };
     // Y = A22 V (A22 = A(r0.., r0..), symmetric, lower triangle read)
     auto form_y = [&](int r0, int m, int bw, const double* V) {
