@@ -522,7 +522,10 @@ void dgemm_splitk(hipStream_t st, char ta, char tb, int m, int n, int k, double 
     int BM, BN;
     tile_shape(m, n, BM, BN);
     const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
-    int nsplit = std::max(1, std::min(512 / std::max(tiles, 1), k / 256));
+    // enough K slices for about 2048 workgroups: the tall-skinny products are
+    // bound by the latency of their operand stream, and more workgroups per CU
+    // keep more of it in flight
+    int nsplit = std::max(1, std::min(2048 / std::max(tiles, 1), k / 256));
     while (nsplit > 1 && (size_t)nsplit * m * n > work_doubles) --nsplit;
     if (nsplit <= 1) {
         dgemm(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 0);
