@@ -37,6 +37,36 @@ __host__ __device__ inline size_t cm(int i, int j, int ld) {
 }
 
 // ---------------------------------------------------------------------------
+// Sum over the 64 lanes of a wave with DPP lane moves (no LDS round trips):
+// swaps inside quads, rotations inside rows of 16, then row broadcasts, which
+// leave the total in lane 63; it is read from there, so every lane gets the
+// same bits.  Each double moves as two 32-bit halves.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add_f64(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    const unsigned long long o = (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32);
+    return v + __builtin_bit_cast(double, o);
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v = dpp_add_f64<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v = dpp_add_f64<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+    v = dpp_add_f64<0x124, 0xf>(v);   // row_ror:4
+    v = dpp_add_f64<0x128, 0xf>(v);   // row_ror:8
+    v = dpp_add_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers implemented in the .hip files
 // ---------------------------------------------------------------------------
 

@@ -66,11 +66,7 @@ __device__ inline void stc(double* p, double v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline double wave_sum64(double v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+__device__ inline double wave_sum64(double v) { return wave_sum_dpp(v); }
 
 // One task runs in a workgroup of 256 threads: thread (i, q) = (tid % 64,
 // tid / 64) keeps entries (i, 16q .. 16q+15) of both blocks in registers.
