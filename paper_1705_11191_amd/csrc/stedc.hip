@@ -297,14 +297,8 @@ __global__ __launch_bounds__(256) void dc_prep_kernel(const MergeDesc* __restric
     ma.zs2[mi] = zs2;
 }
 
-// Sum over the wave by an xor butterfly: every lane ends with the same bits
-// (each step adds two operands, and a + b == b + a exactly).
-__device__ __forceinline__ double wave_allsum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+// Sum over the wave; every lane ends with the same bits (read from one lane).
+__device__ __forceinline__ double wave_allsum(double v) { return wave_sum_dpp(v); }
 
 // One root of 1 + rho sum_i z_i^2 / (d_i - lam) = 0 per wave: the lanes split
 // the sums over i, and the iteration (identical in every lane) follows the

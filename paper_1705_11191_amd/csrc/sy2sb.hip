@@ -25,11 +25,7 @@ constexpr int PR = 256;    // panel rows per workgroup (one row per thread)
 constexpr int BMAX = 64;
 constexpr int GS = BMAX + 2;   // per-block partial record: Gram row (64), tail, spare
 
-__device__ inline double wave_sum(double v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
+__device__ inline double wave_sum(double v) { return wave_sum_dpp(v); }
 
 // c >= 0: apply reflector c (its Gram row is in gin, row c in rin) and form the
 // Gram record of column c+1.  c == -1: only form the record of column 0.
