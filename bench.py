@@ -266,7 +266,7 @@ def main():
     ap.add_argument("--workload", choices=["single", "batch"], default="single",
                     help="single: the N=32768 dm solve; batch: 256 uneven problems in one batched call")
     ap.add_argument("--batch-count", type=int, default=256)
-    ap.add_argument("--batch-workers", type=int, default=4)
+    ap.add_argument("--batch-workers", type=int, default=8)
     args = ap.parse_args()
     if args.workload == "batch":
         if args.gpus != 1:

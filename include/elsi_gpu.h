@@ -176,7 +176,7 @@ int elsi_gpu_dm(elsi_gpu_handle h, double *H, double *S, double *occ, double *D,
  * scheme and parameters, band width, overlap flags); its n_basis, n_state and
  * n_electron are not used.  Problem p has its own column-major device arrays
  * with ld = n[p].  A pool of host worker threads (elsi_gpu_set_batch_workers,
- * default 4), each with its own stream and device workspace (allocated for
+ * default 8), each with its own stream and device workspace (allocated for
  * the duration of the call), solves the problems largest first, so that the
  * kernels of different problems overlap on the device.  The caller's stream
  * is synchronized before the problems start; every output is complete when

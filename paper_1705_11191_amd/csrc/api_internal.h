@@ -53,7 +53,7 @@ struct elsi_gpu_handle_s {
     int overlap_is_unit = 0;
     int overlap_factored = 0;
     int band_width = 64;
-    int batch_workers = 4;
+    int batch_workers = 8;
     void* ws = nullptr;
     size_t ws_bytes = 0;
     int ws_owned = 0;

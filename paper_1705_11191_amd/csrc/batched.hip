@@ -6,13 +6,15 @@
 // own workspace, takes problems largest first (longest-processing-time order)
 // and runs the single-problem driver on them, so that the many small kernels of
 // small problems overlap on the device.  Kernels whose workgroups wait on each
-// other pass a gate while a batch is active (one at a time on the device), and
+// other pass a gate while a batch is active (together at most half of their
+// resident capacity, so all admitted ones fit on the device at once), and
 // the panel factorization of step (1) takes its per-column path, so that no two
 // waiting kernels can hold the device between them.
 #include "api_internal.h"
 
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -24,6 +26,8 @@ namespace {
 
 std::atomic<int> g_batch_depth{0};
 std::mutex g_persistent_mu;
+std::condition_variable g_persistent_cv;
+int g_persistent_used = 0;   // workgroups of admitted persistent kernels
 
 struct BatchDepth {
     BatchDepth() { g_batch_depth.fetch_add(1); }
@@ -89,18 +93,26 @@ int run_pool(elsi_gpu_handle_s* h, int count, const int* n, int* status, Fn fn)
 
 bool batch_mode_active() { return g_batch_depth.load(std::memory_order_relaxed) > 0; }
 
-bool persistent_enter()
+bool persistent_enter(int workgroups, int capacity)
 {
     if (!batch_mode_active()) return false;
-    g_persistent_mu.lock();
+    const int budget = std::max(1, capacity / 2);
+    std::unique_lock<std::mutex> lk(g_persistent_mu);
+    // a kernel larger than the budget is admitted alone
+    g_persistent_cv.wait(lk, [&] { return g_persistent_used == 0 || g_persistent_used + workgroups <= budget; });
+    g_persistent_used += workgroups;
     return true;
 }
 
-void persistent_leave(hipStream_t st, bool entered)
+void persistent_leave(hipStream_t st, bool entered, int workgroups)
 {
     if (!entered) return;
     (void)hipStreamSynchronize(st);
-    g_persistent_mu.unlock();
+    {
+        std::lock_guard<std::mutex> lk(g_persistent_mu);
+        g_persistent_used -= workgroups;
+    }
+    g_persistent_cv.notify_all();
 }
 
 }  // namespace eg

@@ -73,11 +73,15 @@ __device__ __forceinline__ double wave_sum_dpp(double v)
 // Batched calls run several problems at once from host worker threads on
 // their own streams.  While such a call is active, kernels whose workgroups
 // wait on one another (persistent cooperative kernels) are admitted to the
-// device one at a time: enter() takes the gate, leave() waits for the kernel
-// on its stream and releases it.  Outside batched calls both are no-ops.
+// device through a gate counted in workgroups: all admitted kernels together
+// hold at most half of the kernel's resident capacity (`capacity` workgroups
+// on the whole device), so every one of them can be fully resident at once
+// whatever the interleaving of their dispatch.  enter() blocks until the
+// workgroups fit; leave() waits for the kernel on its stream and releases
+// them.  Outside batched calls both are no-ops.
 bool batch_mode_active();
-bool persistent_enter();
-void persistent_leave(hipStream_t st, bool entered);
+bool persistent_enter(int workgroups, int capacity);
+void persistent_leave(hipStream_t st, bool entered, int workgroups);
 
 // Optional device timing of individual launches (off by default).  While it is
 // enabled, the GEMM launchers bracket every launch with a pair of events on the

@@ -257,15 +257,20 @@ int sb2st(hipStream_t st, int n, int b, double* Bd, int ldb, double* d, double* 
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sb2st_kernel, SBT, 0);
         int resident = std::max(1, cus * std::max(1, per_cu));
-        int grid = std::min(nsweeps, std::min(resident, cus > 0 ? cus : 1));
+        // sweep s starts two tasks after sweep s-1, so a workgroup that takes
+        // sweep s + grid after finishing sweep s (ntasks(0) tasks) never holds the
+        // pipeline back once grid >= ntasks(0) / 2; a few spare workgroups absorb
+        // uneven timing
+        const int need = ((n - 2) / b + 1) / 2 + 8;
+        int grid = std::min(nsweeps, std::min(std::min(resident, cus > 0 ? cus : 1), need));
         SbArgs a;
         a.n = n; a.b = b; a.ldb = ldb; a.nsweeps = nsweeps; a.kmax = sb2st_kmax(n, b);
         a.Bd = Bd; a.V2 = V2; a.tau2 = tau2; a.progress = progress; a.err = err;
         a.spin_limit = 1LL << 22;
         void* args[] = {&a};
-        const bool gated = persistent_enter();
+        const bool gated = persistent_enter(grid, resident);
         hipError_t rc = hipLaunchCooperativeKernel((const void*)sb2st_kernel, dim3(grid), dim3(SBT), args, 0, st);
-        persistent_leave(st, gated);
+        persistent_leave(st, gated, grid);
         if (rc != hipSuccess) return kStatusHip;
     }
     hipLaunchKernelGGL(extract_tridiag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, Bd, ldb, d, e);
