@@ -102,7 +102,7 @@ def test_cholesky_reports_first_bad_pivot():
     assert B.cholesky(St) == 151
 
 
-@pytest.mark.parametrize("n", [3, 64, 129, 300])
+@pytest.mark.parametrize("n", [3, 64, 129, 300, 700, 1100, 1600])
 def test_reduce_vs_oracle(n):
     from paper_1705_11191_amd import binding as B
 
