@@ -189,10 +189,9 @@ int elsi_gpu_x_reduce(int n, double* H, int ldh, const double* L, int ldl, void*
     if (!L) return -4;
     if (ldl < n) return -5;
     hipStream_t st = (hipStream_t)hip_stream;
-    DevBuf<double> Linv, work;
-    if (!Linv.alloc((size_t)ceil_div(n, 64) * 64 * 64) || !work.alloc(reduce_workspace_doubles(n)))
-        return ELSI_GPU_ERR_OOM;
-    reduce_to_standard(st, n, H, ldh, L, ldl, Linv.p, work.p);
+    DevBuf<double> Linv;
+    if (!Linv.alloc((size_t)ceil_div(n, 64) * 64 * 64)) return ELSI_GPU_ERR_OOM;
+    reduce_to_standard(st, n, H, ldh, L, ldl, Linv.p);
     return sync_status(st);
 }
 

@@ -31,9 +31,7 @@ inline int sync_status(hipStream_t st)
 }
 
 // H <- L^-1 H L^-T (full symmetric on exit); Linv receives the 64 x 64 block inverses.
-size_t reduce_workspace_doubles(int n);
-void reduce_to_standard(hipStream_t st, int n, double* H, int ldh, const double* L, int ldl, double* Linv,
-                        double* work);
+void reduce_to_standard(hipStream_t st, int n, double* H, int ldh, const double* L, int ldl, double* Linv);
 
 // D = (C sqrt(f)) (C sqrt(f))^T, both triangles; W is n x k scratch.
 void density_matrix(hipStream_t st, int n, int k, const double* C, int ldc, const double* f, double* W,

@@ -66,6 +66,44 @@ __device__ __forceinline__ double wave_sum_dpp(double v)
     return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
 }
 
+// X = L^-1 for the lower triangular jb x jb block L (zero beyond jb, jb <= 64,
+// LDS arrays of pitch 65), by the NT threads of one workgroup: X_cc = 1 / L_cc,
+// then for adjacent blocks A (first) and B of doubling size 2^lg
+// X_BA = -X_BB (L_BA X_AA); Y is LDS scratch.  Only the lower triangle of L is
+// read.
+template <int NT>
+__device__ inline void tri_inverse_lower64(int jb, double (*Lm)[65], double (*X)[65], double (*Y)[65])
+{
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 64 * 64; e += NT) {
+        const int r = e & 63, c = e >> 6;
+        X[r][c] = (r == c && r < jb) ? 1.0 / Lm[r][r] : 0.0;
+    }
+    __syncthreads();
+    for (int lg = 0; lg < 6; ++lg) {
+        const int sz = 1 << lg;
+        const int nout = 32 << lg;   // (64 / 2sz) pairs of sz x sz blocks
+        for (int e = tid; e < nout; e += NT) {
+            const int pr = e >> (2 * lg), rem = e & (sz * sz - 1);
+            const int bb = rem & (sz - 1), a = rem >> lg;
+            const int p0 = pr << (lg + 1), pb = p0 + sz;
+            double y = 0.0;
+            for (int ii = a; ii < sz; ++ii) y += Lm[pb + bb][p0 + ii] * X[p0 + ii][p0 + a];
+            Y[pb + bb][p0 + a] = y;
+        }
+        __syncthreads();
+        for (int e = tid; e < nout; e += NT) {
+            const int pr = e >> (2 * lg), rem = e & (sz * sz - 1);
+            const int bb = rem & (sz - 1), a = rem >> lg;
+            const int p0 = pr << (lg + 1), pb = p0 + sz;
+            double t = 0.0;
+            for (int jj = 0; jj <= bb; ++jj) t += X[pb + bb][pb + jj] * Y[pb + jj][p0 + a];
+            X[pb + bb][p0 + a] = -t;
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers implemented in the .hip files
 // ---------------------------------------------------------------------------

@@ -15,40 +15,6 @@ namespace {
 constexpr int NB = 64;     // diagonal block
 constexpr int NBO = 512;   // outer panel
 
-// X = L^-1 for the lower triangular jb x jb block L (zero beyond jb), in one
-// workgroup of 256 threads: X_cc = 1 / L_cc, then for adjacent blocks A (first)
-// and B of doubling size X_BA = -X_BB (L_BA X_AA); Y is LDS scratch.
-__device__ void tri_inverse_lds(int jb, double (*Lm)[NB + 1], double (*X)[NB + 1], double (*Y)[NB + 1])
-{
-    const int tid = threadIdx.x;
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int r = e % NB, c = e / NB;
-        X[r][c] = (r == c && r < jb) ? 1.0 / Lm[r][r] : 0.0;
-    }
-    __syncthreads();
-    for (int sz = 1; sz < NB; sz *= 2) {
-        const int nout = (NB / (2 * sz)) * sz * sz;
-        for (int e = tid; e < nout; e += 256) {
-            const int pr = e / (sz * sz), rem = e % (sz * sz);
-            const int bb = rem % sz, a = rem / sz;
-            const int p0 = pr * 2 * sz, pb = p0 + sz;
-            double y = 0.0;
-            for (int ii = a; ii < sz; ++ii) y += Lm[pb + bb][p0 + ii] * X[p0 + ii][p0 + a];
-            Y[pb + bb][p0 + a] = y;
-        }
-        __syncthreads();
-        for (int e = tid; e < nout; e += 256) {
-            const int pr = e / (sz * sz), rem = e % (sz * sz);
-            const int bb = rem % sz, a = rem / sz;
-            const int p0 = pr * 2 * sz, pb = p0 + sz;
-            double t = 0.0;
-            for (int jj = 0; jj <= bb; ++jj) t += X[pb + bb][pb + jj] * Y[pb + jj][p0 + a];
-            X[pb + bb][p0 + a] = -t;
-        }
-        __syncthreads();
-    }
-}
-
 // Factor the jb x jb diagonal block at (j0, j0) in LDS and write L and L^-1.
 __global__ __launch_bounds__(256) void potf2_inv_kernel(int jb, int j0, double* A, int lda,
                                                         double* Linv, int* info)
@@ -89,7 +55,7 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(int jb, int j0, double* 
         __syncthreads();
     }
     if (bad) return;
-    tri_inverse_lds(jb, L, X, Y);
+    tri_inverse_lower64<256>(jb, L, X, Y);
     for (int e = tid; e < NB * NB; e += 256) {
         int i = e % NB, c = e / NB;
         if (i < jb && c < jb && i >= c) A[cm(j0 + i, j0 + c, lda)] = L[i][c];
@@ -112,7 +78,7 @@ __global__ __launch_bounds__(256) void trtri_blocks_kernel(int n, const double* 
         Ls[i][c] = (i < jb && c < jb && i >= c) ? L[cm(j0 + i, j0 + c, ldl)] : 0.0;
     }
     __syncthreads();
-    tri_inverse_lds(jb, Ls, X, Y);
+    tri_inverse_lower64<256>(jb, Ls, X, Y);
     double* out = Linv + (size_t)blk * NB * NB;
     for (int e = tid; e < NB * NB; e += 256) out[e] = X[e % NB][e / NB];
 }

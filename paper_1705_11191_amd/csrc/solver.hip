@@ -9,67 +9,16 @@
 
 namespace eg {
 
-// Eq. (11): H~ = L^-1 H L^-T, by the blocked two-sided recurrence.  With
-// H and L split at a block of width w into H11, H21, H22 and L11, L21, L22:
-//   H~11 = L11^-1 H11 L11^-T,
-//   Y    = H21 L11^-T - L21 H~11,
-//   H~21 = L22^-1 Y,
-//   H~22 = L22^-1 (H22 - Y' L21^T - L21 Y'^T) L22^-T,  Y' = H21 L11^-T - L21 H~11 / 2,
-// so each block costs one lower-triangle product of K = 2w, and the solves
-// H~21 = L22^-1 Y (nothing later reads H~21) are gathered into one solve of the
-// strictly block-lower part by L at the end: L^-1 applied to a block column
-// that vanishes above row block k + 1 only involves L22 of block k.  Total
-// n^3 flops against 4n^3/3 for the two full triangular solves.  Only the lower
-// triangle of H is read; work holds reduce_workspace_doubles(n) doubles.
-static constexpr int kRedW = 512;
-
-size_t reduce_workspace_doubles(int n)
+// Eq. (11): W = L^-1 H, then the lower triangle of H~ = W L^-T, mirrored.
+// (The blocked two-sided recurrence needs only n^3 flops against 4n^3/3 here,
+// but its intermediate H21 L11^-T - L21 H~11 carries the large entries of H~
+// that an ill-conditioned S creates and loses accuracy to cancellation.)
+void reduce_to_standard(hipStream_t st, int n, double* H, int ldh, const double* L, int ldl, double* Linv)
 {
-    const int w = std::min(kRedW, n);
-    return (size_t)std::max(n - w, 1) * 3 * (size_t)std::max(w, 1);
-}
-
-void reduce_to_standard(hipStream_t st, int n, double* H, int ldh, const double* L, int ldl, double* Linv,
-                        double* work)
-{
-    if (n <= 0) return;
     dtrtri_diag_blocks(st, n, L, ldl, Linv);
-    for (int k0 = 0; k0 < n; k0 += kRedW) {
-        const int kb = std::min(kRedW, n - k0);
-        const int r0 = k0 + kb, m = n - r0;
-        double* A11 = H + cm(k0, k0, ldh);
-        const double* L11 = L + cm(k0, k0, ldl);
-        const double* Li = Linv + (size_t)(k0 / 64) * 64 * 64;
-        // diagonal block: its upper triangle is stale after the lower-tile updates
-        mirror_lower_to_upper(st, kb, A11, ldh);
-        dtrsm_left_lower_n(st, kb, kb, L11, ldl, Li, A11, ldh);
-        dtrsm_right_lower_t_lowerpart(st, kb, L11, ldl, Li, A11, ldh);
-        mirror_lower_to_upper(st, kb, A11, ldh);
-        if (m == 0) break;
-        double* A21 = H + cm(r0, k0, ldh);
-        const double* L21 = L + cm(r0, k0, ldl);
-        dtrsm_right_lower_t(st, m, kb, L11, ldl, Li, A21, ldh);
-        dgemm(st, 'N', 'N', m, kb, kb, -0.5, L21, ldl, A11, ldh, 1.0, A21, ldh);
-        // work = [Y' | L21 | Y'], so that columns [0, 2kb) times columns
-        // [kb, 3kb) transposed is Y' L21^T + L21 Y'^T
-        double* W0 = work;
-        double* W1 = work + (size_t)m * kb;
-        double* W2 = work + (size_t)2 * m * kb;
-        copy_matrix(st, m, kb, A21, ldh, W0, m);
-        copy_matrix(st, m, kb, L21, ldl, W1, m);
-        copy_matrix(st, m, kb, A21, ldh, W2, m);
-        dgemm(st, 'N', 'T', m, m, 2 * kb, -1.0, W0, m, W1, m, 1.0, H + cm(r0, r0, ldh), ldh, 1);
-        dgemm(st, 'N', 'N', m, kb, kb, -0.5, L21, ldl, A11, ldh, 1.0, A21, ldh);
-    }
-    // strictly block-lower part <- L^-1 (strictly block-lower part): row block
-    // I spans the columns of the earlier blocks only
-    for (int I0 = kRedW; I0 < n; I0 += kRedW) {
-        const int IB = std::min(kRedW, n - I0);
-        dtrsm_left_lower_n(st, IB, I0, L + cm(I0, I0, ldl), ldl, Linv + (size_t)(I0 / 64) * 64 * 64, H + I0, ldh);
-        const int t0 = I0 + IB;
-        if (t0 < n)
-            dgemm(st, 'N', 'N', n - t0, I0, IB, -1.0, L + cm(t0, I0, ldl), ldl, H + I0, ldh, 1.0, H + t0, ldh);
-    }
+    mirror_lower_to_upper(st, n, H, ldh);   // only the lower triangle of H is read
+    dtrsm_left_lower_n(st, n, n, L, ldl, Linv, H, ldh);
+    dtrsm_right_lower_t_lowerpart(st, n, L, ldl, Linv, H, ldh);
     mirror_lower_to_upper(st, n, H, ldh);
 }
 
@@ -230,7 +179,7 @@ static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, cons
             }
         }
         tm.mark(ELSI_GPU_ST_CHOLESKY);
-        reduce_to_standard(st, n, H, n, S, n, Linv, (double*)(ws + L.z));
+        reduce_to_standard(st, n, H, n, S, n, Linv);
     } else {
         tm.mark(ELSI_GPU_ST_CHOLESKY);
         mirror_lower_to_upper(st, n, H, n);

@@ -11,11 +11,15 @@
 // (Y by a symmetric product) and updated (the rank-2b update skips tiles
 // above the diagonal).
 //
-// The panel QR uses one kernel launch per column.  A reflector for column c
-// needs x = P(c:m, c) only through x^T P(c:m, r) (r >= c), so each launch
-// (1) reduces the per-workgroup partial Gram row of column c left by the
-// previous launch, (2) applies reflector c to its rows, and (3) forms the
-// partial Gram row of column c+1 -- one grid-wide reduction per column.
+// The panel QR first tries two CholeskyQR passes with Householder
+// reconstruction in one cooperative launch (five grid-wide reductions per
+// panel), accepted only for well-conditioned panels.  Otherwise it takes
+// Householder reflectors column by column: a reflector for column c needs
+// x = P(c:m, c) only through x^T P(c:m, r) (r >= c), so each step (1) reduces
+// the per-workgroup partial Gram row of column c left by the previous step,
+// (2) applies reflector c to its rows, and (3) forms the partial Gram row of
+// column c+1 -- one grid-wide reduction per column, in one cooperative launch
+// (or one launch per column in batched calls).
 #include "common.h"
 
 namespace eg {
@@ -32,8 +36,9 @@ __device__ inline double wave_sum(double v) { return wave_sum_dpp(v); }
 __global__ __launch_bounds__(PR) void panel_step_kernel(int m, int bw, int c, double* P, int ldp,
                                                         const double* __restrict__ gin, double* gout,
                                                         const double* __restrict__ rin, double* rout,
-                                                        double* tau, int nblk)
+                                                        double* tau, int nblk, const int* skip)
 {
+    if (*skip) return;   // the panel was already factored by the CholeskyQR2 kernel
     __shared__ double G[BMAX + 1];
     __shared__ double scoef[BMAX];
     __shared__ double red[PR / 64][BMAX + 1];
@@ -152,13 +157,15 @@ __device__ inline void bst(__amdgpu_buffer_rsrc_t r, int elem, double v)
 // by a grid barrier (a monotonic arrival counter with a bounded wait).
 __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr, double* P, int ldp,
                                                            double* gbuf, double* rbuf, double* tau,
-                                                           int* counter, int* err, int nblk)
+                                                           int* counter, int* err, int nblk, const int* skip)
 {
+    if (*skip) return;   // the panel was already factored by the CholeskyQR2 kernel
     __shared__ double G[BMAX + 1];
     __shared__ double scoef[BMAX];
     __shared__ double red[PR / 64][BMAX + 1];
     __shared__ double sh[4];
     __shared__ double prow[BMAX];
+    __shared__ double tau_sh[BMAX];
     __shared__ int bad;
     const int tid = threadIdx.x;
     const int blk = blockIdx.x;
@@ -233,7 +240,7 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
                     den = x0 - alpha;
                 }
                 sh[0] = t; sh[1] = alpha; sh[2] = den;
-                if (blk == 0) tau[c] = t;
+                tau_sh[c] = t;
             }
             __syncthreads();
             const double t = sh[0], alpha = sh[1], den = sh[2];
@@ -246,10 +253,13 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
                 // xn of the previous step is this row's entry in column c
                 const double vi = (i == c) ? 1.0 : ((t != 0.0) ? xn / den : 0.0);
                 const double tv = t * vi;
+                // column c is final for this row: alpha on the diagonal, v below
+                // it.  It stays in rowv[c] (no later update touches it, scoef[c]
+                // being zero) and reaches P with the rest of the row at the end: a
+                // store here would make the next step wait for its completion.
+                const double fin = (i == c) ? alpha : vi;
 #pragma unroll
-                for (int r = 0; r < BMAX; ++r) rowv[r] -= tv * scoef[r];
-                // column c is final for this row: alpha on the diagonal, v below it
-                P[cm(i, c, ldp)] = (i == c) ? alpha : vi;
+                for (int r = 0; r < BMAX; ++r) rowv[r] = (r == c) ? fin : rowv[r] - tv * scoef[r];
             }
         }
         const int cn = c + 1;
@@ -331,13 +341,388 @@ __global__ __launch_bounds__(PR) void panel_qr_coop_kernel(int m, int bw, int nr
             if (bad) return;
         }
     }
-    // write back the entries not yet final in P: R above the diagonal and the
-    // columns that needed no reflector
+    // the row into P: R above the diagonal, alpha on it, v below it, and the
+    // columns that needed no reflector; the reflector factors of workgroup 0
     if (i < m) {
 #pragma unroll
         for (int r = 0; r < BMAX; ++r)
-            if (r < bw && !(r < nr && i >= r)) P[cm(i, r, ldp)] = rowv[r];
+            if (r < bw) P[cm(i, r, ldp)] = rowv[r];
     }
+    if (blk == 0 && tid < nr) tau[tid] = tau_sh[tid];
+}
+
+// ---------------------------------------------------------------------------
+// Panel QR in a few grid-wide steps: CholeskyQR2 and Householder reconstruction
+// ---------------------------------------------------------------------------
+// For a well-conditioned panel P (m x 64), two CholeskyQR passes give P = Q R
+// with Q orthonormal to working precision: G = P^T P = L L^T, Q' = P L^-T,
+// then the same for Q' (R = R2 R1 with R_i = L_i^T).  The reflectors follow
+// from Q alone (Householder reconstruction): the LU factorization without
+// pivoting Q1 - S = L U of the top 64 x 64 block, with the sign S_cc = -sign
+// of the c-th pivot chosen during the elimination so that every pivot has
+// magnitude at least 1, gives V = [L; Q2 U^-1] (unit lower trapezoidal) with
+// (I - V T V^T)[:, 0:64] = Q S, hence P = (I - V T V^T) [S R; 0].  The output
+// has the layout of the column-by-column kernel: S R on and above the
+// diagonal of the top block, V below it; T follows from V (tau_c = 2 / v_c^T v_c).
+//
+// The whole panel takes five grid barriers instead of one per column.  Every
+// workgroup factors the 64 x 64 Gram matrices itself (identical inputs and
+// code, so identical bits everywhere); workgroup 0 forms R and the LU and
+// shares U^T.
+//
+// Gram-matrix methods lose the small components of panels whose rows differ
+// greatly in size (the reduced matrix of an ill-conditioned overlap is such a
+// case), where Householder QR keeps them; accepting every panel whose first
+// pass left the columns within 0.1 of orthonormal cost five orders of
+// magnitude in the density matrix of such pencils.  So a panel is taken only
+// when the first pass already left them orthonormal to kCholQrAccept (a panel
+// condition number of order 100 or less); any other panel (and one whose
+// Cholesky factorization breaks down) is left untouched with *status at 0,
+// and the column-by-column kernel factors it.
+constexpr double kCholQrAccept = 1e-12;
+constexpr int CQ_TILES = 10;               // 16 x 16 tiles on and above the diagonal of a 64 x 64 Gram
+constexpr int CQ_REC = CQ_TILES * 256;     // doubles per partial Gram record
+constexpr int LP = BMAX + 1;               // LDS pitch
+
+__device__ inline void cq_tile(int t, int& I, int& J)
+{
+    I = t < 4 ? 0 : (t < 7 ? 1 : (t < 9 ? 2 : 3));
+    J = t < 4 ? t : (t < 7 ? t - 3 : (t < 9 ? t - 5 : 3));
+}
+
+// Grid barrier (monotonic arrival counter, bounded wait).  False on a
+// time-out or when another workgroup reported one.
+__device__ inline bool cq_grid_sync(int* counter, int* err, int& arrive, int nblk, int* bad)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    arrive += nblk;
+    if (threadIdx.x == 0) {
+        *bad = 0;
+        __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        long long spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < arrive) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { *bad = 1; break; }
+            if (++spins > (1LL << 22)) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                *bad = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    return *bad == 0;
+}
+
+constexpr int CQ_NT = 128;   // panel rows (threads) per workgroup
+
+__device__ inline double cq_readlane(double v, int l)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+
+// Orders a wave's LDS accesses across lanes (one wave needs no workgroup barrier).
+__device__ inline void cq_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cholesky G = L L^T of the symmetric 64 x 64 matrix in LDS by one wave, lane
+// r holding row r in registers; each step broadcasts its scaled column
+// through col.  L (lower, with its diagonal) replaces the lower triangle of G.
+// False at a pivot that is not positive and finite (the same in every lane).
+__device__ bool cq_cholesky_wave(double (*__restrict__ G)[LP], double* __restrict__ col)
+{
+    const int lane = threadIdx.x & 63;
+    double g[BMAX];
+#pragma unroll
+    for (int q = 0; q < BMAX; ++q) g[q] = G[lane][q];
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < BMAX; ++c) {
+        const double d = cq_readlane(g[c], c);
+        if (!(d > 0.0) || !isfinite(d)) {
+            ok = false;
+            break;
+        }
+        const double s = sqrt(d);
+        const double l = (lane == c) ? s : g[c] / s;   // lanes below c: L(r, c)
+        g[c] = l;
+        col[lane] = (lane > c) ? l : 0.0;
+        cq_wave_sync();
+#pragma unroll
+        for (int q = c + 1; q < BMAX; ++q) g[q] -= l * col[q];   // only q <= r is kept
+        cq_wave_sync();
+    }
+    if (ok) {
+#pragma unroll
+        for (int q = 0; q < BMAX; ++q)
+            if (q <= lane) G[lane][q] = g[q];
+    }
+    return ok;
+}
+
+// LU without pivoting of A - S by one wave (lane r holding row r of A in a),
+// S_cc = -sign of the c-th pivot (+1 taken as the sign of 0); the pivot row
+// of each step is read from lane c.  On return a holds L strictly below the
+// diagonal (unit diagonal implied) and U on and above it; sgn gets S.
+__device__ void cq_signed_lu_wave(double (&a)[BMAX], double* __restrict__ sgn)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < BMAX; ++c) {
+        const double u = cq_readlane(a[c], c);
+        const double s = (u >= 0.0) ? -1.0 : 1.0;
+        const double pv = u - s;   // |pv| = |u| + 1
+        const double lm = (lane > c) ? a[c] / pv : 0.0;
+        a[c] = (lane > c) ? lm : ((lane == c) ? pv : a[c]);
+        if (lane == 0) sgn[c] = s;
+#pragma unroll
+        for (int q = c + 1; q < BMAX; ++q) a[q] -= lm * cq_readlane(a[q], c);
+    }
+}
+
+// x <- x M^-T for a lower triangular M in LDS (z M^T = x by substitution in
+// blocks of 8 columns; dinv holds 1 / M_kk): with M = L it is one CholeskyQR
+// step x L^-T, with M = U^T it is x U^-1.
+__device__ inline void cq_row_solve(double (&x)[BMAX], const double (*__restrict__ M)[LP],
+                                    const double* __restrict__ dinv)
+{
+#pragma unroll
+    for (int kb = 0; kb < BMAX; kb += 8) {
+#pragma unroll
+        for (int k = kb; k < kb + 8; ++k) {
+            x[k] *= dinv[k];
+#pragma unroll
+            for (int c = k + 1; c < kb + 8; ++c) x[c] -= x[k] * M[c][k];
+        }
+#pragma unroll
+        for (int c = kb + 8; c < BMAX; ++c) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) x[c] -= x[kb + j] * M[c][kb + j];
+        }
+    }
+}
+
+// One thread per panel row (CQ_NT rows per workgroup, m >= 64, 64 columns).
+// rec holds nblk partial Gram records, the summed record, U^T and the
+// first-pass factor L1 (written and read by workgroup 0 only).
+__global__ __launch_bounds__(CQ_NT, 1) void panel_cholqr_kernel(int m, double* P, int ldp, double* rec,
+                                                                int* counter, int* err, int* status, int nblk,
+                                                                double thr)
+{
+    constexpr int NT = CQ_NT;
+    constexpr int NW = NT / 64;
+    constexpr int TPW = (CQ_TILES + NW - 1) / NW;   // Gram tiles per wave
+    __shared__ double Gb[BMAX][LP];   // Gram matrix, then its Cholesky factor; the LU (workgroup 0)
+    __shared__ double Xb[BMAX][LP];   // R (workgroup 0), then U^T
+    __shared__ double St[NT][LP];     // the rows: operand staging of the Gram products, parking
+    __shared__ double red[NT];
+    __shared__ double sgn[BMAX];
+    __shared__ double colv[BMAX];
+    __shared__ double dinv[BMAX];
+    __shared__ int bad;
+    __shared__ int flag;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int blk = blockIdx.x;
+    const int i = blk * NT + tid;
+    const int gfin = nblk * CQ_REC;   // element offsets: summed record, U^T, L1
+    const int mgo = gfin + CQ_REC;
+    const int l1o = mgo + BMAX * BMAX;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        rec, (short)0, (int)(((size_t)l1o + BMAX * BMAX) * 8), 0x00020000);
+
+    double x[BMAX];
+#pragma unroll
+    for (int r = 0; r < BMAX; ++r) x[r] = (i < m) ? P[cm(i, r, ldp)] : 0.0;
+    int arrive = 0;
+
+    for (int ph = 0; ph < 3; ++ph) {
+        // park the rows in LDS (the Gram products read them there; the 64 x 64
+        // factorizations need the registers)
+#pragma unroll
+        for (int r = 0; r < BMAX; ++r) St[tid][r] = x[r];
+        __syncthreads();
+        if (ph < 2) {
+            // partial Gram matrix of this workgroup's rows on the matrix cores
+            double4_t acc[TPW];
+#pragma unroll
+            for (int s = 0; s < TPW; ++s) acc[s] = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+            for (int kk = 0; kk < NT; kk += 4) {
+                const int kr = kk + (lane >> 4);
+#pragma unroll
+                for (int s = 0; s < TPW; ++s) {
+                    const int t = wave + NW * s;
+                    if (t < CQ_TILES) {
+                        int I, J;
+                        cq_tile(t, I, J);
+                        const double a = St[kr][16 * I + (lane & 15)];
+                        const double b = St[kr][16 * J + (lane & 15)];
+                        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < TPW; ++s) {
+                const int t = wave + NW * s;
+                if (t < CQ_TILES) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) bst(rs, blk * CQ_REC + t * 256 + r * 64 + lane, acc[s][r]);
+                }
+            }
+            if (!cq_grid_sync(counter, err, arrive, nblk, &bad)) return;
+            // fixed-order sums of the records: this workgroup takes entries
+            // [e0, e0 + E), each split over S threads by record index mod S
+            {
+                const int E = (CQ_REC + nblk - 1) / nblk;
+                const int S = (E <= NT) ? NT / E : 1;
+                const int e0 = blk * E;
+                for (int w = tid; w < E * S; w += NT) {
+                    const int el = w % E, sp = w / E, e = e0 + el;
+                    double sum = 0.0;
+                    if (e < CQ_REC) {
+                        int p = sp;
+                        for (; p + 7 * S < nblk; p += 8 * S) {
+                            double v[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) v[u] = bld(rs, (p + u * S) * CQ_REC + e);
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) sum += v[u];
+                        }
+                        for (; p < nblk; p += S) sum += bld(rs, p * CQ_REC + e);
+                    }
+                    if (S > 1) red[w] = sum;
+                    else if (e < CQ_REC) bst(rs, gfin + e, sum);
+                }
+                if (S > 1) {
+                    __syncthreads();
+                    if (tid < E && e0 + tid < CQ_REC) {
+                        double sum = 0.0;
+                        for (int sp = 0; sp < S; ++sp) sum += red[sp * E + tid];
+                        bst(rs, gfin + e0 + tid, sum);
+                    }
+                }
+            }
+            if (!cq_grid_sync(counter, err, arrive, nblk, &bad)) return;
+            {
+                // the summed record, all loads in flight together
+                constexpr int PER = CQ_REC / NT;
+                double v[PER];
+#pragma unroll
+                for (int u = 0; u < PER; ++u) v[u] = bld(rs, gfin + tid + u * NT);
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int e = tid + u * NT;
+                    const int t = e >> 8, r = (e >> 6) & 3, l = e & 63;
+                    int I, J;
+                    cq_tile(t, I, J);
+                    const int row = 16 * I + 4 * r + (l >> 4), col = 16 * J + (l & 15);
+                    if (I != J || row >= col) {
+                        Gb[row][col] = v[u];
+                        Gb[col][row] = v[u];
+                    }
+                }
+            }
+            __syncthreads();
+            if (ph == 1) {
+                double dev = 0.0;
+                for (int e = tid; e < BMAX * BMAX; e += NT) {
+                    const int r = e & 63, c = e >> 6;
+                    const double d = fabs(Gb[r][c] - (r == c ? 1.0 : 0.0));
+                    dev = (d > dev || d != d) ? d : dev;   // a NaN counts as a large deviation
+                }
+                red[tid] = dev;
+                __syncthreads();
+                if (tid == 0) {
+                    double mx = 0.0;
+                    for (int t = 0; t < NT; ++t) mx = (red[t] > mx || red[t] != red[t]) ? red[t] : mx;
+                    flag = (mx <= thr) ? 1 : 0;
+                }
+                __syncthreads();
+                if (!flag) return;
+            }
+            if (wave == 0) {
+                const bool ok = cq_cholesky_wave(Gb, colv);
+                if (lane == 0) flag = ok ? 1 : 0;
+            }
+            __syncthreads();
+            if (!flag) return;
+            if (tid < BMAX) dinv[tid] = 1.0 / Gb[tid][tid];
+            if (ph == 0 && blk == 0) {
+                for (int e = tid; e < BMAX * BMAX; e += NT) {
+                    const int r = e & 63, c = e >> 6;
+                    bst(rs, l1o + e, (r >= c) ? Gb[r][c] : 0.0);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < BMAX; ++r) x[r] = St[tid][r];
+            cq_row_solve(x, Gb, dinv);   // x <- x L^-T
+        } else {
+            if (blk == 0 && wave == 0) {
+                // R = R2 R1 = L2^T L1^T, lane c forming column c:
+                // R(r, c) = sum_k L2(k, r) L1(c, k)
+                {
+                    double l1[BMAX];
+#pragma unroll
+                    for (int k = 0; k < BMAX; ++k) l1[k] = bld(rs, l1o + lane + 64 * k);
+#pragma unroll
+                    for (int r = 0; r < BMAX; ++r) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int k = r; k < BMAX; ++k) s += Gb[k][r] * l1[k];
+                        Xb[r][lane] = s;
+                    }
+                }
+                // Q1 = rows 0..63 of the panel = the rows of wave 0
+                double a[BMAX];
+#pragma unroll
+                for (int q = 0; q < BMAX; ++q) a[q] = St[lane][q];
+                cq_signed_lu_wave(a, sgn);
+#pragma unroll
+                for (int q = 0; q < BMAX; ++q) Gb[lane][q] = a[q];
+            }
+            __syncthreads();
+            if (blk == 0) {
+                for (int e = tid; e < BMAX * BMAX; e += NT) {
+                    const int r = e & 63, c = e >> 6;
+                    if (r < m) P[cm(r, c, ldp)] = (r <= c) ? sgn[r] * Xb[r][c] : Gb[r][c];
+                    bst(rs, mgo + e, (r >= c) ? Gb[c][r] : 0.0);   // U^T
+                }
+            }
+            if (!cq_grid_sync(counter, err, arrive, nblk, &bad)) return;
+            {
+                constexpr int PER = BMAX * BMAX / NT;
+                double v[PER];
+#pragma unroll
+                for (int u = 0; u < PER; ++u) v[u] = bld(rs, mgo + tid + u * NT);
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int e = tid + u * NT;
+                    Xb[e & 63][e >> 6] = v[u];
+                }
+            }
+            __syncthreads();
+            if (tid < BMAX) dinv[tid] = 1.0 / Xb[tid][tid];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < BMAX; ++r) x[r] = St[tid][r];
+            if (i >= BMAX) cq_row_solve(x, Xb, dinv);   // V2 = Q2 U^-1
+        }
+        __syncthreads();
+    }
+    if (i >= BMAX && i < m) {
+#pragma unroll
+        for (int c = 0; c < BMAX; ++c) P[cm(i, c, ldp)] = x[c];
+    }
+    if (blk == 0 && tid == 0) *status = 1;
 }
 
 // Explicit V (m x bw, unit lower trapezoidal) of the panel into V (ld ldv),
@@ -355,11 +740,11 @@ __global__ void panel_store_v_kernel(int m, int bw, int nr, const double* P, int
 }
 
 // T (upper triangular, bw x bw, ld ldt) of Q = H_0 ... H_{bw-1} = I - V T V^T
-// from G = V^T V and tau.  T_cc = tau_c, and for two adjacent blocks of
+// from G = V^T V and tau (or 2 / G_cc when *gram_tau is set).  T_cc = tau_c, and for two adjacent blocks of
 // reflectors A, B (A first) T_AB = -T_AA G_AB T_BB; the blocks double in size
 // from 1 to 32, each level two parallel small products over 256 threads.
 __global__ __launch_bounds__(256) void build_t_kernel(int bw, const double* G, int ldg, const double* tau,
-                                                       double* T, int ldt)
+                                                       double* T, int ldt, const int* gram_tau)
 {
     __shared__ double Ts[BMAX][BMAX + 1];
     __shared__ double Gs[BMAX][BMAX + 1];
@@ -368,7 +753,9 @@ __global__ __launch_bounds__(256) void build_t_kernel(int bw, const double* G, i
     for (int e = tid; e < BMAX * BMAX; e += 256) {
         const int r = e % BMAX, c = e / BMAX;
         Gs[r][c] = (r < bw && c < bw) ? G[cm(r, c, ldg)] : 0.0;
-        Ts[r][c] = (r == c && r < bw) ? tau[r] : 0.0;
+        // reflectors from the reconstruction take tau_c = 2 / v_c^T v_c, which makes
+        // each one exactly orthogonal for the stored v_c
+        Ts[r][c] = (r == c && r < bw) ? (*gram_tau ? 2.0 / G[cm(r, r, ldg)] : tau[r]) : 0.0;
     }
     __syncthreads();
     for (int sz = 1; sz < BMAX; sz *= 2) {
@@ -409,6 +796,18 @@ __global__ void extract_band_kernel(int n, int b, const double* A, int lda, doub
     double v = 0.0;
     if (r <= b && c + r < n) v = A[cm(c + r, c, lda)];
     Bd[cm(r, c, ldb)] = v;
+}
+
+int cholqr_max_blocks()
+{
+    static const int cached = [] {
+        int dev = 0, cus = 0, per_cu = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, panel_cholqr_kernel, CQ_NT, 0);
+        return std::max(0, cus * per_cu);
+    }();
+    return cached;
 }
 
 int coop_max_blocks()
@@ -484,9 +883,27 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
         double* P = A + cm(r0, j, lda);
         const int nblk = ceil_div(m, PR);
         bool coop_done = false;
+        // ibuf: per-column kernel counter and error flag, CholeskyQR2 status,
+        // counter and error flag
+        fill_i(st, ibuf, 5, 0);
+        int* cq_status = ibuf + 2;
         // batched calls take the per-column path: its kernels never wait on each other
+        if (!batch_mode_active() && bw == BMAX && nr == BMAX && m >= 2 * BMAX) {
+            int mm = m, ld = lda, nb = 0;
+            double* Pp = P;
+            double* rec = part;
+            int* cnt = ibuf + 3;
+            int* er = ibuf + 4;
+            int* stp = cq_status;
+            double thr = kCholQrAccept;
+            void* args[] = {&mm, &Pp, &ld, &rec, &cnt, &er, &stp, &nb, &thr};
+            nb = ceil_div(m, CQ_NT);
+            if (nb <= cholqr_max_blocks() &&
+                hipLaunchCooperativeKernel((const void*)panel_cholqr_kernel, dim3(nb), dim3(CQ_NT), args, 0, st) !=
+                    hipSuccess)
+                (void)hipGetLastError();
+        }
         if (!batch_mode_active() && nblk <= coop_max_blocks()) {
-            fill_i(st, ibuf, 2, 0);
             int mm = m, bww = bw, nrr = nr, ld = lda, nb = nblk;
             double* Pp = P;
             double* gb = gbuf0;
@@ -494,7 +911,8 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
             double* tp = tau;
             int* cnt = ibuf;
             int* er = ibuf + 1;
-            void* args[] = {&mm, &bww, &nrr, &Pp, &ld, &gb, &rb, &tp, &cnt, &er, &nb};
+            const int* skp = cq_status;
+            void* args[] = {&mm, &bww, &nrr, &Pp, &ld, &gb, &rb, &tp, &cnt, &er, &nb, &skp};
             coop_done = hipLaunchCooperativeKernel((const void*)panel_qr_coop_kernel, dim3(nblk), dim3(PR), args, 0,
                                                    st) == hipSuccess;
             if (!coop_done) (void)hipGetLastError();
@@ -503,12 +921,12 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
             double* gi = gbuf0; double* go = gbuf1;
             double* ri = rbuf0; double* ro = rbuf1;
             hipLaunchKernelGGL(panel_step_kernel, dim3(nblk), dim3(PR), 0, st, m, bw, -1, P, lda, gi, go, ri, ro,
-                               tau, nblk);
+                               tau, nblk, (const int*)cq_status);
             for (int c = 0; c < nr; ++c) {
                 std::swap(gi, go);
                 std::swap(ri, ro);
                 hipLaunchKernelGGL(panel_step_kernel, dim3(nblk), dim3(PR), 0, st, m, bw, c, P, lda, gi, go, ri,
-                                   ro, tau, nblk);
+                                   ro, tau, nblk, (const int*)cq_status);
             }
         }
         if (nr < bw) fill_d(st, tau + nr, (size_t)(bw - nr), 0.0);
@@ -518,7 +936,7 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
                            lda, V, n, zpad);
         double* T = Tall + (size_t)p * b * b;
         dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, V, n, 0.0, Gv, 64, part, npart);
-        hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(256), 0, st, bw, Gv, 64, tau, T, b);
+        hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(256), 0, st, bw, Gv, 64, tau, T, b, cq_status);
     };
     // Y = A22 V (A22 = A(r0.., r0..), symmetric, lower triangle read)
     auto form_y = [&](int r0, int m, int bw, const double* V) {

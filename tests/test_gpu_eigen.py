@@ -52,6 +52,44 @@ def test_band_reduce_keeps_spectrum(n, b):
     assert np.abs(ev - ev_ref).max() <= 64 * n * EPS * np.abs(ev_ref).max()
 
 
+def _panel_kind_matrix(kind, n, seed):
+    """Symmetric matrices whose sub-band panels are full rank, rank deficient or
+    strongly graded, so that the panel factorization takes each of its paths
+    (the two-pass Cholesky QR and the column-by-column fallback)."""
+    rng = np.random.default_rng(seed)
+    if kind == "random":
+        return _sym(n, seed)
+    if kind == "rank40":
+        U = np.linalg.qr(rng.standard_normal((n, 40)))[0]
+        return U @ np.diag(rng.uniform(-3, 3, 40)) @ U.T
+    if kind == "blockdiag":
+        A = np.zeros((n, n))
+        for o in range(0, n, 100):
+            k = min(100, n - o)
+            A[o:o + k, o:o + k] = _sym(k, seed + o)
+        return A
+    if kind == "graded":
+        d = np.logspace(0, -6, n)
+        return d[:, None] * _sym(n, seed) * d[None, :]
+    if kind == "diagonal":
+        return np.diag(rng.standard_normal(n))
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind", ["random", "rank40", "blockdiag", "graded", "diagonal"])
+def test_band_reduce_panel_kinds_keep_spectrum(kind):
+    from paper_1705_11191_amd import binding as B
+
+    n, b = 700, 64
+    A = _panel_kind_matrix(kind, n, 5)
+    band = B.band_reduce(_dev(A), b).cpu().numpy()
+    Bm = _band_dense(band, b, n)
+    ev_ref = np.linalg.eigvalsh(A)
+    d, e, _ = O.tred(Bm)
+    ev = O.tridiag_eigvals(d, e)
+    assert np.abs(ev - ev_ref).max() <= 64 * n * EPS * np.abs(ev_ref).max()
+
+
 @pytest.mark.parametrize("n,b", [(2, 8), (3, 8), (17, 8), (64, 64), (100, 32), (257, 64), (600, 64)])
 def test_tridiagonalize_keeps_spectrum(n, b):
     from paper_1705_11191_amd import binding as B
