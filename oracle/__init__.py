@@ -18,4 +18,10 @@ from .oracle import (  # noqa: F401
     tred,
     tridiag_eig,
     tridiag_eigvals,
+    zdensity,
+    zdm,
+    zgevp,
+    zpotrf,
+    zreduce_standard,
+    ztred,
 )

@@ -20,6 +20,10 @@
  *     states downward (Sec. 4.5, elsi_dm_real);
  *   - the density matrix n_ij = sum_l f_l c_il c_jl, Eq. (9), and the band
  *     energy sum_l f_l eps_l (Sec. 4.5, "energy" output of elsi_dm_real).
+ *   - the same steps for complex Hermitian H and Hermitian positive definite
+ *     S (the complex interface of Sec. 4.3, the k-point problems of periodic
+ *     systems), the Householder tridiagonal made real by a diagonal unitary
+ *     scaling, and n_ij = sum_l f_l c_il conj(c_jl) (see the end of the file).
  *
  * Matrices are column-major with a leading dimension; the lower triangle of
  * the symmetric inputs is the one that is read.
@@ -516,4 +520,274 @@ void orc_residual_norms(int n, int k, const double *H, int ldh, const double *S,
         }
         res[j] = (double)sqrtl(acc);
     }
+}
+
+/* ========================================================================= */
+/* Complex Hermitian path (the complex eigensolver interface of Sec. 4.3,    */
+/* the k-point problems of periodic systems): the same steps in complex      */
+/* arithmetic.  Complex matrices are column-major arrays of double complex   */
+/* (real and imaginary parts interleaved); the lower triangle of the         */
+/* Hermitian inputs is the one that is read.  Eq. (9) becomes                */
+/* D_ij = sum_l f_l c_il conj(c_jl), so that D is Hermitian.                 */
+/* ========================================================================= */
+#include <complex.h>
+typedef double complex zc;
+
+/* Cholesky S = L L^H, column by column.  Returns 0 or j+1 (pivot j not       */
+/* positive).  The strict upper triangle is set to zero.                     */
+int orc_zpotrf(int n, zc *A, int lda)
+{
+    for (int j = 0; j < n; ++j) {
+        double s = creal(A[IDX(j, j, lda)]);
+        for (int k = 0; k < j; ++k) {
+            zc l = A[IDX(j, k, lda)];
+            s -= creal(l) * creal(l) + cimag(l) * cimag(l);
+        }
+        if (!(s > 0.0) || !isfinite(s)) return j + 1;
+        double ljj = sqrt(s);
+        A[IDX(j, j, lda)] = ljj;
+        /* L_ij = (S_ij - sum_k L_ik conj(L_jk)) / L_jj for i > j */
+#pragma omp parallel for schedule(static)
+        for (int i = j + 1; i < n; ++i) {
+            zc t = A[IDX(i, j, lda)];
+            for (int k = 0; k < j; ++k) t -= A[IDX(i, k, lda)] * conj(A[IDX(j, k, lda)]);
+            A[IDX(i, j, lda)] = t / ljj;
+        }
+    }
+    for (int j = 1; j < n; ++j)
+        for (int i = 0; i < j; ++i) A[IDX(i, j, lda)] = 0.0;
+    return 0;
+}
+
+/* x <- L^-1 x (forward substitution, lower triangle of L). */
+static void zfwd_subst(int n, const zc *L, int ldl, zc *x)
+{
+    for (int k = 0; k < n; ++k) {
+        x[k] /= L[IDX(k, k, ldl)];
+        zc xk = x[k];
+        const zc *col = L + IDX(0, k, ldl);
+        for (int i = k + 1; i < n; ++i) x[i] -= col[i] * xk;
+    }
+}
+
+/* x <- L^-H x (back substitution with the conjugate transpose of L). */
+static void zback_subst_h(int n, const zc *L, int ldl, zc *x)
+{
+    for (int i = n - 1; i >= 0; --i) {
+        const zc *col = L + IDX(0, i, ldl);
+        zc t = x[i];
+        for (int j = i + 1; j < n; ++j) t -= conj(col[j]) * x[j];
+        x[i] = t / creal(col[i]);
+    }
+}
+
+/* Eq. (11) for the Hermitian pencil: W = L^-1 H column by column; then       */
+/* H~ = W L^-H = L^-1 W^H (H~ Hermitian), whose column j is L^-1 applied to   */
+/* the conjugated row j of W; finally H~ <- (H~ + H~^H) / 2.                 */
+void orc_zreduce(int n, zc *H, int ldh, const zc *L, int ldl)
+{
+    zc *W = (zc *)malloc(sizeof(zc) * (size_t)n * n);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        zc *w = W + (size_t)j * n;
+        for (int i = 0; i < n; ++i) w[i] = (i >= j) ? H[IDX(i, j, ldh)] : conj(H[IDX(j, i, ldh)]);
+        zfwd_subst(n, L, ldl, w);
+    }
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        zc *x = (zc *)malloc(sizeof(zc) * n);
+        for (int i = 0; i < n; ++i) x[i] = conj(W[(size_t)i * n + j]);
+        zfwd_subst(n, L, ldl, x);
+        for (int i = 0; i < n; ++i) H[IDX(i, j, ldh)] = x[i];
+        free(x);
+    }
+    free(W);
+    for (int j = 0; j < n; ++j) {
+        H[IDX(j, j, ldh)] = creal(H[IDX(j, j, ldh)]);
+        for (int i = j + 1; i < n; ++i) {
+            zc a = 0.5 * (H[IDX(i, j, ldh)] + conj(H[IDX(j, i, ldh)]));
+            H[IDX(i, j, ldh)] = a;
+            H[IDX(j, i, ldh)] = conj(a);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Hermitian Householder tridiagonalization, Eq. (12) in complex arithmetic: */
+/* A = Q T Q^H with T Hermitian tridiagonal, then T = P T_r P^H with the     */
+/* diagonal unitary P (p_0 = 1, p_{k+1} = p_k e_k / |e_k|) so that T_r is    */
+/* real symmetric with off-diagonal |e_k|.  On exit d (n), e (n-1) hold T_r  */
+/* and Q (n x n) is replaced by Q P.  Step k: alpha = -e^{i arg x_0} ||x||   */
+/* for x = A(k+1:n, k), v = (x - alpha e_1) / (x_0 - alpha), beta = 2 /      */
+/* v^H v, p = beta A22 v, w = p - (beta (v^H p) / 2) v (v^H p is real) and   */
+/* A22 <- A22 - v w^H - w v^H.  A (both triangles) is destroyed.             */
+/* ------------------------------------------------------------------------- */
+void orc_ztred(int n, zc *A, int lda, double *d, double *e, zc *Q, int ldq)
+{
+    double *beta = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    zc *p = (zc *)malloc(sizeof(zc) * (size_t)(n > 0 ? n : 1));
+    zc *ec = (zc *)calloc((size_t)(n > 0 ? n : 1), sizeof(zc));
+    for (int k = 0; k + 2 < n; ++k) {
+        int m = n - k - 1;
+        zc *x = A + IDX(k + 1, k, lda);
+        double tail = 0.0;
+        for (int i = 1; i < m; ++i) tail += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
+        zc x0 = x[0];
+        if (tail == 0.0) {   /* already reduced: H_k = I */
+            beta[k] = 0.0;
+            ec[k] = x0;
+            for (int i = 1; i < m; ++i) x[i] = 0.0;
+            continue;
+        }
+        double ax0 = cabs(x0);
+        double nrm = sqrt(ax0 * ax0 + tail);
+        zc ph = (ax0 > 0.0) ? x0 / ax0 : 1.0;
+        zc alpha = -ph * nrm;
+        zc v0 = x0 - alpha;
+        for (int i = 1; i < m; ++i) x[i] /= v0;
+        x[0] = 1.0;
+        double av0 = cabs(v0);
+        double vhv = 1.0 + tail / (av0 * av0);
+        double b = 2.0 / vhv;
+        beta[k] = b;
+        ec[k] = alpha;
+        zc *A22 = A + IDX(k + 1, k + 1, lda);
+        /* p = beta A22 v: row j of A22 is conj of column j (Hermitian) */
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < m; ++j) {
+            const zc *col = A22 + (size_t)j * lda;
+            zc t = 0.0;
+            for (int i = 0; i < m; ++i) t += conj(col[i]) * x[i];
+            p[j] = b * t;
+        }
+        zc vhp = 0.0;
+        for (int i = 0; i < m; ++i) vhp += conj(x[i]) * p[i];
+        double half = 0.5 * b * creal(vhp);
+        for (int i = 0; i < m; ++i) p[i] -= half * x[i];   /* p is now w */
+        /* A22 <- A22 - v w^H - w v^H */
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < m; ++j) {
+            zc *col = A22 + (size_t)j * lda;
+            zc vj = conj(x[j]), wj = conj(p[j]);
+            for (int i = 0; i < m; ++i) col[i] -= x[i] * wj + p[i] * vj;
+        }
+    }
+    for (int i = 0; i < n; ++i) d[i] = creal(A[IDX(i, i, lda)]);
+    if (n >= 2) ec[n - 2] = A[IDX(n - 1, n - 2, lda)];
+
+    /* Q = H_0 H_1 ... H_{n-3} (H_k = I - beta_k v_k v_k^H), backward accumulation */
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) Q[IDX(i, j, ldq)] = (i == j) ? 1.0 : 0.0;
+    for (int k = n - 3; k >= 0; --k) {
+        if (beta[k] == 0.0) continue;
+        int m = n - k - 1;
+        const zc *v = A + IDX(k + 1, k, lda);
+        double b = beta[k];
+#pragma omp parallel for schedule(static)
+        for (int j = k + 1; j < n; ++j) {
+            zc *col = Q + IDX(k + 1, j, ldq);
+            zc t = 0.0;
+            for (int i = 0; i < m; ++i) t += conj(v[i]) * col[i];
+            t *= b;
+            for (int i = 0; i < m; ++i) col[i] -= t * v[i];
+        }
+    }
+    /* the diagonal unitary P: T(k+1, k) = e_k = p_{k+1} |e_k| conj(p_k) */
+    zc pk = 1.0;
+    for (int k = 0; k < n; ++k) {
+        if (k > 0) {
+            double a = cabs(ec[k - 1]);
+            if (a > 0.0) pk = pk * (ec[k - 1] / a);
+            e[k - 1] = a;
+        }
+        zc *col = Q + IDX(0, k, ldq);
+        for (int i = 0; i < n; ++i) col[i] *= pk;
+    }
+    free(beta);
+    free(p);
+    free(ec);
+}
+
+/* Phase convention: the largest-magnitude entry of each column is real > 0. */
+static void znormalize_phase(int n, int k, zc *C, int ldc)
+{
+    for (int j = 0; j < k; ++j) {
+        zc *c = C + (size_t)j * ldc;
+        int imax = 0;
+        for (int i = 1; i < n; ++i) if (cabs(c[i]) > cabs(c[imax])) imax = i;
+        double a = cabs(c[imax]);
+        if (a == 0.0) continue;
+        zc ph = conj(c[imax]) / a;
+        for (int i = 0; i < n; ++i) c[i] *= ph;
+        c[imax] = a;
+    }
+}
+
+/* Complex generalized eigensolve: eval (n, ascending), evec n x n_state     */
+/* (complex, ldc = n).  H and S are destroyed (S -> L).  Returns as orc_gevp. */
+int orc_zgevp(int n, int n_state, zc *H, int ldh, zc *S, int lds, double *eval, zc *evec, int *fail_col)
+{
+    if (fail_col) *fail_col = 0;
+    int info = orc_zpotrf(n, S, lds);
+    if (info) { if (fail_col) *fail_col = info; return 1; }
+    orc_zreduce(n, H, ldh, S, lds);
+    double *d = (double *)malloc(sizeof(double) * n);
+    double *e = (double *)calloc((size_t)n, sizeof(double));
+    zc *Q = (zc *)malloc(sizeof(zc) * (size_t)n * n);
+    orc_ztred(n, H, ldh, d, e, Q, n);
+    /* eigenvectors Z of the real tridiagonal (row-major for the QL sweeps) */
+    double *Zr = (double *)malloc(sizeof(double) * (size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Zr[(size_t)i * n + j] = (i == j) ? 1.0 : 0.0;
+    int st = orc_tql(n, d, e, Zr, 1);
+    if (st) { free(d); free(e); free(Q); free(Zr); return st; }
+    int *perm = (int *)malloc(sizeof(int) * n);
+    stable_argsort(n, d, perm);
+    for (int j = 0; j < n; ++j) eval[j] = d[perm[j]];
+    /* evec = (Q P) Z for the wanted columns, then L^-H */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n_state; ++j) {
+        zc *c = evec + (size_t)j * n;
+        for (int i = 0; i < n; ++i) c[i] = 0.0;
+        for (int k = 0; k < n; ++k) {
+            double z = Zr[(size_t)k * n + perm[j]];
+            const zc *q = Q + (size_t)k * n;
+            for (int i = 0; i < n; ++i) c[i] += q[i] * z;
+        }
+        zback_subst_h(n, S, lds, c);
+    }
+    znormalize_phase(n, n_state, evec, n);
+    free(perm); free(d); free(e); free(Q); free(Zr);
+    return 0;
+}
+
+/* Eq. (9) for complex coefficients: D_ij = sum_{l: f_l > 0} f_l c_il conj(c_jl). */
+void orc_zdensity(int n, int k, const zc *C, int ldc, const double *f, zc *D, int ldd)
+{
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        zc *dcol = D + (size_t)j * ldd;
+        for (int i = 0; i < n; ++i) dcol[i] = 0.0;
+        for (int l = 0; l < k; ++l) {
+            if (!(f[l] > 0.0)) continue;
+            const zc *c = C + (size_t)l * ldc;
+            zc w = f[l] * conj(c[j]);
+            for (int i = 0; i < n; ++i) dcol[i] += c[i] * w;
+        }
+    }
+}
+
+/* Complex density-matrix driver (returns as orc_dm). */
+int orc_zdm(int n, zc *H, int ldh, zc *S, int lds, double n_electron, double kT, double spin,
+            double occ_accuracy, int max_steps, zc *D, int ldd, double *eval, double *occ,
+            double *energy, double *mu, int *fail_col)
+{
+    zc *C = (zc *)malloc(sizeof(zc) * (size_t)n * n);
+    int st = orc_zgevp(n, n, H, ldh, S, lds, eval, C, fail_col);
+    if (st) { free(C); return st; }
+    st = orc_occupations(n, eval, n_electron, kT, spin, occ_accuracy, max_steps, occ, mu);
+    orc_zdensity(n, n, C, n, occ, D, ldd);
+    *energy = orc_band_energy(n, occ, eval);
+    free(C);
+    return st;
 }

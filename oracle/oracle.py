@@ -52,8 +52,18 @@ def _load():
         lib.orc_band_energy.restype = d
         lib.orc_dm.argtypes = [i, _dp, i, _dp, i, d, d, d, d, i, _dp, i, _dp, _dp, _dp, _dp, _ip]
         lib.orc_residual_norms.argtypes = [i, i, _dp, i, _dp, i, _dp, i, _dp, _dp]
+        lib.orc_zpotrf.argtypes = [i, _dp, i]
+        lib.orc_zreduce.argtypes = [i, _dp, i, _dp, i]
+        lib.orc_ztred.argtypes = [i, _dp, i, _dp, _dp, _dp, i]
+        lib.orc_zgevp.argtypes = [i, i, _dp, i, _dp, i, _dp, _dp, _ip]
+        lib.orc_zdensity.argtypes = [i, i, _dp, i, _dp, _dp, i]
+        lib.orc_zdm.argtypes = [i, _dp, i, _dp, i, d, d, d, d, i, _dp, i, _dp, _dp, _dp, _dp, _ip]
         _lib = lib
     return _lib
+
+
+def _c128(a) -> np.ndarray:
+    return np.array(a, dtype=np.complex128, order="F", copy=True)
 
 
 def _f64(a) -> np.ndarray:
@@ -209,3 +219,83 @@ def residual_norms(H, S, X, lam):
     res = np.zeros(k)
     _load().orc_residual_norms(n, k, _p(Hf), n, _p(Sf), n, _p(Xf), n, _p(lf), _p(res))
     return res
+
+
+# ---------------------------------------------------------------------------
+# complex Hermitian path (complex128 arrays; the C side reads them as
+# interleaved real/imaginary doubles)
+# ---------------------------------------------------------------------------
+def zpotrf(S):
+    """Complex Cholesky S = L L^H (lower), strict upper triangle zeroed."""
+    A = _c128(S)
+    st = _load().orc_zpotrf(A.shape[0], _p(A), A.shape[0])
+    if st:
+        raise OracleError(1, f"S not positive definite at column {st - 1}")
+    return A
+
+
+def zreduce_standard(H, L):
+    """H~ = L^-1 H L^-H (Eq. (11)) for Hermitian H, full Hermitian result."""
+    Hf = _c128(H)
+    Lf = _c128(L)
+    n = Hf.shape[0]
+    _load().orc_zreduce(n, _p(Hf), n, _p(Lf), n)
+    return Hf
+
+
+def ztred(A):
+    """Hermitian Householder tridiagonalization made real: (d, e, Q) with
+    A = Q T_r Q^H, T_r real symmetric tridiagonal (d, e)."""
+    Af = _c128(A)
+    n = Af.shape[0]
+    d = np.zeros(n)
+    e = np.zeros(max(n - 1, 1))
+    Q = np.zeros((n, n), dtype=np.complex128, order="F")
+    _load().orc_ztred(n, _p(Af), n, _p(d), _p(e), _p(Q), n)
+    return d, e[: max(n - 1, 0)], Q
+
+
+def zgevp(H, S, n_state=None):
+    """Complex generalized eigenpairs: (eval ascending (n), evec n x n_state, L)."""
+    Hf = _c128(H)
+    Sf = _c128(S)
+    n = Hf.shape[0]
+    k = n if n_state is None else int(n_state)
+    ev = np.zeros(n)
+    C = np.zeros((n, max(k, 1)), dtype=np.complex128, order="F")
+    fail = ctypes.c_int(0)
+    st = _load().orc_zgevp(n, k, _p(Hf), n, _p(Sf), n, _p(ev), _p(C), ctypes.byref(fail))
+    if st == 1:
+        raise OracleError(1, f"S not positive definite at column {fail.value - 1}")
+    if st:
+        raise OracleError(st, "eigensolver failed")
+    return ev, C[:, :k], Sf
+
+
+def zdensity(C, f):
+    """D = sum_l f_l c_l c_l^H over f_l > 0 (Eq. (9), complex)."""
+    Cf = _c128(C)
+    ff = _f64(f)
+    n, k = Cf.shape
+    D = np.zeros((n, n), dtype=np.complex128, order="F")
+    _load().orc_zdensity(n, k, _p(Cf), n, _p(ff), _p(D), n)
+    return D
+
+
+def zdm(H, S, n_electron, kT, spin=1.0, occ_accuracy=1e-13, max_steps=100):
+    """Complex density-matrix driver: returns dict(D, eval, occ, energy, mu, status, L)."""
+    Hf = _c128(H)
+    Sf = _c128(S)
+    n = Hf.shape[0]
+    D = np.zeros((n, n), dtype=np.complex128, order="F")
+    ev = np.zeros(n)
+    occ = np.zeros(n)
+    energy = ctypes.c_double(0.0)
+    mu = ctypes.c_double(0.0)
+    fail = ctypes.c_int(0)
+    st = _load().orc_zdm(n, _p(Hf), n, _p(Sf), n, float(n_electron), float(kT), float(spin),
+                         float(occ_accuracy), int(max_steps), _p(D), n, _p(ev), _p(occ),
+                         ctypes.byref(energy), ctypes.byref(mu), ctypes.byref(fail))
+    if st in (1, 2):
+        raise OracleError(st, "eigensolve failed")
+    return dict(D=D, eval=ev, occ=occ, energy=energy.value, mu=mu.value, status=st, L=Sf)

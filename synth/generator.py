@@ -261,3 +261,75 @@ def toeplitz_pencil(n: int, alpha: float, beta: complex, sigma: complex):
     S[i[:-1], i[1:]] = sigma
     S[i[1:], i[:-1]] = np.conj(sigma)
     return H, S
+
+
+# ----------------------------------------------------------------------------
+# complex Hermitian k-point pencils (periodic cell, Bloch sums)
+# ----------------------------------------------------------------------------
+def make_kpoint_system(cell_sites=(3, 3, 3), kpt=(0.125, 0.25, 0.25), seed: int = 0,
+                       kappa: float = DEFAULT_KAPPA, orbitals_per_atom: int = 4,
+                       spacing: float = 2.5, jitter_amp: float = 0.2, alpha_lo: float = 0.8,
+                       alpha_hi: float = 3.0) -> SystemSpec:
+    """Complex Hermitian H(k), S(k) of a periodic jittered cubic cell.
+
+    The cell holds cell_sites[0] x cell_sites[1] x cell_sites[2] atoms with
+    ``orbitals_per_atom`` s-Gaussians each; the lattice vectors are
+    spacing * cell_sites along x, y, z.  With R running over the 27 images
+    n_R in {-1, 0, 1}^3 (integer lattice coordinates):
+        S(k)_ij = sum_R S_R(i, j) exp(+i 2 pi k . n_R),  S_R(i, j) = overlap of
+                  orbital i in the home cell with orbital j in cell R,
+        H(k)_ij = sum_R H_R(i, j) exp(+i 2 pi k . n_R),  H_R = 1.75 S_R (h_i + h_j) / 2
+                  except H_0(i, i) = h_i,
+    and S(k) += sigma I with sigma = lambda_max(S(k)) / kappa.  k is in units
+    of the reciprocal lattice; k = 0 gives a real pencil.  Exponents default to
+    U(0.8, 3.0) so that the overlaps beyond the 27 images are negligible and
+    the truncated Bloch sum stays positive definite (checked).
+    Random numbers: jitter (atoms x 3), exponents (atoms x orbitals), on-site
+    energies (N), in that order from ``numpy.random.default_rng(seed)``.
+    """
+    mx, my, mz = (int(v) for v in cell_sites)
+    n_atoms = mx * my * mz
+    n = n_atoms * orbitals_per_atom
+    rng = np.random.default_rng(seed)
+    jitter = rng.uniform(-jitter_amp, jitter_amp, size=(n_atoms, 3))
+    alphas = rng.uniform(alpha_lo, alpha_hi, size=(n_atoms, orbitals_per_atom)).reshape(-1)
+    h = rng.uniform(-15.0, -5.0, size=n) * HARTREE_PER_EV
+    idx = np.arange(n_atoms)
+    ix, iy, iz = idx % mx, (idx // mx) % my, idx // (mx * my)
+    pos = spacing * np.stack([ix, iy, iz], axis=1).astype(np.float64) + jitter
+    centers = np.repeat(pos, orbitals_per_atom, axis=0)
+    lat = spacing * np.array([mx, my, mz], dtype=np.float64)
+    k = np.asarray(kpt, dtype=np.float64)
+    S = np.zeros((n, n), dtype=np.complex128)
+    H = np.zeros((n, n), dtype=np.complex128)
+    a = alphas[:, None]
+    b = alphas[None, :]
+    p = a + b
+    pref = (2.0 * np.sqrt(a * b) / p) ** 1.5
+    hh = WH_K * 0.5 * (h[:, None] + h[None, :])
+    for rx in (-1, 0, 1):
+        for ry in (-1, 0, 1):
+            for rz in (-1, 0, 1):
+                nR = np.array([rx, ry, rz], dtype=np.float64)
+                shift = nR * lat
+                d2 = ((centers[:, None, :] - (centers[None, :, :] + shift)) ** 2).sum(axis=2)
+                SR = pref * np.exp(-(a * b / p) * d2)
+                HR = hh * SR
+                if rx == 0 and ry == 0 and rz == 0:
+                    HR[np.arange(n), np.arange(n)] = h
+                ph = np.exp(2j * np.pi * float(k @ nR))
+                S += SR * ph
+                H += HR * ph
+    # exact Hermitian symmetry (the image sum pairs R with -R)
+    S = 0.5 * (S + S.conj().T)
+    H = 0.5 * (H + H.conj().T)
+    w = np.linalg.eigvalsh(S)
+    sigma = 0.0
+    if kappa is not None and kappa > 0:
+        sigma = float(w[-1]) / kappa
+    if not (w[0] + sigma > 0.5 * sigma):
+        raise ValueError("truncated Bloch sum is not positive definite; use larger exponents or cell")
+    S[np.arange(n), np.arange(n)] += sigma
+    return SystemSpec(H, S, n_occ=float(n // 4), kT=DEFAULT_KT,
+                      meta=dict(kind="kpoint3d", cell_sites=(mx, my, mz), kpt=tuple(k), seed=seed,
+                                kappa=kappa, sigma=sigma, orbitals_per_atom=orbitals_per_atom))
