@@ -45,8 +45,18 @@ extern "C" {
 
 typedef struct elsi_gpu_handle_s *elsi_gpu_handle;
 
-/* scalar type of H, S, eigenvectors and D (Sec. 4.5: elsi_ev_real / _complex) */
-enum { ELSI_GPU_REAL64 = 0 };
+/* scalar type of H, S, eigenvectors and D (Sec. 4.5: elsi_ev_real / _complex).
+ * ELSI_GPU_COMPLEX128: complex Hermitian H, Hermitian positive definite S
+ * (the k-point problems of periodic systems, Sec. 4.3).  Every matrix argument
+ * of elsi_gpu_ev / elsi_gpu_dm (and of the batched calls) is then an array of
+ * complex doubles, real and imaginary parts interleaved, column-major with the
+ * same leading dimension n; eigenvalues, occupations, energy and mu stay real.
+ * The library solves the real symmetric 2n x 2n image of the pencil (each
+ * entry x + iy becomes the block [[x, -y], [y, x]]), which holds every complex
+ * eigenvalue twice; D, the eigenvectors and L are read back from it.  This
+ * costs 8x the real n x n flops (a native complex path would cost 4x).  The
+ * stage entry points (elsi_gpu_x_*) are real only. */
+enum { ELSI_GPU_REAL64 = 0, ELSI_GPU_COMPLEX128 = 1 };
 
 /* occupation scheme (Sec. 4.6, broadening_scheme): explicit values given by
  * the caller, or Fermi-Dirac broadening, Eq. (17) */
@@ -145,17 +155,23 @@ int elsi_gpu_set_band_width(elsi_gpu_handle h, int b);
  * every handle.  Errors: -1 null handle, -2 on not 0 or 1. */
 int elsi_gpu_set_launch_timing(elsi_gpu_handle h, int on);
 
-/* Eigenvalues and eigenvectors (elsi_ev_real, Sec. 4.5).
- *   H    device, n x n, in; destroyed on exit;
- *   S    device, n x n, in (SPD); on exit holds L of Eq. (10) (lower, zero above);
+/* Eigenvalues and eigenvectors (elsi_ev_real / elsi_ev_complex, Sec. 4.5).
+ *   H    device, n x n, in; destroyed on exit (complex handles leave it intact);
+ *   S    device, n x n, in (SPD, or HPD); on exit holds L of Eq. (10) (lower,
+ *        zero above; S = L L^H for complex handles);
  *   eval device, n doubles, out: all eigenvalues, ascending;
  *   evec device, n x n_state, out: S-orthonormal eigenvectors of the lowest
- *        n_state eigenvalues (c^T S c = I).
+ *        n_state eigenvalues (c^H S c = I).  For complex handles each
+ *        eigenvector carries an arbitrary phase; within a group of equal
+ *        eigenvalues (to 1e-9 relative) the columns are an orthonormal basis of
+ *        the group's eigenspace (groups of more than 32 equal eigenvalues are
+ *        not reorthogonalized).
  * Errors: -1 handle, -2 H, -3 S, -4 eval, -5 evec; ELSI_GPU_ERR_NOT_PD, _NO_CONV,
  * _HIP, _OOM, _NONFINITE. */
 int elsi_gpu_ev(elsi_gpu_handle h, double *H, double *S, double *eval, double *evec);
 
-/* Density matrix (elsi_dm_real, Sec. 4.5).
+/* Density matrix (elsi_dm_real, Sec. 4.5; for complex handles
+ * D = sum_l f_l c_l c_l^H, Hermitian).
  *   H, S    as for elsi_gpu_ev;
  *   occ     device, n doubles: in for ELSI_GPU_OCC_EXPLICIT (f of the states in
  *           ascending order), out (the Fermi-Dirac occupations) otherwise; may

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libelsi_gpu.so")
 _lib = None
 
 REAL64 = 0
+COMPLEX128 = 1
 OCC_EXPLICIT = 0
 OCC_FERMI = 1
 NSTAGES = 10
@@ -229,13 +230,32 @@ def tridiag_eig(d: torch.Tensor, e: torch.Tensor):
 class Handle:
     """One elsi_gpu handle (elsi_init ... elsi_finalize)."""
 
-    def __init__(self, n_basis: int, n_state: int, n_electron: float, stream=None):
+    def __init__(self, n_basis: int, n_state: int, n_electron: float, stream=None, dtype=REAL64):
+        """dtype REAL64 (float64 matrices) or COMPLEX128 (complex128 matrices, which
+        must be column-major: a transposed view of a contiguous tensor, see
+        fortran_empty / as_fortran)."""
         self._h = ctypes.c_void_p(0)
         s = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
         self.n = n_basis
         self.n_state = n_state
-        _check(lib().elsi_gpu_init(ctypes.byref(self._h), REAL64, n_basis, n_state, n_electron,
+        self.dtype = dtype
+        _check(lib().elsi_gpu_init(ctypes.byref(self._h), dtype, n_basis, n_state, n_electron,
                                    ctypes.c_void_p(s)), "elsi_gpu_init")
+
+    def _mat_dtype(self):
+        return torch.complex128 if self.dtype == COMPLEX128 else torch.float64
+
+    def _check_input(self, *mats):
+        """Complex matrices must be complex128 and column-major (a real symmetric
+        matrix reads the same either way; a Hermitian one would read as its
+        conjugate)."""
+        if self.dtype != COMPLEX128:
+            return
+        for M in mats:
+            if M is None:
+                continue
+            if M.dtype != torch.complex128 or not M.t().is_contiguous():
+                raise ValueError("complex handle: matrices must be column-major complex128 tensors")
 
     def set_occupation(self, scheme=OCC_FERMI, width=0.01, occ_accuracy=1e-13, mu_max_steps=100,
                        spin_factor=1.0):
@@ -268,8 +288,10 @@ class Handle:
     def ev(self, H: torch.Tensor, S: torch.Tensor, eval_out=None, evec_out=None):
         """Eigenpairs; H is destroyed and S receives L.  Returns (eval, evec column-major)."""
         n = self.n
+        self._check_input(H, S)
         ev = eval_out if eval_out is not None else torch.empty(n, device=H.device, dtype=torch.float64)
-        C = evec_out if evec_out is not None else fortran_empty(n, self.n_state, device=H.device)
+        C = evec_out if evec_out is not None else fortran_empty(n, self.n_state, device=H.device,
+                                                                dtype=self._mat_dtype())
         rc = lib().elsi_gpu_ev(self._h, _ptr(H), _ptr(S), _ptr(ev), _ptr(C))
         _check(rc, "elsi_gpu_ev")
         return ev, C
@@ -278,7 +300,8 @@ class Handle:
            ok=(0,)):
         """Density matrix; returns (D, eval, occ, energy, mu, status)."""
         n = self.n
-        D = D_out if D_out is not None else torch.empty((n, n), device=H.device, dtype=torch.float64)
+        self._check_input(H, S)
+        D = D_out if D_out is not None else fortran_empty(n, n, device=H.device, dtype=self._mat_dtype())
         ev = eval_out if eval_out is not None else torch.empty(n, device=H.device, dtype=torch.float64)
         f = occ if occ is not None else torch.empty(n, device=H.device, dtype=torch.float64)
         energy = ctypes.c_double(0.0)
@@ -296,7 +319,8 @@ class Handle:
         count = len(Hs)
         n = [int(H.shape[0]) for H in Hs]
         evals = [torch.empty(m, device=Hs[0].device, dtype=torch.float64) for m in n]
-        evecs = [fortran_empty(m, int(k), device=Hs[0].device) for m, k in zip(n, n_states)]
+        self._check_input(*Hs, *(Ss or []))
+        evecs = [fortran_empty(m, int(k), device=Hs[0].device, dtype=self._mat_dtype()) for m, k in zip(n, n_states)]
         status = (ctypes.c_int * count)()
         rc = lib().elsi_gpu_ev_batched(
             self._h, count, (ctypes.c_int * count)(*n), (ctypes.c_int * count)(*[int(k) for k in n_states]),
@@ -309,7 +333,8 @@ class Handle:
         (Ds, evals, energies, mus, per-problem status, rc)."""
         count = len(Hs)
         n = [int(H.shape[0]) for H in Hs]
-        Ds = [torch.empty((m, m), device=Hs[0].device, dtype=torch.float64) for m in n]
+        self._check_input(*Hs, *(Ss or []))
+        Ds = [fortran_empty(m, m, device=Hs[0].device, dtype=self._mat_dtype()) for m in n]
         evals = [torch.empty(m, device=Hs[0].device, dtype=torch.float64) for m in n]
         energy = (ctypes.c_double * count)()
         mu = (ctypes.c_double * count)()

@@ -33,7 +33,7 @@ int elsi_gpu_init(elsi_gpu_handle* h, int dtype, int n_basis, int n_state, doubl
 {
     if (!h) return -1;
     *h = nullptr;
-    if (dtype != ELSI_GPU_REAL64) return -2;
+    if (dtype != ELSI_GPU_REAL64 && dtype != ELSI_GPU_COMPLEX128) return -2;
     if (n_basis < 1) return -3;
     if (n_state < 1 || n_state > n_basis) return -4;
     if (!(n_electron >= 0.0) || n_electron > (double)n_basis * 2.0) return -5;

@@ -37,6 +37,20 @@ void reduce_to_standard(hipStream_t st, int n, double* H, int ldh, const double*
 void density_matrix(hipStream_t st, int n, int k, const double* C, int ldc, const double* f, double* W,
                     double* D, int ldd);
 
+// Complex Hermitian pencils through their real 2n x 2n image (complex.hip):
+// complex matrices are interleaved (real, imaginary) doubles, column-major.
+void embed_complex(hipStream_t st, int n, const double* Z, int ldz, double* R, int ldr, bool lower_factor);
+void extract_complex(hipStream_t st, int n, const double* R, int ldr, double* Z, int ldz, bool lower_factor);
+void pair_values(hipStream_t st, int n, const double* w2, double* w);
+void extract_vectors(hipStream_t st, int n, int k, const double* U, int ldu, double* C, int ldc);
+void duplicate_values(hipStream_t st, int k, const double* f, double* f2);
+void orthonormalize_complex_images(hipStream_t st, int n, int k, double* U, int ldu, double* JU, double* Bm);
+// One real standard-form eigenvector per wanted complex state (k of them) from
+// the k2 computed ones X (2n rows), w2 the doubled spectrum on the host; dsrc
+// is device scratch of k ints.
+int select_complex_states(hipStream_t st, int n, int k, const double* w2, const double* X, int ldx, int k2,
+                          double* U, int ldu, int* dsrc);
+
 }  // namespace eg
 
 struct elsi_gpu_handle_s {

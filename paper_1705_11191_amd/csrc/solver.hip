@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 namespace eg {
 
@@ -73,8 +74,35 @@ static Layout make_layout(int n, int b, int ncol)
     return L;
 }
 
+// Complex handles solve the real 2n x 2n image of their pencil: the real
+// layout for 2n, then the images of H, S and of the result (D, or the chosen
+// eigenvectors), the doubled occupations and a small index list.
+struct CLayout {
+    size_t h2, s2, x2, f2, idx;
+    size_t total;
+};
+
+static CLayout make_clayout(size_t base, int n)
+{
+    CLayout C{};
+    size_t off = base;
+    auto put = [&](size_t bytes) { size_t r = off; off += align_up(std::max<size_t>(bytes, 8), 256); return r; };
+    const size_t n2 = (size_t)2 * n;
+    C.h2 = put(sizeof(double) * n2 * n2);
+    C.s2 = put(sizeof(double) * n2 * n2);
+    C.x2 = put(sizeof(double) * n2 * n2);
+    C.f2 = put(sizeof(double) * n2);
+    C.idx = put(sizeof(int) * (size_t)n);
+    C.total = off;
+    return C;
+}
+
 size_t workspace_bytes(const elsi_gpu_handle_s* h)
 {
+    if (h->dtype == ELSI_GPU_COMPLEX128) {
+        const size_t base = make_layout(2 * h->n, h->band_width, 2 * h->n).total;
+        return make_clayout(base, h->n).total;
+    }
     return make_layout(h->n, h->band_width, h->n).total;
 }
 
@@ -204,7 +232,8 @@ static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, cons
 }
 
 // X (n x k, in Z) <- L^-T Q1 Q2 X: steps (4), (5) and the back substitution.
-static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L, Timer& tm, int k, DcState* dc)
+static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L, Timer& tm, int k, DcState* dc,
+                      bool backsub = true)
 {
     hipStream_t st = h->stream;
     const int n = h->n, b = std::min(h->band_width, std::max(1, n - 1));
@@ -216,6 +245,7 @@ static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L
     tm.mark(ELSI_GPU_ST_BACK_Q2);
     apply_q1(st, n, b, k, (double*)(ws + L.vall), (double*)(ws + L.tall), X, n, (double*)(ws + L.q1work));
     tm.mark(ELSI_GPU_ST_BACK_Q1);
+    if (!backsub) return;
     if (!h->overlap_is_unit) {
         double* Linv = (double*)(ws + L.linv);
         dtrtri_diag_blocks(st, n, S, n, Linv);
@@ -253,9 +283,7 @@ static int read_flags(hipStream_t st, char* ws, const Layout& L)
 
 using namespace eg;
 
-extern "C" {
-
-int elsi_gpu_ev(elsi_gpu_handle h, double* H, double* S, double* eval, double* evec)
+static int ev_real(elsi_gpu_handle_s* h, double* H, double* S, double* eval, double* evec)
 {
     if (!h) return -1;
     if (!H) return -2;
@@ -285,8 +313,8 @@ int elsi_gpu_ev(elsi_gpu_handle h, double* H, double* S, double* eval, double* e
     return read_flags(st, ws, L);
 }
 
-int elsi_gpu_dm(elsi_gpu_handle h, double* H, double* S, double* occ, double* D, double* eval, double* energy,
-                double* mu)
+static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, double* D, double* eval,
+                   double* energy, double* mu)
 {
     if (!h) return -1;
     if (!H) return -2;
@@ -344,6 +372,160 @@ int elsi_gpu_dm(elsi_gpu_handle h, double* H, double* S, double* occ, double* D,
     rc = read_flags(st, ws, L);
     if (rc) return rc;
     return status;
+}
+
+
+// ---------------------------------------------------------------------------
+// complex Hermitian pencils: the real 2n x 2n image (complex.hip) through the
+// real drivers, results read back
+// ---------------------------------------------------------------------------
+static elsi_gpu_handle_s inner_handle(const elsi_gpu_handle_s* h, int n_state2)
+{
+    elsi_gpu_handle_s r;
+    r.dtype = ELSI_GPU_REAL64;
+    r.n = 2 * h->n;
+    r.n_state = n_state2;
+    r.n_electron = 2.0 * h->n_electron;   // every level appears twice
+    r.stream = h->stream;
+    r.occ_scheme = h->occ_scheme;
+    r.kT = h->kT;
+    r.occ_accuracy = 2.0 * h->occ_accuracy;
+    r.mu_max_steps = h->mu_max_steps;
+    r.spin = h->spin;
+    r.overlap_is_unit = h->overlap_is_unit;
+    r.overlap_factored = h->overlap_factored;
+    r.band_width = h->band_width;
+    r.batch_workers = 1;
+    r.ws = h->ws;
+    r.ws_bytes = make_layout(r.n, r.band_width, r.n).total;
+    r.ws_owned = 0;
+    std::memset(&r.info, 0, sizeof(r.info));
+    r.info.n_basis = r.n;
+    return r;
+}
+
+static void complex_info(elsi_gpu_handle_s* h, const elsi_gpu_handle_s& r)
+{
+    h->info = r.info;
+    h->info.n_basis = h->n;
+    h->info.k_s = (r.info.k_s + 1) / 2;
+    h->info.fail_col = (r.info.fail_col + 1) / 2;   // real pivot 2j+1 or 2j+2 -> complex column j+1
+    h->info.energy = 0.5 * r.info.energy;
+    h->info.charge_residual = 0.5 * r.info.charge_residual;
+}
+
+static int ev_complex(elsi_gpu_handle_s* h, double* H, double* S, double* eval, double* evec)
+{
+    if (!H) return -2;
+    if (!S && !h->overlap_is_unit) return -3;
+    if (!eval) return -4;
+    if (!evec) return -5;
+    int rc = ensure_workspace(h);
+    if (rc) return rc < 0 ? -1 : rc;
+    hipStream_t st = h->stream;
+    const int n = h->n, n2 = 2 * n, k = h->n_state, k2 = std::min(n2, 2 * k);
+    char* ws = (char*)h->ws;
+    const Layout L = make_layout(n2, h->band_width, n2);
+    const CLayout C = make_clayout(L.total, n);
+    double* H2 = (double*)(ws + C.h2);
+    double* S2 = h->overlap_is_unit ? nullptr : (double*)(ws + C.s2);
+    double* U = (double*)(ws + C.x2);
+    embed_complex(st, n, H, n, H2, n2, false);
+    if (S2) embed_complex(st, n, S, n, S2, n2, h->overlap_factored != 0);
+    elsi_gpu_handle_s r = inner_handle(h, k2);
+    r.info.band_width = std::min(r.band_width, std::max(1, n2 - 1));
+    Timer tm(st);
+    DcState dc;
+    rc = front_half(&r, H2, S2, ws, L, tm, &dc);
+    if (rc) {
+        tm.finish(&r.info);
+        complex_info(h, r);
+        return rc;
+    }
+    back_half(&r, S2, ws, L, tm, k2, &dc, false);   // standard-form vectors, n2 x k2, in ws + L.z
+    std::vector<double> w2(n2);
+    if (hipMemcpyAsync(w2.data(), ws + L.w, sizeof(double) * n2, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return kStatusHip;
+    if (hipStreamSynchronize(st) != hipSuccess) return kStatusHip;
+    rc = select_complex_states(st, n, k, w2.data(), (const double*)(ws + L.z), n2, k2, U, n2, (int*)(ws + C.idx));
+    if (rc) return rc;
+    // the standard-form vectors X are consumed: their buffers serve as scratch
+    orthonormalize_complex_images(st, n, k, U, n2, (double*)(ws + L.z), (double*)(ws + L.z2));
+    if (S2) {
+        double* Linv = (double*)(ws + L.linv);
+        dtrtri_diag_blocks(st, n2, S2, n2, Linv);
+        dtrsm_left_lower_t(st, n2, k, S2, n2, Linv, U, n2);
+    }
+    tm.mark(ELSI_GPU_ST_BACKSUB);
+    extract_vectors(st, n, k, U, n2, evec, n);
+    pair_values(st, n, (const double*)(ws + L.w), eval);
+    if (S2 && !h->overlap_factored) extract_complex(st, n, S2, n2, S, n, true);
+    rc = sync_status(st);
+    if (rc) return rc;
+    tm.finish(&r.info);
+    harvest_launch_probe(&r);
+    complex_info(h, r);
+    return read_flags(st, ws, L);
+}
+
+static int dm_complex(elsi_gpu_handle_s* h, double* H, double* S, double* occ, double* D, double* eval,
+                      double* energy, double* mu)
+{
+    if (!H) return -2;
+    if (!S && !h->overlap_is_unit) return -3;
+    if (!occ && h->occ_scheme == ELSI_GPU_OCC_EXPLICIT) return -4;
+    if (!D) return -5;
+    if (!energy) return -7;
+    int rc = ensure_workspace(h);
+    if (rc) return rc < 0 ? -1 : rc;
+    hipStream_t st = h->stream;
+    const int n = h->n, n2 = 2 * n;
+    char* ws = (char*)h->ws;
+    const Layout L = make_layout(n2, h->band_width, n2);
+    const CLayout C = make_clayout(L.total, n);
+    double* H2 = (double*)(ws + C.h2);
+    double* S2 = h->overlap_is_unit ? nullptr : (double*)(ws + C.s2);
+    double* D2 = (double*)(ws + C.x2);
+    double* occ2 = nullptr;
+    embed_complex(st, n, H, n, H2, n2, false);
+    if (S2) embed_complex(st, n, S, n, S2, n2, h->overlap_factored != 0);
+    if (h->occ_scheme == ELSI_GPU_OCC_EXPLICIT) {
+        occ2 = (double*)(ws + C.f2);
+        duplicate_values(st, h->n_state, occ, occ2);
+    }
+    elsi_gpu_handle_s r = inner_handle(h, 2 * h->n_state);
+    double e2 = 0.0, mu2 = 0.0;
+    const int rc2 = dm_real(&r, H2, S2, occ2, D2, nullptr, &e2, &mu2);
+    complex_info(h, r);
+    if (rc2 != 0 && rc2 != ELSI_GPU_ERR_MU) return rc2;
+    extract_complex(st, n, D2, n2, D, n, false);
+    if (eval) pair_values(st, n, (const double*)(ws + L.w), eval);
+    // Fermi-Dirac occupations of the states: the mean over each real pair
+    if (occ && h->occ_scheme == ELSI_GPU_OCC_FERMI) pair_values(st, n, (const double*)(ws + L.f), occ);
+    if (S2 && !h->overlap_factored) extract_complex(st, n, S2, n2, S, n, true);
+    rc = sync_status(st);
+    if (rc) return rc;
+    *energy = 0.5 * e2;
+    if (mu) *mu = mu2;
+    h->info.mu = mu2;
+    return rc2;
+}
+
+extern "C" {
+
+int elsi_gpu_ev(elsi_gpu_handle h, double* H, double* S, double* eval, double* evec)
+{
+    if (!h) return -1;
+    if (h->dtype == ELSI_GPU_COMPLEX128) return ev_complex(h, H, S, eval, evec);
+    return ev_real(h, H, S, eval, evec);
+}
+
+int elsi_gpu_dm(elsi_gpu_handle h, double* H, double* S, double* occ, double* D, double* eval, double* energy,
+                double* mu)
+{
+    if (!h) return -1;
+    if (h->dtype == ELSI_GPU_COMPLEX128) return dm_complex(h, H, S, occ, D, eval, energy, mu);
+    return dm_real(h, H, S, occ, D, eval, energy, mu);
 }
 
 }  // extern "C"

@@ -16,7 +16,9 @@ EPS = np.finfo(np.float64).eps
 
 
 def overlap_condition(S) -> float:
-    w = np.linalg.eigvalsh(np.asarray(S, dtype=np.float64))
+    S = np.asarray(S)
+    S = S.astype(np.complex128) if np.iscomplexobj(S) else S.astype(np.float64)
+    w = np.linalg.eigvalsh(S)
     return float(w[-1] / w[0])
 
 
