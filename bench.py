@@ -248,6 +248,89 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def complex_bench(args):
+    """Complex Hermitian k-point problems: the periodic 8 x 8 x 12 cell of
+    s-Gaussians (768 atoms x 15 = 11,520 basis functions), Bloch sums over the
+    27 nearest images, the first args.kpoints points of the 4 x 2 x 2
+    Monkhorst-Pack grid without Gamma, n_occ = N / 4 per cell, one
+    complex-handle dm call per k-point per step.  Flops are counted as for a
+    complex solver, 4 F(N, k_s) per k-point; the library solves the real
+    2N x 2N image, which takes twice that."""
+    import torch
+
+    from paper_1705_11191_amd import binding as B
+    from synth import generator as G
+
+    dev = torch.device("cuda:0")
+    cell = tuple(int(x) for x in args.cell.split(","))
+    kpts = G.MP_KPOINTS_4x2x2[: args.kpoints]
+    t_gen = time.perf_counter()
+    H0, S0 = [], []
+    for q, k in enumerate(kpts):
+        sp = G.make_kpoint_system_torch(cell, k, seed=0, device=dev)
+        H0.append(sp.H)
+        S0.append(sp.S)
+        nocc = sp.n_occ
+        kT = sp.kT
+    torch.cuda.synchronize()
+    n = int(H0[0].shape[0])
+    print(f"[bench] {len(kpts)} k-point inputs (N = {n} complex) built in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+    H = B.fortran_empty(n, n, device=dev, dtype=torch.complex128)
+    S = B.fortran_empty(n, n, device=dev, dtype=torch.complex128)
+    D = B.fortran_empty(n, n, device=dev, dtype=torch.complex128)
+    h = B.Handle(n, n, nocc, dtype=B.COMPLEX128)
+    h.set_band_width(args.band)
+
+    def step():
+        outs = []
+        for q in range(len(kpts)):
+            H.copy_(H0[q])
+            S.copy_(S0[q])
+            Dq, ev, f, energy, mu, st = h.dm(H, S, D_out=D)
+            outs.append((ev, energy, mu, st, h.info()["k_s"]))
+        return outs
+
+    for w in range(args.warmup):
+        step()
+        print(f"[bench] complex warmup {w} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        outs = step()
+        print(f"[bench] complex step {k} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    F = sum(4.0 * algorithmic_flops(n, o[4]) for o in outs)
+    # checks on the last k-point: D Hermitian, tr(D S) = n_occ
+    herm = float((D - D.conj().t()).abs().max().item())
+    trDS = complex((D * S0[-1].t()).sum().item())
+    h.close()
+    out = {
+        "metric": "complex Hermitian GEVP+density-matrix wall time & TFLOP/s (complex flop count)",
+        "value": F / (ms / 1e3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"kpoint3d_cell{cell[0]}x{cell[1]}x{cell[2]}_N{n}_k{len(kpts)}_complex_dm",
+                   "n_basis": n, "kpoints": len(kpts), "n_occ": int(nocc), "kT_Ha": kT,
+                   "band_width": args.band, "path": "real 2N image"},
+        "ms_per_kpoint": ms / len(kpts),
+        "k_s": [o[4] for o in outs],
+        "mu_Ha": [o[2] for o in outs],
+        "checks": {"status_all_zero": all(o[3] == 0 for o in outs), "D_hermitian_max_abs": herm,
+                   "trace_DS_minus_Ne_last": trDS.real - nocc, "trace_DS_imag_last": trDS.imag},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,11 +346,19 @@ def main():
                     help="write the HBM traffic summary of --kernel from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--kernel", default="dgemm_kernel<128,128,0,true>")
     ap.add_argument("--pmc-command", action="append", default=[])
-    ap.add_argument("--workload", choices=["single", "batch"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "complex"], default="single",
                     help="single: the N=32768 dm solve; batch: 256 uneven problems in one batched call")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--kpoints", type=int, default=4, help="complex workload: k-points per step (1..16)")
+    ap.add_argument("--cell", default="8,8,12", help="complex workload: cell sites along x,y,z")
     ap.add_argument("--batch-workers", type=int, default=8)
     args = ap.parse_args()
+    if args.workload == "complex":
+        if args.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        complex_bench(args)
+        return
     if args.workload == "batch":
         if args.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)

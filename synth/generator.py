@@ -266,6 +266,26 @@ def toeplitz_pencil(n: int, alpha: float, beta: complex, sigma: complex):
 # ----------------------------------------------------------------------------
 # complex Hermitian k-point pencils (periodic cell, Bloch sums)
 # ----------------------------------------------------------------------------
+def _draw_kpoint_cell(cell_sites, seed, orbitals_per_atom, spacing, jitter_amp, alpha_lo, alpha_hi):
+    mx, my, mz = (int(v) for v in cell_sites)
+    n_atoms = mx * my * mz
+    n = n_atoms * orbitals_per_atom
+    rng = np.random.default_rng(seed)
+    jitter = rng.uniform(-jitter_amp, jitter_amp, size=(n_atoms, 3))
+    alphas = rng.uniform(alpha_lo, alpha_hi, size=(n_atoms, orbitals_per_atom)).reshape(-1)
+    h = rng.uniform(-15.0, -5.0, size=n) * HARTREE_PER_EV
+    idx = np.arange(n_atoms)
+    ix, iy, iz = idx % mx, (idx // mx) % my, idx // (mx * my)
+    pos = spacing * np.stack([ix, iy, iz], axis=1).astype(np.float64) + jitter
+    centers = np.repeat(pos, orbitals_per_atom, axis=0)
+    lat = spacing * np.array([mx, my, mz], dtype=np.float64)
+    return (mx, my, mz), centers, alphas, h, lat
+
+
+MP_KPOINTS_4x2x2 = [(k1, k2, k3) for k1 in (-0.375, -0.125, 0.125, 0.375)
+                    for k2 in (-0.25, 0.25) for k3 in (-0.25, 0.25)]
+
+
 def make_kpoint_system(cell_sites=(3, 3, 3), kpt=(0.125, 0.25, 0.25), seed: int = 0,
                        kappa: float = DEFAULT_KAPPA, orbitals_per_atom: int = 4,
                        spacing: float = 2.5, jitter_amp: float = 0.2, alpha_lo: float = 0.8,
@@ -287,18 +307,9 @@ def make_kpoint_system(cell_sites=(3, 3, 3), kpt=(0.125, 0.25, 0.25), seed: int 
     Random numbers: jitter (atoms x 3), exponents (atoms x orbitals), on-site
     energies (N), in that order from ``numpy.random.default_rng(seed)``.
     """
-    mx, my, mz = (int(v) for v in cell_sites)
-    n_atoms = mx * my * mz
-    n = n_atoms * orbitals_per_atom
-    rng = np.random.default_rng(seed)
-    jitter = rng.uniform(-jitter_amp, jitter_amp, size=(n_atoms, 3))
-    alphas = rng.uniform(alpha_lo, alpha_hi, size=(n_atoms, orbitals_per_atom)).reshape(-1)
-    h = rng.uniform(-15.0, -5.0, size=n) * HARTREE_PER_EV
-    idx = np.arange(n_atoms)
-    ix, iy, iz = idx % mx, (idx // mx) % my, idx // (mx * my)
-    pos = spacing * np.stack([ix, iy, iz], axis=1).astype(np.float64) + jitter
-    centers = np.repeat(pos, orbitals_per_atom, axis=0)
-    lat = spacing * np.array([mx, my, mz], dtype=np.float64)
+    (mx, my, mz), centers, alphas, h, lat = _draw_kpoint_cell(cell_sites, seed, orbitals_per_atom, spacing,
+                                                              jitter_amp, alpha_lo, alpha_hi)
+    n = h.shape[0]
     k = np.asarray(kpt, dtype=np.float64)
     S = np.zeros((n, n), dtype=np.complex128)
     H = np.zeros((n, n), dtype=np.complex128)
@@ -330,6 +341,90 @@ def make_kpoint_system(cell_sites=(3, 3, 3), kpt=(0.125, 0.25, 0.25), seed: int 
     if not (w[0] + sigma > 0.5 * sigma):
         raise ValueError("truncated Bloch sum is not positive definite; use larger exponents or cell")
     S[np.arange(n), np.arange(n)] += sigma
+    return SystemSpec(H, S, n_occ=float(n // 4), kT=DEFAULT_KT,
+                      meta=dict(kind="kpoint3d", cell_sites=(mx, my, mz), kpt=tuple(k), seed=seed,
+                                kappa=kappa, sigma=sigma, orbitals_per_atom=orbitals_per_atom))
+
+
+def make_kpoint_system_torch(cell_sites=(8, 8, 12), kpt=(0.125, 0.25, 0.25), seed: int = 0,
+                             kappa: float = DEFAULT_KAPPA, orbitals_per_atom: int = 15,
+                             spacing: float = 2.5, jitter_amp: float = 0.2, alpha_lo: float = 0.8,
+                             alpha_hi: float = 3.0, device="cuda", block: int = 2048,
+                             lanczos_steps: int = 80) -> SystemSpec:
+    """:func:`make_kpoint_system` assembled with torch on ``device`` for large
+    cells (default: the 768-atom 8 x 8 x 12 cell, N = 11,520).  H and S are
+    column-major complex128 tensors; lambda_max(S(k)) comes from a Lanczos run
+    with full reorthogonalization (deterministic start).  The positive
+    definiteness check of the small version is skipped (the cell is 20 x 20 x
+    30 bohr, far larger than the Gaussians' reach)."""
+    import torch
+
+    (mx, my, mz), centers, alphas, h, lat = _draw_kpoint_cell(cell_sites, seed, orbitals_per_atom, spacing,
+                                                              jitter_amp, alpha_lo, alpha_hi)
+    n = h.shape[0]
+    c = torch.as_tensor(centers, dtype=torch.float64, device=device)
+    a = torch.as_tensor(alphas, dtype=torch.float64, device=device)
+    hh = torch.as_tensor(h, dtype=torch.float64, device=device)
+    k = np.asarray(kpt, dtype=np.float64)
+    # row-major buffers of the transposes, returned as column-major views
+    St = torch.zeros((n, n), dtype=torch.complex128, device=device)
+    Ht = torch.zeros((n, n), dtype=torch.complex128, device=device)
+    for i0 in range(0, n, block):
+        i1 = min(n, i0 + block)
+        ai = a[i0:i1, None]
+        p = ai + a[None, :]
+        pref = (2.0 * torch.sqrt(ai * a[None, :]) / p) ** 1.5
+        ex = ai * a[None, :] / p
+        hw = WH_K * 0.5 * (hh[i0:i1, None] + hh[None, :])
+        for rx in (-1, 0, 1):
+            for ry in (-1, 0, 1):
+                for rz in (-1, 0, 1):
+                    nR = np.array([rx, ry, rz], dtype=np.float64)
+                    shift = torch.as_tensor(nR * lat, dtype=torch.float64, device=device)
+                    d2 = torch.zeros((i1 - i0, n), dtype=torch.float64, device=device)
+                    for ax in range(3):
+                        d2 += (c[i0:i1, ax, None] - (c[None, :, ax] + shift[ax])) ** 2
+                    SR = pref * torch.exp(-ex * d2)
+                    HR = hw * SR
+                    if rx == 0 and ry == 0 and rz == 0:
+                        r = torch.arange(i0, i1, device=device)
+                        HR[r - i0, r] = hh[i0:i1]
+                    ang = 2.0 * math.pi * float(k @ nR)
+                    ph = complex(math.cos(ang), math.sin(ang))
+                    # rows i0:i1 of S(k) are columns i0:i1 of the transposed buffer
+                    St[:, i0:i1] += (SR * ph).T
+                    Ht[:, i0:i1] += (HR * ph).T
+                    del d2, SR, HR
+        del ai, p, pref, ex, hw
+    S = St.t()
+    H = Ht.t()
+    # exact Hermitian symmetry
+    S.copy_(0.5 * (S + S.conj().t()))
+    H.copy_(0.5 * (H + H.conj().t()))
+    sigma = 0.0
+    if kappa is not None and kappa > 0:
+        m = min(lanczos_steps, n)
+        Q = torch.zeros((m + 1, n), dtype=torch.complex128, device=device)
+        alpha = np.zeros(m)
+        beta = np.zeros(m)
+        Q[0] = 1.0 / math.sqrt(n)
+        mm = m
+        for j in range(m):
+            w = S @ Q[j]
+            alpha[j] = torch.vdot(Q[j], w).real.item()
+            w = w - Q[: j + 1].T @ (Q[: j + 1].conj() @ w)
+            w = w - Q[: j + 1].T @ (Q[: j + 1].conj() @ w)
+            bj = torch.linalg.norm(w).item()
+            beta[j] = bj
+            if bj < 1e-14:
+                mm = j + 1
+                break
+            Q[j + 1] = w / bj
+        T = np.diag(alpha[:mm]) + np.diag(beta[: mm - 1], 1) + np.diag(beta[: mm - 1], -1)
+        sigma = float(np.linalg.eigvalsh(T)[-1]) / kappa
+        del Q
+    di = torch.arange(n, device=device)
+    S[di, di] += sigma
     return SystemSpec(H, S, n_occ=float(n // 4), kT=DEFAULT_KT,
                       meta=dict(kind="kpoint3d", cell_sites=(mx, my, mz), kpt=tuple(k), seed=seed,
                                 kappa=kappa, sigma=sigma, orbitals_per_atom=orbitals_per_atom))
