@@ -336,7 +336,7 @@ void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const do
 // triangular, built block column by block column from
 //   T'(0:c, block q) = -T'(0:c, 0:c) (V'(:, 0:c)^T V_q) T_q,
 // so that every application is a product with K = Q1G b.
-constexpr int Q1G = 4;
+constexpr int Q1G = kQ1Group;
 
 size_t apply_q1_workspace_doubles(int n, int ncol)
 {

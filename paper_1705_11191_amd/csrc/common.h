@@ -28,6 +28,11 @@ struct HipCheck {
     }
 };
 
+// Panels per block reflector in the back-transformation with Q1; the
+// full -> band stage stores each panel's V with (kQ1Group - 1) b zero rows
+// above it so that a group reads as one matrix.
+constexpr int kQ1Group = 8;
+
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

@@ -931,7 +931,7 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
         }
         if (nr < bw) fill_d(st, tau + nr, (size_t)(bw - nr), 0.0);
         double* V = Vall + cm(r0, j, n);
-        const int zpad = std::min(3 * b, r0);
+        const int zpad = std::min((kQ1Group - 1) * b, r0);
         hipLaunchKernelGGL(panel_store_v_kernel, dim3(ceil_div(m + zpad, 256), bw), dim3(256), 0, st, m, bw, nr, P,
                            lda, V, n, zpad);
         double* T = Tall + (size_t)p * b * b;
