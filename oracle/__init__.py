@@ -14,6 +14,7 @@ from .oracle import (  # noqa: F401
     occupations,
     potrf,
     reduce_standard,
+    refine,
     residual_norms,
     tred,
     tridiag_eig,

@@ -20,6 +20,9 @@
  *     states downward (Sec. 4.5, elsi_dm_real);
  *   - the density matrix n_ij = sum_l f_l c_il c_jl, Eq. (9), and the band
  *     energy sum_l f_l eps_l (Sec. 4.5, "energy" output of elsi_dm_real).
+ *   - FP64 refinement sweeps (CholeskyQR twice, Rayleigh-Ritz, residual
+ *     norms) of an approximate invariant subspace of H~, the last stage of
+ *     the GPU library's mixed-precision mode (orc_refine);
  *   - the same steps for complex Hermitian H and Hermitian positive definite
  *     S (the complex interface of Sec. 4.3, the k-point problems of periodic
  *     systems), the Householder tridiagonal made real by a diagonal unitary
@@ -520,6 +523,118 @@ void orc_residual_norms(int n, int k, const double *H, int ldh, const double *S,
         }
         res[j] = (double)sqrtl(acc);
     }
+}
+
+/* ========================================================================= */
+/* FP64 refinement of an approximate invariant subspace of the standard-form */
+/* matrix H~ = L^-1 H L^-T (Eq. (11)): the last stage of the GPU library's   */
+/* mixed-precision mode (the paper's solvers run in one precision, so this   */
+/* stage has no passage of its own; each step below is the textbook          */
+/* definition).  X is n x k (ldx); on return it holds the refined vectors.    */
+/* One sweep:                                                                */
+/*   CholeskyQR, twice: G = X^T X = L_G L_G^T, X <- X L_G^-T (row by row,     */
+/*   forward substitution with L_G);                                         */
+/*   Rayleigh-Ritz: A = X^T H~ X, A = Q diag(theta) Q^T (orc_gevp with S = I),*/
+/*   X <- X Q;                                                               */
+/*   residuals res_l = ||H~ x_l - theta_l x_l||_2, from the definition.      */
+/* The first kw states decide: stop with 0 when max res_l <= tol; stop with  */
+/* 3 when a sweep does not halve that maximum, after max_sweeps sweeps, or   */
+/* when G is not positive definite (dependent columns).                      */
+/* ========================================================================= */
+int orc_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int ldx, double *theta,
+               double *res, double tol, int max_sweeps, int *sweeps)
+{
+    if (sweeps) *sweeps = 0;
+    if (n <= 0 || k <= 0) return 0;
+    if (kw > k) kw = k;
+    double *G = (double *)malloc(sizeof(double) * (size_t)k * k);
+    double *I = (double *)malloc(sizeof(double) * (size_t)k * k);
+    double *Q = (double *)malloc(sizeof(double) * (size_t)k * k);
+    double *Y = (double *)malloc(sizeof(double) * (size_t)n * k);
+    double prev = -1.0;
+    int status = 3;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        int bad = 0;
+        for (int pass = 0; pass < 2 && !bad; ++pass) {
+#pragma omp parallel for schedule(static)
+            for (int j = 0; j < k; ++j)
+                for (int i = 0; i < k; ++i) {
+                    double t = 0.0;
+                    for (int r = 0; r < n; ++r) t += X[IDX(r, i, ldx)] * X[IDX(r, j, ldx)];
+                    G[IDX(i, j, k)] = t;
+                }
+            if (orc_potrf(k, G, k)) { bad = 1; break; }
+#pragma omp parallel for schedule(static)
+            for (int r = 0; r < n; ++r) {
+                double *row = (double *)malloc(sizeof(double) * k);
+                for (int j = 0; j < k; ++j) row[j] = X[IDX(r, j, ldx)];
+                fwd_subst(k, G, k, row);   /* L_G y = x^T  <=>  y^T = x L_G^-T */
+                for (int j = 0; j < k; ++j) X[IDX(r, j, ldx)] = row[j];
+                free(row);
+            }
+        }
+        if (bad) { status = 3; break; }
+        /* A = X^T (H~ X), lower triangle of H~ read */
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i < n; ++i) {
+                double t = 0.0;
+                for (int c = 0; c < n; ++c) {
+                    const double h = (i >= c) ? Ht[IDX(i, c, ldh)] : Ht[IDX(c, i, ldh)];
+                    t += h * X[IDX(c, j, ldx)];
+                }
+                Y[IDX(i, j, n)] = t;
+            }
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i < k; ++i) {
+                double t = 0.0;
+                for (int r = 0; r < n; ++r) t += X[IDX(r, i, ldx)] * Y[IDX(r, j, n)];
+                G[IDX(i, j, k)] = t;
+            }
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i < j; ++i) {
+                const double a = 0.5 * (G[IDX(i, j, k)] + G[IDX(j, i, k)]);
+                G[IDX(i, j, k)] = a;
+                G[IDX(j, i, k)] = a;
+            }
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i < k; ++i) I[IDX(i, j, k)] = (i == j) ? 1.0 : 0.0;
+        if (orc_gevp(k, k, G, k, I, k, theta, Q, NULL)) { status = 3; break; }
+        /* X <- X Q */
+#pragma omp parallel for schedule(static)
+        for (int r = 0; r < n; ++r) {
+            double *row = (double *)malloc(sizeof(double) * k);
+            for (int j = 0; j < k; ++j) {
+                double t = 0.0;
+                for (int c = 0; c < k; ++c) t += X[IDX(r, c, ldx)] * Q[IDX(c, j, k)];
+                row[j] = t;
+            }
+            for (int j = 0; j < k; ++j) X[IDX(r, j, ldx)] = row[j];
+            free(row);
+        }
+        /* res_l = || H~ x_l - theta_l x_l || */
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < k; ++j) {
+            double acc = 0.0;
+            for (int i = 0; i < n; ++i) {
+                double t = -theta[j] * X[IDX(i, j, ldx)];
+                for (int c = 0; c < n; ++c) {
+                    const double h = (i >= c) ? Ht[IDX(i, c, ldh)] : Ht[IDX(c, i, ldh)];
+                    t += h * X[IDX(c, j, ldx)];
+                }
+                acc += t * t;
+            }
+            res[j] = sqrt(acc);
+        }
+        if (sweeps) *sweeps = sweep + 1;
+        double rmax = 0.0;
+        for (int l = 0; l < kw; ++l) if (res[l] > rmax) rmax = res[l];
+        if (rmax <= tol) { status = 0; break; }
+        if (prev >= 0.0 && rmax > 0.5 * prev) break;
+        prev = rmax;
+    }
+    free(G); free(I); free(Q); free(Y);
+    return status;
 }
 
 /* ========================================================================= */

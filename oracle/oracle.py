@@ -52,6 +52,7 @@ def _load():
         lib.orc_band_energy.restype = d
         lib.orc_dm.argtypes = [i, _dp, i, _dp, i, d, d, d, d, i, _dp, i, _dp, _dp, _dp, _dp, _ip]
         lib.orc_residual_norms.argtypes = [i, i, _dp, i, _dp, i, _dp, i, _dp, _dp]
+        lib.orc_refine.argtypes = [i, i, i, _dp, i, _dp, i, _dp, _dp, d, i, _ip]
         lib.orc_zpotrf.argtypes = [i, _dp, i]
         lib.orc_zreduce.argtypes = [i, _dp, i, _dp, i]
         lib.orc_ztred.argtypes = [i, _dp, i, _dp, _dp, _dp, i]
@@ -225,6 +226,21 @@ def residual_norms(H, S, X, lam):
 # complex Hermitian path (complex128 arrays; the C side reads them as
 # interleaved real/imaginary doubles)
 # ---------------------------------------------------------------------------
+def refine(Ht, X, kw, tol=1e-10, max_sweeps=4):
+    """FP64 refinement sweeps of the subspace X (n x k) of the symmetric Ht
+    (CholeskyQR twice, Rayleigh-Ritz, residual norms); returns
+    (X_refined, theta, res, sweeps, status) with status 0 or 3."""
+    A = _f64(Ht)
+    Xr = _f64(X).copy(order="F")
+    n, k = Xr.shape
+    theta = np.zeros(max(k, 1))
+    res = np.zeros(max(k, 1))
+    sw = ctypes.c_int(0)
+    st = _load().orc_refine(n, k, int(kw), _p(A), n, _p(Xr), n, _p(theta), _p(res), float(tol),
+                            int(max_sweeps), ctypes.byref(sw))
+    return Xr, theta[:k], res[:k], sw.value, st
+
+
 def zpotrf(S):
     """Complex Cholesky S = L L^H (lower), strict upper triangle zeroed."""
     A = _c128(S)
