@@ -488,25 +488,54 @@ __device__ void cq_signed_lu_wave(double (&a)[BMAX], double* __restrict__ sgn)
     }
 }
 
-// x <- x M^-T for a lower triangular M in LDS (z M^T = x by substitution in
-// blocks of 8 columns; dinv holds 1 / M_kk): with M = L it is one CholeskyQR
-// step x L^-T, with M = U^T it is x U^-1.
-__device__ inline void cq_row_solve(double (&x)[BMAX], const double (*__restrict__ M)[LP],
-                                    const double* __restrict__ dinv)
+// The wave's 64 rows of St <- Z with Z M^T = St for a lower triangular M in
+// LDS (dinv holding 1 / M_kk): with M = L one CholeskyQR step X L^-T, with
+// M = U^T the product X U^-1.  Blocked by 16 columns J: the update
+// Y_J = X_J - Z_{<J} M_{J,<J}^T on the matrix cores, then Z_J from
+// Z_J M_JJ^T = Y_J by substitution, each lane taking its own row.  Only the
+// wave's own rows are read or written.
+__device__ void cq_rows_solve(double (*__restrict__ St)[LP], const double (*__restrict__ M)[LP],
+                              const double* __restrict__ dinv)
 {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int r0 = 64 * wave;
 #pragma unroll
-    for (int kb = 0; kb < BMAX; kb += 8) {
+    for (int J = 0; J < 4; ++J) {
+        const int o = 16 * J;
+        if (J > 0) {
+            double4_t acc[4];
 #pragma unroll
-        for (int k = kb; k < kb + 8; ++k) {
-            x[k] *= dinv[k];
+            for (int R = 0; R < 4; ++R)
 #pragma unroll
-            for (int c = k + 1; c < kb + 8; ++c) x[c] -= x[k] * M[c][k];
+                for (int r = 0; r < 4; ++r) acc[R][r] = St[r0 + 16 * R + 4 * r + lk][o + li];
+#pragma unroll
+            for (int kk = 0; kk < o; kk += 4) {
+                const double bm = M[o + li][kk + lk];
+#pragma unroll
+                for (int R = 0; R < 4; ++R)
+                    acc[R] = __builtin_amdgcn_mfma_f64_16x16x4f64(-St[r0 + 16 * R + li][kk + lk], bm, acc[R], 0, 0,
+                                                                  0);
+            }
+#pragma unroll
+            for (int R = 0; R < 4; ++R)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) St[r0 + 16 * R + 4 * r + lk][o + li] = acc[R][r];
+            cq_wave_sync();
+        }
+        double y[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) y[c] = St[r0 + lane][o + c];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            double t = y[c];
+#pragma unroll
+            for (int k = 0; k < c; ++k) t -= y[k] * M[o + c][o + k];
+            y[c] = t * dinv[o + c];
         }
 #pragma unroll
-        for (int c = kb + 8; c < BMAX; ++c) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) x[c] -= x[kb + j] * M[c][kb + j];
-        }
+        for (int c = 0; c < 16; ++c) St[r0 + lane][o + c] = y[c];
+        cq_wave_sync();
     }
 }
 
@@ -538,17 +567,13 @@ __global__ __launch_bounds__(CQ_NT, 1) void panel_cholqr_kernel(int m, double* P
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         rec, (short)0, (int)(((size_t)l1o + BMAX * BMAX) * 8), 0x00020000);
 
-    double x[BMAX];
-#pragma unroll
-    for (int r = 0; r < BMAX; ++r) x[r] = (i < m) ? P[cm(i, r, ldp)] : 0.0;
+    // the rows stay in LDS through all three phases
+#pragma unroll 8
+    for (int r = 0; r < BMAX; ++r) St[tid][r] = (i < m) ? P[cm(i, r, ldp)] : 0.0;
+    __syncthreads();
     int arrive = 0;
 
     for (int ph = 0; ph < 3; ++ph) {
-        // park the rows in LDS (the Gram products read them there; the 64 x 64
-        // factorizations need the registers)
-#pragma unroll
-        for (int r = 0; r < BMAX; ++r) St[tid][r] = x[r];
-        __syncthreads();
         if (ph < 2) {
             // partial Gram matrix of this workgroup's rows on the matrix cores
             double4_t acc[TPW];
@@ -662,9 +687,7 @@ __global__ __launch_bounds__(CQ_NT, 1) void panel_cholqr_kernel(int m, double* P
                 }
             }
             __syncthreads();
-#pragma unroll
-            for (int r = 0; r < BMAX; ++r) x[r] = St[tid][r];
-            cq_row_solve(x, Gb, dinv);   // x <- x L^-T
+            cq_rows_solve(St, Gb, dinv);   // rows <- rows L^-T
         } else {
             if (blk == 0 && wave == 0) {
                 // R = R2 R1 = L2^T L1^T, lane c forming column c:
@@ -712,15 +735,13 @@ __global__ __launch_bounds__(CQ_NT, 1) void panel_cholqr_kernel(int m, double* P
             __syncthreads();
             if (tid < BMAX) dinv[tid] = 1.0 / Xb[tid][tid];
             __syncthreads();
-#pragma unroll
-            for (int r = 0; r < BMAX; ++r) x[r] = St[tid][r];
-            if (i >= BMAX) cq_row_solve(x, Xb, dinv);   // V2 = Q2 U^-1
+            if (blk > 0 || wave > 0) cq_rows_solve(St, Xb, dinv);   // V2 = Q2 U^-1 (rows 64 and on)
         }
         __syncthreads();
     }
     if (i >= BMAX && i < m) {
-#pragma unroll
-        for (int c = 0; c < BMAX; ++c) P[cm(i, c, ldp)] = x[c];
+#pragma unroll 8
+        for (int c = 0; c < BMAX; ++c) P[cm(i, c, ldp)] = St[tid][c];
     }
     if (blk == 0 && tid == 0) *status = 1;
 }
