@@ -352,6 +352,11 @@ def main():
     ap.add_argument("--kpoints", type=int, default=4, help="complex workload: k-points per step (1..16)")
     ap.add_argument("--cell", default="8,8,12", help="complex workload: cell sites along x,y,z")
     ap.add_argument("--batch-workers", type=int, default=8)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="single workload: plain FP64, or FP32 matrix-core products in full -> band and Q1 "
+                         "followed by FP64 refinement")
+    ap.add_argument("--refine-tol", type=float, default=1e-10)
+    ap.add_argument("--max-refine", type=int, default=4)
     args = ap.parse_args()
     if args.workload == "complex":
         if args.gpus != 1:
@@ -393,8 +398,23 @@ def main():
     D = torch.empty_like(H0)
     ev = torch.empty(n, device=dev, dtype=torch.float64)
     f = torch.empty(n, device=dev, dtype=torch.float64)
+    mixed = args.precision == "mixed"
+    ref64 = None
+    if mixed:
+        # untimed FP64 solve of the same input: the accuracy yardstick of the mixed path
+        h64 = B.Handle(n, n, n_occ)
+        h64.set_band_width(args.band)
+        H.copy_(H0)
+        S.copy_(S0)
+        D64, ev64, _, _, _, _ = h64.dm(H, S)
+        ref64 = (D64, ev64, h64.info()["k_s"])
+        h64.close()
+        torch.cuda.empty_cache()
+        print("[bench] FP64 reference solve done", file=sys.stderr, flush=True)
     h = B.Handle(n, n, n_occ)
     h.set_band_width(args.band)
+    if mixed:
+        h.set_precision(B.PREC_MIXED, args.refine_tol, args.max_refine)
     ws = torch.empty(h.workspace_size() // 8 + 1, device=dev, dtype=torch.float64)
     h.set_workspace(ws)
 
@@ -405,10 +425,14 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
+    last_status = [0]
+
     def step():
         H.copy_(H0)
         S.copy_(S0)
-        return h.dm(H, S, occ=f, D_out=D, eval_out=ev)
+        r = h.dm(H, S, occ=f, D_out=D, eval_out=ev, ok=(0, 3) if mixed else (0,))
+        last_status[0] = r[5]
+        return r
 
     for w in range(args.warmup):
         step()
@@ -452,6 +476,15 @@ def main():
     trace_ds = float((D * S0).sum().item())
     ascending = bool(torch.all(ev[1:] >= ev[:-1]).item())
 
+    refine = None
+    if mixed:
+        D64, ev64, ks64 = ref64
+        kk = min(ks, ks64)
+        refine = {"status": last_status[0], "sweeps": info["refine_sweeps"], "states": info["refine_states"],
+                  "resid_Ha": info["refine_resid"], "tol_Ha": args.refine_tol,
+                  "max_abs_dD_vs_fp64": float((D - D64).abs().max().item()),
+                  "max_abs_deig_vs_fp64_Ha": float((ev[:kk] - ev64[:kk]).abs().max().item())}
+        del D64, ev64
     out = {
         "metric": METRIC,
         "value": value,
@@ -463,17 +496,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": wl["name"], "n_basis": n, "n_occ": int(n_occ), "kT_Ha": spec.kT,
                    "kappa_S": spec.meta["kappa"], "band_width": info["band_width"], "k_s": ks,
-                   "path": "plain_fp64"},
+                   "path": "fp32_products_fp64_refine" if mixed else "plain_fp64"},
         "roofline": roofline,
         "algorithmic_flops": F,
         "stage_ms": stage_ms,
         "checks": {"trace_DS_minus_Ne": trace_ds - n_occ, "eigenvalues_ascending": ascending,
                    "mu_Ha": info["mu"]},
     }
+    if refine is not None:
+        out["refine"] = refine
+        out["cpu_baseline_note"] = "the CPU baseline is the FP64 oracle in both precisions"
     h.close()
     del ws, H, S, D, H0, S0
     torch.cuda.empty_cache()

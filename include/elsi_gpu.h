@@ -66,7 +66,8 @@ enum { ELSI_GPU_OCC_EXPLICIT = 0, ELSI_GPU_OCC_FERMI = 1 };
 enum {
     ELSI_GPU_ERR_NOT_PD = 1,      /* S not positive definite; info.fail_col = first bad pivot (1-based) */
     ELSI_GPU_ERR_NO_CONV = 2,     /* tridiagonal eigensolver did not converge */
-    ELSI_GPU_ERR_REFINE = 3,      /* reserved: refinement tolerance not reached */
+    ELSI_GPU_ERR_REFINE = 3,      /* mixed precision: refinement did not reach refine_tol (outputs
+                                     still written; info.refine_resid holds the bound reached) */
     ELSI_GPU_ERR_MU = 4,          /* mu bisection ran out of steps (outputs still written) */
     ELSI_GPU_ERR_HIP = 5,         /* HIP runtime error */
     ELSI_GPU_ERR_OOM = 6,         /* device memory exhausted */
@@ -86,8 +87,12 @@ enum {
     ELSI_GPU_ST_BACK_Q1 = 7,    /* step (5) */
     ELSI_GPU_ST_BACKSUB = 8,    /* c = L^-T c~ */
     ELSI_GPU_ST_DENSITY = 9,    /* Eq. (9) */
-    ELSI_GPU_NSTAGES = 10
+    ELSI_GPU_ST_REFINE = 10,    /* FP64 refinement of the mixed-precision path */
+    ELSI_GPU_NSTAGES = 11
 };
+
+/* arithmetic of elsi_gpu_ev / elsi_gpu_dm (elsi_gpu_set_precision) */
+enum { ELSI_GPU_PREC_FP64 = 0, ELSI_GPU_PREC_MIXED = 1 };
 
 typedef struct elsi_gpu_info {
     double stage_ms[ELSI_GPU_NSTAGES]; /* device time per stage of the last call */
@@ -109,6 +114,13 @@ typedef struct elsi_gpu_info {
     double probe_ms;
     double probe_flops;
     char probe_kernel[48];
+    /* Mixed precision (elsi_gpu_set_precision): refinement sweeps run, states
+     * refined (wanted plus guard), and the largest residual norm
+     * ||H~ x - theta x||_2 of the wanted states after the last sweep (Ha; a
+     * bound on their eigenvalue errors).  Zero in FP64 mode. */
+    int refine_sweeps;
+    int refine_states;
+    double refine_resid;
 } elsi_gpu_info;
 
 /* Create a handle (elsi_init, Sec. 4.4).  n_state: eigenvectors returned by
@@ -146,6 +158,26 @@ int elsi_gpu_set_overlap_factored(elsi_gpu_handle h, int flag);
 
 /* Band width b of step (1) (Eq. (13)); 8 <= b <= 64, multiple of 8. */
 int elsi_gpu_set_band_width(elsi_gpu_handle h, int b);
+
+/* Arithmetic of elsi_gpu_ev / elsi_gpu_dm on a real handle (the paper's
+ * solvers run in one precision; the mixed mode is this library's addition).
+ * ELSI_GPU_PREC_FP64 (default): every step in FP64.
+ * ELSI_GPU_PREC_MIXED: the matrix products of step (1) (full -> band) and of
+ * step (5) (back-transformation by Q1) round their operands to FP32 and
+ * multiply and accumulate in FP32 on the matrix cores; Cholesky, reduction
+ * (Eq. (10), (11)), steps (2)-(4), storage and everything else stay FP64.
+ * The library then carries k' = min(n, k + max(64, ceil(k / 10))) states
+ * (k = n_state for ev, k_s for dm) and refines them in FP64 against
+ * H~ = L^-1 H L^-T: per sweep CholeskyQR twice, Rayleigh-Ritz with the FP64
+ * solver, residual norms r_l = ||H~ x_l - theta_l x_l||_2.  Sweeps stop at
+ * max_l r_l <= refine_tol over the wanted states (status 0), when a sweep
+ * does not halve that maximum, or after max_refine sweeps; the last two end
+ * with ELSI_GPU_ERR_REFINE and all outputs written.  Eigenvalues above the
+ * k' refined ones are the FP32-step values.  Needs n^2 more doubles of
+ * workspace.  Batched calls always run in FP64.
+ * Errors: -1 h NULL, -2 prec unknown or a complex handle asks for MIXED,
+ * -3 refine_tol not >= 0, -4 max_refine < 0. */
+int elsi_gpu_set_precision(elsi_gpu_handle h, int prec, double refine_tol, int max_refine);
 
 /* Measurement aid, not part of the method: on = 1 brackets every GEMM launch
  * with a pair of HIP events on the handle's stream and resets the totals
@@ -291,6 +323,21 @@ int elsi_gpu_x_tridiagonalize(int n, int b, double *A, int lda, double *d, doubl
  * symmetric tridiagonal (d, e) by divide and conquer. */
 int elsi_gpu_x_tridiag_eig(int n, const double *d, const double *e, double *w, double *Z, int ldz,
                            void *hip_stream);
+
+/* FP64 refinement sweeps of the mixed path (elsi_gpu_set_precision) on a
+ * caller's subspace: Ht device n x n symmetric (both triangles, ldh; e.g. the
+ * output of elsi_gpu_x_reduce), X device n x k (ldx) spanning the
+ * approximation, overwritten by the refined vectors (orthonormal, Ritz
+ * order); theta (k) and resid (k) device out: Ritz values ascending and
+ * ||Ht x_l - theta_l x_l||_2.  The first kw states decide convergence
+ * (max resid <= tol); *sweeps (host, may be NULL) receives the sweeps run.
+ * Returns ELSI_GPU_ERR_REFINE when tol was not reached (outputs written; with
+ * max_sweeps = 0 nothing is written) or when the columns of X are
+ * numerically dependent.  Errors: -1 n < 0, -2 k outside 0..n, -3 kw outside
+ * 0..k, -4 Ht / ldh, -6 X / ldx, -8 theta, -9 resid, -10 tol, -11 max_sweeps. */
+int elsi_gpu_x_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int ldx,
+                      double *theta, double *resid, double tol, int max_sweeps, int *sweeps,
+                      void *hip_stream);
 
 #ifdef __cplusplus
 }

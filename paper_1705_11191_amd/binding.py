@@ -22,9 +22,11 @@ REAL64 = 0
 COMPLEX128 = 1
 OCC_EXPLICIT = 0
 OCC_FERMI = 1
-NSTAGES = 10
+PREC_FP64 = 0
+PREC_MIXED = 1
+NSTAGES = 11
 STAGES = ["cholesky", "reduce", "band", "bulge", "tridiag", "occ", "back_q2", "back_q1",
-          "backsub", "density"]
+          "backsub", "density", "refine"]
 
 
 class ElsiGpuError(RuntimeError):
@@ -41,7 +43,9 @@ class Info(ctypes.Structure):
                 ("fail_col", ctypes.c_int), ("mu_steps", ctypes.c_int),
                 ("band_width", ctypes.c_int), ("n_basis", ctypes.c_int),
                 ("probe_launches", ctypes.c_int), ("probe_ms", ctypes.c_double),
-                ("probe_flops", ctypes.c_double), ("probe_kernel", ctypes.c_char * 48)]
+                ("probe_flops", ctypes.c_double), ("probe_kernel", ctypes.c_char * 48),
+                ("refine_sweeps", ctypes.c_int), ("refine_states", ctypes.c_int),
+                ("refine_resid", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "stage_ms"}
@@ -78,6 +82,7 @@ def lib():
         L.elsi_gpu_set_band_width.argtypes = [vp, i]
         L.elsi_gpu_set_launch_timing.argtypes = [vp, i]
         L.elsi_gpu_set_batch_workers.argtypes = [vp, i]
+        L.elsi_gpu_set_precision.argtypes = [vp, i, d, i]
         pp, ip, dp = ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(d)
         L.elsi_gpu_ev_batched.argtypes = [vp, i, ip, ip, pp, pp, pp, pp, ip]
         L.elsi_gpu_dm_batched.argtypes = [vp, i, ip, dp, dp, pp, pp, pp, pp, dp, dp, ip]
@@ -95,6 +100,7 @@ def lib():
         L.elsi_gpu_x_band_reduce.argtypes = [i, i, vp, i, vp, i, vp]
         L.elsi_gpu_x_tridiagonalize.argtypes = [i, i, vp, i, vp, vp, vp]
         L.elsi_gpu_x_tridiag_eig.argtypes = [i, vp, vp, vp, vp, i, vp]
+        L.elsi_gpu_x_refine.argtypes = [i, i, i, vp, i, vp, i, vp, vp, d, i, ctypes.POINTER(i), vp]
         _lib = L
     return _lib
 
@@ -224,6 +230,24 @@ def tridiag_eig(d: torch.Tensor, e: torch.Tensor):
     return w, Z
 
 
+def refine(Ht: torch.Tensor, X: torch.Tensor, kw: int, tol: float = 1e-10, max_sweeps: int = 4):
+    """FP64 refinement sweeps of the mixed path on the subspace X (n x k) of the
+    symmetric Ht; X is overwritten by the refined vectors.  Returns
+    (theta, resid, sweeps, status) with status 0 or 3 (tolerance not reached)."""
+    n = Ht.shape[0]
+    k = X.shape[1]
+    Ht = as_fortran(Ht)
+    if not X.t().is_contiguous():
+        raise ValueError("X must be column-major (see fortran_empty)")
+    theta = torch.zeros(max(k, 1), device=Ht.device, dtype=torch.float64)
+    resid = torch.zeros(max(k, 1), device=Ht.device, dtype=torch.float64)
+    sw = ctypes.c_int(0)
+    rc = lib().elsi_gpu_x_refine(n, k, kw, _ptr(Ht), max(1, n), _ptr(X), max(1, n), _ptr(theta), _ptr(resid),
+                                 float(tol), int(max_sweeps), ctypes.byref(sw), _stream())
+    _check(rc, "elsi_gpu_x_refine", ok=(0, 3))
+    return theta[:k], resid[:k], sw.value, rc
+
+
 # ---------------------------------------------------------------------------
 # handle API
 # ---------------------------------------------------------------------------
@@ -271,6 +295,12 @@ class Handle:
     def set_band_width(self, b: int):
         _check(lib().elsi_gpu_set_band_width(self._h, b), "set_band_width")
 
+    def set_precision(self, prec=PREC_FP64, refine_tol=1e-10, max_refine=4):
+        """PREC_FP64, or PREC_MIXED: FP32 matrix-core products in full -> band and Q1,
+        then FP64 refinement (real handles)."""
+        _check(lib().elsi_gpu_set_precision(self._h, int(prec), float(refine_tol), int(max_refine)),
+               "elsi_gpu_set_precision")
+
     def set_launch_timing(self, on: bool):
         """Per-launch HIP-event timing of the GEMM kernels (measurement aid)."""
         _check(lib().elsi_gpu_set_launch_timing(self._h, int(bool(on))), "set_launch_timing")
@@ -285,15 +315,17 @@ class Handle:
         _check(lib().elsi_gpu_set_workspace(self._h, _ptr(buf), buf.numel() * buf.element_size()),
                "set_workspace")
 
-    def ev(self, H: torch.Tensor, S: torch.Tensor, eval_out=None, evec_out=None):
-        """Eigenpairs; H is destroyed and S receives L.  Returns (eval, evec column-major)."""
+    def ev(self, H: torch.Tensor, S: torch.Tensor, eval_out=None, evec_out=None, ok=(0,)):
+        """Eigenpairs; H is destroyed and S receives L.  Returns (eval, evec column-major);
+        the return code is kept in self.last_status (codes in `ok` do not raise)."""
         n = self.n
         self._check_input(H, S)
         ev = eval_out if eval_out is not None else torch.empty(n, device=H.device, dtype=torch.float64)
         C = evec_out if evec_out is not None else fortran_empty(n, self.n_state, device=H.device,
                                                                 dtype=self._mat_dtype())
         rc = lib().elsi_gpu_ev(self._h, _ptr(H), _ptr(S), _ptr(ev), _ptr(C))
-        _check(rc, "elsi_gpu_ev")
+        self.last_status = rc
+        _check(rc, "elsi_gpu_ev", ok=ok)
         return ev, C
 
     def dm(self, H: torch.Tensor, S: torch.Tensor, occ=None, D_out=None, eval_out=None,

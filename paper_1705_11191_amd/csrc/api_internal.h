@@ -3,6 +3,8 @@
 #include "../../include/elsi_gpu.h"
 #include "common.h"
 
+#include <algorithm>
+
 namespace eg {
 
 constexpr double kFCut = 1e-20;   // eigenvectors with f_l <= kFCut do not enter D
@@ -51,6 +53,31 @@ void orthonormalize_complex_images(hipStream_t st, int n, int k, double* U, int 
 int select_complex_states(hipStream_t st, int n, int k, const double* w2, const double* X, int ldx, int k2,
                           double* U, int ldu, int* dsrc);
 
+// FP64 refinement of an approximate invariant subspace of the standard-form
+// matrix (refine.hip).  bufs[0] holds X (n x k, ld ldb) on entry; bufs[1] and
+// bufs[2] are n x k scratch of the same leading dimension; on return
+// bufs[out->x_buf] holds the refined vectors, theta the Ritz values ascending
+// and r their residual norms.  kw: leading states whose residuals decide
+// convergence.  G, Qm: k x k; Linv: ceil(k / 64) * 4096 doubles; dinfo: one
+// device int; part: npart doubles of split-K scratch.
+struct RefineOutcome {
+    int x_buf;
+    int sweeps;
+    int converged;
+    double rmax;   // largest residual norm of the first kw states after the last sweep
+};
+size_t refine_scratch_doubles(int n, int k);
+int refine_subspace(hipStream_t st, int n, int k, int kw, const double* Ht, int ldh, double* const bufs[3], int ldb,
+                    double* G, double* Qm, double* Linv, int* dinfo, double* part, size_t npart, double* theta,
+                    double* r, double tol, int max_sweeps, RefineOutcome* out);
+
+// Guard states carried beyond the kw wanted ones in the mixed path.
+inline int refine_columns(int n, int kw)
+{
+    const int g = std::max(64, (kw + 9) / 10);
+    return std::min(n, kw + g);
+}
+
 }  // namespace eg
 
 struct elsi_gpu_handle_s {
@@ -68,6 +95,9 @@ struct elsi_gpu_handle_s {
     int overlap_factored = 0;
     int band_width = 64;
     int batch_workers = 8;
+    int precision = ELSI_GPU_PREC_FP64;
+    double refine_tol = 1e-10;
+    int max_refine = 4;
     void* ws = nullptr;
     size_t ws_bytes = 0;
     int ws_owned = 0;

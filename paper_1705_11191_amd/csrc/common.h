@@ -152,6 +152,21 @@ void dgemm(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha,
            const double* A, int lda, const double* B, int ldb, double beta,
            double* C, int ldc, int uplo = 0);
 
+// While an Fp32GemmScope(true) lives, the products that dgemm and dgemm_splitk
+// launch from this host thread round their FP64 operands to FP32 and multiply
+// and accumulate in FP32 on the matrix cores; inputs and outputs stay FP64.
+// (dgemm_tn_small is not affected.)
+class Fp32GemmScope {
+public:
+    explicit Fp32GemmScope(bool on);
+    ~Fp32GemmScope();
+    Fp32GemmScope(const Fp32GemmScope&) = delete;
+    Fp32GemmScope& operator=(const Fp32GemmScope&) = delete;
+
+private:
+    bool on_;
+};
+
 // As dgemm, split over K into partial products (summed in a fixed order) when
 // the output has too few tiles to fill the GPU; `work` holds the partials.
 void dgemm_splitk(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha,

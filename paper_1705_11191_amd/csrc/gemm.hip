@@ -1,4 +1,8 @@
 // FP64 matrix products on the CDNA4 matrix cores (v_mfma_f64_16x16x4f64).
+// Inside an Fp32GemmScope the same products run with FP32 arithmetic: the FP64
+// operands are rounded to FP32 as they are staged in LDS, multiplied and
+// accumulated by v_mfma_f32_16x16x4f32 (twice the FP64 rate), and the result
+// is widened back to FP64 (storage stays FP64 throughout).
 //
 // One workgroup of 256 threads (4 wave64s arranged 2 x 2) computes a BM x BN
 // tile of C; each wave owns a (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA
@@ -14,6 +18,7 @@
 
 #include <cstdio>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 namespace eg {
@@ -27,7 +32,7 @@ constexpr int kOpN = 0, kOpT = 1, kOpSymLower = 2;
 
 // blockIdx.y selects a K range of length kper when the product is split over
 // K: that slice's partial product goes to C + blockIdx.y * cstride.
-template <int BM, int BN, int AM, bool TB>
+template <int BM, int BN, int AM, bool TB, bool F32>
 __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, double alpha,
                                                     const double* __restrict__ A, int lda,
                                                     const double* __restrict__ B, int ldb,
@@ -35,6 +40,8 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
                                                     int tiles_m, int ntiles, int tiles_per_xcd, int kper,
                                                     size_t cstride)
 {
+    using LT = typename std::conditional<F32, float, double>::type;   // LDS and MFMA operand type
+    using AccT = typename std::conditional<F32, float4_t, double4_t>::type;
     constexpr bool TA = (AM == kOpT);
     int kofs = 0;   // first global column of A in this K range (symmetric mode)
     {
@@ -49,8 +56,8 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int A_PER = BM * kBK / 256;   // elements of the A slice per thread
     constexpr int B_PER = BN * kBK / 256;
-    __shared__ double As[kBK][BM + 1];
-    __shared__ double Bs[kBK][BN + 1];
+    __shared__ LT As[kBK][BM + 1];
+    __shared__ LT Bs[kBK][BN + 1];
 
     const int bid = blockIdx.x;
     const int tile = (bid % 8) * tiles_per_xcd + bid / 8;
@@ -78,11 +85,11 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
 
-    double4_t acc[FM][FN];
+    AccT acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < FN; ++j) acc[i][j] = (AccT){0, 0, 0, 0};
 
     double ra[A_PER], rb[B_PER];
     // symmetric mode: slices left of the tile's rows read A (coalesced down
@@ -139,14 +146,14 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
     auto store_slice = [&]() {
         if (AM == kOpSymLower && at) {
 #pragma unroll
-            for (int r = 0; r < A_PER; ++r) As[tid % kBK][tid / kBK + r * (256 / kBK)] = ra[r];
+            for (int r = 0; r < A_PER; ++r) As[tid % kBK][tid / kBK + r * (256 / kBK)] = (LT)ra[r];
         } else {
 #pragma unroll
             for (int r = 0; r < A_PER; ++r) {
                 int i, kk;
                 if (!TA) { i = tid % BM; kk = tid / BM + r * (256 / BM); }
                 else     { kk = tid % kBK; i = tid / kBK + r * (256 / kBK); }
-                As[kk][i] = ra[r];
+                As[kk][i] = (LT)ra[r];
             }
         }
 #pragma unroll
@@ -154,7 +161,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
             int j, kk;
             if (TB) { j = tid % BN; kk = tid / BN + r * (256 / BN); }
             else    { kk = tid % kBK; j = tid / kBK + r * (256 / kBK); }
-            Bs[kk][j] = rb[r];
+            Bs[kk][j] = (LT)rb[r];
         }
     };
 
@@ -167,7 +174,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 4) {
             const int kr = kk + (lane >> 4);
-            double a[FM], b[FN];
+            LT a[FM], b[FN];
 #pragma unroll
             for (int i = 0; i < FM; ++i) a[i] = As[kr][wm * WM + i * 16 + (lane & 15)];
 #pragma unroll
@@ -177,17 +184,23 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < FN; ++j) {
+                    if constexpr (F32)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[i], acc[i][j], 0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+                }
         }
         __syncthreads();
     }
 
-    // D layout of the 16x16 f64 MFMA: lane l, element r holds D(4r + l/16, l%16);
-    // D is the transposed block, so that is C(row l%16, column 4r + l/16).
+    // D layout of the 16x16 f64 MFMA: lane l, element r holds D(4r + l/16, l%16),
+    // and of the f32 one D(4 (l/16) + r, l%16); D is the transposed block, so
+    // that is C(row l%16, column 4r + l/16), resp. column 4 (l/16) + r.
     // The C loads of one 16-row block are all issued before its stores so that they overlap.
     const int rbase = row0 + wm * WM + (lane & 15);
-    const int cbase = col0 + wn * WN + (lane >> 4);
+    const int cbase = col0 + wn * WN + (F32 ? 4 * (lane >> 4) : (lane >> 4));
+    constexpr int RSTEP = F32 ? 1 : 4;   // column step between a lane's result elements
     const bool interior = (row0 + BM <= m) && (col0 + BN <= n) && !(uplo && col0 + BN - 1 > row0);
     auto valid = [&](int gr, int gc) {
         return interior || (gr < m && gc < n && !(uplo && gr < gc));
@@ -200,15 +213,15 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * 4;
+                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * RSTEP;
                     cv[j][r] = valid(gr, gc) ? C[cm(gr, gc, ldc)] : 0.0;
                 }
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * 4;
-                    if (valid(gr, gc)) C[cm(gr, gc, ldc)] = alpha * acc[i][j][r] + beta * cv[j][r];
+                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * RSTEP;
+                    if (valid(gr, gc)) C[cm(gr, gc, ldc)] = alpha * (double)acc[i][j][r] + beta * cv[j][r];
                 }
         }
     } else {
@@ -218,8 +231,8 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * 4;
-                    if (valid(gr, gc)) C[cm(gr, gc, ldc)] = alpha * acc[i][j][r];
+                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * RSTEP;
+                    if (valid(gr, gc)) C[cm(gr, gc, ldc)] = alpha * (double)acc[i][j][r];
                 }
     }
 }
@@ -241,6 +254,8 @@ double product_flops(int m, int n, int k, int uplo)
     return 2.0 * entries * k;
 }
 
+thread_local int g_fp32_depth = 0;   // > 0 inside an Fp32GemmScope on this host thread
+
 template <int BM, int BN, int AM, bool TB>
 void launch_gemm(hipStream_t st, int m, int n, int k, double alpha, const double* A, int lda,
                  const double* B, int ldb, double beta, double* C, int ldc, int uplo, int nsplit,
@@ -256,8 +271,13 @@ void launch_gemm(hipStream_t st, int m, int n, int k, double alpha, const double
     }
     int per = (ntiles + 7) / 8;
     dim3 grid(per * 8, nsplit), block(256);
+    if (g_fp32_depth > 0) {
+        hipLaunchKernelGGL((dgemm_kernel<BM, BN, AM, TB, true>), grid, block, 0, st, m, n, k, alpha, A, lda, B, ldb,
+                           beta, C, ldc, uplo, tiles_m, ntiles, per, kper, cstride);
+        return;
+    }
     const int slot = launch_probe::begin(st);
-    hipLaunchKernelGGL((dgemm_kernel<BM, BN, AM, TB>), grid, block, 0, st, m, n, k, alpha, A, lda,
+    hipLaunchKernelGGL((dgemm_kernel<BM, BN, AM, TB, false>), grid, block, 0, st, m, n, k, alpha, A, lda,
                        B, ldb, beta, C, ldc, uplo, tiles_m, ntiles, per, kper, cstride);
     if (slot >= 0)
         launch_probe::end(st, slot, shape_index(BM, BN) * 6 + AM * 2 + (TB ? 1 : 0),
@@ -506,6 +526,16 @@ bool dominant(int* launches, double* ms, double* flops, const char** name)
     return true;
 }
 }  // namespace launch_probe
+
+Fp32GemmScope::Fp32GemmScope(bool on) : on_(on)
+{
+    if (on_) ++g_fp32_depth;
+}
+
+Fp32GemmScope::~Fp32GemmScope()
+{
+    if (on_) --g_fp32_depth;
+}
 
 void dgemm(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha, const double* A,
            int lda, const double* B, int ldb, double beta, double* C, int ldc, int uplo)

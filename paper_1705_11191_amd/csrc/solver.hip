@@ -42,10 +42,11 @@ void density_matrix(hipStream_t st, int n, int k, const double* C, int ldc, cons
 // ---------------------------------------------------------------------------
 struct Layout {
     size_t linv, bd, vall, tall, v2, tau2, tq2, d, e, w, z, z2, u, sywork, dcwork, q1work, f, scal, ints;
+    size_t hcopy;   // mixed precision: the band reduction's copy of H~ (H keeps H~ for the refinement)
     size_t total;
 };
 
-static Layout make_layout(int n, int b, int ncol)
+static Layout make_layout(int n, int b, int ncol, bool mixed = false)
 {
     Layout L{};
     size_t off = 0;
@@ -70,6 +71,7 @@ static Layout make_layout(int n, int b, int ncol)
     L.f = put(sizeof(double) * n);
     L.scal = put(sizeof(double) * 16);
     L.ints = put(sizeof(int) * ((size_t)n + 64));
+    L.hcopy = mixed ? put(sizeof(double) * nn) : 0;
     L.total = off;
     return L;
 }
@@ -103,7 +105,7 @@ size_t workspace_bytes(const elsi_gpu_handle_s* h)
         const size_t base = make_layout(2 * h->n, h->band_width, 2 * h->n).total;
         return make_clayout(base, h->n).total;
     }
-    return make_layout(h->n, h->band_width, h->n).total;
+    return make_layout(h->n, h->band_width, h->n, h->precision == ELSI_GPU_PREC_MIXED).total;
 }
 
 void release_workspace(elsi_gpu_handle_s* h)
@@ -216,7 +218,16 @@ static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, cons
     double* Bd = (double*)(ws + L.bd);
     double* Vall = (double*)(ws + L.vall);
     double* Tall = (double*)(ws + L.tall);
-    sy2sb(st, n, b, H, n, Vall, Tall, Bd, 2 * b, (double*)(ws + L.sywork));
+    const bool mixed = h->precision == ELSI_GPU_PREC_MIXED;
+    double* A = H;
+    if (mixed) {   // the refinement needs H~ after step (1) has consumed its copy
+        A = (double*)(ws + L.hcopy);
+        copy_matrix(st, n, n, H, n, A, n);
+    }
+    {
+        Fp32GemmScope fp32(mixed);
+        sy2sb(st, n, b, A, n, Vall, Tall, Bd, 2 * b, (double*)(ws + L.sywork));
+    }
     tm.mark(ELSI_GPU_ST_BAND);
     double* d = (double*)(ws + L.d);
     double* e = (double*)(ws + L.e);
@@ -231,6 +242,19 @@ static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, cons
     return 0;
 }
 
+// X (n x k, in Z) <- L^-T X.
+static void back_substitute(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L, Timer& tm, int k)
+{
+    hipStream_t st = h->stream;
+    const int n = h->n;
+    if (!h->overlap_is_unit) {
+        double* Linv = (double*)(ws + L.linv);
+        dtrtri_diag_blocks(st, n, S, n, Linv);
+        dtrsm_left_lower_t(st, n, k, S, n, Linv, (double*)(ws + L.z), n);
+    }
+    tm.mark(ELSI_GPU_ST_BACKSUB);
+}
+
 // X (n x k, in Z) <- L^-T Q1 Q2 X: steps (4), (5) and the back substitution.
 static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L, Timer& tm, int k, DcState* dc,
                       bool backsub = true)
@@ -243,15 +267,43 @@ static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L
     apply_q2(st, n, b, k, (double*)(ws + L.v2), (double*)(ws + L.tau2), sb2st_kmax(n, b), X, n,
              (double*)(ws + L.tq2));
     tm.mark(ELSI_GPU_ST_BACK_Q2);
-    apply_q1(st, n, b, k, (double*)(ws + L.vall), (double*)(ws + L.tall), X, n, (double*)(ws + L.q1work));
-    tm.mark(ELSI_GPU_ST_BACK_Q1);
-    if (!backsub) return;
-    if (!h->overlap_is_unit) {
-        double* Linv = (double*)(ws + L.linv);
-        dtrtri_diag_blocks(st, n, S, n, Linv);
-        dtrsm_left_lower_t(st, n, k, S, n, Linv, X, n);
+    {
+        Fp32GemmScope fp32(h->precision == ELSI_GPU_PREC_MIXED);
+        apply_q1(st, n, b, k, (double*)(ws + L.vall), (double*)(ws + L.tall), X, n, (double*)(ws + L.q1work));
     }
-    tm.mark(ELSI_GPU_ST_BACKSUB);
+    tm.mark(ELSI_GPU_ST_BACK_Q1);
+    if (backsub) back_substitute(h, S, ws, L, tm, k);
+}
+
+// Mixed precision: FP64 refinement of the k' columns in Z against H~ (held in
+// H); on return Z holds the refined vectors and w[0 .. k') their Ritz values.
+// kw leading states decide convergence.  Returns 0, kStatusRefine (outputs
+// usable, tolerance not reached) or an error.
+static int refine_states(elsi_gpu_handle_s* h, const double* Ht, char* ws, const Layout& L, Timer& tm, int kp,
+                         int kw)
+{
+    hipStream_t st = h->stream;
+    const int n = h->n, b = std::min(h->band_width, std::max(1, n - 1));
+    double* const bufs[3] = {(double*)(ws + L.z), (double*)(ws + L.z2), (double*)(ws + L.u)};
+    // free after the back-transformations: the reflector stores (k' x k'
+    // products), the diagonal-block inverses (rebuilt for the back
+    // substitution), d and e, and the band reduction's scratch
+    RefineOutcome out{};
+    int rc = refine_subspace(st, n, kp, kw, Ht, n, bufs, n, (double*)(ws + L.vall), (double*)(ws + L.v2),
+                             (double*)(ws + L.linv), (int*)(ws + L.ints) + 8, (double*)(ws + L.sywork),
+                             sy2sb_workspace_doubles(n, b), (double*)(ws + L.d), (double*)(ws + L.e),
+                             h->refine_tol, h->max_refine, &out);
+    if (rc && rc != kStatusRefine) return rc;
+    if (out.sweeps > 0) {
+        if (out.x_buf != 0) copy_matrix(st, n, kp, bufs[out.x_buf], n, bufs[0], n);
+        if (hipMemcpyAsync(ws + L.w, ws + L.d, sizeof(double) * kp, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return kStatusHip;
+    }
+    h->info.refine_sweeps = out.sweeps;
+    h->info.refine_states = kp;
+    h->info.refine_resid = out.rmax;
+    tm.mark(ELSI_GPU_ST_REFINE);
+    return (rc == kStatusRefine || !out.converged) ? kStatusRefine : 0;
 }
 
 // Fold the launch timings of the finished call into the info record.
@@ -294,23 +346,37 @@ static int ev_real(elsi_gpu_handle_s* h, double* H, double* S, double* eval, dou
     if (rc) return rc < 0 ? -1 : rc;
     hipStream_t st = h->stream;
     const int n = h->n, k = h->n_state;
+    const bool mixed = h->precision == ELSI_GPU_PREC_MIXED;
     char* ws = (char*)h->ws;
-    const Layout L = make_layout(n, h->band_width, n);
+    const Layout L = make_layout(n, h->band_width, n, mixed);
     std::memset(h->info.stage_ms, 0, sizeof(h->info.stage_ms));
     h->info.fail_col = 0;
     h->info.band_width = std::min(h->band_width, std::max(1, n - 1));
+    h->info.refine_sweeps = 0;
+    h->info.refine_states = 0;
+    h->info.refine_resid = 0.0;
     Timer tm(st);
     DcState dc;
     rc = front_half(h, H, S, ws, L, tm, &dc);
     if (rc) { tm.finish(&h->info); return rc; }
-    back_half(h, S, ws, L, tm, k, &dc);
+    int rstat = 0;
+    if (mixed) {
+        const int kp = refine_columns(n, k);
+        back_half(h, S, ws, L, tm, kp, &dc, false);
+        rstat = refine_states(h, H, ws, L, tm, kp, k);
+        if (rstat && rstat != kStatusRefine) { tm.finish(&h->info); return rstat; }
+        back_substitute(h, S, ws, L, tm, k);
+    } else {
+        back_half(h, S, ws, L, tm, k, &dc);
+    }
     copy_matrix(st, n, k, (double*)(ws + L.z), n, evec, n);
     (void)hipMemcpyAsync(eval, ws + L.w, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
     rc = sync_status(st);
     if (rc) return rc;
     tm.finish(&h->info);
     harvest_launch_probe(h);
-    return read_flags(st, ws, L);
+    rc = read_flags(st, ws, L);
+    return rc ? rc : rstat;
 }
 
 static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, double* D, double* eval,
@@ -326,11 +392,15 @@ static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, doub
     if (rc) return rc < 0 ? -1 : rc;
     hipStream_t st = h->stream;
     const int n = h->n;
+    const bool mixed = h->precision == ELSI_GPU_PREC_MIXED;
     char* ws = (char*)h->ws;
-    const Layout L = make_layout(n, h->band_width, n);
+    const Layout L = make_layout(n, h->band_width, n, mixed);
     std::memset(h->info.stage_ms, 0, sizeof(h->info.stage_ms));
     h->info.fail_col = 0;
     h->info.band_width = std::min(h->band_width, std::max(1, n - 1));
+    h->info.refine_sweeps = 0;
+    h->info.refine_states = 0;
+    h->info.refine_resid = 0.0;
     Timer tm(st);
     DcState dc;
     rc = front_half(h, H, S, ws, L, tm, &dc);
@@ -341,20 +411,35 @@ static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, doub
     int status = 0;
     int ks = 0;
     double hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (h->occ_scheme == ELSI_GPU_OCC_FERMI) {
-        fermi_occupations(st, n, w, h->n_electron, h->kT, h->spin, h->occ_accuracy, h->mu_max_steps, kFCut, f, scal);
+    auto occupy = [&]() -> int {
+        if (h->occ_scheme == ELSI_GPU_OCC_FERMI)
+            fermi_occupations(st, n, w, h->n_electron, h->kT, h->spin, h->occ_accuracy, h->mu_max_steps, kFCut, f,
+                              scal);
+        else
+            explicit_occupations(st, n, h->n_state, w, f, kFCut, scal);
         if (hipMemcpyAsync(hs, scal, 6 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return kStatusHip;
         if (hipStreamSynchronize(st) != hipSuccess) return kStatusHip;
-        status = (int)hs[1];
+        status = (h->occ_scheme == ELSI_GPU_OCC_FERMI) ? (int)hs[1] : 0;
         ks = (int)hs[2];
-    } else {
-        explicit_occupations(st, n, h->n_state, w, f, kFCut, scal);
-        if (hipMemcpyAsync(hs, scal, 6 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return kStatusHip;
-        if (hipStreamSynchronize(st) != hipSuccess) return kStatusHip;
-        ks = (int)hs[2];
-    }
+        return 0;
+    };
+    if ((rc = occupy())) return rc;
     tm.mark(ELSI_GPU_ST_OCC);
-    back_half(h, S, ws, L, tm, ks, &dc);
+    int rstat = 0;
+    if (mixed) {
+        // refine k_s states plus guards, then take the occupations again from
+        // the refined eigenvalues
+        const int kp = refine_columns(n, ks);
+        back_half(h, S, ws, L, tm, kp, &dc, false);
+        rstat = refine_states(h, H, ws, L, tm, kp, ks);
+        if (rstat && rstat != kStatusRefine) { tm.finish(&h->info); return rstat; }
+        if ((rc = occupy())) return rc;
+        ks = std::min(ks, kp);
+        tm.mark(ELSI_GPU_ST_OCC);
+        back_substitute(h, S, ws, L, tm, ks);
+    } else {
+        back_half(h, S, ws, L, tm, ks, &dc);
+    }
     density_matrix(st, n, ks, (double*)(ws + L.z), n, f, (double*)(ws + L.z2), D, n);
     tm.mark(ELSI_GPU_ST_DENSITY);
     if (eval) (void)hipMemcpyAsync(eval, w, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
@@ -371,7 +456,7 @@ static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, doub
     h->info.charge_residual = hs[5];
     rc = read_flags(st, ws, L);
     if (rc) return rc;
-    return status;
+    return status ? status : rstat;
 }
 
 

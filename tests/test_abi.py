@@ -49,9 +49,46 @@ def test_strerror_and_argument_checks_without_gpu():
     lib.elsi_gpu_set_band_width.argtypes = [ctypes.c_void_p, ctypes.c_int]
     assert lib.elsi_gpu_set_band_width(h, 12) == -2
     assert lib.elsi_gpu_set_band_width(h, 32) == 0
+    lib.elsi_gpu_set_precision.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+    assert lib.elsi_gpu_set_precision(None, 1, 1e-10, 4) == -1
+    assert lib.elsi_gpu_set_precision(h, 2, 1e-10, 4) == -2
+    assert lib.elsi_gpu_set_precision(h, 1, -1.0, 4) == -3
+    assert lib.elsi_gpu_set_precision(h, 1, float("nan"), 4) == -3
+    assert lib.elsi_gpu_set_precision(h, 1, 1e-10, -1) == -4
+    assert lib.elsi_gpu_set_precision(h, 1, 1e-10, 0) == 0
+    assert lib.elsi_gpu_set_precision(h, 0, 1e-10, 4) == 0
+    # the mixed mode needs n^2 more doubles of workspace than the FP64 mode
+    lib.elsi_gpu_workspace_size.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]
+    ws64, wsmx = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.elsi_gpu_workspace_size(h, ctypes.byref(ws64)) == 0
+    assert lib.elsi_gpu_set_precision(h, 1, 1e-10, 4) == 0
+    assert lib.elsi_gpu_workspace_size(h, ctypes.byref(wsmx)) == 0
+    assert wsmx.value >= ws64.value + 10 * 10 * 8
     lib.elsi_gpu_finalize.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
     assert lib.elsi_gpu_finalize(ctypes.byref(h)) == 0
     assert h.value is None
+    # complex handles have no mixed mode
+    assert lib.elsi_gpu_init(ctypes.byref(h), 1, 10, 10, 5.0, None) == 0
+    assert lib.elsi_gpu_set_precision(h, 1, 1e-10, 4) == -2
+    assert lib.elsi_gpu_set_precision(h, 0, 1e-10, 4) == 0
+    assert lib.elsi_gpu_finalize(ctypes.byref(h)) == 0
+    # refinement stage entry: argument checks return before any device work
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.elsi_gpu_x_refine.argtypes = [i, i, i, vp, i, vp, i, vp, vp, d, i, ctypes.POINTER(i), vp]
+    fake = ctypes.c_void_p(16)
+    sw = ctypes.c_int(7)
+    assert lib.elsi_gpu_x_refine(-1, 0, 0, fake, 1, fake, 1, fake, fake, 1e-10, 4, None, None) == -1
+    assert lib.elsi_gpu_x_refine(4, 5, 0, fake, 4, fake, 4, fake, fake, 1e-10, 4, None, None) == -2
+    assert lib.elsi_gpu_x_refine(4, 2, 3, fake, 4, fake, 4, fake, fake, 1e-10, 4, None, None) == -3
+    assert lib.elsi_gpu_x_refine(4, 2, 2, None, 4, fake, 4, fake, fake, 1e-10, 4, None, None) == -4
+    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 3, fake, 4, fake, fake, 1e-10, 4, None, None) == -4
+    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 4, fake, 3, fake, fake, 1e-10, 4, None, None) == -6
+    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 4, fake, 4, None, fake, 1e-10, 4, None, None) == -8
+    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 4, fake, 4, fake, None, 1e-10, 4, None, None) == -9
+    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 4, fake, 4, fake, fake, -1.0, 4, None, None) == -10
+    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 4, fake, 4, fake, fake, 1e-10, -1, None, None) == -11
+    assert lib.elsi_gpu_x_refine(0, 0, 0, None, 1, None, 1, None, None, 1e-10, 4, ctypes.byref(sw), None) == 0
+    assert sw.value == 0
 
 
 def test_product_path_does_not_import_oracle():

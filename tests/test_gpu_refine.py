@@ -1,0 +1,200 @@
+"""Mixed precision: the FP64 refinement stage against the oracle, and the
+mixed ev / dm paths (FP32 matrix-core products in full -> band and Q1, then
+refinement) against the FP64 oracle.
+
+Refinement parity tolerances: both sides orthonormalize and project in FP64,
+so Ritz values agree to a few rounding errors of ||H~||: 32 n eps ||H~||_2.
+Residual norms are differences of nearly equal vectors; they agree to that
+absolute level plus a relative 1e-6.  Ritz vectors with a relative gap above
+1e-6 to their neighbours agree up to sign to 1e-8.
+
+Mixed-path contract: the refined eigenvalues meet the FP64 eigenvalue gate,
+and whenever the library reports convergence (status 0) the density matrix
+meets its 1e-9 gate too; otherwise it returns status 3 with the residual
+bound it reached in the info record.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from gates import eig_excess
+from synth import generator as G
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), device="cuda", dtype=torch.float64)
+
+
+def _dev_f(a):
+    from paper_1705_11191_amd import binding as B
+
+    a = np.asarray(a, dtype=np.float64)
+    t = B.fortran_empty(a.shape[0], a.shape[1])
+    t.copy_(torch.tensor(a, device="cuda"))
+    return t
+
+
+def _standard_form(sp):
+    L = O.potrf(sp.S)
+    return O.reduce_standard(sp.H, L)
+
+
+def _refine_both(Ht, X0, kw, tol, max_sweeps):
+    from paper_1705_11191_amd import binding as B
+
+    Xd = _dev_f(X0)
+    theta, resid, sweeps, st = B.refine(_dev(Ht), Xd, kw, tol=tol, max_sweeps=max_sweeps)
+    Xo, th_o, r_o, sw_o, st_o = O.refine(Ht, X0, kw, tol=tol, max_sweeps=max_sweeps)
+    return (Xd.cpu().numpy(), theta.cpu().numpy(), resid.cpu().numpy(), sweeps, st), (Xo, th_o, r_o, sw_o, st_o)
+
+
+@pytest.mark.parametrize("n,k,delta", [(300, 90, 1e-6), (700, 200, 1e-5), (700, 129, 0.0)])
+def test_refine_vs_oracle(n, k, delta):
+    sp = G.make_lattice_system(n, seed=100 + n)
+    Ht = _standard_form(sp)
+    w, V = np.linalg.eigh(Ht)
+    rng = np.random.default_rng(n + k)
+    X0 = V[:, :k] + delta * rng.standard_normal((n, k))
+    kw = k - 32
+    print(f"[refine parity] n={n} k={k} delta={delta}", flush=True)
+    (X, th, r, sw, st), (Xo, th_o, r_o, sw_o, st_o) = _refine_both(Ht, X0, kw, 1e-10, 4)
+    nrm = np.abs(w).max()
+    tol = 32 * n * EPS * nrm
+    assert st == st_o and sw == sw_o
+    assert np.abs(th - th_o).max() <= tol
+    assert np.all(np.abs(r - r_o) <= tol + 1e-6 * r_o)
+    assert np.abs(X.T @ X - np.eye(k)).max() <= 64 * n * EPS
+    gap = np.minimum(np.abs(np.diff(th_o, prepend=-np.inf)), np.abs(np.diff(th_o, append=np.inf)))
+    sep = gap > 1e-6 * nrm
+    dots = np.abs(np.sum(X * Xo, axis=0))
+    assert np.all(np.abs(dots[sep] - 1.0) <= 1e-8)
+
+
+def test_refine_closed_form_chain():
+    from paper_1705_11191_amd import binding as B
+
+    n, k = 300, 40
+    Ht = G.tight_binding_chain(n, 0.25, -1.0)
+    j = np.arange(1, n + 1)
+    lam = np.sort(0.25 - 2.0 * np.cos(j * np.pi / (n + 1)))
+    w, V = np.linalg.eigh(Ht)
+    rng = np.random.default_rng(7)
+    X0 = V[:, :k] @ (rng.standard_normal((k, k)) + 4 * np.eye(k))
+    Xd = _dev_f(X0)
+    theta, resid, sweeps, st = B.refine(_dev(Ht), Xd, k, tol=1e-11, max_sweeps=4)
+    assert st == 0 and sweeps == 1
+    assert np.abs(theta.cpu().numpy() - lam[:k]).max() <= 1e-13
+    assert resid.cpu().numpy().max() <= 1e-12
+
+
+def test_refine_no_sweeps_and_dependent_columns():
+    from paper_1705_11191_amd import binding as B
+
+    n, k = 128, 8
+    Ht = G.tight_binding_chain(n, 0.0, 1.0)
+    rng = np.random.default_rng(8)
+    X0 = rng.standard_normal((n, k))
+    Xd = _dev_f(X0)
+    theta, resid, sweeps, st = B.refine(_dev(Ht), Xd, k, tol=1e-10, max_sweeps=0)
+    assert st == 3 and sweeps == 0
+    assert np.array_equal(Xd.cpu().numpy(), X0)
+    X0[:, 3] = 0.0
+    Xd = _dev_f(X0)
+    theta, resid, sweeps, st = B.refine(_dev(Ht), Xd, k, tol=1e-10, max_sweeps=2)
+    assert st == 3 and sweeps == 0
+
+
+def _mixed_dm(sp, tol=1e-10, max_refine=4):
+    from paper_1705_11191_amd import binding as B
+
+    h = B.Handle(sp.n, sp.n, sp.n_occ)
+    h.set_precision(B.PREC_MIXED, tol, max_refine)
+    D, ev, f, energy, mu, st = h.dm(_dev(sp.H), _dev(sp.S), ok=(0, 3))
+    info = h.info()
+    h.close()
+    return D.cpu().numpy(), ev.cpu().numpy(), f.cpu().numpy(), energy, mu, st, info
+
+
+def _ritz_bounds(ev, ref_eval, resid):
+    """Each refined value is a Ritz value of H~: an exact eigenvalue lies within
+    its residual norm (resid bounds them all), and it is not below the exact
+    eigenvalue of the same index (interlacing)."""
+    dist = np.abs(ev[:, None] - ref_eval[None, :]).min(axis=1)
+    assert np.all(dist <= resid * (1 + 1e-6) + 1e-9)
+    assert np.all(ev >= ref_eval[: ev.size] - 1e-8)
+
+
+@pytest.mark.parametrize("which", ["config0", "lattice700", "lattice700_kappa1e2"])
+def test_mixed_dm_vs_oracle(which):
+    if which == "config0":
+        sp = G.make_config(0)
+    elif which == "lattice700":
+        sp = G.make_lattice_system(700, seed=800)
+    else:
+        sp = G.make_lattice_system(700, seed=800, kappa=1e2)
+    print(f"[mixed dm] {which} n={sp.n}", flush=True)
+    ref = O.dm(sp.H, sp.S, sp.n_occ, sp.kT)
+    D, ev, f, energy, mu, st, info = _mixed_dm(sp)
+    assert st in (0, 3)
+    ks = info["k_s"]
+    kp = info["refine_states"]
+    assert info["refine_sweeps"] >= 1 and ks <= kp <= sp.n
+    _ritz_bounds(ev[:ks], ref["eval"], info["refine_resid"])
+    assert np.abs(D - D.T).max() == 0.0
+    derr = np.abs(D - ref["D"]).max()
+    eerr = np.abs(ev[:ks] - ref["eval"][:ks]).max()
+    print(f"[mixed dm] {which}: status {st} sweeps {info['refine_sweeps']} resid {info['refine_resid']:.2e} "
+          f"eig err {eerr:.2e} D err {derr:.2e} mu err {abs(mu - ref['mu']):.2e}", flush=True)
+    if st == 0:
+        # converged: the FP64 gates hold
+        assert info["refine_resid"] <= 1e-10
+        assert eig_excess(ev[:ks], ref["eval"][:ks], sp.S) <= 1.0
+        assert derr <= 1e-9
+    else:
+        assert info["refine_resid"] > 1e-10
+
+
+def test_mixed_ev_config0():
+    from paper_1705_11191_amd import binding as B
+
+    sp = G.make_config(0)
+    k = 200
+    ev_ref, C_ref, _ = O.gevp(sp.H, sp.S)
+    h = B.Handle(sp.n, k, sp.n_occ)
+    h.set_precision(B.PREC_MIXED, 1e-10, 4)
+    ev, C = h.ev(_dev(sp.H), _dev(sp.S), ok=(0, 3))
+    st = h.last_status
+    info = h.info()
+    h.close()
+    ev = ev.cpu().numpy()
+    C = C.cpu().numpy()
+    print(f"[mixed ev] status {st} sweeps {info['refine_sweeps']} resid {info['refine_resid']:.2e}", flush=True)
+    assert info["refine_states"] == min(sp.n, k + max(64, (k + 9) // 10))
+    _ritz_bounds(ev[:k], ev_ref, info["refine_resid"])
+    # the refined vectors are S-orthonormal (CholeskyQR twice in FP64, then L^-T)
+    assert np.abs(C.T @ sp.S @ C - np.eye(k)).max() <= 1e-8
+    assert (st == 0) == (info["refine_resid"] <= 1e-10)
+    if st == 0:
+        assert eig_excess(ev[:k], ev_ref[:k], sp.S) <= 1.0
+
+
+def test_precision_switch_back_to_fp64_is_exact_path():
+    """Switching a handle back to FP64 gives the FP64 result bit for bit."""
+    from paper_1705_11191_amd import binding as B
+
+    sp = G.make_config(0)
+    h = B.Handle(sp.n, sp.n, sp.n_occ)
+    D0, *_ = h.dm(_dev(sp.H), _dev(sp.S))
+    h.set_precision(B.PREC_MIXED, 1e-10, 4)
+    h.dm(_dev(sp.H), _dev(sp.S), ok=(0, 3))
+    h.set_precision(B.PREC_FP64, 1e-10, 4)
+    D1, *_ = h.dm(_dev(sp.H), _dev(sp.S))
+    info = h.info()
+    h.close()
+    assert torch.equal(D0, D1)
+    assert info["refine_sweeps"] == 0 and info["stage_ms"]["refine"] == 0.0
