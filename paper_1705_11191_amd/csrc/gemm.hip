@@ -12,8 +12,8 @@
 // workgroups share a CU (one's barriers and LDS stores hide behind the
 // other's matrix-core work); the epilogue reads C one 16-row block at a time
 // for the same reason.  Workgroups are renumbered so that each of the
-// eight XCDs walks a contiguous range of tiles (its L2 then holds the shared
-// operand panels).
+// eight XCDs walks a contiguous range of tiles, in groups of eight tile rows
+// (its L2 then holds the shared operand panels).
 #include "common.h"
 
 #include <cstdio>
@@ -64,8 +64,15 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
     if (tile >= ntiles) return;
     int tm, tn;
     if (!uplo) {
-        tm = tile % tiles_m;
-        tn = tile / tiles_m;
+        // groups of eight tile rows walked column by column: the 64 tiles an
+        // XCD runs at once form an 8 x 8 block of C and share its A and B panels
+        const int tiles_n = ntiles / tiles_m;
+        const int grp = tile / (8 * tiles_n);
+        const int fm = grp * 8;
+        const int gm = min(tiles_m - fm, 8);
+        const int rem = tile - grp * 8 * tiles_n;
+        tm = fm + rem % gm;
+        tn = rem / gm;
     } else {
         // only the tiles that touch the lower triangle are enumerated (column
         // by column), so every XCD gets the same share of the work
@@ -96,6 +103,8 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
     // columns), slices right of them read the mirrored entries A^T (coalesced
     // along K), and the slices that cross the diagonal select per element
     bool at = TA;   // thread mapping of the slice held in ra
+    // interior tiles load full slices without per-element bounds tests
+    const bool fullmn = (row0 + BM <= m) && (col0 + BN <= n);
 
     auto load_slice = [&](int k0) {
         if (AM == kOpSymLower) {
@@ -120,6 +129,15 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
                     ra[r] = v;
                 }
             }
+        } else if (fullmn && k0 + kBK <= k) {
+#pragma unroll
+            for (int r = 0; r < A_PER; ++r) {
+                int i, kk;
+                if (!TA) { i = tid % BM; kk = tid / BM + r * (256 / BM); }
+                else     { kk = tid % kBK; i = tid / kBK + r * (256 / kBK); }
+                const int gi = row0 + i, gk = k0 + kk;
+                ra[r] = TA ? A[cm(gk, gi, lda)] : A[cm(gi, gk, lda)];
+            }
         } else {
 #pragma unroll
             for (int r = 0; r < A_PER; ++r) {
@@ -132,15 +150,26 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
                 ra[r] = v;
             }
         }
+        if (fullmn && k0 + kBK <= k) {
 #pragma unroll
-        for (int r = 0; r < B_PER; ++r) {
-            int j, kk;
-            if (TB) { j = tid % BN; kk = tid / BN + r * (256 / BN); }
-            else    { kk = tid % kBK; j = tid / kBK + r * (256 / kBK); }
-            int gj = col0 + j, gk = k0 + kk;
-            double v = 0.0;
-            if (gj < n && gk < k) v = TB ? B[cm(gj, gk, ldb)] : B[cm(gk, gj, ldb)];
-            rb[r] = v;
+            for (int r = 0; r < B_PER; ++r) {
+                int j, kk;
+                if (TB) { j = tid % BN; kk = tid / BN + r * (256 / BN); }
+                else    { kk = tid % kBK; j = tid / kBK + r * (256 / kBK); }
+                const int gj = col0 + j, gk = k0 + kk;
+                rb[r] = TB ? B[cm(gj, gk, ldb)] : B[cm(gk, gj, ldb)];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < B_PER; ++r) {
+                int j, kk;
+                if (TB) { j = tid % BN; kk = tid / BN + r * (256 / BN); }
+                else    { kk = tid % kBK; j = tid / kBK + r * (256 / kBK); }
+                int gj = col0 + j, gk = k0 + kk;
+                double v = 0.0;
+                if (gj < n && gk < k) v = TB ? B[cm(gj, gk, ldb)] : B[cm(gk, gj, ldb)];
+                rb[r] = v;
+            }
         }
     };
     auto store_slice = [&]() {
@@ -426,30 +455,30 @@ State& state()
     return s;
 }
 const char* kNames[kIds] = {
-    "dgemm_kernel<128,128,0,false>",
-    "dgemm_kernel<128,128,0,true>",
-    "dgemm_kernel<128,128,1,false>",
-    "dgemm_kernel<128,128,1,true>",
-    "dgemm_kernel<128,128,2,false>",
-    "dgemm_kernel<128,128,2,true>",
-    "dgemm_kernel<128,64,0,false>",
-    "dgemm_kernel<128,64,0,true>",
-    "dgemm_kernel<128,64,1,false>",
-    "dgemm_kernel<128,64,1,true>",
-    "dgemm_kernel<128,64,2,false>",
-    "dgemm_kernel<128,64,2,true>",
-    "dgemm_kernel<64,64,0,false>",
-    "dgemm_kernel<64,64,0,true>",
-    "dgemm_kernel<64,64,1,false>",
-    "dgemm_kernel<64,64,1,true>",
-    "dgemm_kernel<64,64,2,false>",
-    "dgemm_kernel<64,64,2,true>",
-    "dgemm_kernel<64,128,0,false>",
-    "dgemm_kernel<64,128,0,true>",
-    "dgemm_kernel<64,128,1,false>",
-    "dgemm_kernel<64,128,1,true>",
-    "dgemm_kernel<64,128,2,false>",
-    "dgemm_kernel<64,128,2,true>",
+    "dgemm_kernel<128,128,0,false,false>",
+    "dgemm_kernel<128,128,0,true,false>",
+    "dgemm_kernel<128,128,1,false,false>",
+    "dgemm_kernel<128,128,1,true,false>",
+    "dgemm_kernel<128,128,2,false,false>",
+    "dgemm_kernel<128,128,2,true,false>",
+    "dgemm_kernel<128,64,0,false,false>",
+    "dgemm_kernel<128,64,0,true,false>",
+    "dgemm_kernel<128,64,1,false,false>",
+    "dgemm_kernel<128,64,1,true,false>",
+    "dgemm_kernel<128,64,2,false,false>",
+    "dgemm_kernel<128,64,2,true,false>",
+    "dgemm_kernel<64,64,0,false,false>",
+    "dgemm_kernel<64,64,0,true,false>",
+    "dgemm_kernel<64,64,1,false,false>",
+    "dgemm_kernel<64,64,1,true,false>",
+    "dgemm_kernel<64,64,2,false,false>",
+    "dgemm_kernel<64,64,2,true,false>",
+    "dgemm_kernel<64,128,0,false,false>",
+    "dgemm_kernel<64,128,0,true,false>",
+    "dgemm_kernel<64,128,1,false,false>",
+    "dgemm_kernel<64,128,1,true,false>",
+    "dgemm_kernel<64,128,2,false,false>",
+    "dgemm_kernel<64,128,2,true,false>",
 };
 }  // namespace
 
