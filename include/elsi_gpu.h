@@ -286,6 +286,16 @@ int elsi_gpu_x_dgemm(char ta, char tb, int m, int n, int k, double alpha, const 
                      int lda, const double *B, int ldb, double beta, double *C, int ldc,
                      void *hip_stream);
 
+/* The FP32-arithmetic products of the mixed mode (elsi_gpu_set_precision):
+ * as elsi_gpu_x_dgemm with FP64 operands and result, but A and B are rounded
+ * to FP32 and multiplied and accumulated in FP32 on the matrix cores; alpha
+ * and beta are applied in FP64.  uplo = 1 writes only the entries C(i, j)
+ * with i >= j (C square; the strict upper part is left untouched), uplo = 0
+ * all of C.  Errors as elsi_gpu_x_dgemm, and -14 uplo not 0 or 1. */
+int elsi_gpu_x_gemm_fp32(char ta, char tb, int m, int n, int k, double alpha, const double *A,
+                         int lda, const double *B, int ldb, double beta, double *C, int ldc,
+                         int uplo, void *hip_stream);
+
 /* S <- L with S = L L^T, Eq. (10) (lower; strict upper set to zero).
  * *fail_col (host, may be NULL) receives the 1-based first bad pivot. */
 int elsi_gpu_x_cholesky(int n, double *S, int lds, int *fail_col, void *hip_stream);

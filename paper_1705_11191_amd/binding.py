@@ -91,6 +91,7 @@ def lib():
         L.elsi_gpu_get_info.argtypes = [vp, ctypes.POINTER(Info)]
         L.elsi_gpu_finalize.argtypes = [ctypes.POINTER(vp)]
         L.elsi_gpu_x_dgemm.argtypes = [c, c, i, i, i, d, vp, i, vp, i, d, vp, i, vp]
+        L.elsi_gpu_x_gemm_fp32.argtypes = [c, c, i, i, i, d, vp, i, vp, i, d, vp, i, i, vp]
         L.elsi_gpu_x_cholesky.argtypes = [i, vp, i, ctypes.POINTER(i), vp]
         L.elsi_gpu_x_reduce.argtypes = [i, vp, i, vp, i, vp]
         L.elsi_gpu_x_backsub.argtypes = [i, i, vp, i, vp, i, vp]
@@ -152,6 +153,26 @@ def dgemm(ta: str, tb: str, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | 
     _check(rc, "elsi_gpu_x_dgemm")
     if C2.data_ptr() != C.data_ptr():
         C.copy_(C2)
+    return C
+
+
+def gemm_fp32(ta: str, tb: str, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
+              alpha: float = 1.0, beta: float = 0.0, uplo: int = 0) -> torch.Tensor:
+    """As dgemm, with the operands rounded to FP32 and FP32 matrix-core arithmetic
+    (the products of the mixed mode); uplo = 1 writes only the lower triangle."""
+    A, B = as_fortran(A), as_fortran(B)
+    m = A.shape[1] if ta == "T" else A.shape[0]
+    k = A.shape[0] if ta == "T" else A.shape[1]
+    n = B.shape[0] if tb == "T" else B.shape[1]
+    if C is None:
+        C = fortran_empty(m, n, device=A.device)
+        C.zero_()
+        beta = 0.0
+    if not C.t().is_contiguous():
+        raise ValueError("C must be column-major (see fortran_empty)")
+    rc = lib().elsi_gpu_x_gemm_fp32(ta.encode(), tb.encode(), m, n, k, alpha, _ptr(A), max(1, A.shape[0]),
+                                    _ptr(B), max(1, B.shape[0]), beta, _ptr(C), max(1, m), int(uplo), _stream())
+    _check(rc, "elsi_gpu_x_gemm_fp32")
     return C
 
 

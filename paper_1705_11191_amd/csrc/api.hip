@@ -172,6 +172,27 @@ int elsi_gpu_x_dgemm(char ta, char tb, int m, int n, int k, double alpha, const 
     return sync_status(st);
 }
 
+int elsi_gpu_x_gemm_fp32(char ta, char tb, int m, int n, int k, double alpha, const double* A, int lda,
+                         const double* B, int ldb, double beta, double* C, int ldc, int uplo, void* hip_stream)
+{
+    if (ta != 'N' && ta != 'T' && ta != 'S') return -1;
+    if (tb != 'N' && tb != 'T') return -2;
+    if (ta == 'S' && tb != 'N') return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0 || (ta == 'S' && k != m)) return -5;
+    if (uplo != 0 && uplo != 1) return -14;
+    if (m == 0 || n == 0) return 0;
+    if (!C) return -12;
+    if (k > 0 && (!A || !B)) return !A ? -7 : -9;
+    hipStream_t st = (hipStream_t)hip_stream;
+    {
+        Fp32GemmScope fp32(true);
+        dgemm(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo);
+    }
+    return sync_status(st);
+}
+
 int elsi_gpu_x_cholesky(int n, double* S, int lds, int* fail_col, void* hip_stream)
 {
     if (n < 0) return -1;

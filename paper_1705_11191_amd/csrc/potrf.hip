@@ -2,9 +2,10 @@
 // triangular solves that use L (Eq. (11) and the back substitution c = L^-T c~).
 //
 // Blocking: 64 x 64 diagonal blocks are factored (and inverted) by one
-// workgroup entirely in LDS; inside a 512-wide outer panel the 64-column
-// steps update only the panel, and the trailing matrix receives one K = 512
-// update per outer panel on the matrix cores.  Triangular solves multiply by
+// workgroup entirely in LDS; inside a 1024-wide outer panel the 64-column
+// steps update only the panel, and the trailing matrix receives one K = 1024
+// update per outer panel on the matrix cores (1024 beats 512 and 2048: the
+// products run faster at larger K while the K = 64 work inside the panel grows).  Triangular solves multiply by
 // the inverted 64 x 64 diagonal blocks and update with the same two-level
 // scheme.
 #include "common.h"
@@ -13,7 +14,7 @@ namespace eg {
 namespace {
 
 constexpr int NB = 64;     // diagonal block
-constexpr int NBO = 512;   // outer panel
+constexpr int NBO = 1024;   // outer panel
 
 // Factor the jb x jb diagonal block at (j0, j0) in LDS and write L and L^-1.
 __global__ __launch_bounds__(256) void potf2_inv_kernel(int jb, int j0, double* A, int lda,
