@@ -109,24 +109,41 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
     auto load_slice = [&](int k0) {
         if (AM == kOpSymLower) {
             const int c0 = kofs + k0;
+            const bool full = fullmn && k0 + kBK <= k;
             if (c0 >= row0 + BM) {
                 at = true;
+                if (full) {
 #pragma unroll
-                for (int r = 0; r < A_PER; ++r) {
-                    const int kk = tid % kBK, i = tid / kBK + r * (256 / kBK);
-                    const int gi = row0 + i, gk = k0 + kk;
-                    ra[r] = (gi < m && gk < k) ? A[cm(kofs + gk, gi, lda)] : 0.0;
+                    for (int r = 0; r < A_PER; ++r) {
+                        const int kk = tid % kBK, i = tid / kBK + r * (256 / kBK);
+                        ra[r] = A[cm(kofs + k0 + kk, row0 + i, lda)];
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < A_PER; ++r) {
+                        const int kk = tid % kBK, i = tid / kBK + r * (256 / kBK);
+                        const int gi = row0 + i, gk = k0 + kk;
+                        ra[r] = (gi < m && gk < k) ? A[cm(kofs + gk, gi, lda)] : 0.0;
+                    }
                 }
             } else {
                 at = false;
                 const bool cross = c0 + kBK > row0;
+                if (full && !cross) {
 #pragma unroll
-                for (int r = 0; r < A_PER; ++r) {
-                    const int i = tid % BM, kk = tid / BM + r * (256 / BM);
-                    const int gi = row0 + i, gk = k0 + kk, gc = kofs + gk;
-                    double v = 0.0;
-                    if (gi < m && gk < k) v = (!cross || gc <= gi) ? A[cm(gi, gc, lda)] : A[cm(gc, gi, lda)];
-                    ra[r] = v;
+                    for (int r = 0; r < A_PER; ++r) {
+                        const int i = tid % BM, kk = tid / BM + r * (256 / BM);
+                        ra[r] = A[cm(row0 + i, kofs + k0 + kk, lda)];
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < A_PER; ++r) {
+                        const int i = tid % BM, kk = tid / BM + r * (256 / BM);
+                        const int gi = row0 + i, gk = k0 + kk, gc = kofs + gk;
+                        double v = 0.0;
+                        if (gi < m && gk < k) v = (!cross || gc <= gi) ? A[cm(gi, gc, lda)] : A[cm(gc, gi, lda)];
+                        ra[r] = v;
+                    }
                 }
             }
         } else if (fullmn && k0 + kBK <= k) {
