@@ -73,6 +73,37 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
         const int rem = tile - grp * 8 * tiles_n;
         tm = fm + rem % gm;
         tn = rem / gm;
+    } else if (BM == BN) {
+        // only the tiles on or below the diagonal (tm >= tn) are enumerated, so
+        // every XCD gets the same share of the work; tile columns are taken in
+        // groups of eight, each group row by row (first the rows that cross the
+        // diagonal, r + 1 tiles in its r-th row, then the full rows), so that
+        // an XCD's concurrent tiles share their A and B panels
+        const int tiles_n = (n + BN - 1) / BN;
+        int rem = tile;
+        tm = 0;
+        tn = 0;
+        for (int c0 = 0; c0 < tiles_n; c0 += 8) {
+            const int w = min(8, tiles_n - c0);
+            const int tri_rows = min(w, max(0, tiles_m - c0));
+            const int tri = tri_rows * (tri_rows + 1) / 2;
+            const int cnt = tri + max(0, tiles_m - c0 - w) * w;
+            if (rem < cnt) {
+                if (rem < tri) {
+                    int r = (int)((sqrt(8.0 * rem + 1.0) - 1.0) * 0.5);
+                    while ((r + 1) * (r + 2) / 2 <= rem) ++r;
+                    while (r * (r + 1) / 2 > rem) --r;
+                    tm = c0 + r;
+                    tn = c0 + rem - r * (r + 1) / 2;
+                } else {
+                    const int q = rem - tri;
+                    tm = c0 + w + q / w;
+                    tn = c0 + q % w;
+                }
+                break;
+            }
+            rem -= cnt;
+        }
     } else {
         // only the tiles that touch the lower triangle are enumerated (column
         // by column), so every XCD gets the same share of the work
