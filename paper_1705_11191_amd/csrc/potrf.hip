@@ -16,13 +16,33 @@ namespace {
 constexpr int NB = 64;     // diagonal block
 constexpr int NBO = 1024;   // outer panel
 
-// Factor the jb x jb diagonal block at (j0, j0) in LDS and write L and L^-1.
+__device__ inline double lane_value(double v, int l)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+
+// Orders one wave's LDS accesses across its lanes (no workgroup barrier needed).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Factor the jb x jb diagonal block at (j0, j0) and write L and L^-1.  The
+// factorization is done by one wave with lane r holding row r in registers
+// (column c: the pivot is read from lane c, the new column is broadcast
+// through LDS); the inverse by the whole workgroup in LDS.
 __global__ __launch_bounds__(256) void potf2_inv_kernel(int jb, int j0, double* A, int lda,
                                                         double* Linv, int* info)
 {
     __shared__ double L[NB][NB + 1];
     __shared__ double X[NB][NB + 1];
     __shared__ double Y[NB][NB + 1];
+    __shared__ double col[NB];
     __shared__ int bad;
     const int tid = threadIdx.x;
     if (tid == 0) bad = (*info != 0);
@@ -32,29 +52,38 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(int jb, int j0, double* 
     }
     __syncthreads();
     if (bad) return;
-    for (int c = 0; c < jb; ++c) {
-        double s = L[c][c];
-        __syncthreads();
-        if (!(s > 0.0) || !isfinite(s)) {
-            if (tid == 0) { atomicCAS(info, 0, j0 + c + 1); bad = 1; }
-            __syncthreads();
-            break;
+    if (tid < 64) {
+        // rows and columns beyond jb are padded with the identity, so all 64
+        // steps run unconditionally (the loop unrolls and g stays in registers);
+        // after a non-positive pivot the remaining steps only produce values
+        // that are discarded
+        const int lane = tid;
+        double g[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) g[q] = (lane >= jb && q == lane) ? 1.0 : L[lane][q];
+        int fail = 0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const double s = lane_value(g[c], c);
+            if (!fail && (!(s > 0.0) || !isfinite(s))) fail = c + 1;
+            const double d = sqrt(s);
+            const double l = (lane == c) ? d : g[c] / d;   // rows below c: L(r, c)
+            if (lane >= c) g[c] = l;
+            col[lane] = (lane > c) ? l : 0.0;
+            wave_lds_sync();
+#pragma unroll
+            for (int q = c + 1; q < NB; ++q) g[q] -= l * col[q];   // only q <= r is kept
+            wave_lds_sync();
         }
-        double d = sqrt(s);
-        if (tid == 0) L[c][c] = d;
-        for (int i = c + 1 + tid; i < jb; i += 256) L[i][c] /= d;
-        __syncthreads();
-        // trailing update: thread (i, r) = (tid % 64, tid / 64) takes row i and
-        // every fourth column from c + 1 + r
-        {
-            const int i = tid & 63, r = tid >> 6;
-            if (i > c && i < jb) {
-                const double lic = L[i][c];
-                for (int c2 = c + 1 + r; c2 <= i; c2 += 4) L[i][c2] -= lic * L[c2][c];
-            }
+        if (!fail) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) L[lane][q] = (q <= lane && lane < jb) ? g[q] : 0.0;
+        } else if (lane == 0) {
+            atomicCAS(info, 0, j0 + fail);
+            bad = 1;
         }
-        __syncthreads();
     }
+    __syncthreads();
     if (bad) return;
     tri_inverse_lower64<256>(jb, L, X, Y);
     for (int e = tid; e < NB * NB; e += 256) {
