@@ -58,7 +58,7 @@ __device__ void q2_load_v(int n, int b, int g, int k, const double* __restrict__
 }
 
 // T of P = H_{s_lo} H_{s_lo+1} ... H_{s_hi} = I - V T V^T for every (g, k)
-// (forward accumulation from G = V^T V and the tau's).
+// (from G = V^T V and the tau's, by block doubling).
 __global__ __launch_bounds__(256) void q2_build_t_kernel(int n, int b, const double* __restrict__ V2,
                                                          const double* __restrict__ tau2, int kmax, double* Tq)
 {
@@ -84,16 +84,32 @@ __global__ __launch_bounds__(256) void q2_build_t_kernel(int n, int b, const dou
             for (int r = 0; r < 2 * NB2; ++r) acc += Vs[r][i] * Vs[r][j];
         }
         Gs[i][j] = acc;
-        Ts[i][j] = 0.0;
+        Ts[i][j] = (i == j) ? tau[i] : 0.0;   // tau is zero beyond the block's reflectors
     }
     __syncthreads();
-    for (int c = 0; c < b; ++c) {
-        if (tid < c) {
-            double acc = 0.0;
-            for (int j = tid; j < c; ++j) acc += Ts[tid][j] * Gs[j][c];
-            Ts[tid][c] = -tau[c] * acc;
+    // T by doubling: for adjacent reflector blocks A, B (A first),
+    // T_AB = -T_AA G_AB T_BB; blocks of 1, 2, 4, ... 32, each level two
+    // parallel small products.  Y reuses the V area (V is no longer needed).
+    double(*Ys)[NB2 + 1] = Vs;
+    for (int sz = 1; sz < NB2; sz *= 2) {
+        const int nout = (NB2 / (2 * sz)) * sz * sz;
+        for (int e = tid; e < nout; e += 256) {
+            const int pr = e / (sz * sz), rem = e % (sz * sz);
+            const int a = rem % sz, bb = rem / sz;
+            const int p0 = pr * 2 * sz, pb = p0 + sz;
+            double y = 0.0;
+            for (int jj = 0; jj <= bb; ++jj) y += Gs[p0 + a][pb + jj] * Ts[pb + jj][pb + bb];
+            Ys[p0 + a][pb + bb] = y;
         }
-        if (tid == c) Ts[c][c] = tau[c];
+        __syncthreads();
+        for (int e = tid; e < nout; e += 256) {
+            const int pr = e / (sz * sz), rem = e % (sz * sz);
+            const int a = rem % sz, bb = rem / sz;
+            const int p0 = pr * 2 * sz, pb = p0 + sz;
+            double t = 0.0;
+            for (int ii = a; ii < sz; ++ii) t += Ts[p0 + a][p0 + ii] * Ys[p0 + ii][pb + bb];
+            Ts[p0 + a][pb + bb] = -t;
+        }
         __syncthreads();
     }
     double* T = Tq + ((size_t)g * kmax + k) * NB2 * NB2;
