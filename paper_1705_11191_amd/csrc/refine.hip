@@ -67,6 +67,16 @@ int refine_subspace(hipStream_t st, int n, int k, int kw, const double* Ht, int 
     int xi = 0;
     double prev = -1.0;
     std::vector<double> hr((size_t)k);
+    // the k x k eigensolver of the Rayleigh-Ritz step (S = I), kept for all sweeps
+    struct SubSolver {
+        elsi_gpu_handle h = nullptr;
+        ~SubSolver() { if (h) elsi_gpu_finalize(&h); }
+    } sub;
+    if (max_sweeps > 0) {
+        int rc = elsi_gpu_init(&sub.h, ELSI_GPU_REAL64, k, k, 0.0, st);
+        if (!rc) rc = elsi_gpu_set_overlap_is_unit(sub.h, 1);
+        if (rc) return rc > 0 ? rc : kStatusHip;
+    }
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         double* X = bufs[xi];
         double* W = bufs[(xi + 1) % 3];
@@ -87,12 +97,7 @@ int refine_subspace(hipStream_t st, int n, int k, int kw, const double* Ht, int 
         dgemm_splitk(st, 'T', 'N', k, k, n, 1.0, X, ldb, W, ldb, 0.0, G, k, part, npart);
         symmetrize_average(st, k, G, k);
         {
-            elsi_gpu_handle sub = nullptr;
-            int rc = elsi_gpu_init(&sub, ELSI_GPU_REAL64, k, k, 0.0, st);
-            if (rc) return rc > 0 ? rc : kStatusHip;
-            rc = elsi_gpu_set_overlap_is_unit(sub, 1);
-            if (!rc) rc = elsi_gpu_ev(sub, G, nullptr, theta, Qm);
-            elsi_gpu_finalize(&sub);
+            const int rc = elsi_gpu_ev(sub.h, G, nullptr, theta, Qm);
             if (rc) return rc > 0 ? rc : kStatusHip;
         }
         dgemm(st, 'N', 'N', n, k, k, 1.0, X, ldb, Qm, k, 0.0, X2, ldb);   // refined vectors
