@@ -234,27 +234,39 @@ __global__ __launch_bounds__(256) void dc_prep_kernel(const MergeDesc* __restric
     const double rho = fabs(rho0) * zz;
     for (int q = tid; q < ns; q += blockDim.x) zf[q] = (znorm > 0.0) ? zf[q] / znorm : 0.0;
     __syncthreads();
+    // weights and poles gathered into ascending pole order (the sort-key area
+    // of this merge is free until the final ordering), so that the sequential
+    // scan below reads memory in order
+    double* zsort = ma.skey + 2 * o;
+    double* dsort = zsort + ns;
+    for (int t = tid; t < ns; t += blockDim.x) {
+        const int q = perm[t];
+        zsort[t] = zf[q];
+        dsort[t] = df[q];
+    }
+    __syncthreads();
     if (tid != 0) return;
-    // sequential deflation scan over the ascending poles
+    // sequential deflation scan over the ascending poles; the pending
+    // candidate's weight and pole are carried in registers
     const double tol = 8.0 * kEps * fmax(dmax, rho);
     int K = 0, ndf = 0, nrot = 0;
     int pcand = -1;   // local row of the pending non-deflated candidate
+    double zp = 0.0, dp = 0.0;
     double zs2 = 0.0;
     for (int t = 0; t < ns; ++t) {
         const int q = perm[t];
-        double zq = zf[q];
+        const double zq = zsort[t];
+        const double dq = dsort[t];
         if (rho * fabs(zq) <= tol) {
-            ma.dfv[o + ndf] = df[q];
+            ma.dfv[o + ndf] = dq;
             ma.dfrow[o + ndf] = q;
             ma.rowpos[o + q] = -1 - ndf;
             ++ndf;
             continue;
         }
         if (pcand >= 0) {
-            double zp = zf[pcand];
-            double r = sqrt(zp * zp + zq * zq);
-            double c = zq / r, s = zp / r;
-            double dp = df[pcand], dq = df[q];
+            const double r = sqrt(zp * zp + zq * zq);
+            const double c = zq / r, s = zp / r;
             if (fabs(c * s * (dp - dq)) <= tol) {
                 // rotate the weight of pcand onto q and deflate pcand
                 ma.rot_p[o + nrot] = pcand;
@@ -262,33 +274,39 @@ __global__ __launch_bounds__(256) void dc_prep_kernel(const MergeDesc* __restric
                 ma.rot_c[o + nrot] = c;
                 ma.rot_s[o + nrot] = s;
                 ++nrot;
+                const double dpn = c * c * dp + s * s * dq;
+                const double dqn = s * s * dp + c * c * dq;
                 zf[q] = r;
                 zf[pcand] = 0.0;
-                df[pcand] = c * c * dp + s * s * dq;
-                df[q] = s * s * dp + c * c * dq;
-                ma.dfv[o + ndf] = df[pcand];
+                df[pcand] = dpn;
+                df[q] = dqn;
+                ma.dfv[o + ndf] = dpn;
                 ma.dfrow[o + ndf] = pcand;
                 ma.rowpos[o + pcand] = -1 - ndf;
                 ++ndf;
                 pcand = q;
+                zp = r;
+                dp = dqn;
                 continue;
             }
             // pcand is final
-            ma.ds[o + K] = df[pcand];
-            ma.zs[o + K] = zf[pcand];
+            ma.ds[o + K] = dp;
+            ma.zs[o + K] = zp;
             ma.ndrow[o + K] = pcand;
             ma.rowpos[o + pcand] = K;
-            zs2 += zf[pcand] * zf[pcand];
+            zs2 += zp * zp;
             ++K;
         }
         pcand = q;
+        zp = zq;
+        dp = dq;
     }
     if (pcand >= 0) {
-        ma.ds[o + K] = df[pcand];
-        ma.zs[o + K] = zf[pcand];
+        ma.ds[o + K] = dp;
+        ma.zs[o + K] = zp;
         ma.ndrow[o + K] = pcand;
         ma.rowpos[o + pcand] = K;
-        zs2 += zf[pcand] * zf[pcand];
+        zs2 += zp * zp;
         ++K;
     }
     ma.K[mi] = K;
