@@ -343,8 +343,10 @@ int elsi_gpu_x_tridiag_eig(int n, const double *d, const double *e, double *w, d
  * (max resid <= tol); *sweeps (host, may be NULL) receives the sweeps run.
  * Returns ELSI_GPU_ERR_REFINE when tol was not reached (outputs written; with
  * max_sweeps = 0 nothing is written) or when the columns of X are
- * numerically dependent (X, theta and resid are then unspecified: the
- * orthonormalization works on X in place).  Errors: -1 n < 0, -2 k outside 0..n, -3 kw outside
+ * numerically dependent (the factorization is checked before X is touched:
+ * X then holds the vectors of the last completed sweep, theta and resid that
+ * sweep's values, and with no completed sweep X is unchanged).  Errors: -1
+ * n < 0, -2 k outside 0..n, -3 kw outside
  * 0..k, -4 Ht / ldh, -6 X / ldx, -8 theta, -9 resid, -10 tol, -11 max_sweeps. */
 int elsi_gpu_x_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int ldx,
                       double *theta, double *resid, double tol, int max_sweeps, int *sweeps,

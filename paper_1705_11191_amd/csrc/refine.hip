@@ -81,17 +81,20 @@ int refine_subspace(hipStream_t st, int n, int k, int kw, const double* Ht, int 
         double* X = bufs[xi];
         double* W = bufs[(xi + 1) % 3];
         double* X2 = bufs[(xi + 2) % 3];
-        // (1) two CholeskyQR passes
+        // (1) two CholeskyQR passes; each factorization is checked before X is
+        // touched, so that a failure leaves the vectors of the last completed
+        // sweep (or the starting ones) in bufs[out->x_buf]
         fill_i(st, dinfo, 1, 0);
         for (int pass = 0; pass < 2; ++pass) {
             dgemm_splitk(st, 'T', 'N', k, k, n, 1.0, X, ldb, X, ldb, 0.0, G, k, part, npart);
             dpotrf(st, k, G, k, Linv, dinfo);
+            int hinfo = 0;
+            if (hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+                return kStatusHip;
+            if (hipStreamSynchronize(st) != hipSuccess) return kStatusHip;
+            if (hinfo) return kStatusRefine;   // the columns of X are numerically dependent
             dtrsm_right_lower_t(st, n, k, G, k, Linv, X, ldb);
         }
-        int hinfo = 0;
-        if (hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return kStatusHip;
-        if (hipStreamSynchronize(st) != hipSuccess) return kStatusHip;
-        if (hinfo) return kStatusRefine;   // the columns of X are numerically dependent
         // (2) Rayleigh-Ritz
         dgemm(st, 'N', 'N', n, k, n, 1.0, Ht, ldh, X, ldb, 0.0, W, ldb);
         dgemm_splitk(st, 'T', 'N', k, k, n, 1.0, X, ldb, W, ldb, 0.0, G, k, part, npart);
@@ -166,10 +169,11 @@ extern "C" int elsi_gpu_x_refine(int n, int k, int kw, const double* Ht, int ldh
     RefineOutcome out{};
     int rc = refine_subspace(st, n, k, kw, Ht, ldh, bufs, n, G, Qm, Linv, dinfo.p, part.p, npart, theta, r, tol,
                              max_sweeps, &out);
-    if (rc) {
+    if (rc && rc != kStatusRefine) {
         (void)hipStreamSynchronize(st);
         return rc;
     }
+    const bool dependent = (rc == kStatusRefine);
     if (out.sweeps > 0) {
         copy_matrix(st, n, k, bufs[out.x_buf], n, X, ldx);
         (void)hipMemcpyAsync(resid, r, sizeof(double) * k, hipMemcpyDeviceToDevice, st);
@@ -177,5 +181,5 @@ extern "C" int elsi_gpu_x_refine(int n, int k, int kw, const double* Ht, int ldh
     if (sweeps) *sweeps = out.sweeps;
     rc = sync_status(st);
     if (rc) return rc;
-    return out.converged ? 0 : kStatusRefine;
+    return (out.converged && !dependent) ? 0 : kStatusRefine;
 }

@@ -257,3 +257,19 @@ def test_mixed_dm_other_modes(mode):
         S_gate = np.eye(n) if mode == "unit_overlap" else sp.S
         assert eig_excess(ev[:ks], ref["eval"][:ks], S_gate) <= 1.0
         assert np.abs(D - ref["D"]).max() <= 1e-9
+
+
+def test_refine_failure_keeps_last_vectors():
+    """A singular Gram matrix is detected before the vectors are touched: with
+    no completed sweep the caller's X comes back unchanged."""
+    from paper_1705_11191_amd import binding as B
+
+    n, k = 200, 12
+    Ht = G.tight_binding_chain(n, 0.0, 1.0)
+    rng = np.random.default_rng(9)
+    X0 = rng.standard_normal((n, k))
+    X0[:, 5] = 0.0
+    Xd = _dev_f(X0)
+    theta, resid, sweeps, st = B.refine(_dev(Ht), Xd, k, tol=1e-10, max_sweeps=3)
+    assert st == 3 and sweeps == 0
+    assert np.array_equal(Xd.cpu().numpy(), X0)
