@@ -537,9 +537,10 @@ void orc_residual_norms(int n, int k, const double *H, int ldh, const double *S,
 /*   Rayleigh-Ritz: A = X^T H~ X, A = Q diag(theta) Q^T (orc_gevp with S = I),*/
 /*   X <- X Q;                                                               */
 /*   residuals res_l = ||H~ x_l - theta_l x_l||_2, from the definition.      */
-/* The first kw states decide: stop with 0 when max res_l <= tol; stop with  */
-/* 3 when a sweep does not halve that maximum, after max_sweeps sweeps, or   */
-/* when G is not positive definite (dependent columns).                      */
+/* The first kw states decide: stop with 0 when max res_l <= tol; otherwise  */
+/* stop with 3 after that sweep (its Rayleigh-Ritz step leaves the subspace   */
+/* unchanged, so a further sweep cannot lower the residual), and with 3 when  */
+/* G is not positive definite (dependent columns) or max_sweeps is 0.         */
 /* ========================================================================= */
 int orc_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int ldx, double *theta,
                double *res, double tol, int max_sweeps, int *sweeps)
@@ -551,7 +552,6 @@ int orc_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int l
     double *I = (double *)malloc(sizeof(double) * (size_t)k * k);
     double *Q = (double *)malloc(sizeof(double) * (size_t)k * k);
     double *Y = (double *)malloc(sizeof(double) * (size_t)n * k);
-    double prev = -1.0;
     int status = 3;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         int bad = 0;
@@ -629,9 +629,8 @@ int orc_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int l
         if (sweeps) *sweeps = sweep + 1;
         double rmax = 0.0;
         for (int l = 0; l < kw; ++l) if (res[l] > rmax) rmax = res[l];
-        if (rmax <= tol) { status = 0; break; }
-        if (prev >= 0.0 && rmax > 0.5 * prev) break;
-        prev = rmax;
+        status = (rmax <= tol) ? 0 : 3;
+        break;
     }
     free(G); free(I); free(Q); free(Y);
     return status;

@@ -99,10 +99,13 @@ def test_stop_rules():
     # no sweeps: not converged, X untouched
     X, theta, res, sweeps, st = O.refine(Ht, X0, k, tol=1e-10, max_sweeps=0)
     assert st == 3 and sweeps == 0 and np.array_equal(X, X0)
-    # Rayleigh-Ritz does not change the subspace, so a second sweep cannot halve
-    # the residual: stop after two sweeps, not converged
+    # Rayleigh-Ritz does not change the subspace, so a second sweep could not
+    # lower the residual: stop after the first one, not converged
     X, theta, res, sweeps, st = O.refine(Ht, X0, k, tol=1e-14, max_sweeps=4)
-    assert st == 3 and sweeps == 2
+    assert st == 3 and sweeps == 1
+    # ... and a second call on its output reproduces the same Ritz values
+    X2, theta2, res2, sweeps2, st2 = O.refine(Ht, X, k, tol=1e-14, max_sweeps=4)
+    assert np.abs(theta2 - theta).max() <= 1e-14 and np.allclose(res2, res, rtol=1e-6, atol=1e-15)
     # a loose tolerance is met after one sweep
     X, theta, res, sweeps, st = O.refine(Ht, X0, k, tol=1e-2, max_sweeps=4)
     assert st == 0 and sweeps == 1
