@@ -169,10 +169,12 @@ int elsi_gpu_set_band_width(elsi_gpu_handle h, int b);
  * The library then carries k' = min(n, k + max(64, ceil(k / 10))) states
  * (k = n_state for ev, k_s for dm) and refines them in FP64 against
  * H~ = L^-1 H L^-T: per sweep CholeskyQR twice, Rayleigh-Ritz with the FP64
- * solver, residual norms r_l = ||H~ x_l - theta_l x_l||_2.  Sweeps stop at
- * max_l r_l <= refine_tol over the wanted states (status 0), when a sweep
- * does not halve that maximum, or after max_refine sweeps; the last two end
- * with ELSI_GPU_ERR_REFINE and all outputs written.  Eigenvalues above the
+ * solver, residual norms r_l = ||H~ x_l - theta_l x_l||_2.  A sweep that
+ * leaves max_l r_l over the wanted states at most refine_tol ends with status
+ * 0; one that does not ends the refinement with ELSI_GPU_ERR_REFINE and all
+ * outputs written (a Rayleigh-Ritz sweep does not change the subspace, so a
+ * second one could not help; max_refine = 0 skips the refinement and also
+ * ends with ELSI_GPU_ERR_REFINE).  Eigenvalues above the
  * k' refined ones are the FP32-step values.  Needs n^2 more doubles of
  * workspace.  Batched calls always run in FP64.
  * Errors: -1 h NULL, -2 prec unknown or a complex handle asks for MIXED,
@@ -340,7 +342,9 @@ int elsi_gpu_x_tridiag_eig(int n, const double *d, const double *e, double *w, d
  * approximation, overwritten by the refined vectors (orthonormal, Ritz
  * order); theta (k) and resid (k) device out: Ritz values ascending and
  * ||Ht x_l - theta_l x_l||_2.  The first kw states decide convergence
- * (max resid <= tol); *sweeps (host, may be NULL) receives the sweeps run.
+ * (max resid <= tol); a sweep that misses it ends the call (at most one
+ * sweep does work: Rayleigh-Ritz leaves the subspace unchanged); *sweeps
+ * (host, may be NULL) receives the sweeps run.
  * Returns ELSI_GPU_ERR_REFINE when tol was not reached (outputs written; with
  * max_sweeps = 0 nothing is written) or when the columns of X are
  * numerically dependent (the factorization is checked before X is touched:

@@ -8,9 +8,9 @@
 //       solver of this library (S = I), X <- X Q;
 //   (3) residuals r_l = || H~ x_l - theta_l x_l ||_2, which bound the error of
 //       theta_l (the pencil residual H c - theta S c equals L r for c = L^-T x).
-// Sweeps stop when the wanted states' largest residual is at most tol, when a
-// sweep fails to halve it (a Rayleigh-Ritz step does not change the subspace,
-// so repeating it cannot help), or after max_sweeps.
+// A sweep that leaves the wanted states' largest residual above tol ends the
+// refinement (not converged): its Rayleigh-Ritz step does not change the
+// subspace, so a further sweep could not lower the residual.
 #include "api_internal.h"
 
 #include <algorithm>
@@ -65,7 +65,6 @@ int refine_subspace(hipStream_t st, int n, int k, int kw, const double* Ht, int 
     }
     kw = std::min(std::max(kw, 0), k);
     int xi = 0;
-    double prev = -1.0;
     std::vector<double> hr((size_t)k);
     // the k x k eigensolver of the Rayleigh-Ritz step (S = I), kept for all sweeps
     struct SubSolver {
@@ -116,12 +115,8 @@ int refine_subspace(hipStream_t st, int n, int k, int kw, const double* Ht, int 
         double rmax = 0.0;
         for (int l = 0; l < kw; ++l) rmax = std::max(rmax, hr[l]);
         out->rmax = rmax;
-        if (rmax <= tol) {
-            out->converged = 1;
-            break;
-        }
-        if (prev >= 0.0 && rmax > 0.5 * prev) break;   // stagnated
-        prev = rmax;
+        out->converged = (rmax <= tol) ? 1 : 0;
+        break;
     }
     return 0;
 }
