@@ -85,6 +85,26 @@ def test_batched_worker_count_changes_no_bit():
     assert out[0][2] == out[1][2] and out[0][3] == out[1][3]
 
 
+def test_batched_calls_run_fp64_on_a_mixed_handle():
+    """The precision setting applies to the single-problem calls only: a handle
+    switched to the mixed mode returns the FP64 batched results bit for bit."""
+    from paper_1705_11191_amd import binding as B
+
+    sps = _systems(SIZES[:5], seed0=70)
+    out = []
+    for prec in (B.PREC_FP64, B.PREC_MIXED):
+        h = B.Handle(8, 8, 2)
+        h.set_batch_workers(2)
+        h.set_precision(prec, 1e-10, 4)
+        Ds, evals, energy, mu, status, rc = h.dm_batched([_dev(sp.H) for sp in sps], [_dev(sp.S) for sp in sps],
+                                                         [sp.n_occ for sp in sps])
+        h.close()
+        assert rc == 0 and status == [0] * len(sps)
+        out.append([D.cpu().numpy() for D in Ds])
+    for q in range(len(sps)):
+        assert np.array_equal(out[0][q], out[1][q]), q
+
+
 def test_ev_batched_union_of_block_diagonal():
     """blockdiag(H1, H2, H3) x = lambda blockdiag(S1, S2, S3) x has exactly the
     union of the three spectra."""
