@@ -344,7 +344,7 @@ def main():
                     help="run one plain copy kernel of known size first (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary of --kernel from two rocprofv3 --pmc runs and exit")
-    ap.add_argument("--kernel", default="dgemm_kernel<128,128,0,false,false>")
+    ap.add_argument("--kernel", default="dgemm_kernel<128,128,0,false,false,false>")
     ap.add_argument("--pmc-command", action="append", default=[])
     ap.add_argument("--workload", choices=["single", "batch", "complex"], default="single",
                     help="single: the N=32768 dm solve; batch: 256 uneven problems in one batched call")

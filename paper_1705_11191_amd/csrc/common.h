@@ -173,6 +173,11 @@ void dgemm_splitk(hipStream_t st, char ta, char tb, int m, int n, int k, double 
                   const double* A, int lda, const double* B, int ldb, double beta, double* C,
                   int ldc, double* work, size_t work_doubles);
 
+// C(:, cmap[j]) = alpha A B(:, j) + beta C(:, cmap[j]) for j < n (op = 'N' for
+// both; cmap on the device, a map into C's columns without repeats).
+void dgemm_colmap(hipStream_t st, int m, int n, int k, double alpha, const double* A, int lda, const double* B,
+                  int ldb, double beta, double* C, int ldc, const int* cmap);
+
 // Deterministic split-K product W = A^T B for tall A (k x m), B (k x n),
 // m, n <= 64: partial products over row chunks are summed in a fixed order.
 // `part` needs ceil(k / chunk) * m * n doubles.
@@ -243,9 +248,11 @@ struct DcState {
     double* Z = nullptr;      // where the eigenvectors end up
     double* Zin = nullptr;    // solved halves of the last merge
     double* Zout = nullptr;
-    double* U = nullptr;      // coefficient blocks of the last merge
+    double* U = nullptr;      // coefficient blocks of the last merge (root columns first)
     bool have_last = false;
     std::vector<MergeDescH> last;
+    const MergeDescH* last_dev = nullptr;   // the last merge's descriptor on the device
+    void* work = nullptr;                   // the solver's scratch (merge bookkeeping)
 };
 size_t stedc_workspace_bytes(int n);
 int stedc_values(hipStream_t st, int n, const double* d, const double* e, double* w, double* Z, double* Z2,

@@ -32,13 +32,13 @@ constexpr int kOpN = 0, kOpT = 1, kOpSymLower = 2;
 
 // blockIdx.y selects a K range of length kper when the product is split over
 // K: that slice's partial product goes to C + blockIdx.y * cstride.
-template <int BM, int BN, int AM, bool TB, bool F32>
+template <int BM, int BN, int AM, bool TB, bool F32, bool CMAP>
 __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, double alpha,
                                                     const double* __restrict__ A, int lda,
                                                     const double* __restrict__ B, int ldb,
                                                     double beta, double* C, int ldc, int uplo,
                                                     int tiles_m, int ntiles, int tiles_per_xcd, int kper,
-                                                    size_t cstride)
+                                                    size_t cstride, const int* __restrict__ cmap)
 {
     using LT = typename std::conditional<F32, float, double>::type;   // LDS and MFMA operand type
     using AccT = typename std::conditional<F32, float4_t, double4_t>::type;
@@ -275,6 +275,11 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
     // and of the f32 one D(4 (l/16) + r, l%16); D is the transposed block, so
     // that is C(row l%16, column 4r + l/16), resp. column 4 (l/16) + r.
     // The C loads of one 16-row block are all issued before its stores so that they overlap.
+    // cmap (optional): logical column gc of C is stored at column cmap[gc]
+    auto ccol = [&](int gc) {
+        if constexpr (CMAP) return cmap[gc];
+        else return gc;
+    };
     const int rbase = row0 + wm * WM + (lane & 15);
     const int cbase = col0 + wn * WN + (F32 ? 4 * (lane >> 4) : (lane >> 4));
     constexpr int RSTEP = F32 ? 1 : 4;   // column step between a lane's result elements
@@ -291,14 +296,14 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int gr = rbase + i * 16, gc = cbase + j * 16 + r * RSTEP;
-                    cv[j][r] = valid(gr, gc) ? C[cm(gr, gc, ldc)] : 0.0;
+                    cv[j][r] = valid(gr, gc) ? C[cm(gr, ccol(gc), ldc)] : 0.0;
                 }
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int gr = rbase + i * 16, gc = cbase + j * 16 + r * RSTEP;
-                    if (valid(gr, gc)) C[cm(gr, gc, ldc)] = alpha * (double)acc[i][j][r] + beta * cv[j][r];
+                    if (valid(gr, gc)) C[cm(gr, ccol(gc), ldc)] = alpha * (double)acc[i][j][r] + beta * cv[j][r];
                 }
         }
     } else {
@@ -309,7 +314,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int gr = rbase + i * 16, gc = cbase + j * 16 + r * RSTEP;
-                    if (valid(gr, gc)) C[cm(gr, gc, ldc)] = alpha * (double)acc[i][j][r];
+                    if (valid(gr, gc)) C[cm(gr, ccol(gc), ldc)] = alpha * (double)acc[i][j][r];
                 }
     }
 }
@@ -336,7 +341,7 @@ thread_local int g_fp32_depth = 0;   // > 0 inside an Fp32GemmScope on this host
 template <int BM, int BN, int AM, bool TB>
 void launch_gemm(hipStream_t st, int m, int n, int k, double alpha, const double* A, int lda,
                  const double* B, int ldb, double beta, double* C, int ldc, int uplo, int nsplit,
-                 int kper, size_t cstride)
+                 int kper, size_t cstride, const int* cmap)
 {
     int tiles_m = (m + BM - 1) / BM;
     int tiles_n = (n + BN - 1) / BN;
@@ -348,14 +353,20 @@ void launch_gemm(hipStream_t st, int m, int n, int k, double alpha, const double
     }
     int per = (ntiles + 7) / 8;
     dim3 grid(per * 8, nsplit), block(256);
+    if (cmap) {   // only the merge products of the tridiagonal solver remap C's columns
+        if constexpr (AM == kOpN && !TB)
+            hipLaunchKernelGGL((dgemm_kernel<BM, BN, AM, TB, false, true>), grid, block, 0, st, m, n, k, alpha, A,
+                               lda, B, ldb, beta, C, ldc, uplo, tiles_m, ntiles, per, kper, cstride, cmap);
+        return;
+    }
     if (g_fp32_depth > 0) {
-        hipLaunchKernelGGL((dgemm_kernel<BM, BN, AM, TB, true>), grid, block, 0, st, m, n, k, alpha, A, lda, B, ldb,
-                           beta, C, ldc, uplo, tiles_m, ntiles, per, kper, cstride);
+        hipLaunchKernelGGL((dgemm_kernel<BM, BN, AM, TB, true, false>), grid, block, 0, st, m, n, k, alpha, A, lda,
+                           B, ldb, beta, C, ldc, uplo, tiles_m, ntiles, per, kper, cstride, nullptr);
         return;
     }
     const int slot = launch_probe::begin(st);
-    hipLaunchKernelGGL((dgemm_kernel<BM, BN, AM, TB, false>), grid, block, 0, st, m, n, k, alpha, A, lda,
-                       B, ldb, beta, C, ldc, uplo, tiles_m, ntiles, per, kper, cstride);
+    hipLaunchKernelGGL((dgemm_kernel<BM, BN, AM, TB, false, false>), grid, block, 0, st, m, n, k, alpha, A, lda,
+                       B, ldb, beta, C, ldc, uplo, tiles_m, ntiles, per, kper, cstride, nullptr);
     if (slot >= 0)
         launch_probe::end(st, slot, shape_index(BM, BN) * 6 + AM * 2 + (TB ? 1 : 0),
                           product_flops(m, n, k, uplo));
@@ -364,7 +375,7 @@ void launch_gemm(hipStream_t st, int m, int n, int k, double alpha, const double
 template <int BM, int BN>
 void dispatch_t(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha,
                 const double* A, int lda, const double* B, int ldb, double beta, double* C,
-                int ldc, int uplo, int nsplit = 1, int kper = 0, size_t cstride = 0)
+                int ldc, int uplo, int nsplit = 1, int kper = 0, size_t cstride = 0, const int* cmap = nullptr)
 {
     if (nsplit <= 1) { nsplit = 1; kper = k; cstride = 0; }
     const bool TA = (ta == 'T' || ta == 't'), SY = (ta == 'S' || ta == 's'), TB = (tb == 'T' || tb == 't');
@@ -373,15 +384,15 @@ void dispatch_t(hipStream_t st, char ta, char tb, int m, int n, int k, double al
         return;
     }
     if (SY)
-        launch_gemm<BM, BN, kOpSymLower, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        launch_gemm<BM, BN, kOpSymLower, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride, cmap);
     else if (!TA && !TB)
-        launch_gemm<BM, BN, kOpN, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        launch_gemm<BM, BN, kOpN, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride, cmap);
     else if (!TA && TB)
-        launch_gemm<BM, BN, kOpN, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        launch_gemm<BM, BN, kOpN, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride, cmap);
     else if (TA && !TB)
-        launch_gemm<BM, BN, kOpT, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        launch_gemm<BM, BN, kOpT, false>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride, cmap);
     else
-        launch_gemm<BM, BN, kOpT, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        launch_gemm<BM, BN, kOpT, true>(st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride, cmap);
 }
 
 // C = alpha * sum_s P_s + beta * C, partials summed in split order.
@@ -409,18 +420,18 @@ void tile_shape(int m, int n, int& BM, int& BN)
 
 void dispatch_shape(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha, const double* A, int lda,
                     const double* B, int ldb, double beta, double* C, int ldc, int uplo, int nsplit, int kper,
-                    size_t cstride)
+                    size_t cstride, const int* cmap = nullptr)
 {
     int BM, BN;
     tile_shape(m, n, BM, BN);
     if (BM == 128 && BN == 64)
-        dispatch_t<128, 64>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        dispatch_t<128, 64>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride, cmap);
     else if (BM == 64 && BN == 64)
-        dispatch_t<64, 64>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        dispatch_t<64, 64>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride, cmap);
     else if (BM == 64)
-        dispatch_t<64, 128>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        dispatch_t<64, 128>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride, cmap);
     else
-        dispatch_t<128, 128>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride);
+        dispatch_t<128, 128>(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, nsplit, kper, cstride, cmap);
 }
 
 // ---------------------------------------------------------------------------
@@ -503,30 +514,30 @@ State& state()
     return s;
 }
 const char* kNames[kIds] = {
-    "dgemm_kernel<128,128,0,false,false>",
-    "dgemm_kernel<128,128,0,true,false>",
-    "dgemm_kernel<128,128,1,false,false>",
-    "dgemm_kernel<128,128,1,true,false>",
-    "dgemm_kernel<128,128,2,false,false>",
-    "dgemm_kernel<128,128,2,true,false>",
-    "dgemm_kernel<128,64,0,false,false>",
-    "dgemm_kernel<128,64,0,true,false>",
-    "dgemm_kernel<128,64,1,false,false>",
-    "dgemm_kernel<128,64,1,true,false>",
-    "dgemm_kernel<128,64,2,false,false>",
-    "dgemm_kernel<128,64,2,true,false>",
-    "dgemm_kernel<64,64,0,false,false>",
-    "dgemm_kernel<64,64,0,true,false>",
-    "dgemm_kernel<64,64,1,false,false>",
-    "dgemm_kernel<64,64,1,true,false>",
-    "dgemm_kernel<64,64,2,false,false>",
-    "dgemm_kernel<64,64,2,true,false>",
-    "dgemm_kernel<64,128,0,false,false>",
-    "dgemm_kernel<64,128,0,true,false>",
-    "dgemm_kernel<64,128,1,false,false>",
-    "dgemm_kernel<64,128,1,true,false>",
-    "dgemm_kernel<64,128,2,false,false>",
-    "dgemm_kernel<64,128,2,true,false>",
+    "dgemm_kernel<128,128,0,false,false,false>",
+    "dgemm_kernel<128,128,0,true,false,false>",
+    "dgemm_kernel<128,128,1,false,false,false>",
+    "dgemm_kernel<128,128,1,true,false,false>",
+    "dgemm_kernel<128,128,2,false,false,false>",
+    "dgemm_kernel<128,128,2,true,false,false>",
+    "dgemm_kernel<128,64,0,false,false,false>",
+    "dgemm_kernel<128,64,0,true,false,false>",
+    "dgemm_kernel<128,64,1,false,false,false>",
+    "dgemm_kernel<128,64,1,true,false,false>",
+    "dgemm_kernel<128,64,2,false,false,false>",
+    "dgemm_kernel<128,64,2,true,false,false>",
+    "dgemm_kernel<64,64,0,false,false,false>",
+    "dgemm_kernel<64,64,0,true,false,false>",
+    "dgemm_kernel<64,64,1,false,false,false>",
+    "dgemm_kernel<64,64,1,true,false,false>",
+    "dgemm_kernel<64,64,2,false,false,false>",
+    "dgemm_kernel<64,64,2,true,false,false>",
+    "dgemm_kernel<64,128,0,false,false,false>",
+    "dgemm_kernel<64,128,0,true,false,false>",
+    "dgemm_kernel<64,128,1,false,false,false>",
+    "dgemm_kernel<64,128,1,true,false,false>",
+    "dgemm_kernel<64,128,2,false,false,false>",
+    "dgemm_kernel<64,128,2,true,false,false>",
 };
 }  // namespace
 
@@ -619,6 +630,13 @@ void dgemm(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha, 
 {
     if (m <= 0 || n <= 0) return;
     dispatch_shape(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, uplo, 1, k, 0);
+}
+
+void dgemm_colmap(hipStream_t st, int m, int n, int k, double alpha, const double* A, int lda, const double* B,
+                  int ldb, double beta, double* C, int ldc, const int* cmap)
+{
+    if (m <= 0 || n <= 0) return;
+    dispatch_shape(st, 'N', 'N', m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 0, 1, k, 0, cmap);
 }
 
 void dgemm_splitk(hipStream_t st, char ta, char tb, int m, int n, int k, double alpha, const double* A,

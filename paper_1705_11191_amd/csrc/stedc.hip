@@ -483,7 +483,9 @@ __global__ __launch_bounds__(1024) void dc_order_kernel(const MergeDesc* __restr
     }
 }
 
-// One output column of U (ns x ns at (o, o), ld ldu) per workgroup.
+// One column of U (ns x ns at (o, o), ld ldu) per workgroup: the K root
+// columns first, then the deflated ones (the merged eigenvectors are written
+// to their ascending places by the products below).
 __global__ __launch_bounds__(256) void dc_vectors_kernel(const MergeDesc* __restrict__ md, MergeArrays ma,
                                                          double* U, int ldu)
 {
@@ -497,13 +499,13 @@ __global__ __launch_bounds__(256) void dc_vectors_kernel(const MergeDesc* __rest
     const int tid = threadIdx.x;
     if (t >= K) {
         const int slot = t - K;
-        const int col = ma.coldef[o + slot];
+        const int col = K + slot;   // deflated columns after the K root columns
         const int row = ma.dfrow[o + slot];
         for (int r = tid; r < ns; r += blockDim.x) U[cm(o + r, o + col, ldu)] = (r == row) ? 1.0 : 0.0;
         return;
     }
     const int j = t;
-    const int col = ma.colroot[o + j];
+    const int col = j;   // root columns first; their final (sorted) places are colroot
     const double* ds = ma.ds + o;
     const double dorg = ds[ma.org[o + j]];
     const double tj = ma.tau[o + j];
@@ -542,6 +544,74 @@ __global__ __launch_bounds__(256) void dc_rot_kernel(const MergeDesc* __restrict
     }
 }
 
+// Deflated columns of the merged eigenvector block: column K + slot of U is
+// G e_row (a few nonzeros along its rotation chain), so its eigenvector is a
+// short combination of columns of the block-diagonal input, written to its
+// ascending place coldef[slot] when that is below ncol.  One workgroup per
+// deflated column; the nonzeros are gathered and put in row order, so the
+// sums run in a fixed order.
+__global__ __launch_bounds__(256) void dc_deflated_kernel(const MergeDesc* __restrict__ md, MergeArrays ma,
+                                                          const double* __restrict__ Zin, double* Zout, int ldz,
+                                                          const double* __restrict__ U, int ldu, int ncol)
+{
+    __shared__ int nzr[256];
+    __shared__ double nzv[256];
+    __shared__ int cnt;
+    const int mi = blockIdx.y;
+    const MergeDesc D = md[mi];
+    const int o = D.o, n1 = D.n1, ns = D.n1 + D.n2;
+    const int K = ma.K[mi];
+    const int slot = blockIdx.x;
+    if (slot >= ns - K) return;
+    const int col = ma.coldef[o + slot];
+    if (col >= ncol) return;
+    const int tid = threadIdx.x;
+    const double* u = U + cm(o, o + K + slot, ldu);
+    if (tid == 0) cnt = 0;
+    __syncthreads();
+    for (int r = tid; r < ns; r += blockDim.x) {
+        const double v = u[r];
+        if (v != 0.0) {
+            const int p = atomicAdd(&cnt, 1);
+            if (p < 256) { nzr[p] = r; nzv[p] = v; }
+        }
+    }
+    __syncthreads();
+    const int c = cnt;
+    if (c <= 256) {
+        if (tid == 0) {   // insertion sort by row: a fixed summation order
+            for (int a = 1; a < c; ++a) {
+                const int r = nzr[a];
+                const double v = nzv[a];
+                int b = a - 1;
+                while (b >= 0 && nzr[b] > r) { nzr[b + 1] = nzr[b]; nzv[b + 1] = nzv[b]; --b; }
+                nzr[b + 1] = r;
+                nzv[b + 1] = v;
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < ns; i += blockDim.x) {
+            const bool top = i < n1;
+            double acc = 0.0;
+            for (int q = 0; q < c; ++q) {
+                const int r = nzr[q];
+                if ((r < n1) == top) acc += Zin[cm(o + i, o + r, ldz)] * nzv[q];
+            }
+            Zout[cm(o + i, o + col, ldz)] = acc;
+        }
+    } else {
+        for (int i = tid; i < ns; i += blockDim.x) {
+            const int r0 = (i < n1) ? 0 : n1, r1 = (i < n1) ? n1 : ns;
+            double acc = 0.0;
+            for (int r = r0; r < r1; ++r) {
+                const double v = u[r];
+                if (v != 0.0) acc += Zin[cm(o + i, o + r, ldz)] * v;
+            }
+            Zout[cm(o + i, o + col, ldz)] = acc;
+        }
+    }
+}
+
 }  // namespace
 
 size_t stedc_workspace_bytes(int n)
@@ -559,8 +629,9 @@ size_t stedc_workspace_bytes(int n)
 // is left ready.  Phase 2 (stedc_vectors) forms the eigenvectors of the
 // lowest ncol eigenvalues only -- the top merge dominates the cost, and the
 // density matrix needs only the states with non-negligible occupation.
-int stedc_values(hipStream_t st, int n, const double* d, const double* e, double* w, double* Z, double* Z2,
-                 double* U, int ldz, void* work, int* err, DcState* state)
+// The merge bookkeeping laid out in the solver's scratch (the same layout for
+// both phases).
+static MergeArrays merge_arrays(void* work, int n, MergeDesc** mdev_out)
 {
     char* p = (char*)work;
     auto take = [&](size_t bytes) { void* r = p; p += align_up(bytes, 256); return r; };
@@ -590,6 +661,15 @@ int stedc_values(hipStream_t st, int n, const double* d, const double* e, double
     ma.dfull = (double*)take(sizeof(double) * n);
     ma.skey = (double*)take(sizeof(double) * 2 * n);
     MergeDesc* mdev = (MergeDesc*)take(sizeof(MergeDesc) * (n / LEAF + 2));
+    *mdev_out = mdev;
+    return ma;
+}
+
+int stedc_values(hipStream_t st, int n, const double* d, const double* e, double* w, double* Z, double* Z2,
+                 double* U, int ldz, void* work, int* err, DcState* state)
+{
+    MergeDesc* mdev = nullptr;
+    MergeArrays ma = merge_arrays(work, n, &mdev);
 
     state->n = n;
     state->ldz = ldz;
@@ -640,6 +720,8 @@ int stedc_values(hipStream_t st, int n, const double* d, const double* e, double
             state->Zin = Zin;
             state->Zout = Zout;
             state->last = md;
+            state->last_dev = mdl;
+            state->work = work;
             state->have_last = true;
             return 0;
         }
@@ -648,13 +730,24 @@ int stedc_values(hipStream_t st, int n, const double* d, const double* e, double
             int n1 = std::min(size, n - o);
             if (n - o - n1 <= 0) copy_matrix(st, n1, n1, Zin + cm(o, o, ldz), ldz, Zout + cm(o, o, ldz), ldz);
         }
-        for (const MergeDesc& m : md) {
-            const int ns = m.n1 + m.n2;
-            dgemm(st, 'N', 'N', m.n1, ns, m.n1, 1.0, Zin + cm(m.o, m.o, ldz), ldz, U + cm(m.o, m.o, ldz), ldz,
-                  0.0, Zout + cm(m.o, m.o, ldz), ldz, 0);
-            dgemm(st, 'N', 'N', m.n2, ns, m.n2, 1.0, Zin + cm(m.o + m.n1, m.o + m.n1, ldz), ldz,
-                  U + cm(m.o + m.n1, m.o, ldz), ldz, 0.0, Zout + cm(m.o + m.n1, m.o, ldz), ldz, 0);
+        // merged eigenvectors: the root columns by two products each (written
+        // to their ascending places), the deflated ones from their few nonzeros
+        std::vector<int> Ks(nm);
+        if (hipMemcpyAsync(Ks.data(), ma.K + 0, sizeof(int) * nm, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return kStatusHip;
+        for (int q = 0; q < nm; ++q) {
+            const MergeDesc& m = md[q];
+            const int K = Ks[q];
+            if (K <= 0) continue;
+            dgemm_colmap(st, m.n1, K, m.n1, 1.0, Zin + cm(m.o, m.o, ldz), ldz, U + cm(m.o, m.o, ldz), ldz, 0.0,
+                         Zout + cm(m.o, m.o, ldz), ldz, ma.colroot + m.o);
+            dgemm_colmap(st, m.n2, K, m.n2, 1.0, Zin + cm(m.o + m.n1, m.o + m.n1, ldz), ldz,
+                         U + cm(m.o + m.n1, m.o, ldz), ldz, 0.0, Zout + cm(m.o + m.n1, m.o, ldz), ldz,
+                         ma.colroot + m.o);
         }
+        hipLaunchKernelGGL(dc_deflated_kernel, dim3(maxns, nm), dim3(256), 0, st, mdl, ma, Zin, Zout, ldz, U, ldz,
+                           maxns);
         std::swap(Zin, Zout);
     }
     return 0;
@@ -668,13 +761,40 @@ void stedc_vectors(hipStream_t st, DcState& state, int ncol)
     double* Zin = state.Zin;
     double* Zout = state.Zout;
     double* U = state.U;
-    for (const MergeDesc& m : state.last) {
-        const int nc = std::min(m.n1 + m.n2, ncol);
-        dgemm(st, 'N', 'N', m.n1, nc, m.n1, 1.0, Zin + cm(m.o, m.o, ldz), ldz, U + cm(m.o, m.o, ldz), ldz, 0.0,
-              Zout + cm(m.o, m.o, ldz), ldz, 0);
-        dgemm(st, 'N', 'N', m.n2, nc, m.n2, 1.0, Zin + cm(m.o + m.n1, m.o + m.n1, ldz), ldz,
-              U + cm(m.o + m.n1, m.o, ldz), ldz, 0.0, Zout + cm(m.o + m.n1, m.o, ldz), ldz, 0);
+    MergeDesc* mdev_all = nullptr;
+    MergeArrays ma = merge_arrays(state.work, state.n, &mdev_all);
+    const int nm = (int)state.last.size();
+    // the last level is one merge (its two halves span all n rows)
+    std::vector<int> Ks(nm);
+    if (hipMemcpyAsync(Ks.data(), ma.K, sizeof(int) * nm, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return;
+    int maxns = 0;
+    for (int q = 0; q < nm; ++q) {
+        const MergeDesc& m = state.last[q];
+        const int ns = m.n1 + m.n2;
+        maxns = std::max(maxns, ns);
+        // roots ascend with their index, so the wanted ones (ascending place
+        // below ncol) are a leading run of the K root columns; the run is taken
+        // up to the last wanted root, so an equal-valued neighbour cannot be lost
+        const int K = Ks[q];
+        std::vector<int> cr(std::max(K, 1));
+        if (K > 0 && (hipMemcpyAsync(cr.data(), ma.colroot + m.o, sizeof(int) * K, hipMemcpyDeviceToHost, st) !=
+                          hipSuccess ||
+                      hipStreamSynchronize(st) != hipSuccess))
+            return;
+        int J = 0;
+        for (int j = 0; j < K; ++j)
+            if (cr[j] < ncol) J = j + 1;
+        if (J == 0) continue;
+        dgemm_colmap(st, m.n1, J, m.n1, 1.0, Zin + cm(m.o, m.o, ldz), ldz, U + cm(m.o, m.o, ldz), ldz, 0.0,
+                     Zout + cm(m.o, m.o, ldz), ldz, ma.colroot + m.o);
+        dgemm_colmap(st, m.n2, J, m.n2, 1.0, Zin + cm(m.o + m.n1, m.o + m.n1, ldz), ldz,
+                     U + cm(m.o + m.n1, m.o, ldz), ldz, 0.0, Zout + cm(m.o + m.n1, m.o, ldz), ldz,
+                     ma.colroot + m.o);
     }
+    hipLaunchKernelGGL(dc_deflated_kernel, dim3(maxns, nm), dim3(256), 0, st, state.last_dev, ma, Zin, Zout, ldz,
+                       U, ldz, ncol);
     if (Zout != state.Z) copy_matrix(st, state.n, std::min(state.n, ncol), Zout, ldz, state.Z, ldz);
     state.have_last = false;
 }
