@@ -354,9 +354,12 @@ void launch_gemm(hipStream_t st, int m, int n, int k, double alpha, const double
     int per = (ntiles + 7) / 8;
     dim3 grid(per * 8, nsplit), block(256);
     if (cmap) {   // only the merge products of the tridiagonal solver remap C's columns
-        if constexpr (AM == kOpN && !TB)
+        if constexpr (AM == kOpN && !TB) {
+            const int cslot = launch_probe::begin(st);
             hipLaunchKernelGGL((dgemm_kernel<BM, BN, AM, TB, false, true>), grid, block, 0, st, m, n, k, alpha, A,
                                lda, B, ldb, beta, C, ldc, uplo, tiles_m, ntiles, per, kper, cstride, cmap);
+            if (cslot >= 0) launch_probe::end(st, cslot, 24 + shape_index(BM, BN), product_flops(m, n, k, 0));
+        }
         return;
     }
     if (g_fp32_depth > 0) {
@@ -496,7 +499,7 @@ __global__ void tn_small_reduce(int m, int n, int nchunks, double alpha, const d
 namespace launch_probe {
 namespace {
 constexpr int kSlots = 16384;
-constexpr int kIds = 24;
+constexpr int kIds = 28;
 struct State {
     std::mutex mu;   // batched calls launch from several host threads
     bool on = false;
@@ -538,6 +541,10 @@ const char* kNames[kIds] = {
     "dgemm_kernel<64,128,1,true,false,false>",
     "dgemm_kernel<64,128,2,false,false,false>",
     "dgemm_kernel<64,128,2,true,false,false>",
+    "dgemm_kernel<128,128,0,false,false,true>",
+    "dgemm_kernel<128,64,0,false,false,true>",
+    "dgemm_kernel<64,64,0,false,false,true>",
+    "dgemm_kernel<64,128,0,false,false,true>",
 };
 }  // namespace
 
