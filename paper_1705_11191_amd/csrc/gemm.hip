@@ -11,7 +11,7 @@
 // are multiplied out of LDS.  The kernel is held to 256 VGPRs so that two
 // workgroups share a CU (one's barriers and LDS stores hide behind the
 // other's matrix-core work); the epilogue reads C one 16-row block at a time
-// for the same reason.  Workgroups are renumbered so that each of the
+// for the same reason, the first block while the last K slice is multiplied.  Workgroups are renumbered so that each of the
 // eight XCDs walks a contiguous range of tiles, in groups of eight tile rows
 // (its L2 then holds the shared operand panels).
 #include "common.h"
@@ -242,12 +242,37 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
         }
     };
 
-    const int nk = (k + kBK - 1) / kBK;
-    if (nk > 0) load_slice(0);
-    for (int kt = 0; kt < nk; ++kt) {
-        store_slice();
-        __syncthreads();
-        if (kt + 1 < nk) load_slice((kt + 1) * kBK);
+    // D layout of the 16x16 f64 MFMA: lane l, element r holds D(4r + l/16, l%16),
+    // and of the f32 one D(4 (l/16) + r, l%16); D is the transposed block, so
+    // that is C(row l%16, column 4r + l/16), resp. column 4 (l/16) + r.
+    // cmap (optional): logical column gc of C is stored at column cmap[gc]
+    auto ccol = [&](int gc) {
+        if constexpr (CMAP) return cmap[gc];
+        else return gc;
+    };
+    // (computed where used, so that the instances without the early C fetch
+    // hold none of it in registers across the K loop)
+    constexpr int RSTEP = F32 ? 1 : 4;   // column step between a lane's result elements
+    auto crow = [&](int i) { return row0 + wm * WM + (lane & 15) + i * 16; };
+    auto ccolumn = [&](int j, int r) {
+        return col0 + wn * WN + (F32 ? 4 * (lane >> 4) : (lane >> 4)) + j * 16 + r * RSTEP;
+    };
+    auto valid = [&](int gr, int gc) {
+        const bool interior = (row0 + BM <= m) && (col0 + BN <= n) && !(uplo && col0 + BN - 1 > row0);
+        return interior || (gr < m && gc < n && !(uplo && gr < gc));
+    };
+    // the lane's entries of C in the i-th 16-row block of its sub-tile
+    auto load_cblock = [&](int i, double (&cv)[FN][4]) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gr = crow(i), gc = ccolumn(j, r);
+                cv[j][r] = valid(gr, gc) ? C[cm(gr, ccol(gc), ldc)] : 0.0;
+            }
+    };
+
+    auto mma_slice = [&]() {
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 4) {
             const int kr = kk + (lane >> 4);
@@ -268,42 +293,53 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
                         acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
                 }
         }
-        __syncthreads();
+    };
+
+    // FP64 instances with a plain or transposed A fetch the first 16-row block
+    // of C while the last K slice is multiplied out, so that the latency of
+    // those reads hides behind matrix-core work.  The symmetric-operand and
+    // FP32 instances keep the plain loop: the early fetch pushed the former
+    // past the register budget and measured slower in the latter.
+    constexpr bool kEarlyC = (AM != kOpSymLower) && !F32;
+    double cv[FN][4];
+    const int nk = (k + kBK - 1) / kBK;
+    if constexpr (kEarlyC) {
+        if (nk > 0) {
+            load_slice(0);
+            for (int kt = 0; kt + 1 < nk; ++kt) {
+                store_slice();
+                __syncthreads();
+                load_slice((kt + 1) * kBK);
+                mma_slice();
+                __syncthreads();
+            }
+            store_slice();   // the last slice
+            __syncthreads();
+            if (beta != 0.0) load_cblock(0, cv);
+            mma_slice();
+        }
+    } else {
+        if (nk > 0) load_slice(0);
+        for (int kt = 0; kt < nk; ++kt) {
+            store_slice();
+            __syncthreads();
+            if (kt + 1 < nk) load_slice((kt + 1) * kBK);
+            mma_slice();
+            __syncthreads();
+        }
     }
 
-    // D layout of the 16x16 f64 MFMA: lane l, element r holds D(4r + l/16, l%16),
-    // and of the f32 one D(4 (l/16) + r, l%16); D is the transposed block, so
-    // that is C(row l%16, column 4r + l/16), resp. column 4 (l/16) + r.
-    // The C loads of one 16-row block are all issued before its stores so that they overlap.
-    // cmap (optional): logical column gc of C is stored at column cmap[gc]
-    auto ccol = [&](int gc) {
-        if constexpr (CMAP) return cmap[gc];
-        else return gc;
-    };
-    const int rbase = row0 + wm * WM + (lane & 15);
-    const int cbase = col0 + wn * WN + (F32 ? 4 * (lane >> 4) : (lane >> 4));
-    constexpr int RSTEP = F32 ? 1 : 4;   // column step between a lane's result elements
-    const bool interior = (row0 + BM <= m) && (col0 + BN <= n) && !(uplo && col0 + BN - 1 > row0);
-    auto valid = [&](int gr, int gc) {
-        return interior || (gr < m && gc < n && !(uplo && gr < gc));
-    };
     if (beta != 0.0) {
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-            double cv[FN][4];
+            if (i > 0 || !kEarlyC || nk == 0) load_cblock(i, cv);
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * RSTEP;
-                    cv[j][r] = valid(gr, gc) ? C[cm(gr, ccol(gc), ldc)] : 0.0;
-                }
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * RSTEP;
-                    if (valid(gr, gc)) C[cm(gr, ccol(gc), ldc)] = alpha * (double)acc[i][j][r] + beta * cv[j][r];
+                    const int gr = crow(i), gc = ccolumn(j, r);
+                    if (valid(gr, gc))
+                        C[cm(gr, ccol(gc), ldc)] = alpha * (double)acc[i][j][r] + beta * cv[j][r];
                 }
         }
     } else {
@@ -313,7 +349,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(int m, int n, int k, doub
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int gr = rbase + i * 16, gc = cbase + j * 16 + r * RSTEP;
+                    const int gr = crow(i), gc = ccolumn(j, r);
                     if (valid(gr, gc)) C[cm(gr, ccol(gc), ldc)] = alpha * (double)acc[i][j][r];
                 }
     }
