@@ -131,7 +131,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, kernel: str, workload: str, co
 
 
 def _kernel_matches(full_name: str, short: str) -> bool:
-    """rocprofv3 prints e.g. 'void eg::(anonymous namespace)::dgemm_kernel<128, 128, false, true>(...)'."""
+    """rocprofv3 prints e.g. 'void eg::(anonymous namespace)::dgemm_kernel<128, 128, 0, true, false, false>(...)'."""
     return full_name.replace(" ", "").find(short.replace(" ", "") + "(") >= 0
 
 
@@ -344,7 +344,7 @@ def main():
                     help="run one plain copy kernel of known size first (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary of --kernel from two rocprofv3 --pmc runs and exit")
-    ap.add_argument("--kernel", default="dgemm_kernel<128,128,0,false,false,false>")
+    ap.add_argument("--kernel", default="dgemm_kernel<128,128,0,true,false,false>")
     ap.add_argument("--pmc-command", action="append", default=[])
     ap.add_argument("--workload", choices=["single", "batch", "complex"], default="single",
                     help="single: the N=32768 dm solve; batch: 256 uneven problems in one batched call")
