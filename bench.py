@@ -161,7 +161,9 @@ def cpu_baseline(n_sample: int):
 def batch_bench(args):
     """256 independent lattice problems, sizes log-uniform in [256, 4096] rounded
     to multiples of 15, problem i from seed i, n_occ = n // 4: one batched dm
-    call vs a loop of single-problem dm calls on the same inputs."""
+    call vs a loop of single-problem dm calls (band width 64) on the same
+    inputs.  With --tune, the tuner first picks the batched calls' band width
+    per size bucket on samples of this batch (outside the timed steps)."""
     import torch
 
     from paper_1705_11191_amd import binding as B
@@ -183,6 +185,16 @@ def batch_bench(args):
     S = [torch.empty_like(x) for x in S0]
     h = B.Handle(8, 8, 2)
     h.set_batch_workers(args.batch_workers)
+    tuned = None
+    if args.tune:
+        # the band width per size bucket, timed on samples of this batch (not part of the timed steps)
+        from paper_1705_11191_amd import tune
+
+        tuned = tune.tune_batch_band_widths(h, H0, S0, nocc, workers=args.batch_workers,
+                                            cache_path=args.tune_cache,
+                                            log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(f"[bench] band widths per bucket: {tuned['n_max']} -> {tuned['b']} "
+              f"({tuned['tune_ms']:.0f} ms of tuning)", file=sys.stderr, flush=True)
 
     def batched():
         for a, b in zip(H, H0):
@@ -240,6 +252,8 @@ def batch_bench(args):
         "data": "synthetic",
         "config": {"workload": f"lattice3d_batch{len(sizes)}_loguniform256_4096_plain_fp64_dm",
                    "problems": len(sizes), "sum_n": sum(sizes), "workers": args.batch_workers},
+        "band_table": ({"n_max": tuned["n_max"], "b": tuned["b"], "tune_ms": tuned["tune_ms"],
+                        "cached": tuned["cached"]} if tuned else None),
         "sequential_single_calls_ms": ms_seq,
         "speedup_vs_sequential": ms_seq / ms_batched,
         "checks": {"status_all_zero": all(x == 0 for x in status),
@@ -352,6 +366,10 @@ def main():
     ap.add_argument("--kpoints", type=int, default=4, help="complex workload: k-points per step (1..16)")
     ap.add_argument("--cell", default="8,8,12", help="complex workload: cell sites along x,y,z")
     ap.add_argument("--batch-workers", type=int, default=8)
+    ap.add_argument("--tune", action="store_true",
+                    help="batch workload: tune the band width per size bucket before the timed steps")
+    ap.add_argument("--tune-cache", default=None,
+                    help="batch workload: JSON cache of tuned band-width tables (default: $ELSI_GPU_TUNE_CACHE)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="single workload: plain FP64, or FP32 matrix-core products in full -> band and Q1 "
                          "followed by FP64 refinement")

@@ -241,6 +241,18 @@ int elsi_gpu_dm(elsi_gpu_handle h, double *H, double *S, double *occ, double *D,
  * Errors: -1 handle, -2 workers. */
 int elsi_gpu_set_batch_workers(elsi_gpu_handle h, int workers);
 
+/* Band widths b of step (1) per problem size for the batched calls (the
+ * table an autotuner writes after timing each size bucket).  count entries
+ * (0 <= count <= 16; 0 clears the table), host arrays: a problem of size n
+ * takes b[i] of the first i with n <= n_max[i]; larger problems, and every
+ * problem while the table is empty, take the handle's band width
+ * (elsi_gpu_set_band_width).  n_max strictly increasing and >= 1; each b[i]
+ * a multiple of 8 in [8, 64].  The table is copied; single-problem calls do
+ * not use it.
+ * Errors: -1 handle, -2 count, -3 n_max (NULL with count > 0, or not
+ * increasing), -4 b (NULL with count > 0, or an invalid width). */
+int elsi_gpu_set_batch_band_table(elsi_gpu_handle h, int count, const int *n_max, const int *b);
+
 /* elsi_gpu_ev for count problems: n[p] basis functions, the n_state[p]
  * lowest eigenpairs into eval[p] (n[p] doubles) and evec[p] (n[p] x
  * n_state[p]); H[p] destroyed, S[p] receives L (S may be NULL with the unit

@@ -82,6 +82,7 @@ def lib():
         L.elsi_gpu_set_band_width.argtypes = [vp, i]
         L.elsi_gpu_set_launch_timing.argtypes = [vp, i]
         L.elsi_gpu_set_batch_workers.argtypes = [vp, i]
+        L.elsi_gpu_set_batch_band_table.argtypes = [vp, i, vp, vp]
         L.elsi_gpu_set_precision.argtypes = [vp, i, d, i]
         pp, ip, dp = ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(d)
         L.elsi_gpu_ev_batched.argtypes = [vp, i, ip, ip, pp, pp, pp, pp, ip]
@@ -366,6 +367,18 @@ class Handle:
 
     def set_batch_workers(self, workers: int):
         _check(lib().elsi_gpu_set_batch_workers(self._h, workers), "set_batch_workers")
+
+    def set_batch_band_table(self, n_max, b):
+        """Band widths of the batched calls per size bucket: a problem of size n
+        takes b[i] of the first i with n <= n_max[i] (empty lists clear the table)."""
+        n_max, b = [int(x) for x in n_max], [int(x) for x in b]
+        if len(n_max) != len(b):
+            raise ValueError("n_max and b differ in length")
+        cnt = len(n_max)
+        arr_n = (ctypes.c_int * max(cnt, 1))(*n_max)
+        arr_b = (ctypes.c_int * max(cnt, 1))(*b)
+        _check(lib().elsi_gpu_set_batch_band_table(self._h, cnt, arr_n if cnt else None, arr_b if cnt else None),
+               "set_batch_band_table")
 
     def ev_batched(self, Hs, Ss, n_states, ok=(0,)):
         """Batched eigenpairs: returns (evals, evecs column-major, per-problem status, rc)."""

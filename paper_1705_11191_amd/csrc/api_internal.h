@@ -95,6 +95,9 @@ struct elsi_gpu_handle_s {
     int overlap_factored = 0;
     int band_width = 64;
     int batch_workers = 8;
+    int band_tab_count = 0;       // per-size band widths of the batched calls
+    int band_tab_nmax[16] = {};
+    int band_tab_b[16] = {};
     int precision = ELSI_GPU_PREC_FP64;
     double refine_tol = 1e-10;
     int max_refine = 4;

@@ -35,7 +35,7 @@ struct BatchDepth {
 };
 
 // Worker-local copy of the caller's handle: settings shared, stream and
-// workspace private.
+// workspace private (the band width is set per problem).
 elsi_gpu_handle_s worker_handle(const elsi_gpu_handle_s* proto, hipStream_t st)
 {
     elsi_gpu_handle_s w;
@@ -52,6 +52,15 @@ elsi_gpu_handle_s worker_handle(const elsi_gpu_handle_s* proto, hipStream_t st)
     w.stream = st;
     std::memset(&w.info, 0, sizeof(w.info));
     return w;
+}
+
+// Band width of a problem of size n in a batched call: the first table entry
+// that covers n, else the handle's own.
+int batch_band(const elsi_gpu_handle_s* h, int n)
+{
+    for (int i = 0; i < h->band_tab_count; ++i)
+        if (n <= h->band_tab_nmax[i]) return h->band_tab_b[i];
+    return h->band_width;
 }
 
 // Run fn(worker handle, problem index) over all problems with the pool.
@@ -129,6 +138,24 @@ int elsi_gpu_set_batch_workers(elsi_gpu_handle h, int workers)
     return 0;
 }
 
+int elsi_gpu_set_batch_band_table(elsi_gpu_handle h, int count, const int* n_max, const int* b)
+{
+    if (!h) return -1;
+    if (count < 0 || count > 16) return -2;
+    if (count > 0 && !n_max) return -3;
+    if (count > 0 && !b) return -4;
+    for (int i = 0; i < count; ++i) {
+        if (n_max[i] < 1 || (i > 0 && n_max[i] <= n_max[i - 1])) return -3;
+        if (b[i] < 8 || b[i] > 64 || b[i] % 8 != 0) return -4;
+    }
+    for (int i = 0; i < count; ++i) {
+        h->band_tab_nmax[i] = n_max[i];
+        h->band_tab_b[i] = b[i];
+    }
+    h->band_tab_count = count;
+    return 0;
+}
+
 int elsi_gpu_ev_batched(elsi_gpu_handle h, int count, const int* n, const int* n_state, double* const* H,
                         double* const* S, double* const* eval, double* const* evec, int* status)
 {
@@ -148,6 +175,7 @@ int elsi_gpu_ev_batched(elsi_gpu_handle h, int count, const int* n, const int* n
             return -3;
     return run_pool(h, count, n, status, [&](elsi_gpu_handle_s* w, int p) {
         w->n = n[p];
+        w->band_width = batch_band(h, n[p]);
         w->n_state = n_state[p];
         w->n_electron = 0.0;
         return elsi_gpu_ev(w, H[p], S ? S[p] : nullptr, eval[p], evec[p]);
@@ -176,6 +204,7 @@ int elsi_gpu_dm_batched(elsi_gpu_handle h, int count, const int* n, const double
             return -3;
     return run_pool(h, count, n, status, [&](elsi_gpu_handle_s* w, int p) {
         w->n = n[p];
+        w->band_width = batch_band(h, n[p]);
         w->n_state = n[p];
         w->n_electron = n_electron[p];
         double e = 0.0, m = 0.0;

@@ -49,6 +49,21 @@ def test_strerror_and_argument_checks_without_gpu():
     lib.elsi_gpu_set_band_width.argtypes = [ctypes.c_void_p, ctypes.c_int]
     assert lib.elsi_gpu_set_band_width(h, 12) == -2
     assert lib.elsi_gpu_set_band_width(h, 32) == 0
+    # per-size band widths of the batched calls
+    IA = ctypes.c_int * 3
+    lib.elsi_gpu_set_batch_band_table.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    nmax, bw = IA(512, 1024, 4096), IA(32, 48, 64)
+    assert lib.elsi_gpu_set_batch_band_table(None, 3, nmax, bw) == -1
+    assert lib.elsi_gpu_set_batch_band_table(h, -1, nmax, bw) == -2
+    assert lib.elsi_gpu_set_batch_band_table(h, 17, nmax, bw) == -2
+    assert lib.elsi_gpu_set_batch_band_table(h, 3, None, bw) == -3
+    assert lib.elsi_gpu_set_batch_band_table(h, 3, IA(512, 512, 4096), bw) == -3
+    assert lib.elsi_gpu_set_batch_band_table(h, 3, IA(0, 512, 4096), bw) == -3
+    assert lib.elsi_gpu_set_batch_band_table(h, 3, nmax, None) == -4
+    assert lib.elsi_gpu_set_batch_band_table(h, 3, nmax, IA(32, 12, 64)) == -4
+    assert lib.elsi_gpu_set_batch_band_table(h, 3, nmax, IA(32, 48, 72)) == -4
+    assert lib.elsi_gpu_set_batch_band_table(h, 3, nmax, bw) == 0
+    assert lib.elsi_gpu_set_batch_band_table(h, 0, None, None) == 0
     lib.elsi_gpu_set_precision.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int]
     assert lib.elsi_gpu_set_precision(None, 1, 1e-10, 4) == -1
     assert lib.elsi_gpu_set_precision(h, 2, 1e-10, 4) == -2

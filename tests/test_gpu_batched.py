@@ -174,3 +174,62 @@ def test_batched_tiny_and_empty():
     disc = np.sqrt(qb * qb - 4 * qa * qc)
     lam = np.sort([(-qb - disc) / (2 * qa), (-qb + disc) / (2 * qa)])
     assert np.abs(evals[1].cpu().numpy() - lam).max() <= 1e-14
+
+
+def test_batched_band_table_routes_each_size_to_its_width():
+    """With a table, each problem runs with its bucket's band width: it matches,
+    bit for bit, the same problem in a batched call with that width set on the
+    handle, and every problem meets the oracle gates."""
+    from paper_1705_11191_amd import binding as B
+
+    sizes = [40, 90, 130, 260, 300]
+    sps = _systems(sizes, seed0=40)
+    ne = [sp.n_occ for sp in sps]
+
+    def run(table=None, b=None):
+        h = B.Handle(8, 8, 2)
+        if table:
+            h.set_batch_band_table(*table)
+        if b:
+            h.set_band_width(b)
+        out = h.dm_batched([_dev(sp.H) for sp in sps], [_dev(sp.S) for sp in sps], ne)
+        h.close()
+        assert out[5] == 0
+        return [D.cpu().numpy() for D in out[0]]
+
+    D_tab = run(table=([64, 256], [16, 32]))
+    D16, D32, D64 = run(b=16), run(b=32), run(b=64)
+    want = {40: D16, 90: D32, 130: D32, 260: D64, 300: D64}
+    for q, n in enumerate(sizes):
+        assert np.array_equal(D_tab[q], want[n][q]), n
+        ref = O.dm(sps[q].H, sps[q].S, sps[q].n_occ, sps[q].kT)
+        assert np.abs(D_tab[q] - ref["D"]).max() <= 1e-9
+
+
+def test_tuner_sets_a_width_per_bucket_and_caches_it(tmp_path):
+    from paper_1705_11191_amd import binding as B
+    from paper_1705_11191_amd import tune
+
+    sizes = [60, 100, 200, 300, 520]
+    sps = _systems(sizes, seed0=60)
+    Hs = [_dev(sp.H) for sp in sps]
+    Ss = [_dev(sp.S) for sp in sps]
+    H0 = [x.clone() for x in Hs]
+    S0 = [x.clone() for x in Ss]
+    ne = [sp.n_occ for sp in sps]
+    cache = str(tmp_path / "tune.json")
+    h = B.Handle(8, 8, 2)
+    rec = tune.tune_batch_band_widths(h, Hs, Ss, ne, candidates=(32, 64), per_bucket=2, workers=4,
+                                      cache_path=cache)
+    assert rec["n_max"] == [512, 1024] and all(b in (32, 64) for b in rec["b"]) and not rec["cached"]
+    assert all(torch.equal(a, b) for a, b in zip(Hs, H0)) and all(torch.equal(a, b) for a, b in zip(Ss, S0))
+    rec2 = tune.tune_batch_band_widths(h, Hs, Ss, ne, candidates=(32, 64), per_bucket=2, workers=4,
+                                       cache_path=cache)
+    assert rec2["cached"] and rec2["n_max"] == rec["n_max"] and rec2["b"] == rec["b"]
+    Ds, evals, energy, mu, status, rc = h.dm_batched(Hs, Ss, ne)
+    h.close()
+    assert rc == 0
+    for q, sp in enumerate(sps):
+        ref = O.dm(sp.H, sp.S, sp.n_occ, sp.kT)
+        assert np.abs(Ds[q].cpu().numpy() - ref["D"]).max() <= 1e-9
+        assert eig_excess(evals[q].cpu().numpy(), ref["eval"], sp.S) <= 1.0
