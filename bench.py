@@ -46,6 +46,40 @@ def algorithmic_flops(n: int, ks: int) -> float:
     return (8.0 / 3.0) * n ** 3 + 6.0 * n * n * ks
 
 
+FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix-core peak
+
+
+def stage_roofline(stage_ms: dict, n: int, k: int, b: int, mixed: bool = False) -> dict:
+    """Achieved rate of each stage against the peak of the unit it runs on.
+
+    Algorithmic flops per stage (k = eigenvector columns the path carries for
+    the density matrix, b = band width): Cholesky n^3/3, reduction n^3,
+    full -> band 4n^3/3, bulge chasing 6 b n^2 (vector ALU, latency bound),
+    Q2 and Q1 2 n^2 k each, back substitution n^2 k, density matrix n^2 k.
+    `peak_of` names the unit whose peak `frac` is taken against; it says
+    nothing about what bounds the stage (Q2 streams its columns from HBM).
+    The matrix-core stages sum to 8/3 n^3 + 6 n^2 k, the benchmark's count.
+    The divide-and-conquer merges and the refinement have no closed form
+    here and carry their time only."""
+    n3, n2k = float(n) ** 3, float(n) * n * k
+    work = {"cholesky": (n3 / 3, "fp64_mfma"), "reduce": (n3, "fp64_mfma"), "band": (4 * n3 / 3, "fp64_mfma"),
+            "bulge": (6.0 * b * n * n, "fp64_valu"), "back_q2": (2 * n2k, "fp64_mfma"),
+            "back_q1": (2 * n2k, "fp64_mfma"), "backsub": (n2k, "fp64_mfma"), "density": (n2k, "fp64_mfma")}
+    fp32_stages = ("band", "back_q1") if mixed else ()
+    out = {}
+    for st, ms in stage_ms.items():
+        if st not in work or ms <= 0.0:
+            out[st] = {"ms": ms}
+            continue
+        flops, unit = work[st]
+        if st in fp32_stages:
+            unit = "fp32_mfma"
+        peak = FP32_PEAK_TFLOPS if unit == "fp32_mfma" else FP64_PEAK_TFLOPS   # FP64 vector peak = FP64 MFMA peak
+        tf = flops / (ms * 1e-3) / 1e12
+        out[st] = {"ms": ms, "flops": flops, "tflops": tf, "peak": peak, "frac": tf / peak, "peak_of": unit}
+    return out
+
+
 def _sha256(path: str) -> str:
     import hashlib
 
@@ -522,6 +556,7 @@ def main():
         "roofline": roofline,
         "algorithmic_flops": F,
         "stage_ms": stage_ms,
+        "stage_roofline": stage_roofline(stage_ms, n, ks, info["band_width"], mixed),
         "checks": {"trace_DS_minus_Ne": trace_ds - n_occ, "eigenvalues_ascending": ascending,
                    "mu_Ha": info["mu"]},
     }

@@ -1,0 +1,37 @@
+"""Host logic of the benchmark report: the per-stage rates and the flop count
+they are quoted on (no GPU)."""
+import math
+
+import bench
+
+
+def _stages(ms=100.0):
+    return {s: ms for s in ["cholesky", "reduce", "band", "bulge", "tridiag", "occ", "back_q2", "back_q1",
+                            "backsub", "density", "refine"]}
+
+
+def test_matrix_core_stages_sum_to_the_benchmark_flop_count():
+    n, k, b = 32768, 8194, 64
+    rep = bench.stage_roofline(_stages(), n, k, b)
+    mfma = sum(v["flops"] for v in rep.values() if v.get("peak_of") == "fp64_mfma")
+    assert math.isclose(mfma, bench.algorithmic_flops(n, k), rel_tol=1e-12)
+    assert math.isclose(rep["bulge"]["flops"], 6.0 * b * n * n) and rep["bulge"]["peak_of"] == "fp64_valu"
+    # the divide-and-conquer merges, occupations and refinement carry their time only
+    for st in ("tridiag", "occ", "refine"):
+        assert rep[st] == {"ms": 100.0}
+
+
+def test_rates_and_peaks_per_precision():
+    n, k, b = 1000, 300, 64
+    st = _stages(ms=2.0)
+    plain = bench.stage_roofline(st, n, k, b)
+    mixed = bench.stage_roofline(st, n, k, b, mixed=True)
+    assert math.isclose(plain["reduce"]["tflops"], n ** 3 / 2e-3 / 1e12)
+    assert math.isclose(plain["reduce"]["frac"], plain["reduce"]["tflops"] / 78.6)
+    # in the mixed mode full -> band and Q1 run on the FP32 matrix cores
+    assert mixed["band"]["peak"] == 157.3 and mixed["back_q1"]["peak"] == 157.3
+    assert mixed["band"]["peak_of"] == "fp32_mfma" and mixed["reduce"]["peak_of"] == "fp64_mfma"
+    assert mixed["back_q2"]["peak"] == 78.6 and plain["band"]["peak"] == 78.6
+    # a stage that did not run is reported by its time alone
+    st["refine"] = 0.0
+    assert bench.stage_roofline(st, n, k, b)["refine"] == {"ms": 0.0}
