@@ -76,6 +76,7 @@ def tune_batch_band_widths(handle: B.Handle, Hs, Ss, n_electrons, buckets=None,
     cache_path = cache_path or os.environ.get("ELSI_GPU_TUNE_CACHE")
     dev_name = torch.cuda.get_device_name(Hs[0].device)
     key = _cache_key(dev_name, buckets, candidates, sampled_sizes, workers)
+    handle.set_batch_workers(workers)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
@@ -86,7 +87,6 @@ def tune_batch_band_widths(handle: B.Handle, Hs, Ss, n_electrons, buckets=None,
             return dict(rec, tune_ms=0.0, cached=True)
 
     t_start = time.perf_counter()
-    handle.set_batch_workers(workers)
     n_max, widths, timings = [], [], {}
     for hi, sample in zip(buckets, samples):
         if not sample:
