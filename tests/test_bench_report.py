@@ -35,3 +35,19 @@ def test_rates_and_peaks_per_precision():
     # a stage that did not run is reported by its time alone
     st["refine"] = 0.0
     assert bench.stage_roofline(st, n, k, b)["refine"] == {"ms": 0.0}
+
+
+def test_tuner_buckets_and_samples():
+    from paper_1705_11191_amd import tune
+
+    # power-of-two upper bounds from 512 up to the first that covers the largest size
+    assert tune.default_buckets([255, 300]) == [512]
+    assert tune.default_buckets([256, 4095]) == [512, 1024, 2048, 4096]
+    assert tune.default_buckets([4097]) == [512, 1024, 2048, 4096, 8192]
+    # a bucket's sample spreads evenly over its members and never repeats one
+    members = list(range(100, 140))
+    s = tune._sample(members, 8)
+    assert len(s) == 8 and len(set(s)) == 8 and all(x in members for x in s)
+    assert s == sorted(s) and s[0] < 105 and s[-1] > 134
+    assert tune._sample([3, 4], 8) == [3, 4]
+    assert tune._sample([], 8) == []
