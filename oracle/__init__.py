@@ -5,13 +5,21 @@ check and the benchmark's CPU-baseline leg may import this package; the GPU
 library never does, and it shares no code with it.
 """
 from .oracle import (  # noqa: F401
+    FERMI,
+    GAUSSIAN,
+    MP0,
+    MP1,
     backsub,
     band_energy,
     build,
     density,
     dm,
+    dm_checked,
+    dm_shared_mu,
     gevp,
+    gevp_checked,
     occupations,
+    occupation_value,
     potrf,
     reduce_standard,
     refine,
@@ -19,6 +27,7 @@ from .oracle import (  # noqa: F401
     tred,
     tridiag_eig,
     tridiag_eigvals,
+    tridiag_shift_solve,
     zdensity,
     zdm,
     zgevp,

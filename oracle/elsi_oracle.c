@@ -20,9 +20,10 @@
  *     states downward (Sec. 4.5, elsi_dm_real);
  *   - the density matrix n_ij = sum_l f_l c_il c_jl, Eq. (9), and the band
  *     energy sum_l f_l eps_l (Sec. 4.5, "energy" output of elsi_dm_real).
- *   - FP64 refinement sweeps (CholeskyQR twice, Rayleigh-Ritz, residual
- *     norms) of an approximate invariant subspace of H~, the last stage of
- *     the GPU library's mixed-precision mode (orc_refine);
+ *   - FP64 refinement sweeps (CholeskyQR twice, Rayleigh-Ritz, residuals
+ *     and a Newton correction through an approximate factorization of H~)
+ *     of an approximate invariant subspace of H~, the last stage of the GPU
+ *     library's mixed-precision mode (orc_refine);
  *   - the same steps for complex Hermitian H and Hermitian positive definite
  *     S (the complex interface of Sec. 4.3, the k-point problems of periodic
  *     systems), the Householder tridiagonal made real by a diagonal unitary
@@ -356,6 +357,100 @@ int orc_gevp(int n, int n_state, double *H, int ldh, double *S, int lds,
     return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Singularity check of the overlap and the eigendecomposition transform     */
+/* (Sec. 4.5, Eq. (20)).  All eigenvalues lam of S are compared with the     */
+/* tolerance tau; when the smallest is >= tau (S well conditioned) the call   */
+/* is orc_gevp.  Otherwise S = x diag(lam) x^T = X X^T with X = x sqrt(lam), */
+/* and the N_nonsing = m eigenvectors with lam >= tau are kept: with          */
+/* Y = x_keep diag(lam_keep)^(-1/2) (n x m),                                  */
+/*   H~ = Y^T H Y (m x m),  H~ c~ = eps c~,  c = Y c~   (c^T S c = I).        */
+/* eval[0 .. m) receives the m eigenvalues ascending and eval[m .. n) the     */
+/* value +HUGE_VAL (no state there); evec (n x n_state) the first             */
+/* min(n_state, m) vectors c (largest |component| positive), later columns   */
+/* zero; S is overwritten by X's kept columns [0 .. m) (the rest zero).       */
+/* *n_nonsing = m (n on the Cholesky route).  Returns as orc_gevp.           */
+/* ------------------------------------------------------------------------- */
+int orc_gevp_checked(int n, int n_state, double *H, int ldh, double *S, int lds, double tau, double *eval,
+                     double *evec, int *n_nonsing, int *fail_col)
+{
+    double *Sc = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *I = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *lam = (double *)malloc(sizeof(double) * n);
+    double *xv = (double *)malloc(sizeof(double) * (size_t)n * n);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            Sc[IDX(i, j, n)] = (i >= j) ? S[IDX(i, j, lds)] : S[IDX(j, i, lds)];
+            I[IDX(i, j, n)] = (i == j) ? 1.0 : 0.0;
+        }
+    int st = orc_gevp(n, n, Sc, n, I, n, lam, xv, NULL);   /* S = x diag(lam) x^T */
+    if (st) { free(Sc); free(I); free(lam); free(xv); return st; }
+    if (lam[0] >= tau) {
+        free(Sc); free(I); free(lam); free(xv);
+        if (n_nonsing) *n_nonsing = n;
+        return orc_gevp(n, n_state, H, ldh, S, lds, eval, evec, fail_col);
+    }
+    if (fail_col) *fail_col = 0;
+    int m = 0;
+    for (int l = 0; l < n; ++l) if (lam[l] >= tau) ++m;
+    const int first = n - m;   /* lam ascending: the kept ones are the last m */
+    if (n_nonsing) *n_nonsing = m;
+    double *Y = (double *)malloc(sizeof(double) * (size_t)n * (m > 0 ? m : 1));
+    for (int j = 0; j < m; ++j) {
+        const double sc = 1.0 / sqrt(lam[first + j]);
+        for (int i = 0; i < n; ++i) Y[IDX(i, j, n)] = xv[IDX(i, first + j, n)] * sc;
+    }
+    /* H~ = Y^T H Y, lower triangle of H read */
+    double *HY = (double *)malloc(sizeof(double) * (size_t)n * (m > 0 ? m : 1));
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < n; ++i) {
+            double t = 0.0;
+            for (int c = 0; c < n; ++c) {
+                const double h = (i >= c) ? H[IDX(i, c, ldh)] : H[IDX(c, i, ldh)];
+                t += h * Y[IDX(c, j, n)];
+            }
+            HY[IDX(i, j, n)] = t;
+        }
+    double *Ht = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1));
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+            double t = 0.0;
+            for (int r = 0; r < n; ++r) t += Y[IDX(r, i, n)] * HY[IDX(r, j, n)];
+            Ht[IDX(i, j, m)] = t;
+        }
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < j; ++i) {
+            const double a = 0.5 * (Ht[IDX(i, j, m)] + Ht[IDX(j, i, m)]);
+            Ht[IDX(i, j, m)] = a;
+            Ht[IDX(j, i, m)] = a;
+        }
+    double *Im = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1));
+    double *ct = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1));
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) Im[IDX(i, j, m)] = (i == j) ? 1.0 : 0.0;
+    st = (m > 0) ? orc_gevp(m, m, Ht, m, Im, m, eval, ct, NULL) : 0;
+    if (!st) {
+        for (int l = m; l < n; ++l) eval[l] = HUGE_VAL;
+        const int kk = n_state < m ? n_state : m;
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < n_state; ++j)
+            for (int i = 0; i < n; ++i) {
+                double t = 0.0;
+                if (j < kk)
+                    for (int c = 0; c < m; ++c) t += Y[IDX(i, c, n)] * ct[IDX(c, j, m)];
+                evec[IDX(i, j, n)] = t;
+            }
+        normalize_sign(n, kk, evec, n);
+        /* S <- X = x_keep diag(sqrt(lam_keep)) */
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i)
+                S[IDX(i, j, lds)] = (j < m) ? xv[IDX(i, first + j, n)] * sqrt(lam[first + j]) : 0.0;
+    }
+    free(Sc); free(I); free(lam); free(xv); free(Y); free(HY); free(Ht); free(Im); free(ct);
+    return st;
+}
+
 /* Tridiagonal eigenvalues only (QL without vectors), ascending. */
 int orc_tridiag_eigvals(int n, double *d, double *e, double *w)
 {
@@ -390,42 +485,73 @@ int orc_tridiag_eig(int n, double *d, double *e, double *w, double *Z)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Fermi-Dirac occupations, Eq. (17), written so that no exponential         */
-/* overflows:  x = (eps - mu) / kT;  f = spin * e^-x / (1 + e^-x), x >= 0;   */
-/*                                   f = spin / (1 + e^x),          x <  0.  */
+/* Occupation of one state, x = (eps - mu) / width, for the broadening       */
+/* schemes of Sec. 4.6 (broadening_scheme):                                  */
+/*   1 Fermi-Dirac, Eq. (17), written so that no exponential overflows:      */
+/*       f = spin e^-x / (1 + e^-x) for x >= 0, spin / (1 + e^x) for x < 0;  */
+/*   2 Gaussian, Eq. (21): f = spin (1 - erf x) / 2, evaluated as            */
+/*       spin erfc(x) / 2 (the same function, without the cancellation);     */
+/*   3 Methfessel-Paxton of order 0: the Gaussian step;                      */
+/*   4 Methfessel-Paxton of order 1 (Methfessel & Paxton, Phys. Rev. B 40,   */
+/*       3616 (1989): S_N = S_0 + sum_{n=1..N} A_n H_{2n-1}(x) e^{-x^2},     */
+/*       A_n = (-1)^n / (n! 4^n sqrt(pi)); for N = 1, A_1 H_1(x) =           */
+/*       -x / (2 sqrt(pi))):  f = spin (erfc(x)/2 - x e^{-x^2}/(2 sqrt(pi))).*/
+/*       These occupations leave [0, spin] near mu.                          */
 /* ------------------------------------------------------------------------- */
-static double fermi(double eps, double mu, double kT, double spin)
+double orc_occupation_value(int scheme, double eps, double mu, double width, double spin)
 {
-    double x = (eps - mu) / kT;
-    if (x >= 0.0) { double t = exp(-x); return spin * t / (1.0 + t); }
-    return spin / (1.0 + exp(x));
+    const double x = (eps - mu) / width;
+    switch (scheme) {
+    case 2:
+    case 3:
+        return spin * 0.5 * erfc(x);
+    case 4:
+        return spin * (0.5 * erfc(x) - x * exp(-x * x) / (2.0 * sqrt(3.14159265358979323846)));
+    default:
+        if (x >= 0.0) { double t = exp(-x); return spin * t / (1.0 + t); }
+        return spin / (1.0 + exp(x));
+    }
 }
 
-static double electron_count(int n, const double *eps, double mu, double kT, double spin)
+/* electrons at mu: sum_l w_l f_l (w NULL: all 1) */
+static double electron_count(int n, const double *eps, const double *w, int scheme, double mu, double width,
+                             double spin)
 {
     double s = 0.0;
-    for (int l = 0; l < n; ++l) s += fermi(eps[l], mu, kT, spin);
+    for (int l = 0; l < n; ++l) s += (w ? w[l] : 1.0) * orc_occupation_value(scheme, eps[l], mu, width, spin);
     return s;
 }
 
 /* ------------------------------------------------------------------------- */
-/* Chemical potential by bisection on  sum_l f_l(mu) - N_e, Eq. (18)         */
-/* (Sec. 4.5): interval [eps_min - 10 kT, eps_max + 10 kT], widened (the     */
-/* step doubling each time) until it brackets the root; halved until the     */
-/* electron count is within occ_accuracy, the interval cannot shrink any     */
-/* further in floating point, or max_steps halvings were made.  mu is the    */
-/* upper bound (surplus >= 0), and the surplus is then removed from the      */
-/* highest occupied states downward so that sum f = N_e.                     */
-/* eps must be ascending.  Returns 0, or 4 when max_steps ran out first.     */
+/* Chemical potential by bisection on  sum_l w_l f_l(mu) - N_e, Eq. (18)     */
+/* (Sec. 4.5; with weights the sum runs over k-points and spin channels):    */
+/* interval [min eps - 10 width, max eps + 10 width], widened (the step      */
+/* doubling each time) until it brackets the root; halved until the electron */
+/* count is within occ_accuracy, the interval cannot shrink any further in   */
+/* floating point, or max_steps halvings were made.  mu is the upper bound   */
+/* (surplus >= 0); f_l = w_l f(eps_l); the surplus is then removed from the  */
+/* highest-index states with f > 0 downward so that sum f = N_e.             */
+/* eps ascending within each problem; w (per state, may be NULL).  Returns   */
+/* 0, or 4 when max_steps ran out first.                                     */
 /* ------------------------------------------------------------------------- */
-int orc_occupations(int n, const double *eps, double n_electron, double kT, double spin,
-                    double occ_accuracy, int max_steps, double *f, double *mu_out)
+int orc_occupations_scheme(int n, const double *eps, const double *w, int scheme, double n_electron,
+                           double width, double spin, double occ_accuracy, int max_steps, double *f,
+                           double *mu_out)
 {
-    double lo = eps[0] - 10.0 * kT, hi = eps[n - 1] + 10.0 * kT;
+    double emin = eps[0], emax = eps[0];
+    for (int l = 1; l < n; ++l) {
+        if (eps[l] < emin) emin = eps[l];
+        if (eps[l] > emax) emax = eps[l];
+    }
+    double lo = emin - 10.0 * width, hi = emax + 10.0 * width;
     double step = hi - lo;
-    while (electron_count(n, eps, lo, kT, spin) - n_electron > 0.0) { lo -= step; step *= 2.0; }
+    for (int t = 0; t < 64 && electron_count(n, eps, w, scheme, lo, width, spin) - n_electron > 0.0; ++t) {
+        lo -= step; step *= 2.0;
+    }
     step = hi - lo;
-    while (electron_count(n, eps, hi, kT, spin) - n_electron < 0.0) { hi += step; step *= 2.0; }
+    for (int t = 0; t < 64 && electron_count(n, eps, w, scheme, hi, width, spin) - n_electron < 0.0; ++t) {
+        hi += step; step *= 2.0;
+    }
     /* the upper bound always carries a surplus g(hi) >= 0; stop once it is    */
     /* within occ_accuracy or the midpoint no longer differs from the bounds   */
     int status = 0, steps = 0;
@@ -434,7 +560,7 @@ int orc_occupations(int n, const double *eps, double n_electron, double kT, doub
         if (!(lo < mid && mid < hi)) break;
         if (steps >= max_steps) { status = 4; break; }
         ++steps;
-        double g = electron_count(n, eps, mid, kT, spin) - n_electron;
+        double g = electron_count(n, eps, w, scheme, mid, width, spin) - n_electron;
         if (g >= 0.0) {
             hi = mid;
             if (g <= occ_accuracy) break;
@@ -443,8 +569,8 @@ int orc_occupations(int n, const double *eps, double n_electron, double kT, doub
         }
     }
     double mu = hi;
-    for (int l = 0; l < n; ++l) f[l] = fermi(eps[l], mu, kT, spin);
-    double surplus = electron_count(n, eps, mu, kT, spin) - n_electron;
+    for (int l = 0; l < n; ++l) f[l] = (w ? w[l] : 1.0) * orc_occupation_value(scheme, eps[l], mu, width, spin);
+    double surplus = electron_count(n, eps, w, scheme, mu, width, spin) - n_electron;
     for (int l = n - 1; l >= 0 && surplus > 0.0; --l) {
         if (f[l] <= 0.0) continue;
         double take = f[l] < surplus ? f[l] : surplus;
@@ -455,8 +581,16 @@ int orc_occupations(int n, const double *eps, double n_electron, double kT, doub
     return status;
 }
 
+/* Fermi-Dirac occupations of one problem (scheme 1, no weights). */
+int orc_occupations(int n, const double *eps, double n_electron, double kT, double spin,
+                    double occ_accuracy, int max_steps, double *f, double *mu_out)
+{
+    return orc_occupations_scheme(n, eps, NULL, 1, n_electron, kT, spin, occ_accuracy, max_steps, f, mu_out);
+}
+
 /* ------------------------------------------------------------------------- */
-/* Density matrix, Eq. (9):  D_ij = sum_{l: f_l > 0} f_l c_il c_jl.          */
+/* Density matrix, Eq. (9):  D_ij = sum_l f_l c_il c_jl over every state     */
+/* with f_l != 0 (Methfessel-Paxton occupations can be negative).            */
 /* C is n x k (column-major, ldc), D is n x n (ldd), both triangles written. */
 /* ------------------------------------------------------------------------- */
 void orc_density(int n, int k, const double *C, int ldc, const double *f, double *D, int ldd)
@@ -466,7 +600,7 @@ void orc_density(int n, int k, const double *C, int ldc, const double *f, double
         double *dcol = D + (size_t)j * ldd;
         for (int i = 0; i < n; ++i) dcol[i] = 0.0;
         for (int l = 0; l < k; ++l) {
-            if (!(f[l] > 0.0)) continue;
+            if (f[l] == 0.0) continue;
             const double *c = C + (size_t)l * ldc;
             double w = f[l] * c[j];
             for (int i = 0; i < n; ++i) dcol[i] += w * c[i];
@@ -486,18 +620,45 @@ double orc_band_energy(int n, const double *f, const double *eps)
 /* Density-matrix driver: eigensolve, occupations, D and energy.             */
 /* Returns 0 / 1 / 2 as orc_gevp, or 4 when the bisection ran out of steps.  */
 /* ------------------------------------------------------------------------- */
-int orc_dm(int n, double *H, int ldh, double *S, int lds, double n_electron, double kT,
-           double spin, double occ_accuracy, int max_steps, double *D, int ldd,
-           double *eval, double *occ, double *energy, double *mu, int *fail_col)
+int orc_dm_scheme(int n, double *H, int ldh, double *S, int lds, int scheme, double n_electron, double kT,
+                  double spin, double occ_accuracy, int max_steps, double *D, int ldd,
+                  double *eval, double *occ, double *energy, double *mu, int *fail_col)
 {
     double *C = (double *)malloc(sizeof(double) * (size_t)n * n);
     int st = orc_gevp(n, n, H, ldh, S, lds, eval, C, fail_col);
     if (st) { free(C); return st; }
-    st = orc_occupations(n, eval, n_electron, kT, spin, occ_accuracy, max_steps, occ, mu);
+    st = orc_occupations_scheme(n, eval, NULL, scheme, n_electron, kT, spin, occ_accuracy, max_steps, occ, mu);
     orc_density(n, n, C, n, occ, D, ldd);
     *energy = orc_band_energy(n, occ, eval);
     free(C);
     return st;
+}
+
+/* Density matrix with the singularity check (Eq. (20)): the occupations and  */
+/* D run over the n_nonsing states of orc_gevp_checked.                       */
+int orc_dm_checked(int n, double *H, int ldh, double *S, int lds, double tau, int scheme, double n_electron,
+                   double kT, double spin, double occ_accuracy, int max_steps, double *D, int ldd, double *eval,
+                   double *occ, double *energy, double *mu, int *n_nonsing, int *fail_col)
+{
+    double *C = (double *)malloc(sizeof(double) * (size_t)n * n);
+    int m = n;
+    int st = orc_gevp_checked(n, n, H, ldh, S, lds, tau, eval, C, &m, fail_col);
+    if (st) { free(C); return st; }
+    if (n_nonsing) *n_nonsing = m;
+    for (int l = 0; l < n; ++l) occ[l] = 0.0;
+    st = orc_occupations_scheme(m, eval, NULL, scheme, n_electron, kT, spin, occ_accuracy, max_steps, occ, mu);
+    orc_density(n, m, C, n, occ, D, ldd);
+    *energy = orc_band_energy(m, occ, eval);
+    free(C);
+    return st;
+}
+
+int orc_dm(int n, double *H, int ldh, double *S, int lds, double n_electron, double kT,
+           double spin, double occ_accuracy, int max_steps, double *D, int ldd,
+           double *eval, double *occ, double *energy, double *mu, int *fail_col)
+{
+    return orc_dm_scheme(n, H, ldh, S, lds, 1, n_electron, kT, spin, occ_accuracy, max_steps, D, ldd, eval, occ,
+                         energy, mu, fail_col);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -525,70 +686,186 @@ void orc_residual_norms(int n, int k, const double *H, int ldh, const double *S,
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* (T - shift I) x = b for the symmetric tridiagonal T = tridiag(e, d, e)    */
+/* (d: n, e: n-1) by Gaussian elimination with partial (row) pivoting: at    */
+/* step k the row with the larger |entry| in column k (the current row on a  */
+/* tie) becomes the pivot row, so U has at most two superdiagonals.  A pivot */
+/* that is exactly zero is replaced by DBL_EPSILON times the largest row sum */
+/* of |T - shift I|, the usual guard of inverse iteration.                   */
+/* ------------------------------------------------------------------------- */
+void orc_tridiag_shift_solve(int n, const double *d, const double *e, double shift, const double *b,
+                             double *x)
+{
+    if (n <= 0) return;
+    double *u0 = (double *)malloc(sizeof(double) * n);
+    double *u1 = (double *)malloc(sizeof(double) * n);
+    double *u2 = (double *)malloc(sizeof(double) * n);
+    double *y = (double *)malloc(sizeof(double) * n);
+    double tnorm = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double r = fabs(d[i] - shift);
+        if (i > 0) r += fabs(e[i - 1]);
+        if (i + 1 < n) r += fabs(e[i]);
+        if (r > tnorm) tnorm = r;
+        y[i] = b[i];
+    }
+    double tiny = DBL_EPSILON * tnorm;
+    if (tiny == 0.0) tiny = DBL_MIN;
+    double p = d[0] - shift;                 /* current row: (p, q) in columns k, k+1 */
+    double q = (n > 1) ? e[0] : 0.0;
+    for (int k = 0; k + 1 < n; ++k) {
+        const double a = e[k];               /* row k+1: (a, bb, c) in columns k, k+1, k+2 */
+        const double bb = d[k + 1] - shift;
+        const double c = (k + 2 < n) ? e[k + 1] : 0.0;
+        if (fabs(p) >= fabs(a)) {
+            if (p == 0.0) p = tiny;
+            const double m = a / p;
+            u0[k] = p; u1[k] = q; u2[k] = 0.0;
+            y[k + 1] -= m * y[k];
+            p = bb - m * q;
+            q = c;
+        } else {
+            const double m = p / a;
+            u0[k] = a; u1[k] = bb; u2[k] = c;
+            const double yk = y[k], yk1 = y[k + 1];
+            y[k] = yk1;
+            y[k + 1] = yk - m * yk1;
+            const double pn = q - m * bb;
+            q = -m * c;
+            p = pn;
+        }
+    }
+    if (p == 0.0) p = tiny;
+    u0[n - 1] = p; u1[n - 1] = 0.0; u2[n - 1] = 0.0;
+    for (int k = n - 1; k >= 0; --k) {
+        double t = y[k];
+        if (k + 1 < n) t -= u1[k] * x[k + 1];
+        if (k + 2 < n) t -= u2[k] * x[k + 2];
+        x[k] = t / u0[k];
+    }
+    free(u0); free(u1); free(u2); free(y);
+}
+
+/* X <- X L_G^-T with G = X^T X = L_G L_G^T (CholeskyQR), twice.  Returns 0, */
+/* or 1 when a Gram matrix is not positive definite (X untouched then, or    */
+/* after the first pass).                                                    */
+static int cholesky_qr2(int n, int k, double *X, int ldx, double *G)
+{
+    for (int pass = 0; pass < 2; ++pass) {
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i < k; ++i) {
+                double t = 0.0;
+                for (int r = 0; r < n; ++r) t += X[IDX(r, i, ldx)] * X[IDX(r, j, ldx)];
+                G[IDX(i, j, k)] = t;
+            }
+        if (orc_potrf(k, G, k)) return 1;
+#pragma omp parallel for schedule(static)
+        for (int r = 0; r < n; ++r) {
+            double *row = (double *)malloc(sizeof(double) * k);
+            for (int j = 0; j < k; ++j) row[j] = X[IDX(r, j, ldx)];
+            fwd_subst(k, G, k, row);   /* L_G y = x^T  <=>  y^T = x L_G^-T */
+            for (int j = 0; j < k; ++j) X[IDX(r, j, ldx)] = row[j];
+            free(row);
+        }
+    }
+    return 0;
+}
+
 /* ========================================================================= */
 /* FP64 refinement of an approximate invariant subspace of the standard-form */
 /* matrix H~ = L^-1 H L^-T (Eq. (11)): the last stage of the GPU library's   */
 /* mixed-precision mode (the paper's solvers run in one precision, so this   */
-/* stage has no passage of its own; each step below is the textbook          */
-/* definition).  X is n x k (ldx); on return it holds the refined vectors.    */
-/* One sweep:                                                                */
-/*   CholeskyQR, twice: G = X^T X = L_G L_G^T, X <- X L_G^-T (row by row,     */
-/*   forward substitution with L_G);                                         */
-/*   Rayleigh-Ritz: A = X^T H~ X, A = Q diag(theta) Q^T (orc_gevp with S = I),*/
-/*   X <- X Q;                                                               */
-/*   residuals res_l = ||H~ x_l - theta_l x_l||_2, from the definition.      */
-/* The first kw states decide: stop with 0 when max res_l <= tol; otherwise  */
-/* stop with 3 after that sweep (its Rayleigh-Ritz step leaves the subspace   */
-/* unchanged, so a further sweep cannot lower the residual), and with 3 when  */
-/* G is not positive definite (dependent columns) or max_sweeps is 0.         */
+/* stage has no passage of its own).  X is n x k (ldx), approximating the    */
+/* invariant subspace of the k lowest eigenvalues; on return it holds the    */
+/* refined vectors.                                                          */
+/*                                                                           */
+/* Each sweep:                                                               */
+/*   (1) CholeskyQR twice: G = X^T X = L_G L_G^T, X <- X L_G^-T;             */
+/*   (2) Rayleigh-Ritz: A = X^T H~ X = W diag(theta) W^T (orc_gevp, S = I),  */
+/*       X <- X W;                                                           */
+/*   (3) residuals r_l = H~ x_l - theta_l x_l, res_l = ||r_l||_2.            */
+/* Rayleigh-Ritz picks the best vectors inside span(X) but never moves that  */
+/* span, so without more information one sweep is all that can be done: the */
+/* call then ends with 0 when max res_l <= tol over the first kw states, 3   */
+/* otherwise (Qp == NULL).                                                   */
+/*                                                                           */
+/* With an approximate factorization H~ ~ Qp T Qp^T (Qp n x n orthogonal,   */
+/* T = tridiag(eT, dT, eT); in the mixed mode these are the reduced-         */
+/* precision reduction's own Q1 Q2 and T) each sweep also forms the Newton   */
+/* correction of the subspace: with Z the eigenvectors of T for its k lowest */
+/* eigenvalues (computed here by QL) and P = I - Z Z^T,                      */
+/*   (4) y_l = -P (T - theta_l I)^-1 P Qp^T r_l,   step_l = ||y_l||_2;        */
+/* this solves the correction equation (H~ - theta_l) d_l = -r_l on the      */
+/* complement of the subspace with T standing in for Qp^T H~ Qp, so it       */
+/* removes the subspace's error up to the factorization's error over the     */
+/* gap between theta_l and the complement's spectrum.  Unless it was the     */
+/* last allowed sweep (status 3, X as that sweep's Rayleigh-Ritz left it),   */
+/* X_l += Qp y_l for every l with step_l <= 1/2 (a larger step lies outside  */
+/* the region where the linear model holds and is not taken) and the next    */
+/* sweep starts.  When the largest weighted step max_{l<kw} w_l step_l was   */
+/* <= tol (weight NULL: w_l = 1), that step is still taken and the next      */
+/* sweep, steps (1)-(3) only, closes the call with 0: the error left is then */
+/* the step's own error, of the order of the contraction rate times tol      */
+/* (the untaken step itself would be amplified by L^-T in c = L^-T x).       */
+/* Dependent columns (G not positive definite)                               */
+/* end the call with 3 and leave X as the last completed sweep left it.      */
+/* step (k, may be NULL) receives the last computed steps (0 without Qp).    */
 /* ========================================================================= */
-int orc_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int ldx, double *theta,
-               double *res, double tol, int max_sweeps, int *sweeps)
+int orc_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int ldx, const double *Qp,
+               int ldq, const double *dT, const double *eT, const double *weight, double *theta, double *res,
+               double *step, double tol, int max_sweeps, int *sweeps)
 {
     if (sweeps) *sweeps = 0;
     if (n <= 0 || k <= 0) return 0;
     if (kw > k) kw = k;
+    if (kw < 0) kw = 0;
     double *G = (double *)malloc(sizeof(double) * (size_t)k * k);
     double *I = (double *)malloc(sizeof(double) * (size_t)k * k);
-    double *Q = (double *)malloc(sizeof(double) * (size_t)k * k);
+    double *Wq = (double *)malloc(sizeof(double) * (size_t)k * k);
+    double *Xs = (double *)malloc(sizeof(double) * (size_t)n * k);
+    double *R = (double *)malloc(sizeof(double) * (size_t)n * k);
     double *Y = (double *)malloc(sizeof(double) * (size_t)n * k);
-    int status = 3;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        int bad = 0;
-        for (int pass = 0; pass < 2 && !bad; ++pass) {
-#pragma omp parallel for schedule(static)
-            for (int j = 0; j < k; ++j)
-                for (int i = 0; i < k; ++i) {
-                    double t = 0.0;
-                    for (int r = 0; r < n; ++r) t += X[IDX(r, i, ldx)] * X[IDX(r, j, ldx)];
-                    G[IDX(i, j, k)] = t;
-                }
-            if (orc_potrf(k, G, k)) { bad = 1; break; }
-#pragma omp parallel for schedule(static)
-            for (int r = 0; r < n; ++r) {
-                double *row = (double *)malloc(sizeof(double) * k);
-                for (int j = 0; j < k; ++j) row[j] = X[IDX(r, j, ldx)];
-                fwd_subst(k, G, k, row);   /* L_G y = x^T  <=>  y^T = x L_G^-T */
-                for (int j = 0; j < k; ++j) X[IDX(r, j, ldx)] = row[j];
-                free(row);
-            }
+    double *stp = (double *)malloc(sizeof(double) * (size_t)k);
+    double *Z = NULL;
+    for (int j = 0; j < k; ++j) if (step) step[j] = 0.0;
+    if (Qp) {
+        /* Z: eigenvectors of T for its k lowest eigenvalues */
+        double *dd = (double *)malloc(sizeof(double) * n);
+        double *ee = (double *)malloc(sizeof(double) * n);
+        double *wt = (double *)malloc(sizeof(double) * n);
+        double *Zt = (double *)malloc(sizeof(double) * (size_t)n * n);
+        for (int i = 0; i < n; ++i) { dd[i] = dT[i]; ee[i] = (i + 1 < n) ? eT[i] : 0.0; }
+        int st = orc_tridiag_eig(n, dd, ee, wt, Zt);
+        if (!st) {
+            Z = (double *)malloc(sizeof(double) * (size_t)n * k);
+            memcpy(Z, Zt, sizeof(double) * (size_t)n * k);
         }
-        if (bad) { status = 3; break; }
-        /* A = X^T (H~ X), lower triangle of H~ read */
+        free(dd); free(ee); free(wt); free(Zt);
+        if (st) { free(G); free(I); free(Wq); free(Xs); free(R); free(Y); free(stp); return 3; }
+    }
+    int status = 3, finishing = 0;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        /* (1) orthonormalize a copy, so that a failure leaves X as it was */
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i < n; ++i) Xs[IDX(i, j, n)] = X[IDX(i, j, ldx)];
+        if (cholesky_qr2(n, k, Xs, n, G)) { status = 3; break; }
+        /* (2) A = X^T (H~ X), lower triangle of H~ read */
 #pragma omp parallel for schedule(static)
         for (int j = 0; j < k; ++j)
             for (int i = 0; i < n; ++i) {
                 double t = 0.0;
                 for (int c = 0; c < n; ++c) {
                     const double h = (i >= c) ? Ht[IDX(i, c, ldh)] : Ht[IDX(c, i, ldh)];
-                    t += h * X[IDX(c, j, ldx)];
+                    t += h * Xs[IDX(c, j, n)];
                 }
                 Y[IDX(i, j, n)] = t;
             }
         for (int j = 0; j < k; ++j)
             for (int i = 0; i < k; ++i) {
                 double t = 0.0;
-                for (int r = 0; r < n; ++r) t += X[IDX(r, i, ldx)] * Y[IDX(r, j, n)];
+                for (int r = 0; r < n; ++r) t += Xs[IDX(r, i, n)] * Y[IDX(r, j, n)];
                 G[IDX(i, j, k)] = t;
             }
         for (int j = 0; j < k; ++j)
@@ -599,20 +876,16 @@ int orc_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int l
             }
         for (int j = 0; j < k; ++j)
             for (int i = 0; i < k; ++i) I[IDX(i, j, k)] = (i == j) ? 1.0 : 0.0;
-        if (orc_gevp(k, k, G, k, I, k, theta, Q, NULL)) { status = 3; break; }
-        /* X <- X Q */
+        if (orc_gevp(k, k, G, k, I, k, theta, Wq, NULL)) { status = 3; break; }
+        /* X <- X W */
 #pragma omp parallel for schedule(static)
-        for (int r = 0; r < n; ++r) {
-            double *row = (double *)malloc(sizeof(double) * k);
+        for (int r = 0; r < n; ++r)
             for (int j = 0; j < k; ++j) {
                 double t = 0.0;
-                for (int c = 0; c < k; ++c) t += X[IDX(r, c, ldx)] * Q[IDX(c, j, k)];
-                row[j] = t;
+                for (int c = 0; c < k; ++c) t += Xs[IDX(r, c, n)] * Wq[IDX(c, j, k)];
+                X[IDX(r, j, ldx)] = t;
             }
-            for (int j = 0; j < k; ++j) X[IDX(r, j, ldx)] = row[j];
-            free(row);
-        }
-        /* res_l = || H~ x_l - theta_l x_l || */
+        /* (3) r_l = H~ x_l - theta_l x_l from the definition */
 #pragma omp parallel for schedule(static)
         for (int j = 0; j < k; ++j) {
             double acc = 0.0;
@@ -622,17 +895,77 @@ int orc_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int l
                     const double h = (i >= c) ? Ht[IDX(i, c, ldh)] : Ht[IDX(c, i, ldh)];
                     t += h * X[IDX(c, j, ldx)];
                 }
+                R[IDX(i, j, n)] = t;
                 acc += t * t;
             }
             res[j] = sqrt(acc);
         }
         if (sweeps) *sweeps = sweep + 1;
-        double rmax = 0.0;
-        for (int l = 0; l < kw; ++l) if (res[l] > rmax) rmax = res[l];
-        status = (rmax <= tol) ? 0 : 3;
-        break;
+        if (finishing) { status = 0; break; }   /* the closing Rayleigh-Ritz sweep */
+        if (!Qp) {
+            double rmax = 0.0;
+            for (int l = 0; l < kw; ++l) if (res[l] > rmax) rmax = res[l];
+            status = (rmax <= tol) ? 0 : 3;
+            break;
+        }
+        /* (4) y_l = -P (T - theta_l)^-1 P Qp^T r_l */
+#pragma omp parallel for schedule(dynamic)
+        for (int j = 0; j < k; ++j) {
+            double *rho = (double *)malloc(sizeof(double) * n);
+            double *yv = (double *)malloc(sizeof(double) * n);
+            double *cz = (double *)malloc(sizeof(double) * k);
+            for (int i = 0; i < n; ++i) {
+                double t = 0.0;
+                for (int r = 0; r < n; ++r) t += Qp[IDX(r, i, ldq)] * R[IDX(r, j, n)];
+                rho[i] = -t;
+            }
+            for (int c = 0; c < k; ++c) {
+                double t = 0.0;
+                for (int i = 0; i < n; ++i) t += Z[IDX(i, c, n)] * rho[i];
+                cz[c] = t;
+            }
+            for (int i = 0; i < n; ++i) {
+                double t = rho[i];
+                for (int c = 0; c < k; ++c) t -= Z[IDX(i, c, n)] * cz[c];
+                rho[i] = t;
+            }
+            orc_tridiag_shift_solve(n, dT, eT, theta[j], rho, yv);
+            for (int c = 0; c < k; ++c) {
+                double t = 0.0;
+                for (int i = 0; i < n; ++i) t += Z[IDX(i, c, n)] * yv[i];
+                cz[c] = t;
+            }
+            double nrm = 0.0;
+            for (int i = 0; i < n; ++i) {
+                double t = yv[i];
+                for (int c = 0; c < k; ++c) t -= Z[IDX(i, c, n)] * cz[c];
+                Y[IDX(i, j, n)] = t;
+                nrm += t * t;
+            }
+            stp[j] = sqrt(nrm);
+            free(rho); free(yv); free(cz);
+        }
+        double worst = 0.0;
+        for (int l = 0; l < k; ++l) {
+            if (step) step[l] = stp[l];
+            if (l < kw) {
+                const double w = weight ? weight[l] : 1.0;
+                if (w * stp[l] > worst) worst = w * stp[l];
+            }
+        }
+        if (sweep == max_sweeps - 1) { status = 3; break; }
+        if (worst <= tol) finishing = 1;        /* take this last step, then one closing sweep */
+        /* X_l += Qp y_l for the steps inside the linear region */
+#pragma omp parallel for schedule(static)
+        for (int r = 0; r < n; ++r)
+            for (int j = 0; j < k; ++j) {
+                if (!(stp[j] <= 0.5)) continue;
+                double t = 0.0;
+                for (int c = 0; c < n; ++c) t += Qp[IDX(r, c, ldq)] * Y[IDX(c, j, n)];
+                X[IDX(r, j, ldx)] += t;
+            }
     }
-    free(G); free(I); free(Q); free(Y);
+    free(G); free(I); free(Wq); free(Xs); free(R); free(Y); free(stp); free(Z);
     return status;
 }
 
@@ -883,7 +1216,7 @@ void orc_zdensity(int n, int k, const zc *C, int ldc, const double *f, zc *D, in
         zc *dcol = D + (size_t)j * ldd;
         for (int i = 0; i < n; ++i) dcol[i] = 0.0;
         for (int l = 0; l < k; ++l) {
-            if (!(f[l] > 0.0)) continue;
+            if (f[l] == 0.0) continue;
             const zc *c = C + (size_t)l * ldc;
             zc w = f[l] * conj(c[j]);
             for (int i = 0; i < n; ++i) dcol[i] += c[i] * w;

@@ -51,8 +51,16 @@ def _load():
         lib.orc_band_energy.argtypes = [i, _dp, _dp]
         lib.orc_band_energy.restype = d
         lib.orc_dm.argtypes = [i, _dp, i, _dp, i, d, d, d, d, i, _dp, i, _dp, _dp, _dp, _dp, _ip]
+        lib.orc_dm_scheme.argtypes = [i, _dp, i, _dp, i, i, d, d, d, d, i, _dp, i, _dp, _dp, _dp, _dp, _ip]
+        lib.orc_gevp_checked.argtypes = [i, i, _dp, i, _dp, i, d, _dp, _dp, _ip, _ip]
+        lib.orc_dm_checked.argtypes = [i, _dp, i, _dp, i, d, i, d, d, d, d, i, _dp, i, _dp, _dp, _dp, _dp, _ip,
+                                       _ip]
+        lib.orc_occupations_scheme.argtypes = [i, _dp, _dp, i, d, d, d, d, i, _dp, _dp]
+        lib.orc_occupation_value.argtypes = [i, d, d, d, d]
+        lib.orc_occupation_value.restype = d
         lib.orc_residual_norms.argtypes = [i, i, _dp, i, _dp, i, _dp, i, _dp, _dp]
-        lib.orc_refine.argtypes = [i, i, i, _dp, i, _dp, i, _dp, _dp, d, i, _ip]
+        lib.orc_refine.argtypes = [i, i, i, _dp, i, _dp, i, _dp, i, _dp, _dp, _dp, _dp, _dp, _dp, d, i, _ip]
+        lib.orc_tridiag_shift_solve.argtypes = [i, _dp, _dp, d, _dp, _dp]
         lib.orc_zpotrf.argtypes = [i, _dp, i]
         lib.orc_zreduce.argtypes = [i, _dp, i, _dp, i]
         lib.orc_ztred.argtypes = [i, _dp, i, _dp, _dp, _dp, i]
@@ -164,15 +172,28 @@ def gevp(H, S, n_state=None):
     return ev, C[:, :k], Sf
 
 
-def occupations(eps, n_electron, kT, spin=1.0, occ_accuracy=1e-13, max_steps=100):
-    """Fermi-Dirac occupations (Eq. (17)) with mu from Eq. (18); returns (f, mu, status)."""
+FERMI, GAUSSIAN, MP0, MP1 = 1, 2, 3, 4   # broadening schemes (Sec. 4.6 broadening_scheme)
+
+
+def occupations(eps, n_electron, kT, spin=1.0, occ_accuracy=1e-13, max_steps=100, scheme=FERMI, weight=None):
+    """Occupations of a broadening scheme (Fermi-Dirac Eq. (17), Gaussian Eq. (21),
+    Methfessel-Paxton orders 0 and 1) with mu from Eq. (18); weight: per-state
+    weights (k-points / spin channels sharing one mu), f_l = w_l f(eps_l).
+    Returns (f, mu, status)."""
     e = _f64(eps)
     n = e.shape[0]
     f = np.zeros(n)
     mu = ctypes.c_double(0.0)
-    st = _load().orc_occupations(n, _p(e), float(n_electron), float(kT), float(spin),
-                                 float(occ_accuracy), int(max_steps), _p(f), ctypes.byref(mu))
+    w = _f64(weight) if weight is not None else None
+    st = _load().orc_occupations_scheme(n, _p(e), _p(w) if w is not None else ctypes.POINTER(ctypes.c_double)(),
+                                        int(scheme), float(n_electron), float(kT), float(spin),
+                                        float(occ_accuracy), int(max_steps), _p(f), ctypes.byref(mu))
     return f, mu.value, st
+
+
+def occupation_value(scheme, eps, mu, width, spin=1.0):
+    """The occupation of one state at eps for chemical potential mu."""
+    return float(_load().orc_occupation_value(int(scheme), float(eps), float(mu), float(width), float(spin)))
 
 
 def density(C, f):
@@ -191,7 +212,7 @@ def band_energy(f, eps):
     return float(_load().orc_band_energy(ff.shape[0], _p(ff), _p(e)))
 
 
-def dm(H, S, n_electron, kT, spin=1.0, occ_accuracy=1e-13, max_steps=100):
+def dm(H, S, n_electron, kT, spin=1.0, occ_accuracy=1e-13, max_steps=100, scheme=FERMI):
     """Density-matrix driver: returns dict(D, eval, occ, energy, mu, status)."""
     Hf = _f64(H)
     Sf = _f64(S)
@@ -202,9 +223,9 @@ def dm(H, S, n_electron, kT, spin=1.0, occ_accuracy=1e-13, max_steps=100):
     energy = ctypes.c_double(0.0)
     mu = ctypes.c_double(0.0)
     fail = ctypes.c_int(0)
-    st = _load().orc_dm(n, _p(Hf), n, _p(Sf), n, float(n_electron), float(kT), float(spin),
-                        float(occ_accuracy), int(max_steps), _p(D), n, _p(ev), _p(occ),
-                        ctypes.byref(energy), ctypes.byref(mu), ctypes.byref(fail))
+    st = _load().orc_dm_scheme(n, _p(Hf), n, _p(Sf), n, int(scheme), float(n_electron), float(kT), float(spin),
+                               float(occ_accuracy), int(max_steps), _p(D), n, _p(ev), _p(occ),
+                               ctypes.byref(energy), ctypes.byref(mu), ctypes.byref(fail))
     if st in (1, 2):
         raise OracleError(st, "eigensolve failed")
     return dict(D=D, eval=ev, occ=occ, energy=energy.value, mu=mu.value, status=st, L=Sf)
@@ -226,19 +247,40 @@ def residual_norms(H, S, X, lam):
 # complex Hermitian path (complex128 arrays; the C side reads them as
 # interleaved real/imaginary doubles)
 # ---------------------------------------------------------------------------
-def refine(Ht, X, kw, tol=1e-10, max_sweeps=4):
-    """FP64 refinement sweeps of the subspace X (n x k) of the symmetric Ht
-    (CholeskyQR twice, Rayleigh-Ritz, residual norms); returns
-    (X_refined, theta, res, sweeps, status) with status 0 or 3."""
+def refine(Ht, X, kw, tol=1e-10, max_sweeps=4, Q=None, d=None, e=None, weight=None):
+    """FP64 refinement sweeps of the subspace X (n x k) of the symmetric Ht:
+    CholeskyQR twice, Rayleigh-Ritz, residuals and, given an approximate
+    factorization Ht ~ Q T Q^T (Q orthogonal n x n, T = tridiag(e, d, e)),
+    the Newton correction through it.  Returns
+    (X_refined, theta, res, step, sweeps, status) with status 0 or 3."""
     A = _f64(Ht)
     Xr = _f64(X).copy(order="F")
     n, k = Xr.shape
     theta = np.zeros(max(k, 1))
     res = np.zeros(max(k, 1))
+    step = np.zeros(max(k, 1))
     sw = ctypes.c_int(0)
-    st = _load().orc_refine(n, k, int(kw), _p(A), n, _p(Xr), n, _p(theta), _p(res), float(tol),
-                            int(max_sweeps), ctypes.byref(sw))
-    return Xr, theta[:k], res[:k], sw.value, st
+    null = ctypes.POINTER(ctypes.c_double)()
+    if Q is not None:
+        Qf, df, ef = _f64(Q), _f64(d), _f64(np.append(np.asarray(e, dtype=float), 0.0))
+        qargs = (_p(Qf), n, _p(df), _p(ef))
+    else:
+        qargs = (null, 1, null, null)
+    wf = _f64(weight) if weight is not None else None
+    st = _load().orc_refine(n, k, int(kw), _p(A), n, _p(Xr), n, *qargs, _p(wf) if wf is not None else null,
+                            _p(theta), _p(res), _p(step), float(tol), int(max_sweeps), ctypes.byref(sw))
+    return Xr, theta[:k], res[:k], step[:k], sw.value, st
+
+
+def tridiag_shift_solve(d, e, shift, b):
+    """x with (T - shift I) x = b, T = tridiag(e, d, e), by Gaussian elimination
+    with partial pivoting."""
+    df = _f64(d)
+    ef = _f64(np.append(np.asarray(e, dtype=float), 0.0))
+    bf = _f64(b)
+    x = np.zeros_like(bf)
+    _load().orc_tridiag_shift_solve(len(df), _p(df), _p(ef), float(shift), _p(bf), _p(x))
+    return x
 
 
 def zpotrf(S):
@@ -315,3 +357,72 @@ def zdm(H, S, n_electron, kT, spin=1.0, occ_accuracy=1e-13, max_steps=100):
     if st in (1, 2):
         raise OracleError(st, "eigensolve failed")
     return dict(D=D, eval=ev, occ=occ, energy=energy.value, mu=mu.value, status=st, L=Sf)
+
+
+def dm_shared_mu(Hs, Ss, n_electrons, weights, kT, spin=1.0, occ_accuracy=1e-13, max_steps=100, scheme=FERMI):
+    """Density matrices of several problems (k-points / spin channels of one
+    system) with one chemical potential (Sec. 4.5, the electron count summed
+    over k-points and spin channels): every problem's eigenpairs, then mu over
+    all states with each state weighted by its problem's weight and
+    N_e = sum_p w_p n_electron_p, then D_p = sum_l f_pl c_pl c_pl^H with the
+    weighted occupations f_pl.  Complex (complex128) inputs take the complex
+    path.  Returns a list of dict(D, eval, occ, energy) and mu."""
+    evs, Cs = [], []
+    for H, S in zip(Hs, Ss):
+        if np.iscomplexobj(H) or np.iscomplexobj(S):
+            ev, C, _ = zgevp(H, S)
+        else:
+            ev, C, _ = gevp(H, S)
+        evs.append(ev)
+        Cs.append(C)
+    w = np.concatenate([np.full(len(ev), float(wp)) for ev, wp in zip(evs, weights)])
+    ne = float(sum(float(wp) * float(n) for wp, n in zip(weights, n_electrons)))
+    f, mu, st = occupations(np.concatenate(evs), ne, kT, spin=spin, occ_accuracy=occ_accuracy,
+                            max_steps=max_steps, scheme=scheme, weight=w)
+    out, o = [], 0
+    for ev, C in zip(evs, Cs):
+        fp = f[o:o + len(ev)]
+        o += len(ev)
+        D = zdensity(C, fp) if np.iscomplexobj(C) else density(C, fp)
+        out.append(dict(D=D, eval=ev, occ=fp, energy=band_energy(fp, ev)))
+    return out, mu, st
+
+
+def gevp_checked(H, S, tau, n_state=None):
+    """Eigenpairs with the singularity check of the overlap (Eq. (20)): the
+    Cholesky route when every eigenvalue of S is >= tau, else the
+    eigendecomposition transform keeping the n_nonsing eigenvectors of S with
+    eigenvalues >= tau.  Returns (eval (n; +inf beyond n_nonsing), evec
+    (n x n_state), S_out (L or X), n_nonsing)."""
+    Hf, Sf = _f64(H), _f64(S)
+    n = Hf.shape[0]
+    k = n if n_state is None else int(n_state)
+    ev = np.zeros(n)
+    C = np.zeros((n, k), order="F")
+    m = ctypes.c_int(0)
+    fail = ctypes.c_int(0)
+    st = _load().orc_gevp_checked(n, k, _p(Hf), n, _p(Sf), n, float(tau), _p(ev), _p(C), ctypes.byref(m),
+                                  ctypes.byref(fail))
+    if st:
+        raise OracleError(st, "eigensolve failed")
+    return ev, C, Sf, m.value
+
+
+def dm_checked(H, S, n_electron, kT, tau, spin=1.0, occ_accuracy=1e-13, max_steps=100, scheme=FERMI):
+    """dm with the singularity check (Eq. (20)): returns dict(D, eval, occ,
+    energy, mu, status, S_out, n_nonsing)."""
+    Hf, Sf = _f64(H), _f64(S)
+    n = Hf.shape[0]
+    D = np.zeros((n, n), order="F")
+    ev = np.zeros(n)
+    occ = np.zeros(n)
+    energy = ctypes.c_double(0.0)
+    mu = ctypes.c_double(0.0)
+    m = ctypes.c_int(0)
+    fail = ctypes.c_int(0)
+    st = _load().orc_dm_checked(n, _p(Hf), n, _p(Sf), n, float(tau), int(scheme), float(n_electron), float(kT),
+                                float(spin), float(occ_accuracy), int(max_steps), _p(D), n, _p(ev), _p(occ),
+                                ctypes.byref(energy), ctypes.byref(mu), ctypes.byref(m), ctypes.byref(fail))
+    if st in (1, 2):
+        raise OracleError(st, "eigensolve failed")
+    return dict(D=D, eval=ev, occ=occ, energy=energy.value, mu=mu.value, status=st, S_out=Sf, n_nonsing=m.value)
