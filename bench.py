@@ -9,6 +9,11 @@ jittered-lattice Gaussian-basis system with N = 32768 basis functions,
 n_occ = 8192, kT = 0.01 Ha, seed 0 (synthetic, standing in for the paper's
 FHI-aims / DGDFT matrices).
 
+The same line carries a `mixed` object: the same dm timed with FP32
+matrix-core products in full -> band and Q1 followed by the FP64 refinement,
+with its status and its deviation from the FP64 result (the metric's
+comparison).
+
 Prints one JSON line: throughput in algorithmic TFLOP/s,
 F = 8/3 N^3 + 6 N^2 k_s (Cholesky N^3/3, reduction N^3, full -> band 4N^3/3,
 two back-transformations 2 N^2 k each, back substitution N^2 k, density
@@ -169,6 +174,18 @@ def _kernel_matches(full_name: str, short: str) -> bool:
     return full_name.replace(" ", "").find(short.replace(" ", "") + "(") >= 0
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first 'model name' line of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n_sample: int):
     """The CPU oracle (plain C, OpenMP) on a bounded sample of the same workload."""
     import numpy as np
@@ -186,6 +203,7 @@ def cpu_baseline(n_sample: int):
         "value": algorithmic_flops(n_sample, ks) / dt / 1e12,
         "unit": "TFLOP/s",
         "cores": cores,
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": (f"one oracle dm solve of the same 3D-lattice generator at N={n_sample} "
                    f"(n_occ={n_sample // 4}, k_s={ks}), {dt:.1f} s; rate = algorithmic flops / time"),
@@ -405,10 +423,15 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="batch workload: JSON cache of tuned band-width tables (default: $ELSI_GPU_TUNE_CACHE)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
-                    help="single workload: plain FP64, or FP32 matrix-core products in full -> band and Q1 "
+                    help="single workload: fp64 times plain FP64 (headline) and, unless --no-mixed, the mixed "
+                         "path beside it; mixed times only FP32 matrix-core products in full -> band and Q1 "
                          "followed by FP64 refinement")
     ap.add_argument("--refine-tol", type=float, default=1e-10)
-    ap.add_argument("--max-refine", type=int, default=4)
+    ap.add_argument("--max-refine", type=int, default=6)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="single workload: skip the FP32+refine run that the default line reports beside FP64")
+    ap.add_argument("--mixed-steps", type=int, default=1,
+                    help="single workload: timed steps of the FP32+refine run (after one warm-up)")
     args = ap.parse_args()
     if args.workload == "complex":
         if args.gpus != 1:
@@ -450,25 +473,6 @@ def main():
     D = torch.empty_like(H0)
     ev = torch.empty(n, device=dev, dtype=torch.float64)
     f = torch.empty(n, device=dev, dtype=torch.float64)
-    mixed = args.precision == "mixed"
-    ref64 = None
-    if mixed:
-        # untimed FP64 solve of the same input: the accuracy yardstick of the mixed path
-        h64 = B.Handle(n, n, n_occ)
-        h64.set_band_width(args.band)
-        H.copy_(H0)
-        S.copy_(S0)
-        D64, ev64, _, _, _, _ = h64.dm(H, S)
-        ref64 = (D64, ev64, h64.info()["k_s"])
-        h64.close()
-        torch.cuda.empty_cache()
-        print("[bench] FP64 reference solve done", file=sys.stderr, flush=True)
-    h = B.Handle(n, n, n_occ)
-    h.set_band_width(args.band)
-    if mixed:
-        h.set_precision(B.PREC_MIXED, args.refine_tol, args.max_refine)
-    ws = torch.empty(h.workspace_size() // 8 + 1, device=dev, dtype=torch.float64)
-    h.set_workspace(ws)
 
     if args.calibrate_copy:
         x = torch.ones(COPY_ELEMS, device=dev, dtype=torch.float64)
@@ -477,97 +481,164 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    last_status = [0]
+    def run_path(mixed: bool, steps: int, warmup: int, probe: bool):
+        """warmup + timed steps of one path on a fresh handle; then, when probe,
+        one more step with HIP events around every GEMM launch (a separate,
+        untimed pass, so the headline carries no probe overhead)."""
+        h = B.Handle(n, n, n_occ)
+        h.set_band_width(args.band)
+        if mixed:
+            h.set_precision(B.PREC_MIXED, args.refine_tol, args.max_refine)
+        ws = torch.empty(h.workspace_size() // 8 + 1, device=dev, dtype=torch.float64)
+        h.set_workspace(ws)
+        status = [0]
+        tag = "mixed" if mixed else "fp64"
 
-    def step():
-        H.copy_(H0)
-        S.copy_(S0)
-        r = h.dm(H, S, occ=f, D_out=D, eval_out=ev, ok=(0, 3) if mixed else (0,))
-        last_status[0] = r[5]
-        return r
+        def step():
+            H.copy_(H0)
+            S.copy_(S0)
+            r = h.dm(H, S, occ=f, D_out=D, eval_out=ev, ok=(0, 3) if mixed else (0,))
+            status[0] = r[5]
+            return r
 
-    for w in range(args.warmup):
-        step()
-        print(f"[bench] warmup {w} done: {h.info()['total_ms']:.1f} ms", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    h.set_launch_timing(True)   # HIP events around each GEMM launch, on the library's stream
-    t0 = time.perf_counter()
-    stage_ms = None
-    for k in range(args.steps):
-        step()
-        inf = h.info()
-        print(f"[bench] step {k}: {inf['total_ms']:.1f} ms", file=sys.stderr, flush=True)
-        if stage_ms is None:
-            stage_ms = {s: 0.0 for s in inf["stage_ms"]}
-        for s, v in inf["stage_ms"].items():
-            stage_ms[s] += v / args.steps
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    info = h.info()
-    h.set_launch_timing(False)
-    ks = info["k_s"]
-    F = algorithmic_flops(n, ks)
-    value = F / (ms / 1e3) / 1e12
-    kname = info["probe_kernel"]
-    launches = max(info["probe_launches"], 1)
-    achieved = info["probe_flops"] / (info["probe_ms"] * 1e-3) / 1e12 if info["probe_ms"] > 0 else 0.0
-    roofline = {
-        "bound": "mfma",
-        "achieved": achieved,
-        "peak": FP64_PEAK_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": achieved / FP64_PEAK_TFLOPS,
-        "traffic": load_traffic(kname, wl["name"]),
-        "kernel": kname,
-        "launches_per_step": info["probe_launches"] / args.steps,
-        "avg_launch_ms": info["probe_ms"] / launches,
-        "flops_per_launch": info["probe_flops"] / launches,
-    }
-    # quick invariants on the last step: tr(D S) = N_e, ascending eigenvalues
-    trace_ds = float((D * S0).sum().item())
-    ascending = bool(torch.all(ev[1:] >= ev[:-1]).item())
+        for w in range(warmup):
+            step()
+            print(f"[bench] {tag} warmup {w} done: {h.info()['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stage_ms = None
+        for k in range(steps):
+            step()
+            inf = h.info()
+            print(f"[bench] {tag} step {k}: {inf['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+            if stage_ms is None:
+                stage_ms = {st: 0.0 for st in inf["stage_ms"]}
+            for st, v in inf["stage_ms"].items():
+                stage_ms[st] += v / steps
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        info = h.info()
+        probe_info = None
+        if probe:
+            h.set_launch_timing(True)   # HIP events around each GEMM launch, on the library's stream
+            step()
+            probe_info = h.info()
+            h.set_launch_timing(False)
+            print(f"[bench] {tag} probe step: {probe_info['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+        h.close()
+        del ws
+        return ms, stage_ms, info, probe_info, status[0]
 
-    refine = None
-    if mixed:
+    mixed_only = args.precision == "mixed"
+    out = None
+    ref64 = None
+    if not mixed_only:
+        ms, stage_ms, info, pinfo, _ = run_path(False, args.steps, args.warmup, probe=True)
+        ks = info["k_s"]
+        F = algorithmic_flops(n, ks)
+        value = F / (ms / 1e3) / 1e12
+        kname = pinfo["probe_kernel"]
+        launches = max(pinfo["probe_launches"], 1)
+        achieved = pinfo["probe_flops"] / (pinfo["probe_ms"] * 1e-3) / 1e12 if pinfo["probe_ms"] > 0 else 0.0
+        roofline = {
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": load_traffic(kname, wl["name"]),
+            "kernel": kname,
+            "launches_per_step": pinfo["probe_launches"],
+            "avg_launch_ms": pinfo["probe_ms"] / launches,
+            "flops_per_launch": pinfo["probe_flops"] / launches,
+            "measured": "HIP events around every launch of the kernel on the library's stream, over one step "
+                        "run after the timed steps",
+        }
+        # quick invariants on the last step: tr(D S) = N_e, ascending eigenvalues
+        trace_ds = float((D * S0).sum().item())
+        ascending = bool(torch.all(ev[1:] >= ev[:-1]).item())
+        out = {
+            "metric": METRIC,
+            "value": value,
+            "unit": "TFLOP/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": ms,
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": wl["name"], "n_basis": n, "n_occ": int(n_occ), "kT_Ha": spec.kT,
+                       "kappa_S": spec.meta["kappa"], "band_width": info["band_width"], "k_s": ks,
+                       "path": "plain_fp64"},
+            "roofline": roofline,
+            "algorithmic_flops": F,
+            "stage_ms": stage_ms,
+            "stage_roofline": stage_roofline(stage_ms, n, ks, info["band_width"], False),
+            "checks": {"trace_DS_minus_Ne": trace_ds - n_occ, "eigenvalues_ascending": ascending,
+                       "mu_Ha": info["mu"]},
+        }
+    if not args.no_mixed:
+        if out is not None:
+            ref64 = (D.clone(), ev.clone(), out["config"]["k_s"])
+        else:
+            # untimed FP64 solve of the same input: the accuracy yardstick of the mixed path
+            _, _, info64, _, _ = run_path(False, 1, 0, probe=False)
+            ref64 = (D.clone(), ev.clone(), info64["k_s"])
+        torch.cuda.empty_cache()
+        msteps = args.steps if mixed_only else args.mixed_steps
+        ms_m, stage_m, info_m, _, st_m = run_path(True, msteps, args.warmup if mixed_only else 1, probe=False)
         D64, ev64, ks64 = ref64
-        kk = min(ks, ks64)
-        refine = {"status": last_status[0], "sweeps": info["refine_sweeps"], "states": info["refine_states"],
-                  "resid_Ha": info["refine_resid"], "tol_Ha": args.refine_tol,
-                  "max_abs_dD_vs_fp64": float((D - D64).abs().max().item()),
-                  "max_abs_deig_vs_fp64_Ha": float((ev[:kk] - ev64[:kk]).abs().max().item())}
-        del D64, ev64
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "TFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if mixed else "f64",
-        "data": "synthetic",
-        "config": {"workload": wl["name"], "n_basis": n, "n_occ": int(n_occ), "kT_Ha": spec.kT,
-                   "kappa_S": spec.meta["kappa"], "band_width": info["band_width"], "k_s": ks,
-                   "path": "fp32_products_fp64_refine" if mixed else "plain_fp64"},
-        "roofline": roofline,
-        "algorithmic_flops": F,
-        "stage_ms": stage_ms,
-        "stage_roofline": stage_roofline(stage_ms, n, ks, info["band_width"], mixed),
-        "checks": {"trace_DS_minus_Ne": trace_ds - n_occ, "eigenvalues_ascending": ascending,
-                   "mu_Ha": info["mu"]},
-    }
-    if refine is not None:
-        out["refine"] = refine
-        out["cpu_baseline_note"] = "the CPU baseline is the FP64 oracle in both precisions"
-    h.close()
-    del ws, H, S, D, H0, S0
+        ks_m = info_m["k_s"]
+        kk = min(ks_m, ks64)
+        F_m = algorithmic_flops(n, ks_m)
+        mixed = {
+            "path": "fp32_products_fp64_refine",
+            "ms_per_step": ms_m,
+            "steps": msteps,
+            "tflops_algorithmic": F_m / (ms_m / 1e3) / 1e12,
+            "status": st_m,
+            "refine_sweeps": info_m["refine_sweeps"],
+            "refine_states": info_m["refine_states"],
+            "refine_step": info_m["refine_step"],
+            "refine_tol": args.refine_tol,
+            "residual_Ha": info_m["refine_resid"],
+            "k_s": ks_m,
+            "max_abs_dD_vs_fp64": float((D - D64).abs().max().item()),
+            "max_abs_deig_vs_fp64_Ha": float((ev[:kk] - ev64[:kk]).abs().max().item()),
+            "stage_ms": stage_m,
+            "stage_roofline": stage_roofline(stage_m, n, ks_m, info_m["band_width"], True),
+        }
+        if out is not None:
+            mixed["speedup_vs_fp64"] = out["ms_per_step"] / ms_m
+            out["mixed"] = mixed
+        else:
+            out = {
+                "metric": METRIC,
+                "value": F_m / (ms_m / 1e3) / 1e12,
+                "unit": "TFLOP/s",
+                "n_gpus": 1,
+                "steps": msteps,
+                "warmup": args.warmup,
+                "ms_per_step": ms_m,
+                "higher_is_better": True,
+                "scaling": "weak",
+                "vs_baseline": None,
+                "dtype": "f32+f64",
+                "data": "synthetic",
+                "config": {"workload": wl["name"].replace("plain_fp64", "mixed"), "n_basis": n,
+                           "n_occ": int(n_occ), "kT_Ha": spec.kT, "kappa_S": spec.meta["kappa"],
+                           "band_width": info_m["band_width"], "k_s": ks_m, "path": "fp32_products_fp64_refine"},
+                "mixed": mixed,
+            }
+        del ref64, D64, ev64
+    del H, S, D, H0, S0
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n)
+        out["cpu_baseline_note"] = "the CPU baseline is the FP64 oracle, for both precisions"
     print(json.dumps(out), flush=True)
 
 

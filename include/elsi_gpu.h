@@ -59,15 +59,29 @@ typedef struct elsi_gpu_handle_s *elsi_gpu_handle;
 enum { ELSI_GPU_REAL64 = 0, ELSI_GPU_COMPLEX128 = 1 };
 
 /* occupation scheme (Sec. 4.6, broadening_scheme): explicit values given by
- * the caller, or Fermi-Dirac broadening, Eq. (17) */
-enum { ELSI_GPU_OCC_EXPLICIT = 0, ELSI_GPU_OCC_FERMI = 1 };
+ * the caller, or a broadening of width w with x = (eps - mu) / w:
+ *   FERMI     Fermi-Dirac, Eq. (17): f = spin / (1 + e^x);
+ *   GAUSSIAN  Gaussian, Eq. (21): f = spin (1 - erf x) / 2;
+ *   MP0       Methfessel-Paxton of order 0 (the Gaussian step);
+ *   MP1       Methfessel-Paxton of order 1 (Phys. Rev. B 40, 3616 (1989)):
+ *             f = spin (erfc(x) / 2 - x e^{-x^2} / (2 sqrt(pi))), which is
+ *             negative for some states above mu and above spin for some
+ *             below it.
+ * (ELSI numbers them 2, 1, 3, 4.) */
+enum {
+    ELSI_GPU_OCC_EXPLICIT = 0,
+    ELSI_GPU_OCC_FERMI = 1,
+    ELSI_GPU_OCC_GAUSSIAN = 2,
+    ELSI_GPU_OCC_MP0 = 3,
+    ELSI_GPU_OCC_MP1 = 4
+};
 
 /* failure codes (positive return values) */
 enum {
     ELSI_GPU_ERR_NOT_PD = 1,      /* S not positive definite; info.fail_col = first bad pivot (1-based) */
     ELSI_GPU_ERR_NO_CONV = 2,     /* tridiagonal eigensolver did not converge */
     ELSI_GPU_ERR_REFINE = 3,      /* mixed precision: refinement did not reach refine_tol (outputs
-                                     still written; info.refine_resid holds the bound reached) */
+                                     still written; info.refine_step holds the step reached) */
     ELSI_GPU_ERR_MU = 4,          /* mu bisection ran out of steps (outputs still written) */
     ELSI_GPU_ERR_HIP = 5,         /* HIP runtime error */
     ELSI_GPU_ERR_OOM = 6,         /* device memory exhausted */
@@ -115,12 +129,21 @@ typedef struct elsi_gpu_info {
     double probe_flops;
     char probe_kernel[48];
     /* Mixed precision (elsi_gpu_set_precision): refinement sweeps run, states
-     * refined (wanted plus guard), and the largest residual norm
+     * refined (wanted plus guard), the largest residual norm
      * ||H~ x - theta x||_2 of the wanted states after the last sweep (Ha; a
-     * bound on their eigenvalue errors).  Zero in FP64 mode. */
+     * bound on their eigenvalue errors), and the largest weighted Newton
+     * step of the wanted states (the estimate of their distance to the exact
+     * invariant subspace that decides convergence; weights: the occupations
+     * in dm, 1 in ev).  Zero in FP64 mode. */
     int refine_sweeps;
     int refine_states;
     double refine_resid;
+    double refine_step;
+    /* Singularity check (elsi_gpu_set_singularity): the smallest eigenvalue
+     * of S found by the last check (0 when none ran), and N_nonsing, the
+     * number of states of the last call (n_basis on the Cholesky route). */
+    double overlap_min_eig;
+    int n_nonsing;
 } elsi_gpu_info;
 
 /* Create a handle (elsi_init, Sec. 4.4).  n_state: eigenvectors returned by
@@ -144,10 +167,34 @@ int elsi_gpu_workspace_size(elsi_gpu_handle h, size_t *bytes);
 int elsi_gpu_set_workspace(elsi_gpu_handle h, void *dev_ptr, size_t bytes);
 
 /* Occupation and chemical potential options (elsi_customize_mu, Sec. 4.6):
- * scheme ELSI_GPU_OCC_*, width = k_B T in Ha (> 0), occ_accuracy (> 0),
- * mu_max_steps (>= 1), spin_factor (> 0; f ranges over [0, spin_factor]). */
+ * scheme ELSI_GPU_OCC_*, width = the broadening width in Ha (k_B T for
+ * Fermi-Dirac; > 0), occ_accuracy (> 0), mu_max_steps (>= 1), spin_factor
+ * (> 0; Fermi-Dirac and Gaussian f range over [0, spin_factor]).
+ * Errors: -1 handle, -2 scheme, -3 width, -4 occ_accuracy, -5 mu_max_steps,
+ * -6 spin_factor. */
 int elsi_gpu_set_occupation(elsi_gpu_handle h, int scheme, double width,
                             double occ_accuracy, int mu_max_steps, double spin_factor);
+
+/* Singularity check of the overlap (Sec. 4.5, Eq. (20); Sec. 4.6
+ * no_singularity_check, singularity_tolerance), real handles.  With check = 1
+ * every elsi_gpu_ev / elsi_gpu_dm whose S is not already factored first
+ * computes all eigenvalues lam of S (by this library's FP64 path, an n^3 cost
+ * comparable to the solve).  If the smallest is below tolerance, S is
+ * singular for the purpose of the calculation and the Cholesky factorization
+ * is replaced by the eigendecomposition S = x lam x^T = X X^T, X = x
+ * lam^(1/2), keeping the N_nonsing eigenvectors with lam >= tolerance:
+ * H~ = Y^T H Y with Y = x_keep lam_keep^(-1/2) is solved at size N_nonsing
+ * (in FP64, whatever the handle's precision), and c = Y c~.  Then eval[0 ..
+ * N_nonsing) holds the eigenvalues and eval[N_nonsing .. n) +HUGE_VAL (no
+ * state there), occupations beyond N_nonsing are 0, eigenvector columns beyond
+ * N_nonsing are 0, S receives X (n x N_nonsing in its first columns, the rest
+ * zero) and info.n_nonsing = N_nonsing; with elsi_gpu_set_overlap_factored a
+ * later call reuses that X (lam_j = ||X_j||^2).  check = 0 (default): the
+ * Cholesky factorization, which reports a non-positive pivot.  Batched calls
+ * do not run the check.
+ * Errors: -1 handle, -2 check not 0 or 1, or a complex handle, -3 tolerance
+ * not > 0. */
+int elsi_gpu_set_singularity(elsi_gpu_handle h, int check, double tolerance);
 
 /* overlap_is_unit (Sec. 4.6): S is the identity and is not read. */
 int elsi_gpu_set_overlap_is_unit(elsi_gpu_handle h, int flag);
@@ -168,15 +215,21 @@ int elsi_gpu_set_band_width(elsi_gpu_handle h, int b);
  * (Eq. (10), (11)), steps (2)-(4), storage and everything else stay FP64.
  * The library then carries k' = min(n, k + max(64, ceil(k / 10))) states
  * (k = n_state for ev, k_s for dm) and refines them in FP64 against
- * H~ = L^-1 H L^-T: per sweep CholeskyQR twice, Rayleigh-Ritz with the FP64
- * solver, residual norms r_l = ||H~ x_l - theta_l x_l||_2.  A sweep that
- * leaves max_l r_l over the wanted states at most refine_tol ends with status
- * 0; one that does not ends the refinement with ELSI_GPU_ERR_REFINE and all
- * outputs written (a Rayleigh-Ritz sweep does not change the subspace, so a
- * second one could not help; max_refine = 0 skips the refinement and also
- * ends with ELSI_GPU_ERR_REFINE).  Eigenvalues above the
- * k' refined ones are the FP32-step values.  Needs n^2 more doubles of
- * workspace.  Batched calls always run in FP64.
+ * H~ = L^-1 H L^-T.  Each sweep: CholeskyQR twice, Rayleigh-Ritz with the
+ * FP64 solver, residuals r_l = H~ x_l - theta_l x_l, and the Newton
+ * correction of the subspace through the factorization H~ ~ Q T Q^T that
+ * steps (1)-(3) produced (Q = Q1 Q2, Z the eigenvectors of T of the k'
+ * states, P = I - Z Z^T): y_l = -P (T - theta_l)^-1 P Q^T r_l, with the
+ * shifted tridiagonal systems solved per state.  When the largest weighted
+ * step max_l w_l ||y_l||_2 over the wanted states (w_l = f_l in dm, 1 in ev)
+ * is at most refine_tol, that step is taken and one closing Rayleigh-Ritz
+ * sweep ends the call with status 0 (an untaken step would be amplified by
+ * L^-T in the eigenvectors c = L^-T x); otherwise x_l += Q y_l and the next
+ * sweep starts, up to max_refine sweeps in all (default 6; then
+ * ELSI_GPU_ERR_REFINE with all outputs written; max_refine = 0 skips the
+ * refinement and also ends with ELSI_GPU_ERR_REFINE).  Eigenvalues above the
+ * k' refined ones are the FP32-step values.  Needs about 3n^2 more doubles
+ * of workspace.  Batched calls always run in FP64.
  * Errors: -1 h NULL, -2 prec unknown or a complex handle asks for MIXED,
  * -3 refine_tol not >= 0, -4 max_refine < 0. */
 int elsi_gpu_set_precision(elsi_gpu_handle h, int prec, double refine_tol, int max_refine);
@@ -208,12 +261,13 @@ int elsi_gpu_ev(elsi_gpu_handle h, double *H, double *S, double *eval, double *e
  * D = sum_l f_l c_l c_l^H, Hermitian).
  *   H, S    as for elsi_gpu_ev;
  *   occ     device, n doubles: in for ELSI_GPU_OCC_EXPLICIT (f of the states in
- *           ascending order), out (the Fermi-Dirac occupations) otherwise; may
- *           be NULL in Fermi-Dirac mode;
+ *           ascending order, of either sign), out (the broadening scheme's
+ *           occupations) otherwise; may be NULL for a broadening scheme;
  *   D       device, n x n, out: both triangles;
  *   eval    device, n doubles, out (may be NULL);
  *   energy  host, out: sum_l f_l eps_l;   mu  host, out (may be NULL).
- * Only the eigenvectors with f_l > 1e-20 are formed and used for D.
+ * Only the eigenvectors up to the last state with |f_l| > 1e-20 are formed
+ * and used for D.
  * Errors: -1 handle, -2 H, -3 S, -4 occ (NULL in explicit mode), -5 D, -7 energy;
  * positive codes as for elsi_gpu_ev, plus ELSI_GPU_ERR_MU (outputs still written). */
 int elsi_gpu_dm(elsi_gpu_handle h, double *H, double *S, double *occ, double *D,
@@ -262,15 +316,27 @@ int elsi_gpu_ev_batched(elsi_gpu_handle h, int count, const int *n, const int *n
                         double *const *H, double *const *S, double *const *eval,
                         double *const *evec, int *status);
 
-/* elsi_gpu_dm for count problems with Fermi-Dirac occupations (the handle's
- * scheme must be ELSI_GPU_OCC_FERMI) and an independent chemical potential
- * per problem (Eq. (18) per problem): D[p] (n[p] x n[p], both triangles),
- * eval[p] (may be NULL, or eval itself NULL), energy[p] and mu[p] (host
- * arrays; mu may be NULL).  kweight must be NULL: a chemical potential shared
- * across problems with k-point weights is not provided.
+/* elsi_gpu_dm for count problems with the handle's broadening scheme (not
+ * ELSI_GPU_OCC_EXPLICIT): D[p] (n[p] x n[p], both triangles), eval[p] (may
+ * be NULL, or eval itself NULL), energy[p] and mu[p] (host arrays; mu may be
+ * NULL).
+ * kweight NULL: an independent chemical potential per problem, Eq. (18)
+ * with n_electron[p] electrons, and f in [0, spin] as in elsi_gpu_dm.
+ * kweight (host, count weights > 0): the problems are the k-points and spin
+ * channels of one system sharing one chemical potential (the sum over k-points
+ * and spin channels of Sec. 4.5): mu solves
+ *   sum_p kweight[p] sum_l f(eps_pl - mu) = sum_p kweight[p] n_electron[p],
+ * each problem's occupations include its weight, f_pl = kweight[p] f(eps_pl
+ * - mu) (the bisection and the charge fix-up of Sec. 4.5 run over all states
+ * of all problems, the fix-up from the last state of the last problem
+ * downward), D[p] = sum_l f_pl c_pl c_pl^T (so sum_p tr(D[p] S[p]) is the
+ * electron count), energy[p] = sum_l f_pl eps_pl and mu[p] the shared mu.
+ * The eigenvalues of every problem are computed first (H and S are read,
+ * not destroyed, by that pass), then each problem is solved with its
+ * occupations fixed.
  * Errors: -1 handle or explicit occupation scheme, -2 count < 0, -3 n or a
- * per-problem entry, -4 n_electron, -5 kweight not NULL, -6 H, -7 S, -8 D,
- * -10 energy, -12 status. */
+ * per-problem entry, -4 n_electron, -5 a kweight entry not > 0, -6 H, -7 S,
+ * -8 D, -10 energy, -12 status. */
 int elsi_gpu_dm_batched(elsi_gpu_handle h, int count, const int *n, const double *n_electron,
                         const double *kweight, double *const *H, double *const *S,
                         double *const *D, double *const *eval, double *energy, double *mu,
@@ -321,14 +387,20 @@ int elsi_gpu_x_reduce(int n, double *H, int ldh, const double *L, int ldl, void 
 int elsi_gpu_x_backsub(int n, int k, const double *L, int ldl, double *X, int ldx,
                        void *hip_stream);
 
-/* Occupations, Eq. (17), and mu, Eq. (18) (Sec. 4.5): eps device (n,
- * ascending), f device out; mu, k_s (f > 1e-20 count) and status to host. */
-int elsi_gpu_x_occupations(int n, const double *eps, double n_electron, double kT,
-                           double spin, double occ_accuracy, int mu_max_steps, double *f,
+/* Occupations of a broadening scheme (Eq. (17), Eq. (21), Methfessel-Paxton)
+ * and mu, Eq. (18) (Sec. 4.5): eps device (n; ascending within each problem
+ * when several are concatenated), weight device (n per-state weights of a mu
+ * shared by k-points / spin channels, f_l = w_l f(eps_l); NULL: 1), f device
+ * out; mu, k_s (one past the last |f| > 1e-20) to host; returns the status
+ * (0, or ELSI_GPU_ERR_MU).  Errors: -1 n, -2 eps, -4 scheme, -5 n_electron,
+ * -6 width, -7 spin, -8 occ_accuracy, -9 mu_max_steps, -10 f. */
+int elsi_gpu_x_occupations(int n, const double *eps, const double *weight, int scheme, double n_electron,
+                           double width, double spin, double occ_accuracy, int mu_max_steps, double *f,
                            double *mu, int *k_s, void *hip_stream);
 
-/* D = sum_{l<k} f_l c_l c_l^T, Eq. (9): C device n x k (ldc), f device (k),
- * D device n x n (ldd), both triangles written. */
+/* D = sum_{l<k} f_l c_l c_l^T, Eq. (9), for occupations of either sign:
+ * C device n x k (ldc), f device (k), D device n x n (ldd), both triangles
+ * written. */
 int elsi_gpu_x_density(int n, int k, const double *C, int ldc, const double *f, double *D,
                        int ldd, void *hip_stream);
 
@@ -343,6 +415,17 @@ int elsi_gpu_x_band_reduce(int n, int b, double *A, int lda, double *band, int l
 int elsi_gpu_x_tridiagonalize(int n, int b, double *A, int lda, double *d, double *e,
                               void *hip_stream);
 
+/* Steps (1)+(2) on A as elsi_gpu_x_tridiagonalize (d, e receive T), then
+ * X (n x ncol, ldx, device) <- Q X (trans 0: steps (4) and (5), Q2 then Q1)
+ * or Q^T X (trans 1: Q1^T then Q2^T, the map the mixed mode's refinement
+ * takes residuals through), Q = Q1 Q2 the product of the reflectors with
+ * T = Q^T A Q (Eq. (13)).  slab: columns of X per workgroup in the
+ * application of Q2 (0 automatic; 128, 256 or 512).
+ * Errors: -1 n < 1, -2 b outside 1..64, -3 A NULL, -4 lda < n, -5 d NULL,
+ * -6 e NULL, -7 X NULL, -8 ldx < n, -9 ncol < 0, -10 trans, -11 slab. */
+int elsi_gpu_x_backtransform(int n, int b, const double *A, int lda, double *d, double *e,
+                             double *X, int ldx, int ncol, int trans, int slab, void *hip_stream);
+
 /* Step (3): eigenvalues w (ascending) and eigenvectors Z (n x n, ldz) of the
  * symmetric tridiagonal (d, e) by divide and conquer. */
 int elsi_gpu_x_tridiag_eig(int n, const double *d, const double *e, double *w, double *Z, int ldz,
@@ -350,23 +433,34 @@ int elsi_gpu_x_tridiag_eig(int n, const double *d, const double *e, double *w, d
 
 /* FP64 refinement sweeps of the mixed path (elsi_gpu_set_precision) on a
  * caller's subspace: Ht device n x n symmetric (both triangles, ldh; e.g. the
- * output of elsi_gpu_x_reduce), X device n x k (ldx) spanning the
- * approximation, overwritten by the refined vectors (orthonormal, Ritz
- * order); theta (k) and resid (k) device out: Ritz values ascending and
- * ||Ht x_l - theta_l x_l||_2.  The first kw states decide convergence
- * (max resid <= tol); a sweep that misses it ends the call (at most one
- * sweep does work: Rayleigh-Ritz leaves the subspace unchanged); *sweeps
- * (host, may be NULL) receives the sweeps run.
+ * output of elsi_gpu_x_reduce), X device n x k (ldx) approximating the
+ * invariant subspace of the k lowest eigenvalues, overwritten by the refined
+ * vectors (orthonormal, Ritz order); theta (k) and resid (k) device out: Ritz
+ * values ascending and ||Ht x_l - theta_l x_l||_2.
+ * Q (device n x n, ldq, orthogonal), d (n) and e (n-1) (device) give an
+ * approximate factorization Ht ~ Q T Q^T, T = tridiag(e, d, e); each sweep
+ * then takes the Newton step y_l = -P (T - theta_l)^-1 P Q^T r_l (Z the
+ * eigenvectors of T for its k lowest eigenvalues, P = I - Z Z^T; step (k,
+ * device, may be NULL) receives ||y_l||_2) and ends the call with 0 when
+ * max_{l < kw} w_l ||y_l||_2 <= tol (weight: device, k values, or NULL for
+ * w = 1) after adding that step and one closing Rayleigh-Ritz sweep; until
+ * then it adds Q y_l to x_l (only where ||y_l||_2 <= 1/2) and goes on, up to
+ * max_sweeps sweeps in all.  Q NULL: one Rayleigh-Ritz sweep (it cannot move
+ * span(X)), converged when max_{l < kw} resid_l <= tol.  *sweeps (host, may be
+ * NULL) receives the sweeps run.
  * Returns ELSI_GPU_ERR_REFINE when tol was not reached (outputs written; with
  * max_sweeps = 0 nothing is written) or when the columns of X are
  * numerically dependent (the factorization is checked before X is touched:
  * X then holds the vectors of the last completed sweep, theta and resid that
- * sweep's values, and with no completed sweep X is unchanged).  Errors: -1
- * n < 0, -2 k outside 0..n, -3 kw outside
- * 0..k, -4 Ht / ldh, -6 X / ldx, -8 theta, -9 resid, -10 tol, -11 max_sweeps. */
+ * sweep's values, and with no completed sweep X is unchanged);
+ * ELSI_GPU_ERR_NO_CONV when the eigenvectors of T could not be computed.
+ * Errors: -1 n < 0, -2 k outside 0..n, -3 kw outside 0..k, -4 Ht / ldh, -6 X /
+ * ldx, -9 ldq, -10 d NULL with Q, -11 e NULL with Q, -13 theta, -14 resid,
+ * -16 tol, -17 max_sweeps. */
 int elsi_gpu_x_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int ldx,
-                      double *theta, double *resid, double tol, int max_sweeps, int *sweeps,
-                      void *hip_stream);
+                      const double *Q, int ldq, const double *d, const double *e,
+                      const double *weight, double *theta, double *resid, double *step, double tol,
+                      int max_sweeps, int *sweeps, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -9,8 +9,11 @@ of the method, and it raises when the library is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import torch
 
@@ -22,6 +25,9 @@ REAL64 = 0
 COMPLEX128 = 1
 OCC_EXPLICIT = 0
 OCC_FERMI = 1
+OCC_GAUSSIAN = 2
+OCC_MP0 = 3
+OCC_MP1 = 4
 PREC_FP64 = 0
 PREC_MIXED = 1
 NSTAGES = 11
@@ -45,7 +51,8 @@ class Info(ctypes.Structure):
                 ("probe_launches", ctypes.c_int), ("probe_ms", ctypes.c_double),
                 ("probe_flops", ctypes.c_double), ("probe_kernel", ctypes.c_char * 48),
                 ("refine_sweeps", ctypes.c_int), ("refine_states", ctypes.c_int),
-                ("refine_resid", ctypes.c_double)]
+                ("refine_resid", ctypes.c_double), ("refine_step", ctypes.c_double),
+                ("overlap_min_eig", ctypes.c_double), ("n_nonsing", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "stage_ms"}
@@ -78,6 +85,7 @@ def lib():
         L.elsi_gpu_set_workspace.argtypes = [vp, vp, sz]
         L.elsi_gpu_set_occupation.argtypes = [vp, i, d, d, i, d]
         L.elsi_gpu_set_overlap_is_unit.argtypes = [vp, i]
+        L.elsi_gpu_set_singularity.argtypes = [vp, i, d]
         L.elsi_gpu_set_overlap_factored.argtypes = [vp, i]
         L.elsi_gpu_set_band_width.argtypes = [vp, i]
         L.elsi_gpu_set_launch_timing.argtypes = [vp, i]
@@ -96,13 +104,15 @@ def lib():
         L.elsi_gpu_x_cholesky.argtypes = [i, vp, i, ctypes.POINTER(i), vp]
         L.elsi_gpu_x_reduce.argtypes = [i, vp, i, vp, i, vp]
         L.elsi_gpu_x_backsub.argtypes = [i, i, vp, i, vp, i, vp]
-        L.elsi_gpu_x_occupations.argtypes = [i, vp, d, d, d, d, i, vp, ctypes.POINTER(d),
+        L.elsi_gpu_x_occupations.argtypes = [i, vp, vp, i, d, d, d, d, i, vp, ctypes.POINTER(d),
                                              ctypes.POINTER(i), vp]
         L.elsi_gpu_x_density.argtypes = [i, i, vp, i, vp, vp, i, vp]
         L.elsi_gpu_x_band_reduce.argtypes = [i, i, vp, i, vp, i, vp]
         L.elsi_gpu_x_tridiagonalize.argtypes = [i, i, vp, i, vp, vp, vp]
         L.elsi_gpu_x_tridiag_eig.argtypes = [i, vp, vp, vp, vp, i, vp]
-        L.elsi_gpu_x_refine.argtypes = [i, i, i, vp, i, vp, i, vp, vp, d, i, ctypes.POINTER(i), vp]
+        L.elsi_gpu_x_refine.argtypes = [i, i, i, vp, i, vp, i, vp, i, vp, vp, vp, vp, vp, vp, d, i,
+                                        ctypes.POINTER(i), vp]
+        L.elsi_gpu_x_backtransform.argtypes = [i, i, vp, i, vp, vp, vp, i, i, i, i, vp]
         _lib = L
     return _lib
 
@@ -201,13 +211,17 @@ def backsub(L: torch.Tensor, X: torch.Tensor) -> None:
 
 
 def occupations(eps: torch.Tensor, n_electron: float, kT: float, spin: float = 1.0,
-                occ_accuracy: float = 1e-13, max_steps: int = 100):
-    """Fermi-Dirac occupations and mu on the device: returns (f, mu, k_s, status)."""
+                occ_accuracy: float = 1e-13, max_steps: int = 100, scheme: int = None, weight=None):
+    """Occupations of a broadening scheme (default Fermi-Dirac) and mu on the
+    device; weight: per-state weights of a mu shared by several problems.
+    Returns (f, mu, k_s, status)."""
     f = torch.empty_like(eps)
     mu = ctypes.c_double(0.0)
     ks = ctypes.c_int(0)
-    rc = lib().elsi_gpu_x_occupations(eps.shape[0], _ptr(eps), n_electron, kT, spin, occ_accuracy,
-                                      max_steps, _ptr(f), ctypes.byref(mu), ctypes.byref(ks), _stream())
+    scheme = OCC_FERMI if scheme is None else scheme
+    rc = lib().elsi_gpu_x_occupations(eps.shape[0], _ptr(eps), _ptr(weight), int(scheme), n_electron, kT, spin,
+                                      occ_accuracy, max_steps, _ptr(f), ctypes.byref(mu), ctypes.byref(ks),
+                                      _stream())
     _check(rc, "elsi_gpu_x_occupations", ok=(0, 4))
     return f, mu.value, ks.value, rc
 
@@ -252,10 +266,28 @@ def tridiag_eig(d: torch.Tensor, e: torch.Tensor):
     return w, Z
 
 
-def refine(Ht: torch.Tensor, X: torch.Tensor, kw: int, tol: float = 1e-10, max_sweeps: int = 4):
+def backtransform(A: torch.Tensor, b: int, X: torch.Tensor, trans: bool = False, slab: int = 0):
+    """X <- Q X (or Q^T X) in place, Q = Q1 Q2 the reflectors of the two-stage
+    tridiagonalization of symmetric A; returns (d, e) of T = Q^T A Q."""
+    n = A.shape[0]
+    ncol = X.shape[1]
+    if not X.t().is_contiguous():
+        raise ValueError("X must be column-major (see fortran_empty)")
+    d = torch.empty(n, device=A.device, dtype=torch.float64)
+    e = torch.empty(max(n - 1, 1), device=A.device, dtype=torch.float64)
+    rc = lib().elsi_gpu_x_backtransform(n, b, _ptr(A), n, _ptr(d), _ptr(e), _ptr(X), n, ncol, int(bool(trans)),
+                                        int(slab), _stream())
+    _check(rc, "elsi_gpu_x_backtransform")
+    return d, e[: n - 1]
+
+
+def refine(Ht: torch.Tensor, X: torch.Tensor, kw: int, tol: float = 1e-10, max_sweeps: int = 4, Q=None, d=None,
+           e=None, weight=None):
     """FP64 refinement sweeps of the mixed path on the subspace X (n x k) of the
-    symmetric Ht; X is overwritten by the refined vectors.  Returns
-    (theta, resid, sweeps, status) with status 0 or 3 (tolerance not reached)."""
+    symmetric Ht; X is overwritten by the refined vectors.  Q (column-major
+    n x n), d, e: an approximate factorization Ht ~ Q T Q^T through which the
+    Newton correction runs (None: one Rayleigh-Ritz sweep).  Returns
+    (theta, resid, step, sweeps, status) with status 0 or 3 (tolerance not reached)."""
     n = Ht.shape[0]
     k = X.shape[1]
     Ht = as_fortran(Ht)
@@ -263,16 +295,41 @@ def refine(Ht: torch.Tensor, X: torch.Tensor, kw: int, tol: float = 1e-10, max_s
         raise ValueError("X must be column-major (see fortran_empty)")
     theta = torch.zeros(max(k, 1), device=Ht.device, dtype=torch.float64)
     resid = torch.zeros(max(k, 1), device=Ht.device, dtype=torch.float64)
+    step = torch.zeros(max(k, 1), device=Ht.device, dtype=torch.float64)
     sw = ctypes.c_int(0)
-    rc = lib().elsi_gpu_x_refine(n, k, kw, _ptr(Ht), max(1, n), _ptr(X), max(1, n), _ptr(theta), _ptr(resid),
-                                 float(tol), int(max_sweeps), ctypes.byref(sw), _stream())
+    if Q is not None:
+        Q = as_fortran(Q)
+        ee = e if e.numel() > 0 else torch.zeros(1, device=Ht.device, dtype=torch.float64)
+        qargs = (_ptr(Q), max(1, n), _ptr(d), _ptr(ee))
+    else:
+        qargs = (_ptr(None), max(1, n), _ptr(None), _ptr(None))
+    rc = lib().elsi_gpu_x_refine(n, k, kw, _ptr(Ht), max(1, n), _ptr(X), max(1, n), *qargs, _ptr(weight),
+                                 _ptr(theta), _ptr(resid), _ptr(step), float(tol), int(max_sweeps),
+                                 ctypes.byref(sw), _stream())
     _check(rc, "elsi_gpu_x_refine", ok=(0, 3))
-    return theta[:k], resid[:k], sw.value, rc
+    return theta[:k], resid[:k], step[:k], sw.value, rc
 
 
 # ---------------------------------------------------------------------------
 # handle API
 # ---------------------------------------------------------------------------
+_live_handles: "weakref.WeakSet[Handle]" = weakref.WeakSet()
+
+
+def _close_live_handles():
+    """Finalize every handle still open at interpreter exit, while the HIP
+    runtime is certainly alive (registered after torch is imported, so it
+    runs before torch's own exit handlers)."""
+    for h in list(_live_handles):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_live_handles)
+
+
 class Handle:
     """One elsi_gpu handle (elsi_init ... elsi_finalize)."""
 
@@ -287,6 +344,7 @@ class Handle:
         self.dtype = dtype
         _check(lib().elsi_gpu_init(ctypes.byref(self._h), dtype, n_basis, n_state, n_electron,
                                    ctypes.c_void_p(s)), "elsi_gpu_init")
+        _live_handles.add(self)
 
     def _mat_dtype(self):
         return torch.complex128 if self.dtype == COMPLEX128 else torch.float64
@@ -308,6 +366,11 @@ class Handle:
         _check(lib().elsi_gpu_set_occupation(self._h, scheme, width, occ_accuracy, mu_max_steps,
                                              spin_factor), "elsi_gpu_set_occupation")
 
+    def set_singularity(self, check=True, tolerance=1e-5):
+        """Singularity check of S (Eq. (20)): below `tolerance` the eigendecomposition
+        transform replaces the Cholesky factorization (real handles)."""
+        _check(lib().elsi_gpu_set_singularity(self._h, int(bool(check)), float(tolerance)), "set_singularity")
+
     def set_overlap_is_unit(self, flag=True):
         _check(lib().elsi_gpu_set_overlap_is_unit(self._h, int(flag)), "set_overlap_is_unit")
 
@@ -317,7 +380,7 @@ class Handle:
     def set_band_width(self, b: int):
         _check(lib().elsi_gpu_set_band_width(self._h, b), "set_band_width")
 
-    def set_precision(self, prec=PREC_FP64, refine_tol=1e-10, max_refine=4):
+    def set_precision(self, prec=PREC_FP64, refine_tol=1e-10, max_refine=6):
         """PREC_FP64, or PREC_MIXED: FP32 matrix-core products in full -> band and Q1,
         then FP64 refinement (real handles)."""
         _check(lib().elsi_gpu_set_precision(self._h, int(prec), float(refine_tol), int(max_refine)),
@@ -394,9 +457,11 @@ class Handle:
         _check(rc, "elsi_gpu_ev_batched", ok=ok)
         return evals, evecs, list(status), rc
 
-    def dm_batched(self, Hs, Ss, n_electrons, ok=(0,)):
-        """Batched density matrices (independent mu per problem): returns
-        (Ds, evals, energies, mus, per-problem status, rc)."""
+    def dm_batched(self, Hs, Ss, n_electrons, kweight=None, ok=(0,)):
+        """Batched density matrices: an independent mu per problem, or with
+        kweight one mu shared by all problems (k-points / spin channels, each
+        problem's occupations weighted).  Returns (Ds, evals, energies, mus,
+        per-problem status, rc)."""
         count = len(Hs)
         n = [int(H.shape[0]) for H in Hs]
         self._check_input(*Hs, *(Ss or []))
@@ -407,7 +472,8 @@ class Handle:
         status = (ctypes.c_int * count)()
         rc = lib().elsi_gpu_dm_batched(
             self._h, count, (ctypes.c_int * count)(*n), (ctypes.c_double * count)(*[float(x) for x in n_electrons]),
-            None, _ptrs(Hs), _ptrs(Ss) if Ss is not None else None, _ptrs(Ds), _ptrs(evals), energy, mu, status)
+            (ctypes.c_double * count)(*[float(x) for x in kweight]) if kweight is not None else None,
+            _ptrs(Hs), _ptrs(Ss) if Ss is not None else None, _ptrs(Ds), _ptrs(evals), energy, mu, status)
         _check(rc, "elsi_gpu_dm_batched", ok=ok)
         return Ds, evals, list(energy), list(mu), list(status), rc
 
@@ -420,8 +486,14 @@ class Handle:
         if self._h:
             lib().elsi_gpu_finalize(ctypes.byref(self._h))
             self._h = ctypes.c_void_p(0)
+        _live_handles.discard(self)
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # during interpreter shutdown the atexit hook has already closed every
+        # live handle; no HIP call is made from a finalizer at that point
+        # (the check is bound at definition: module globals may be gone then)
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -74,7 +74,7 @@ int elsi_gpu_set_occupation(elsi_gpu_handle h, int scheme, double width, double 
                             int mu_max_steps, double spin_factor)
 {
     if (!h) return -1;
-    if (scheme != ELSI_GPU_OCC_EXPLICIT && scheme != ELSI_GPU_OCC_FERMI) return -2;
+    if (scheme < ELSI_GPU_OCC_EXPLICIT || scheme > ELSI_GPU_OCC_MP1) return -2;
     if (!(width > 0.0)) return -3;
     if (!(occ_accuracy > 0.0)) return -4;
     if (mu_max_steps < 1) return -5;
@@ -84,6 +84,17 @@ int elsi_gpu_set_occupation(elsi_gpu_handle h, int scheme, double width, double 
     h->occ_accuracy = occ_accuracy;
     h->mu_max_steps = mu_max_steps;
     h->spin = spin_factor;
+    return 0;
+}
+
+int elsi_gpu_set_singularity(elsi_gpu_handle h, int check, double tolerance)
+{
+    if (!h) return -1;
+    if (check != 0 && check != 1) return -2;
+    if (check && h->dtype != ELSI_GPU_REAL64) return -2;
+    if (!(tolerance > 0.0)) return -3;
+    h->sing_check = check;
+    h->sing_tol = tolerance;
     return 0;
 }
 
@@ -246,22 +257,23 @@ int elsi_gpu_x_backsub(int n, int k, const double* L, int ldl, double* X, int ld
     return sync_status(st);
 }
 
-int elsi_gpu_x_occupations(int n, const double* eps, double n_electron, double kT, double spin,
-                           double occ_accuracy, int mu_max_steps, double* f, double* mu, int* k_s,
-                           void* hip_stream)
+int elsi_gpu_x_occupations(int n, const double* eps, const double* weight, int scheme, double n_electron,
+                           double width, double spin, double occ_accuracy, int mu_max_steps, double* f, double* mu,
+                           int* k_s, void* hip_stream)
 {
     if (n < 1) return -1;
     if (!eps) return -2;
-    if (!(n_electron >= 0.0) || n_electron > spin * n) return -3;
-    if (!(kT > 0.0)) return -4;
-    if (!(spin > 0.0)) return -5;
-    if (!(occ_accuracy > 0.0)) return -6;
-    if (mu_max_steps < 1) return -7;
-    if (!f) return -8;
+    if (scheme < ELSI_GPU_OCC_FERMI || scheme > ELSI_GPU_OCC_MP1) return -4;
+    if (!(n_electron >= 0.0)) return -5;
+    if (!(width > 0.0)) return -6;
+    if (!(spin > 0.0)) return -7;
+    if (!(occ_accuracy > 0.0)) return -8;
+    if (mu_max_steps < 1) return -9;
+    if (!f) return -10;
     hipStream_t st = (hipStream_t)hip_stream;
     DevBuf<double> scal;
     if (!scal.alloc(8)) return ELSI_GPU_ERR_OOM;
-    fermi_occupations(st, n, eps, n_electron, kT, spin, occ_accuracy, mu_max_steps, kFCut, f, scal.p);
+    occupations(st, n, eps, weight, scheme, n_electron, width, spin, occ_accuracy, mu_max_steps, kFCut, f, scal.p);
     double hs[8];
     if (hipMemcpyAsync(hs, scal.p, 6 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
         return ELSI_GPU_ERR_HIP;
@@ -284,9 +296,9 @@ int elsi_gpu_x_density(int n, int k, const double* C, int ldc, const double* f, 
     if (!D) return -6;
     if (ldd < n) return -7;
     hipStream_t st = (hipStream_t)hip_stream;
-    DevBuf<double> W;
-    if (k > 0 && !W.alloc((size_t)n * k)) return ELSI_GPU_ERR_OOM;
-    density_matrix(st, n, k, C, ldc, f, W.p, D, ldd);
+    DevBuf<double> W, W2;
+    if (k > 0 && (!W.alloc((size_t)n * k) || !W2.alloc((size_t)n * k))) return ELSI_GPU_ERR_OOM;
+    density_matrix(st, n, k, C, ldc, f, W.p, W2.p, D, ldd);
     return sync_status(st);
 }
 
@@ -336,6 +348,54 @@ int elsi_gpu_x_tridiagonalize(int n, int b, double* A, int lda, double* d, doubl
     int rc = sb2st(st, n, bb, Bd.p, 2 * bb, d, ee.p, V2.p, tau2.p, ints.p + 64, ints.p);
     if (rc) return rc;
     if (n > 1) (void)hipMemcpyAsync(e, ee.p, sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, st);
+    int herr = 0;
+    (void)hipMemcpyAsync(&herr, ints.p, sizeof(int), hipMemcpyDeviceToHost, st);
+    rc = sync_status(st);
+    if (rc) return rc;
+    return herr ? ELSI_GPU_ERR_NO_CONV : 0;
+}
+
+int elsi_gpu_x_backtransform(int n, int b, const double* A, int lda, double* d, double* e, double* X, int ldx,
+                             int ncol, int trans, int slab, void* hip_stream)
+{
+    if (n < 1) return -1;
+    if (b < 1 || b > 64) return -2;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (!d) return -5;
+    if (!e && n > 1) return -6;
+    if (!X && ncol > 0) return -7;
+    if (ldx < n) return -8;
+    if (ncol < 0) return -9;
+    if (trans != 0 && trans != 1) return -10;
+    if (slab != 0 && slab != 128 && slab != 256 && slab != 512) return -11;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int bb = std::min(b, std::max(1, n - 1));
+    const int kmax = sb2st_kmax(n, bb);
+    DevBuf<double> Vall, Tall, Bd, work, Acopy, V2, tau2, ee, Tq, q1work;
+    DevBuf<int> ints;
+    if (!Vall.alloc((size_t)n * n) || !Tall.alloc((size_t)ceil_div(n, bb) * bb * bb) ||
+        !Bd.alloc((size_t)2 * bb * n) || !work.alloc(sy2sb_workspace_doubles(n, bb)) ||
+        !Acopy.alloc((size_t)n * n) || !V2.alloc((size_t)n * n) ||
+        !tau2.alloc((size_t)std::max(n - 2, 1) * kmax) || !ee.alloc((size_t)n) ||
+        !ints.alloc((size_t)n + 64) || !Tq.alloc(apply_q2_workspace_doubles(n, bb)) ||
+        !q1work.alloc(apply_q1_workspace_doubles(n, std::max(ncol, 1))))
+        return ELSI_GPU_ERR_OOM;
+    copy_matrix(st, n, n, A, lda, Acopy.p, n);
+    mirror_lower_to_upper(st, n, Acopy.p, n);
+    sy2sb(st, n, bb, Acopy.p, n, Vall.p, Tall.p, Bd.p, 2 * bb, work.p);
+    int rc = sb2st(st, n, bb, Bd.p, 2 * bb, d, ee.p, V2.p, tau2.p, ints.p + 64, ints.p);
+    if (rc) return rc;
+    if (n > 1) (void)hipMemcpyAsync(e, ee.p, sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, st);
+    if (ncol > 0) {
+        if (trans) {
+            apply_q1(st, n, bb, ncol, Vall.p, Tall.p, X, ldx, q1work.p, true);
+            apply_q2(st, n, bb, ncol, V2.p, tau2.p, kmax, X, ldx, Tq.p, true, false, slab);
+        } else {
+            apply_q2(st, n, bb, ncol, V2.p, tau2.p, kmax, X, ldx, Tq.p, false, false, slab);
+            apply_q1(st, n, bb, ncol, Vall.p, Tall.p, X, ldx, q1work.p, false);
+        }
+    }
     int herr = 0;
     (void)hipMemcpyAsync(&herr, ints.p, sizeof(int), hipMemcpyDeviceToHost, st);
     rc = sync_status(st);

@@ -20,6 +20,10 @@
 // Step (5).  Q1 = Q_0 Q_1 ... with Q_p = I - V_p T_p V_p^T from the panels of
 // step (1); X <- Q1 X applies groups of panels last to first, each as three
 // FP64 matrix-core products (V^T X with a deterministic split over rows).
+//
+// The transposed applications (X <- Q2^T X, X <- Q1^T X, in the reverse order
+// and with each block's T transposed) carry residuals into the basis of the
+// tridiagonal matrix for the refinement of the mixed-precision mode.
 #include "common.h"
 
 namespace eg {
@@ -129,10 +133,6 @@ __global__ __launch_bounds__(256) void q2_build_t_kernel(int n, int b, const dou
 // LDS holds only the current 32-column chunk of X and the two 64 x 32
 // intermediates, which lets two workgroups share a CU.  Workgroups are
 // numbered so that all slabs of one block run on one XCD (one L2 copy of V).
-// columns of X per workgroup: wide slabs amortize the loads of V and T, narrow
-// ones keep enough workgroups in flight when X has few columns
-int q2_slab_width(int ncol) { return ncol >= 8192 ? 512 : (ncol >= 2048 ? 256 : 128); }
-
 // Phase-3 row blocks of each wave (16-row blocks of the 128-row window with
 // their first nonzero 4-column step), balanced to 20 MFMA steps per wave.
 __device__ __forceinline__ void q2_rowblocks(int wave, int& rbA, int& kA0, int& nA, int& rbB, int& kB0)
@@ -145,6 +145,11 @@ __device__ __forceinline__ void q2_rowblocks(int wave, int& rbA, int& kA0, int& 
     }
 }
 
+// TRANS: apply the transposed block I - V T^T V^T (Q2^T runs the anti-diagonal
+// steps in the opposite order); T^T is lower triangular, so row block rb of
+// T^T W needs the K steps 0 .. 4 rb + 3, and the same row-block pairs keep 20
+// MFMA steps per wave.
+template <bool TRANS>
 __global__ __launch_bounds__(256, 2) void q2_apply_step_kernel(int n, int b, int ncol, int qw, int t, int nb, int nslab,
                                                                const double* __restrict__ V2,
                                                                const double* __restrict__ Tq, int kmax, double* X,
@@ -182,14 +187,24 @@ __global__ __launch_bounds__(256, 2) void q2_apply_step_kernel(int n, int b, int
     const int t_cb = wave & 1;
     const int t_rb0 = (wave >> 1) ? 1 : 0, t_rb1 = 3 - t_rb0;
     double treg[20];
+    const int tA = TRANS ? 4 * t_rb0 + 4 : 0;   // (TRANS) steps of the first row block (4 or 8)
     {
         const double* T = Tq + ((size_t)g * kmax + k) * NB2 * NB2;
-        const int n0 = 16 - 4 * t_rb0;   // steps of the first row block (16 or 12)
+        if (TRANS) {
 #pragma unroll
-        for (int q = 0; q < 20; ++q) {
-            const int rb = (q < n0) ? t_rb0 : t_rb1;
-            const int kq = (q < n0) ? 4 * t_rb0 + q : 4 * t_rb1 + (q - n0);
-            treg[q] = T[(rb * 16 + li) + (size_t)(4 * kq + lk) * NB2];
+            for (int q = 0; q < 20; ++q) {
+                const int rb = (q < tA) ? t_rb0 : t_rb1;
+                const int kq = (q < tA) ? q : q - tA;
+                treg[q] = T[(4 * kq + lk) + (size_t)(rb * 16 + li) * NB2];   // T^T(16 rb + li, 4 kq + lk)
+            }
+        } else {
+            const int n0 = 16 - 4 * t_rb0;   // steps of the first row block (16 or 12)
+#pragma unroll
+            for (int q = 0; q < 20; ++q) {
+                const int rb = (q < n0) ? t_rb0 : t_rb1;
+                const int kq = (q < n0) ? 4 * t_rb0 + q : 4 * t_rb1 + (q - n0);
+                treg[q] = T[(rb * 16 + li) + (size_t)(4 * kq + lk) * NB2];
+            }
         }
     }
     const int xr = tid & 127, xc = tid >> 7;
@@ -238,8 +253,31 @@ __global__ __launch_bounds__(256, 2) void q2_apply_step_kernel(int n, int b, int
             }
         }
         __syncthreads();
-        // W2 = T W (64 x 32)
-        {
+        // W2 = T W (64 x 32), or T^T W
+        if (TRANS) {
+            double4_t a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+            const int cc = 16 * t_cb + li;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q], Ws[4 * q + lk][cc], a0, 0, 0, 0);
+            if (tA == 8) {
+#pragma unroll
+                for (int q = 4; q < 8; ++q)
+                    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q], Ws[4 * q + lk][cc], a0, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int q = 4; q < 8; ++q)
+                    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q], Ws[4 * (q - 4) + lk][cc], a1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 8; q < 20; ++q)
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(treg[q], Ws[4 * (q - tA) + lk][cc], a1, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                W2s[16 * t_rb0 + 4 * r + lk][cc] = a0[r];
+                W2s[16 * t_rb1 + 4 * r + lk][cc] = a1[r];
+            }
+        } else {
             double4_t a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
             const int n0 = 16 - 4 * t_rb0;
             const int cc = 16 * t_cb + li;
@@ -321,6 +359,10 @@ __global__ __launch_bounds__(256, 2) void q2_apply_step_kernel(int n, int b, int
 
 }  // namespace
 
+// columns of X per workgroup: wide slabs amortize the loads of V and T, narrow
+// ones keep enough workgroups in flight when X has few columns
+int q2_slab_width(int ncol) { return ncol >= 8192 ? 512 : (ncol >= 2048 ? 256 : 128); }
+
 size_t apply_q2_workspace_doubles(int n, int b)
 {
     const int ngroups = std::max(1, ceil_div(std::max(n - 2, 1), b));
@@ -328,21 +370,30 @@ size_t apply_q2_workspace_doubles(int n, int b)
     return (size_t)ngroups * kmax * NB2 * NB2;
 }
 
-// X (n x ncol) <- Q2 X; Tq: apply_q2_workspace_doubles(n, b) doubles.
+// X (n x ncol) <- Q2 X, or Q2^T X (trans); Tq: apply_q2_workspace_doubles(n, b)
+// doubles, rebuilt from the reflectors unless tq_ready says a previous call on
+// the same reflectors left it there.  slab: columns per workgroup (0 picks
+// q2_slab_width(ncol); otherwise 128, 256 or 512).
 void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const double* tau2, int kmax, double* X,
-              int ldx, double* Tq)
+              int ldx, double* Tq, bool trans, bool tq_ready, int slab)
 {
     if (n <= 2 || ncol <= 0) return;
     const int ngroups = ceil_div(n - 2, b);
-    hipLaunchKernelGGL(q2_build_t_kernel, dim3(ngroups, kmax), dim3(256), 0, st, n, b, V2, tau2, kmax, Tq);
-    const int qw = q2_slab_width(ncol);
+    if (!tq_ready)
+        hipLaunchKernelGGL(q2_build_t_kernel, dim3(ngroups, kmax), dim3(256), 0, st, n, b, V2, tau2, kmax, Tq);
+    const int qw = slab > 0 ? slab : q2_slab_width(ncol);
     const int nslab = ceil_div(ncol, qw);
     const int tmax = (ngroups - 1) + kmax;   // last step: g = 0 with its last block
-    for (int t = 0; t < tmax; ++t) {
+    for (int s = 0; s < tmax; ++s) {
+        const int t = trans ? tmax - 1 - s : s;
         const int nb = std::min(ngroups, t + 1);   // block index G-1-g ranges over 0 .. min(G-1, t)
         const int nwg = ceil_div(nb, 8) * 8 * nslab;
-        hipLaunchKernelGGL(q2_apply_step_kernel, dim3(nwg), dim3(256), 0, st, n, b, ncol, qw, t, nb, nslab, V2, Tq,
-                           kmax, X, ldx);
+        if (trans)
+            hipLaunchKernelGGL(q2_apply_step_kernel<true>, dim3(nwg), dim3(256), 0, st, n, b, ncol, qw, t, nb, nslab,
+                               V2, Tq, kmax, X, ldx);
+        else
+            hipLaunchKernelGGL(q2_apply_step_kernel<false>, dim3(nwg), dim3(256), 0, st, n, b, ncol, qw, t, nb, nslab,
+                               V2, Tq, kmax, X, ldx);
     }
 }
 
@@ -362,9 +413,10 @@ size_t apply_q1_workspace_doubles(int n, int ncol)
     return 2 * w * c + 8 * w * c + 2 * w * w + w * 64;
 }
 
-// X (n x ncol) <- Q1 X with the panel reflectors of step (1).
+// X (n x ncol) <- Q1 X with the panel reflectors of step (1), or Q1^T X
+// (trans: the groups first to last, each with its T'^T).
 void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const double* Tall, double* X, int ldx,
-              double* work)
+              double* work, bool trans)
 {
     if (ncol <= 0) return;
     const int wmax = Q1G * 64;
@@ -379,7 +431,9 @@ void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const 
     int nvalid = 0;
     while (n - (nvalid + 1) * b >= 2) ++nvalid;
     const int ngroups = ceil_div(nvalid, Q1G);
-    for (int g = ngroups - 1; g >= 0; --g) {
+    const char tt = trans ? 'T' : 'N';
+    for (int gi = 0; gi < ngroups; ++gi) {
+        const int g = trans ? gi : ngroups - 1 - gi;
         const int p0 = g * Q1G;
         const int np = std::min(Q1G, nvalid - p0);
         const int w = np * b;
@@ -390,7 +444,7 @@ void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const 
         const double* T = Tall + (size_t)p0 * b * b;
         if (np == 1) {
             dgemm_splitk(st, 'T', 'N', b, ncol, m, 1.0, V, n, X + r0, ldx, 0.0, W, wmax, part, npart);
-            dgemm(st, 'N', 'N', b, ncol, b, 1.0, T, b, W, wmax, 0.0, W2, wmax);
+            dgemm(st, tt, 'N', b, ncol, b, 1.0, T, b, W, wmax, 0.0, W2, wmax);
             dgemm(st, 'N', 'N', m, ncol, b, -1.0, V, n, W2, wmax, 1.0, X + r0, ldx);
             continue;
         }
@@ -405,7 +459,7 @@ void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const 
             dgemm(st, 'N', 'N', c, b, c, -1.0, Tg, wmax, tmp, wmax, 0.0, Tg + cm(0, c, wmax), wmax);
         }
         dgemm_splitk(st, 'T', 'N', w, ncol, m, 1.0, V, n, X + r0, ldx, 0.0, W, wmax, part, npart);
-        dgemm(st, 'N', 'N', w, ncol, w, 1.0, Tg, wmax, W, wmax, 0.0, W2, wmax);
+        dgemm(st, tt, 'N', w, ncol, w, 1.0, Tg, wmax, W, wmax, 0.0, W2, wmax);
         dgemm(st, 'N', 'N', m, ncol, w, -1.0, V, n, W2, wmax, 1.0, X + r0, ldx);
     }
 }

@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
+#include <cstdint>
 #include <condition_variable>
 #include <cstring>
 #include <mutex>
@@ -187,12 +189,11 @@ int elsi_gpu_dm_batched(elsi_gpu_handle h, int count, const int* n, const double
                         double* const* eval, double* energy, double* mu, int* status)
 {
     if (!h) return -1;
-    if (h->occ_scheme != ELSI_GPU_OCC_FERMI) return -1;
+    if (h->occ_scheme == ELSI_GPU_OCC_EXPLICIT) return -1;
     if (count < 0) return -2;
     if (count == 0) return 0;
     if (!n) return -3;
     if (!n_electron) return -4;
-    if (kweight) return -5;
     if (!H) return -6;
     if (!S && !h->overlap_is_unit) return -7;
     if (!D) return -8;
@@ -202,16 +203,66 @@ int elsi_gpu_dm_batched(elsi_gpu_handle h, int count, const int* n, const double
         if (n[p] < 1 || !(n_electron[p] >= 0.0) || n_electron[p] > 2.0 * n[p] || !H[p] ||
             (!h->overlap_is_unit && !S[p]) || !D[p])
             return -3;
+    if (kweight)
+        for (int p = 0; p < count; ++p)
+            if (!(kweight[p] > 0.0)) return -5;
+    if (!kweight)
+        return run_pool(h, count, n, status, [&](elsi_gpu_handle_s* w, int p) {
+            w->n = n[p];
+            w->band_width = batch_band(h, n[p]);
+            w->n_state = n[p];
+            w->n_electron = n_electron[p];
+            double e = 0.0, m = 0.0;
+            const int rc = elsi_gpu_dm(w, H[p], S ? S[p] : nullptr, nullptr, D[p], eval ? eval[p] : nullptr, &e, &m);
+            energy[p] = e;
+            if (mu) mu[p] = m;
+            return rc;
+        });
+
+    // One chemical potential for all problems (k-points and spin channels of
+    // one system, Sec. 4.5): every problem's eigenvalues first, then mu over
+    // all of them with each state weighted by its problem's weight, then each
+    // problem's density matrix with those occupations fixed.
+    std::vector<size_t> off((size_t)count + 1, 0);
+    for (int p = 0; p < count; ++p) off[p + 1] = off[p] + (size_t)n[p];
+    const size_t ntot = off[count];
+    if (ntot > (size_t)INT32_MAX) return -3;
+    DevBuf<double> E, Wt, F, scal;
+    if (!E.alloc(ntot) || !Wt.alloc(ntot) || !F.alloc(ntot) || !scal.alloc(8)) return kStatusOom;
+    int rc = run_pool(h, count, n, status, [&](elsi_gpu_handle_s* w, int p) {
+        w->n = n[p];
+        w->band_width = batch_band(h, n[p]);
+        w->n_state = n[p];
+        w->values_copies = 1;
+        return eigenvalues_only(w, H[p], S ? S[p] : nullptr, E.p + off[p]);
+    });
+    if (rc) return rc;
+    hipStream_t st = h->stream;
+    double ne = 0.0;
+    for (int p = 0; p < count; ++p) {
+        fill_d(st, Wt.p + off[p], (size_t)n[p], kweight[p]);
+        ne += kweight[p] * n_electron[p];
+    }
+    occupations(st, (int)ntot, E.p, Wt.p, h->occ_scheme, ne, h->kT, h->spin, h->occ_accuracy, h->mu_max_steps, kFCut,
+                F.p, scal.p);
+    double hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (hipMemcpyAsync(hs, scal.p, 6 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return kStatusHip;
+    rc = sync_status(st);
+    if (rc) return rc;
+    const double mu_all = hs[0];
+    const int mu_status = (int)hs[1];
     return run_pool(h, count, n, status, [&](elsi_gpu_handle_s* w, int p) {
         w->n = n[p];
         w->band_width = batch_band(h, n[p]);
         w->n_state = n[p];
         w->n_electron = n_electron[p];
+        w->occ_scheme = ELSI_GPU_OCC_EXPLICIT;
+        w->values_copies = 0;
         double e = 0.0, m = 0.0;
-        const int rc = elsi_gpu_dm(w, H[p], S ? S[p] : nullptr, nullptr, D[p], eval ? eval[p] : nullptr, &e, &m);
+        const int r = elsi_gpu_dm(w, H[p], S ? S[p] : nullptr, F.p + off[p], D[p], eval ? eval[p] : nullptr, &e, &m);
         energy[p] = e;
-        if (mu) mu[p] = m;
-        return rc;
+        if (mu) mu[p] = mu_all;
+        return r ? r : mu_status;
     });
 }
 

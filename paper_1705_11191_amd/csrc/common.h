@@ -218,11 +218,18 @@ void scale_columns_sqrt(hipStream_t st, int n, int k, const double* C, int ldc, 
                         double* out, int ldo);
 void check_finite(hipStream_t st, int m, int n, const double* A, int lda, int* flag);
 
-// Occupations and chemical potential on the device (one workgroup).
-//   eps ascending (n); f (n) out; scal (device, 4 doubles) out: mu, status, k_s, energy.
-void fermi_occupations(hipStream_t st, int n, const double* eps, double n_electron, double kT,
-                       double spin, double occ_accuracy, int max_steps, double f_cut,
-                       double* f, double* scal);
+// Occupations and chemical potential on the device (one workgroup) for a
+// broadening scheme (ELSI_GPU_OCC_FERMI, _GAUSSIAN, _MP0, _MP1) of width
+// `width`: eps (n; ascending within each problem), weight (n per-state
+// weights for a mu shared by several problems, or NULL); f (n) out, w_l f_l;
+// scal (device, 6 doubles) out: mu, status, k_s (one past the last |f| >
+// f_cut), energy sum f eps, bisection steps, surplus left.
+void occupations(hipStream_t st, int n, const double* eps, const double* weight, int scheme, double n_electron,
+                 double width, double spin, double occ_accuracy, int max_steps, double f_cut, double* f,
+                 double* scal);
+// out = C sqrt|f|, out2 = C sign(f) sqrt|f| (n x k, ldo): out out2^T = C F C^T.
+void scale_columns_signed(hipStream_t st, int n, int k, const double* C, int ldc, const double* f, double* out,
+                          double* out2, int ldo);
 
 // Explicit occupations: f given for all n states; scal: mu (0), status (0),
 // k_s (1 + last index with f > f_cut), energy (sum f eps).
@@ -264,9 +271,10 @@ int stedc(hipStream_t st, int n, const double* d, const double* e, double* w, do
 // Steps (4) and (5): back-transformations; see backtx.hip.
 size_t apply_q2_workspace_doubles(int n, int b);
 void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const double* tau2, int kmax,
-              double* X, int ldx, double* Tq);
+              double* X, int ldx, double* Tq, bool trans = false, bool tq_ready = false, int slab = 0);
+int q2_slab_width(int ncol);
 size_t apply_q1_workspace_doubles(int n, int ncol);
 void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const double* Tall, double* X,
-              int ldx, double* work);
+              int ldx, double* work, bool trans = false);
 
 }  // namespace eg

@@ -587,12 +587,22 @@ const char* kNames[kIds] = {
 void enable(bool on)
 {
     State& s = state();
+    std::lock_guard<std::mutex> lk(s.mu);
     if (on && s.ev.empty()) {
         s.ev.resize(2 * kSlots, nullptr);
         for (auto& e : s.ev)
             if (hipEventCreate(&e) != hipSuccess) { e = nullptr; }
         s.id.assign(kSlots, 0);
         s.flops.assign(kSlots, 0.0);
+        s.used = 0;
+    }
+    if (!on && !s.ev.empty()) {
+        // switching the timing off returns the events to the runtime, so that
+        // none outlives the caller's use of the library
+        for (auto& e : s.ev)
+            if (e) (void)hipEventDestroy(e);
+        s.ev.clear();
+        s.used = 0;
     }
     s.on = on;
 }
@@ -604,7 +614,7 @@ int begin(hipStream_t st)
     State& s = state();
     if (!s.on) return -1;
     std::lock_guard<std::mutex> lk(s.mu);
-    if (s.used >= kSlots || !s.ev[2 * s.used] || !s.ev[2 * s.used + 1]) return -1;
+    if (!s.on || s.ev.empty() || s.used >= kSlots || !s.ev[2 * s.used] || !s.ev[2 * s.used + 1]) return -1;
     const int slot = s.used++;
     (void)hipEventRecord(s.ev[2 * slot], st);
     return slot;
@@ -614,6 +624,7 @@ void end(hipStream_t st, int slot, int kernel_id, double flops)
 {
     State& s = state();
     std::lock_guard<std::mutex> lk(s.mu);
+    if (slot < 0 || 2 * (size_t)slot + 1 >= s.ev.size()) return;   // timing switched off meanwhile
     (void)hipEventRecord(s.ev[2 * slot + 1], st);
     s.id[slot] = kernel_id;
     s.flops[slot] = flops;

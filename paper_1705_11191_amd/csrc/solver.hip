@@ -23,17 +23,18 @@ void reduce_to_standard(hipStream_t st, int n, double* H, int ldh, const double*
     mirror_lower_to_upper(st, n, H, ldh);
 }
 
-// Eq. (9): D = sum_l f_l c_l c_l^T = (C F^1/2)(C F^1/2)^T, lower tiles on the
-// matrix cores, then mirrored.
-void density_matrix(hipStream_t st, int n, int k, const double* C, int ldc, const double* f, double* W,
+// Eq. (9): D = sum_l f_l c_l c_l^T = (C |F|^1/2)(C sign(F) |F|^1/2)^T (the
+// two factors are equal when every f_l >= 0), lower tiles on the matrix
+// cores, then mirrored.
+void density_matrix(hipStream_t st, int n, int k, const double* C, int ldc, const double* f, double* W, double* W2,
                     double* D, int ldd)
 {
     if (k <= 0) {
         for (int j = 0; j < n; ++j) fill_d(st, D + cm(0, j, ldd), (size_t)n, 0.0);
         return;
     }
-    scale_columns_sqrt(st, n, k, C, ldc, f, W, n);
-    dgemm(st, 'N', 'T', n, n, k, 1.0, W, n, W, n, 0.0, D, ldd, 1);
+    scale_columns_signed(st, n, k, C, ldc, f, W, W2, n);
+    dgemm(st, 'N', 'T', n, n, k, 1.0, W, n, W2, n, 0.0, D, ldd, 1);
     mirror_lower_to_upper(st, n, D, ldd);
 }
 
@@ -42,11 +43,16 @@ void density_matrix(hipStream_t st, int n, int k, const double* C, int ldc, cons
 // ---------------------------------------------------------------------------
 struct Layout {
     size_t linv, bd, vall, tall, v2, tau2, tq2, d, e, w, z, z2, u, sywork, dcwork, q1work, f, scal, ints;
-    size_t hcopy;   // mixed precision: the band reduction's copy of H~ (H keeps H~ for the refinement)
+    // mixed precision: the band reduction's copy of H~ (H keeps H~ for the
+    // refinement), which afterwards holds the eigenvectors of T of the carried
+    // states; the refinement's k' x k' blocks, per-state values and the
+    // factors of its tridiagonal solves
+    size_t hcopy, rg, rq, rtheta, rres, rstep, tri1, trisw;
+    size_t hv, sv;   // eigenvalue pass of a shared-mu batch: copies of H and S (the inputs stay intact)
     size_t total;
 };
 
-static Layout make_layout(int n, int b, int ncol, bool mixed = false)
+static Layout make_layout(int n, int b, int ncol, bool mixed = false, bool vcopy = false)
 {
     Layout L{};
     size_t off = 0;
@@ -71,7 +77,20 @@ static Layout make_layout(int n, int b, int ncol, bool mixed = false)
     L.f = put(sizeof(double) * n);
     L.scal = put(sizeof(double) * 16);
     L.ints = put(sizeof(int) * ((size_t)n + 64));
-    L.hcopy = mixed ? put(sizeof(double) * nn) : 0;
+    if (mixed) {
+        L.hcopy = put(sizeof(double) * nn);
+        L.rg = put(sizeof(double) * nn);
+        L.rq = put(sizeof(double) * nn);
+        L.rtheta = put(sizeof(double) * n);
+        L.rres = put(sizeof(double) * n);
+        L.rstep = put(sizeof(double) * n);
+        L.tri1 = put(sizeof(double) * nn);
+        L.trisw = put(nn);
+    }
+    if (vcopy) {
+        L.hv = put(sizeof(double) * nn);
+        L.sv = put(sizeof(double) * nn);
+    }
     L.total = off;
     return L;
 }
@@ -105,7 +124,7 @@ size_t workspace_bytes(const elsi_gpu_handle_s* h)
         const size_t base = make_layout(2 * h->n, h->band_width, 2 * h->n).total;
         return make_clayout(base, h->n).total;
     }
-    return make_layout(h->n, h->band_width, h->n, h->precision == ELSI_GPU_PREC_MIXED).total;
+    return make_layout(h->n, h->band_width, h->n, h->precision == ELSI_GPU_PREC_MIXED, h->values_copies != 0).total;
 }
 
 void release_workspace(elsi_gpu_handle_s* h)
@@ -256,13 +275,15 @@ static void back_substitute(elsi_gpu_handle_s* h, double* S, char* ws, const Lay
 }
 
 // X (n x k, in Z) <- L^-T Q1 Q2 X: steps (4), (5) and the back substitution.
+// zsave (n x k, may be NULL) receives the eigenvectors of T before step (4).
 static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L, Timer& tm, int k, DcState* dc,
-                      bool backsub = true)
+                      bool backsub = true, double* zsave = nullptr)
 {
     hipStream_t st = h->stream;
     const int n = h->n, b = std::min(h->band_width, std::max(1, n - 1));
     double* X = (double*)(ws + L.z);
     stedc_vectors(st, *dc, k);   // top merge of step (3) restricted to the k wanted columns
+    if (zsave) copy_matrix(st, n, k, X, n, zsave, n);
     tm.mark(ELSI_GPU_ST_TRIDIAG);
     apply_q2(st, n, b, k, (double*)(ws + L.v2), (double*)(ws + L.tau2), sb2st_kmax(n, b), X, n,
              (double*)(ws + L.tq2));
@@ -275,33 +296,80 @@ static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L
     if (backsub) back_substitute(h, S, ws, L, tm, k);
 }
 
+// The factorization H~ ~ (Q1 Q2) T (Q1 Q2)^T left by steps (1) and (2): Q1 from
+// the panel reflectors, Q2 from the bulge-chasing reflectors (their block T
+// factors already built by the forward application of step (4)).
+struct ReflectorPrecond : RefinePrecond {
+    int n = 0, b = 0, kmax = 0;
+    const double *Vall = nullptr, *Tall = nullptr, *V2 = nullptr, *tau2 = nullptr;
+    double *Tq = nullptr, *q1work = nullptr;
+    void apply_qt(hipStream_t st, double* X, int ld, int ncol, double* tmp) override
+    {
+        (void)tmp;
+        apply_q1(st, n, b, ncol, Vall, Tall, X, ld, q1work, true);
+        apply_q2(st, n, b, ncol, V2, tau2, kmax, X, ld, Tq, true, true);
+    }
+    void apply_q(hipStream_t st, double* X, int ld, int ncol, double* tmp) override
+    {
+        (void)tmp;
+        apply_q2(st, n, b, ncol, V2, tau2, kmax, X, ld, Tq, false, true);
+        apply_q1(st, n, b, ncol, Vall, Tall, X, ld, q1work, false);
+    }
+};
+
 // Mixed precision: FP64 refinement of the k' columns in Z against H~ (held in
-// H); on return Z holds the refined vectors and w[0 .. k') their Ritz values.
-// kw leading states decide convergence.  Returns 0, kStatusRefine (outputs
-// usable, tolerance not reached) or an error.
+// H), with the Newton correction through the reduced-precision factorization;
+// the eigenvectors of T of the k' states are in hcopy.  On return Z holds the
+// refined vectors and w[0 .. k') their Ritz values.  kw leading states decide
+// convergence, each step weighted by weight[l] (device; NULL: 1).  Returns 0,
+// kStatusRefine (outputs usable, tolerance not reached) or an error.
 static int refine_states(elsi_gpu_handle_s* h, const double* Ht, char* ws, const Layout& L, Timer& tm, int kp,
-                         int kw)
+                         int kw, const double* weight)
 {
     hipStream_t st = h->stream;
     const int n = h->n, b = std::min(h->band_width, std::max(1, n - 1));
-    double* const bufs[3] = {(double*)(ws + L.z), (double*)(ws + L.z2), (double*)(ws + L.u)};
-    // free after the back-transformations: the reflector stores (k' x k'
-    // products), the diagonal-block inverses (rebuilt for the back
-    // substitution), d and e, and the band reduction's scratch
+    RefineBuffers B{};
+    B.X[0] = (double*)(ws + L.z);
+    B.X[1] = (double*)(ws + L.z2);
+    B.X[2] = (double*)(ws + L.u);
+    B.ldb = n;
+    B.G = (double*)(ws + L.rg);
+    B.Qm = (double*)(ws + L.rq);
+    B.Linv = (double*)(ws + L.linv);   // rebuilt for the back substitution
+    B.theta = (double*)(ws + L.rtheta);
+    B.r = (double*)(ws + L.rres);
+    B.step = (double*)(ws + L.rstep);
+    B.dinfo = (int*)(ws + L.ints) + 8;
+    B.part = (double*)(ws + L.sywork);   // free after step (1)
+    B.npart = sy2sb_workspace_doubles(n, b);
+    B.U1 = (double*)(ws + L.tri1);
+    B.SW = (unsigned char*)(ws + L.trisw);
+    ReflectorPrecond pc;
+    pc.n = n;
+    pc.b = b;
+    pc.kmax = sb2st_kmax(n, b);
+    pc.Vall = (const double*)(ws + L.vall);
+    pc.Tall = (const double*)(ws + L.tall);
+    pc.V2 = (const double*)(ws + L.v2);
+    pc.tau2 = (const double*)(ws + L.tau2);
+    pc.Tq = (double*)(ws + L.tq2);
+    pc.q1work = (double*)(ws + L.q1work);
+    pc.Z = (const double*)(ws + L.hcopy);
+    pc.ldz = n;
+    pc.d = (const double*)(ws + L.d);
+    pc.e = (const double*)(ws + L.e);
     RefineOutcome out{};
-    int rc = refine_subspace(st, n, kp, kw, Ht, n, bufs, n, (double*)(ws + L.vall), (double*)(ws + L.v2),
-                             (double*)(ws + L.linv), (int*)(ws + L.ints) + 8, (double*)(ws + L.sywork),
-                             sy2sb_workspace_doubles(n, b), (double*)(ws + L.d), (double*)(ws + L.e),
-                             h->refine_tol, h->max_refine, &out);
+    int rc = refine_subspace(st, n, kp, kw, Ht, n, B, &pc, weight, h->refine_tol, h->max_refine, &out);
     if (rc && rc != kStatusRefine) return rc;
     if (out.sweeps > 0) {
-        if (out.x_buf != 0) copy_matrix(st, n, kp, bufs[out.x_buf], n, bufs[0], n);
-        if (hipMemcpyAsync(ws + L.w, ws + L.d, sizeof(double) * kp, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        if (out.x_buf != 0) copy_matrix(st, n, kp, B.X[out.x_buf], n, B.X[0], n);
+        if (hipMemcpyAsync(ws + L.w, B.theta, sizeof(double) * kp, hipMemcpyDeviceToDevice, st) != hipSuccess)
             return kStatusHip;
     }
     h->info.refine_sweeps = out.sweeps;
     h->info.refine_states = kp;
     h->info.refine_resid = out.rmax;
+    h->info.refine_step = out.smax;
     tm.mark(ELSI_GPU_ST_REFINE);
     return (rc == kStatusRefine || !out.converged) ? kStatusRefine : 0;
 }
@@ -355,6 +423,7 @@ static int ev_real(elsi_gpu_handle_s* h, double* H, double* S, double* eval, dou
     h->info.refine_sweeps = 0;
     h->info.refine_states = 0;
     h->info.refine_resid = 0.0;
+    h->info.refine_step = 0.0;
     Timer tm(st);
     DcState dc;
     rc = front_half(h, H, S, ws, L, tm, &dc);
@@ -362,8 +431,8 @@ static int ev_real(elsi_gpu_handle_s* h, double* H, double* S, double* eval, dou
     int rstat = 0;
     if (mixed) {
         const int kp = refine_columns(n, k);
-        back_half(h, S, ws, L, tm, kp, &dc, false);
-        rstat = refine_states(h, H, ws, L, tm, kp, k);
+        back_half(h, S, ws, L, tm, kp, &dc, false, (double*)(ws + L.hcopy));
+        rstat = refine_states(h, H, ws, L, tm, kp, k, nullptr);
         if (rstat && rstat != kStatusRefine) { tm.finish(&h->info); return rstat; }
         back_substitute(h, S, ws, L, tm, k);
     } else {
@@ -401,6 +470,7 @@ static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, doub
     h->info.refine_sweeps = 0;
     h->info.refine_states = 0;
     h->info.refine_resid = 0.0;
+    h->info.refine_step = 0.0;
     Timer tm(st);
     DcState dc;
     rc = front_half(h, H, S, ws, L, tm, &dc);
@@ -412,14 +482,14 @@ static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, doub
     int ks = 0;
     double hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     auto occupy = [&]() -> int {
-        if (h->occ_scheme == ELSI_GPU_OCC_FERMI)
-            fermi_occupations(st, n, w, h->n_electron, h->kT, h->spin, h->occ_accuracy, h->mu_max_steps, kFCut, f,
-                              scal);
+        if (h->occ_scheme != ELSI_GPU_OCC_EXPLICIT)
+            occupations(st, n, w, nullptr, h->occ_scheme, h->n_electron, h->kT, h->spin, h->occ_accuracy,
+                        h->mu_max_steps, kFCut, f, scal);
         else
             explicit_occupations(st, n, h->n_state, w, f, kFCut, scal);
         if (hipMemcpyAsync(hs, scal, 6 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return kStatusHip;
         if (hipStreamSynchronize(st) != hipSuccess) return kStatusHip;
-        status = (h->occ_scheme == ELSI_GPU_OCC_FERMI) ? (int)hs[1] : 0;
+        status = (h->occ_scheme != ELSI_GPU_OCC_EXPLICIT) ? (int)hs[1] : 0;
         ks = (int)hs[2];
         return 0;
     };
@@ -430,8 +500,8 @@ static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, doub
         // refine k_s states plus guards, then take the occupations again from
         // the refined eigenvalues
         const int kp = refine_columns(n, ks);
-        back_half(h, S, ws, L, tm, kp, &dc, false);
-        rstat = refine_states(h, H, ws, L, tm, kp, ks);
+        back_half(h, S, ws, L, tm, kp, &dc, false, (double*)(ws + L.hcopy));
+        rstat = refine_states(h, H, ws, L, tm, kp, ks, f);   // each state weighted by its occupation
         if (rstat && rstat != kStatusRefine) { tm.finish(&h->info); return rstat; }
         if ((rc = occupy())) return rc;
         ks = std::min(ks, kp);
@@ -440,7 +510,7 @@ static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, doub
     } else {
         back_half(h, S, ws, L, tm, ks, &dc);
     }
-    density_matrix(st, n, ks, (double*)(ws + L.z), n, f, (double*)(ws + L.z2), D, n);
+    density_matrix(st, n, ks, (double*)(ws + L.z), n, f, (double*)(ws + L.z2), (double*)(ws + L.u), D, n);
     tm.mark(ELSI_GPU_ST_DENSITY);
     if (eval) (void)hipMemcpyAsync(eval, w, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
     rc = sync_status(st);
@@ -586,7 +656,7 @@ static int dm_complex(elsi_gpu_handle_s* h, double* H, double* S, double* occ, d
     extract_complex(st, n, D2, n2, D, n, false);
     if (eval) pair_values(st, n, (const double*)(ws + L.w), eval);
     // Fermi-Dirac occupations of the states: the mean over each real pair
-    if (occ && h->occ_scheme == ELSI_GPU_OCC_FERMI) pair_values(st, n, (const double*)(ws + L.f), occ);
+    if (occ && h->occ_scheme != ELSI_GPU_OCC_EXPLICIT) pair_values(st, n, (const double*)(ws + L.f), occ);
     if (S2 && !h->overlap_factored) extract_complex(st, n, S2, n2, S, n, true);
     rc = sync_status(st);
     if (rc) return rc;
@@ -596,12 +666,272 @@ static int dm_complex(elsi_gpu_handle_s* h, double* H, double* S, double* occ, d
     return rc2;
 }
 
+// All n eigenvalues of the pencil (ascending), with H and S only read: the
+// steps up to divide and conquer run on copies (real handles; the handle must
+// carry values_copies for the workspace), or on the real image (complex
+// handles, R8: each value the mean of its pair).
+int eg::eigenvalues_only(elsi_gpu_handle_s* h, const double* H, const double* S, double* eval)
+{
+    if (!H) return -2;
+    if (!S && !h->overlap_is_unit) return -3;
+    if (!eval) return -4;
+    int rc = ensure_workspace(h);
+    if (rc) return rc < 0 ? -1 : rc;
+    hipStream_t st = h->stream;
+    const int n = h->n;
+    char* ws = (char*)h->ws;
+    std::memset(h->info.stage_ms, 0, sizeof(h->info.stage_ms));
+    h->info.fail_col = 0;
+    if (h->dtype == ELSI_GPU_COMPLEX128) {
+        const int n2 = 2 * n;
+        const Layout L = make_layout(n2, h->band_width, n2);
+        const CLayout C = make_clayout(L.total, n);
+        double* H2 = (double*)(ws + C.h2);
+        double* S2 = h->overlap_is_unit ? nullptr : (double*)(ws + C.s2);
+        embed_complex(st, n, H, n, H2, n2, false);
+        if (S2) embed_complex(st, n, S, n, S2, n2, h->overlap_factored != 0);
+        elsi_gpu_handle_s r = inner_handle(h, n2);
+        r.info.band_width = std::min(r.band_width, std::max(1, n2 - 1));
+        Timer tm(st);
+        DcState dc;
+        rc = front_half(&r, H2, S2, ws, L, tm, &dc);
+        tm.finish(&r.info);
+        complex_info(h, r);
+        if (rc) return rc;
+        pair_values(st, n, (const double*)(ws + L.w), eval);
+        rc = sync_status(st);
+        if (rc) return rc;
+        return read_flags(st, ws, L);
+    }
+    const Layout L = make_layout(n, h->band_width, n, false, true);
+    double* Hc = (double*)(ws + L.hv);
+    double* Sc = h->overlap_is_unit ? nullptr : (double*)(ws + L.sv);
+    copy_matrix(st, n, n, H, n, Hc, n);
+    if (Sc) copy_matrix(st, n, n, S, n, Sc, n);
+    h->info.band_width = std::min(h->band_width, std::max(1, n - 1));
+    Timer tm(st);
+    DcState dc;
+    rc = front_half(h, Hc, Sc, ws, L, tm, &dc);
+    tm.finish(&h->info);
+    if (rc) return rc;
+    (void)hipMemcpyAsync(eval, ws + L.w, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    rc = sync_status(st);
+    if (rc) return rc;
+    return read_flags(st, ws, L);
+}
+
+// ---------------------------------------------------------------------------
+// Singularity check of the overlap and the eigendecomposition transform
+// (Sec. 4.5, Eq. (20)): when S has an eigenvalue below tau, S = x lam x^T =
+// X X^T replaces the Cholesky factor, and only the m = N_nonsing eigenvectors
+// with lam >= tau are kept: Y = x_keep lam_keep^(-1/2) (n x m), the standard
+// problem H~ = Y^T H Y of size m is solved, and c = Y c~.
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ void scale_cols_kernel(int n, int m, const double* A, int lda, const double* v, int first, int mode,
+                                  double* B, int ldb)
+{
+    // mode 0: B(:, j) = A(:, first + j) / sqrt(v[first + j]);  mode 1: times sqrt;
+    // mode 2: B(:, j) = A(:, j) / v[j]
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= n || j >= m) return;
+    if (mode == 2) {
+        B[cm(i, j, ldb)] = A[cm(i, j, lda)] / v[j];
+        return;
+    }
+    const double s = sqrt(v[first + j]);
+    B[cm(i, j, ldb)] = (mode == 0) ? A[cm(i, first + j, lda)] / s : A[cm(i, first + j, lda)] * s;
+}
+
+__global__ void col_sqnorm_kernel(int n, const double* A, int lda, double* out)
+{
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += A[cm(i, j, lda)] * A[cm(i, j, lda)];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// A sub-handle for a standard (S = I) problem of size m on the caller's stream,
+// with the caller's occupation settings.
+int standard_subhandle(const elsi_gpu_handle_s* h, int m, int n_state, elsi_gpu_handle* out)
+{
+    int rc = elsi_gpu_init(out, ELSI_GPU_REAL64, m, n_state, std::min(h->n_electron, (double)m * h->spin), h->stream);
+    if (rc) return rc > 0 ? rc : kStatusHip;
+    (*out)->overlap_is_unit = 1;
+    (*out)->occ_scheme = h->occ_scheme;
+    (*out)->kT = h->kT;
+    (*out)->occ_accuracy = h->occ_accuracy;
+    (*out)->mu_max_steps = h->mu_max_steps;
+    (*out)->spin = h->spin;
+    (*out)->band_width = h->band_width;
+    return 0;
+}
+
+struct SubHandle {
+    elsi_gpu_handle h = nullptr;
+    ~SubHandle() { if (h) elsi_gpu_finalize(&h); }
+};
+
+// Decide the route and, for the eigendecomposition one, build Y (n x m).
+// Returns 0 with *m = 0 for the Cholesky route, 0 with *m > 0 and Y filled,
+// or an error.  S is overwritten by X on the eigendecomposition route.
+int overlap_transform(elsi_gpu_handle_s* h, double* S, DevBuf<double>& Y, int* m_out)
+{
+    hipStream_t st = h->stream;
+    const int n = h->n;
+    *m_out = 0;
+    if (h->overlap_factored) {
+        const int m = h->sing_m;
+        if (m <= 0) return 0;   // S holds L
+        // S holds X (n x m): lam_j = ||X_j||^2, Y_j = X_j / lam_j
+        DevBuf<double> lam;
+        if (!Y.alloc((size_t)n * m) || !lam.alloc(m)) return kStatusOom;
+        hipLaunchKernelGGL(col_sqnorm_kernel, dim3(m), dim3(256), 0, st, n, S, n, lam.p);
+        hipLaunchKernelGGL(scale_cols_kernel, dim3(ceil_div(n, 256), m), dim3(256), 0, st, n, m, S, n, lam.p, 0, 2,
+                           Y.p, n);
+        *m_out = m;
+        return sync_status(st);
+    }
+    if (!h->sing_check) {
+        h->sing_m = 0;
+        return 0;
+    }
+    // all eigenvalues of S, by the library's own path with S as a standard matrix
+    DevBuf<double> Sc, lam, xv;
+    if (!Sc.alloc((size_t)n * n) || !lam.alloc(n) || !xv.alloc((size_t)n * n)) return kStatusOom;
+    copy_matrix(st, n, n, S, n, Sc.p, n);
+    SubHandle sub;
+    int rc = standard_subhandle(h, n, n, &sub.h);
+    if (rc) return rc;
+    rc = elsi_gpu_ev(sub.h, Sc.p, nullptr, lam.p, xv.p);
+    if (rc) return rc;
+    std::vector<double> hl((size_t)n);
+    if (hipMemcpyAsync(hl.data(), lam.p, sizeof(double) * n, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return kStatusHip;
+    rc = sync_status(st);
+    if (rc) return rc;
+    h->info.overlap_min_eig = hl[0];
+    if (hl[0] >= h->sing_tol) {   // not singular: the Cholesky route
+        h->sing_m = 0;
+        return 0;
+    }
+    int m = 0;
+    for (int l = 0; l < n; ++l) m += (hl[l] >= h->sing_tol) ? 1 : 0;
+    if (m == 0) return kStatusNotPD;
+    const int first = n - m;
+    if (!Y.alloc((size_t)n * m)) return kStatusOom;
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(ceil_div(n, 256), m), dim3(256), 0, st, n, m, xv.p, n, lam.p, first, 0,
+                       Y.p, n);
+    // S <- X = x_keep lam_keep^(1/2), the remaining columns zero
+    fill_d(st, S, (size_t)n * n, 0.0);
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(ceil_div(n, 256), m), dim3(256), 0, st, n, m, xv.p, n, lam.p, first, 1,
+                       S, n);
+    h->sing_m = m;
+    *m_out = m;
+    return sync_status(st);
+}
+
+// H~ = Y^T H Y (m x m, full) into Ht; H symmetric, lower triangle read.
+void transform_h(hipStream_t st, int n, int m, const double* H, const double* Y, double* W, double* Ht)
+{
+    dgemm(st, 'S', 'N', n, m, n, 1.0, H, n, Y, n, 0.0, W, n);
+    dgemm(st, 'T', 'N', m, m, n, 1.0, Y, n, W, n, 0.0, Ht, m);
+    symmetrize_average(st, m, Ht, m);
+}
+
+int ev_singular(elsi_gpu_handle_s* h, double* H, const DevBuf<double>& Y, int m, double* eval, double* evec)
+{
+    hipStream_t st = h->stream;
+    const int n = h->n, k = h->n_state, km = std::min(k, m);
+    DevBuf<double> W, Ht, Ct;
+    if (!W.alloc((size_t)n * m) || !Ht.alloc((size_t)m * m) || !Ct.alloc((size_t)m * km)) return kStatusOom;
+    transform_h(st, n, m, H, Y.p, W.p, Ht.p);
+    SubHandle sub;
+    int rc = standard_subhandle(h, m, km, &sub.h);
+    if (rc) return rc;
+    rc = elsi_gpu_ev(sub.h, Ht.p, nullptr, W.p, Ct.p);   // eigenvalues into W (m doubles)
+    if (rc) return rc;
+    (void)hipMemcpyAsync(eval, W.p, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
+    if (m < n) fill_d(st, eval + m, (size_t)(n - m), HUGE_VAL);
+    dgemm(st, 'N', 'N', n, km, m, 1.0, Y.p, n, Ct.p, m, 0.0, evec, n);   // c = Y c~
+    if (km < k) fill_d(st, evec + (size_t)n * km, (size_t)n * (k - km), 0.0);
+    h->info.n_nonsing = m;
+    return sync_status(st);
+}
+
+int dm_singular(elsi_gpu_handle_s* h, double* H, const DevBuf<double>& Y, int m, double* occ, double* D, double* eval,
+                double* energy, double* mu)
+{
+    hipStream_t st = h->stream;
+    const int n = h->n;
+    DevBuf<double> W, Ht, Dt, ev, f, T1;
+    if (!W.alloc((size_t)n * m) || !Ht.alloc((size_t)m * m) || !Dt.alloc((size_t)m * m) || !ev.alloc(m) ||
+        !f.alloc(m) || !T1.alloc((size_t)m * n))
+        return kStatusOom;
+    transform_h(st, n, m, H, Y.p, W.p, Ht.p);
+    SubHandle sub;
+    int rc = standard_subhandle(h, m, m, &sub.h);
+    if (rc) return rc;
+    const bool explicit_occ = h->occ_scheme == ELSI_GPU_OCC_EXPLICIT;
+    if (explicit_occ) (void)hipMemcpyAsync(f.p, occ, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
+    double e = 0.0, mm = 0.0;
+    const int rcd = elsi_gpu_dm(sub.h, Ht.p, nullptr, f.p, Dt.p, ev.p, &e, &mm);
+    if (rcd != 0 && rcd != ELSI_GPU_ERR_MU) return rcd;
+    // D = Y D~ Y^T: T1 = D~ Y^T, then the lower tiles of Y T1, mirrored
+    dgemm(st, 'N', 'T', m, n, m, 1.0, Dt.p, m, Y.p, n, 0.0, T1.p, m);
+    dgemm(st, 'N', 'N', n, n, m, 1.0, Y.p, n, T1.p, m, 0.0, D, n, 1);
+    mirror_lower_to_upper(st, n, D, n);
+    if (eval) {
+        (void)hipMemcpyAsync(eval, ev.p, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
+        if (m < n) fill_d(st, eval + m, (size_t)(n - m), HUGE_VAL);
+    }
+    if (occ && !explicit_occ) {
+        (void)hipMemcpyAsync(occ, f.p, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
+        if (m < n) fill_d(st, occ + m, (size_t)(n - m), 0.0);
+    }
+    elsi_gpu_info sinfo;
+    elsi_gpu_get_info(sub.h, &sinfo);
+    h->info.mu = sinfo.mu;
+    h->info.energy = sinfo.energy;
+    h->info.k_s = sinfo.k_s;
+    h->info.mu_steps = sinfo.mu_steps;
+    h->info.charge_residual = sinfo.charge_residual;
+    h->info.n_nonsing = m;
+    *energy = e;
+    if (mu) *mu = mm;
+    rc = sync_status(st);
+    return rc ? rc : rcd;
+}
+
+}  // namespace
+
 extern "C" {
 
 int elsi_gpu_ev(elsi_gpu_handle h, double* H, double* S, double* eval, double* evec)
 {
     if (!h) return -1;
     if (h->dtype == ELSI_GPU_COMPLEX128) return ev_complex(h, H, S, eval, evec);
+    h->info.n_nonsing = h->n;
+    h->info.overlap_min_eig = 0.0;
+    if (!h->overlap_is_unit && S && (h->sing_check || (h->overlap_factored && h->sing_m > 0))) {
+        if (!H) return -2;
+        if (!eval) return -4;
+        if (!evec) return -5;
+        DevBuf<double> Y;
+        int m = 0;
+        const int rc = overlap_transform(h, S, Y, &m);
+        if (rc) return rc;
+        if (m > 0) return ev_singular(h, H, Y, m, eval, evec);
+    }
     return ev_real(h, H, S, eval, evec);
 }
 
@@ -610,6 +940,19 @@ int elsi_gpu_dm(elsi_gpu_handle h, double* H, double* S, double* occ, double* D,
 {
     if (!h) return -1;
     if (h->dtype == ELSI_GPU_COMPLEX128) return dm_complex(h, H, S, occ, D, eval, energy, mu);
+    h->info.n_nonsing = h->n;
+    h->info.overlap_min_eig = 0.0;
+    if (!h->overlap_is_unit && S && (h->sing_check || (h->overlap_factored && h->sing_m > 0))) {
+        if (!H) return -2;
+        if (!occ && h->occ_scheme == ELSI_GPU_OCC_EXPLICIT) return -4;
+        if (!D) return -5;
+        if (!energy) return -7;
+        DevBuf<double> Y;
+        int m = 0;
+        const int rc = overlap_transform(h, S, Y, &m);
+        if (rc) return rc;
+        if (m > 0) return dm_singular(h, H, Y, m, occ, D, eval, energy, mu);
+    }
     return dm_real(h, H, S, occ, D, eval, energy, mu);
 }
 

@@ -1,6 +1,7 @@
 // Element-wise helpers, the density-matrix column scaling and the chemical
 // potential / occupation kernel.
 #include "common.h"
+#include "../../include/elsi_gpu.h"
 
 namespace eg {
 namespace {
@@ -96,6 +97,24 @@ __global__ void scale_sqrt_kernel(int n, int k, const double* C, int ldc, const 
     }
 }
 
+// out = C sqrt|f| and out2 = C sign(f) sqrt|f| (columnwise), so that
+// out out2^T = C diag(f) C^T for occupations of either sign
+__global__ void scale_signed_kernel(int n, int k, const double* C, int ldc, const double* f, double* out,
+                                   double* out2, int ldo)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    for (; j < k; j += gridDim.y) {
+        const double fj = f[j];
+        const double s = sqrt(fabs(fj));
+        if (i < n) {
+            const double v = s * C[cm(i, j, ldc)];
+            out[cm(i, j, ldo)] = v;
+            out2[cm(i, j, ldo)] = (fj < 0.0) ? -v : v;
+        }
+    }
+}
+
 __global__ void finite_kernel(int m, int n, const double* A, int lda, int* flag)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -116,9 +135,18 @@ __global__ void finite_kernel(int m, int n, const double* A, int lda, int* flag)
 // ---------------------------------------------------------------------------
 constexpr int FD_THREADS = 1024;
 
-__device__ inline double fd_occ(double eps, double mu, double kT, double spin)
+// Occupation of one state, x = (eps - mu) / width, for the broadening schemes
+// (Sec. 4.6): Fermi-Dirac, Eq. (17), without overflowing exponentials;
+// Gaussian, Eq. (21), f = spin (1 - erf x) / 2 = spin erfc(x) / 2;
+// Methfessel-Paxton order 0 (the Gaussian step) and order 1,
+// f = spin (erfc(x) / 2 - x e^{-x^2} / (2 sqrt(pi))) (Methfessel & Paxton,
+// Phys. Rev. B 40, 3616 (1989)), which leaves [0, spin] near mu.
+__device__ inline double occ_value(int scheme, double eps, double mu, double width, double spin)
 {
-    double x = (eps - mu) / kT;
+    const double x = (eps - mu) / width;
+    if (scheme == ELSI_GPU_OCC_GAUSSIAN || scheme == ELSI_GPU_OCC_MP0) return spin * 0.5 * erfc(x);
+    if (scheme == ELSI_GPU_OCC_MP1)
+        return spin * (0.5 * erfc(x) - x * exp(-x * x) / (2.0 * sqrt(3.14159265358979323846)));
     if (x >= 0.0) {
         double t = exp(-x);
         return spin * t / (1.0 + t);
@@ -142,27 +170,65 @@ __device__ double block_sum(double v, double* red)
     return red[FD_THREADS / 64];
 }
 
-__device__ double count_electrons(int n, const double* eps, double mu, double kT, double spin, double* red)
+// max (is_max) or min of v over the block
+__device__ double block_extreme(double v, double* red, bool is_max)
+{
+    const int tid = threadIdx.x;
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_down(v, off, 64);
+        v = is_max ? fmax(v, o) : fmin(v, o);
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        double s = red[0];
+        for (int w = 1; w < FD_THREADS / 64; ++w) s = is_max ? fmax(s, red[w]) : fmin(s, red[w]);
+        red[FD_THREADS / 64] = s;
+    }
+    __syncthreads();
+    return red[FD_THREADS / 64];
+}
+
+// electrons at mu: sum_l w_l f_l (w NULL: all 1)
+__device__ double count_electrons(int n, const double* eps, const double* w, int scheme, double mu, double width,
+                                  double spin, double* red)
 {
     double s = 0.0;
-    for (int l = threadIdx.x; l < n; l += FD_THREADS) s += fd_occ(eps[l], mu, kT, spin);
+    for (int l = threadIdx.x; l < n; l += FD_THREADS) s += (w ? w[l] : 1.0) * occ_value(scheme, eps[l], mu, width, spin);
     return block_sum(s, red);
 }
 
-__global__ __launch_bounds__(FD_THREADS) void fermi_kernel(int n, const double* eps, double ne, double kT,
-                                                          double spin, double acc, int max_steps,
-                                                          double f_cut, double* f, double* scal)
+// The chemical potential by bisection (Eq. (18), Sec. 4.5; with per-state
+// weights the electron count runs over k-points and spin channels): the
+// interval [min eps - 10 width, max eps + 10 width] is widened (the step
+// doubling, at most 64 times per side) until it brackets N_e, then halved
+// keeping a surplus at the upper bound until that surplus is within
+// occ_accuracy, the midpoint stops moving, or max_steps halvings were made;
+// mu is the upper bound, f_l = w_l f(eps_l), and the remaining surplus is
+// stripped from the highest-index states with f > 0 downward.  k_s: one past
+// the last state with |f| > f_cut.
+__global__ __launch_bounds__(FD_THREADS) void occupations_kernel(int n, const double* eps, const double* w, int scheme,
+                                                                double ne, double width, double spin, double acc,
+                                                                int max_steps, double f_cut, double* f, double* scal)
 {
     __shared__ double red[FD_THREADS / 64 + 1];
     __shared__ double sh_surplus;
-    double lo = eps[0] - 10.0 * kT, hi = eps[n - 1] + 10.0 * kT;
+    double vmin = INFINITY, vmax = -INFINITY;
+    for (int l = threadIdx.x; l < n; l += FD_THREADS) {
+        vmin = fmin(vmin, eps[l]);
+        vmax = fmax(vmax, eps[l]);
+    }
+    vmin = block_extreme(vmin, red, false);
+    vmax = block_extreme(vmax, red, true);
+    double lo = vmin - 10.0 * width, hi = vmax + 10.0 * width;
     double step = hi - lo;
-    for (int w = 0; w < 64 && count_electrons(n, eps, lo, kT, spin, red) - ne > 0.0; ++w) {
+    for (int t = 0; t < 64 && count_electrons(n, eps, w, scheme, lo, width, spin, red) - ne > 0.0; ++t) {
         lo -= step;
         step *= 2.0;
     }
     step = hi - lo;
-    for (int w = 0; w < 64 && count_electrons(n, eps, hi, kT, spin, red) - ne < 0.0; ++w) {
+    for (int t = 0; t < 64 && count_electrons(n, eps, w, scheme, hi, width, spin, red) - ne < 0.0; ++t) {
         hi += step;
         step *= 2.0;
     }
@@ -172,7 +238,7 @@ __global__ __launch_bounds__(FD_THREADS) void fermi_kernel(int n, const double* 
         if (!(lo < mid && mid < hi)) break;
         if (steps >= max_steps) { status = kStatusMu; break; }
         ++steps;
-        double g = count_electrons(n, eps, mid, kT, spin, red) - ne;
+        double g = count_electrons(n, eps, w, scheme, mid, width, spin, red) - ne;
         if (g >= 0.0) {
             hi = mid;
             if (g <= acc) break;
@@ -181,8 +247,8 @@ __global__ __launch_bounds__(FD_THREADS) void fermi_kernel(int n, const double* 
         }
     }
     const double mu = hi;
-    for (int l = threadIdx.x; l < n; l += FD_THREADS) f[l] = fd_occ(eps[l], mu, kT, spin);
-    double total = count_electrons(n, eps, mu, kT, spin, red);
+    for (int l = threadIdx.x; l < n; l += FD_THREADS) f[l] = (w ? w[l] : 1.0) * occ_value(scheme, eps[l], mu, width, spin);
+    double total = count_electrons(n, eps, w, scheme, mu, width, spin, red);
     __syncthreads();
     if (threadIdx.x == 0) {
         double surplus = total - ne;
@@ -196,14 +262,13 @@ __global__ __launch_bounds__(FD_THREADS) void fermi_kernel(int n, const double* 
         sh_surplus = surplus;
     }
     __syncthreads();
-    // k_s: number of leading states with f > f_cut (f is non-increasing in l)
-    double cnt = 0.0, en = 0.0;
+    double last = -1.0, en = 0.0;
     for (int l = threadIdx.x; l < n; l += FD_THREADS) {
         double fl = f[l];
-        cnt += (fl > f_cut) ? 1.0 : 0.0;
+        if (fabs(fl) > f_cut) last = fmax(last, (double)l);
         en += fl * eps[l];
     }
-    double ks = block_sum(cnt, red);
+    double ks = block_extreme(last, red, true) + 1.0;
     double energy = block_sum(en, red);
     if (threadIdx.x == 0) {
         scal[0] = mu;
@@ -222,7 +287,7 @@ __global__ __launch_bounds__(FD_THREADS) void explicit_occ_kernel(int n, const d
     double en = 0.0, last = -1.0;
     for (int l = threadIdx.x; l < n; l += FD_THREADS) {
         en += f[l] * eps[l];
-        if (f[l] > f_cut) last = fmax(last, (double)l);
+        if (fabs(f[l]) > f_cut) last = fmax(last, (double)l);
     }
     double energy = block_sum(en, red);
     // maximum of `last` through the same reduction shape
@@ -301,6 +366,14 @@ void scale_columns_sqrt(hipStream_t st, int n, int k, const double* C, int ldc, 
     hipLaunchKernelGGL(scale_sqrt_kernel, grid, dim3(256), 0, st, n, k, C, ldc, f, out, ldo);
 }
 
+void scale_columns_signed(hipStream_t st, int n, int k, const double* C, int ldc, const double* f, double* out,
+                          double* out2, int ldo)
+{
+    if (n <= 0 || k <= 0) return;
+    dim3 grid(ceil_div(n, 256), std::min(k, 65535));
+    hipLaunchKernelGGL(scale_signed_kernel, grid, dim3(256), 0, st, n, k, C, ldc, f, out, out2, ldo);
+}
+
 void check_finite(hipStream_t st, int m, int n, const double* A, int lda, int* flag)
 {
     if (m <= 0 || n <= 0) return;
@@ -308,12 +381,11 @@ void check_finite(hipStream_t st, int m, int n, const double* A, int lda, int* f
     hipLaunchKernelGGL(finite_kernel, grid, dim3(256), 0, st, m, n, A, lda, flag);
 }
 
-void fermi_occupations(hipStream_t st, int n, const double* eps, double n_electron, double kT,
-                       double spin, double occ_accuracy, int max_steps, double f_cut, double* f,
-                       double* scal)
+void occupations(hipStream_t st, int n, const double* eps, const double* weight, int scheme, double n_electron,
+                 double width, double spin, double occ_accuracy, int max_steps, double f_cut, double* f, double* scal)
 {
-    hipLaunchKernelGGL(fermi_kernel, dim3(1), dim3(FD_THREADS), 0, st, n, eps, n_electron, kT, spin,
-                       occ_accuracy, max_steps, f_cut, f, scal);
+    hipLaunchKernelGGL(occupations_kernel, dim3(1), dim3(FD_THREADS), 0, st, n, eps, weight, scheme, n_electron,
+                       width, spin, occ_accuracy, max_steps, f_cut, f, scal);
 }
 
 }  // namespace eg

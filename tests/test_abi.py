@@ -89,21 +89,37 @@ def test_strerror_and_argument_checks_without_gpu():
     assert lib.elsi_gpu_finalize(ctypes.byref(h)) == 0
     # refinement stage entry: argument checks return before any device work
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
-    lib.elsi_gpu_x_refine.argtypes = [i, i, i, vp, i, vp, i, vp, vp, d, i, ctypes.POINTER(i), vp]
+    lib.elsi_gpu_x_refine.argtypes = [i, i, i, vp, i, vp, i, vp, i, vp, vp, vp, vp, vp, vp, d, i,
+                                      ctypes.POINTER(i), vp]
     fake = ctypes.c_void_p(16)
     sw = ctypes.c_int(7)
-    assert lib.elsi_gpu_x_refine(-1, 0, 0, fake, 1, fake, 1, fake, fake, 1e-10, 4, None, None) == -1
-    assert lib.elsi_gpu_x_refine(4, 5, 0, fake, 4, fake, 4, fake, fake, 1e-10, 4, None, None) == -2
-    assert lib.elsi_gpu_x_refine(4, 2, 3, fake, 4, fake, 4, fake, fake, 1e-10, 4, None, None) == -3
-    assert lib.elsi_gpu_x_refine(4, 2, 2, None, 4, fake, 4, fake, fake, 1e-10, 4, None, None) == -4
-    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 3, fake, 4, fake, fake, 1e-10, 4, None, None) == -4
-    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 4, fake, 3, fake, fake, 1e-10, 4, None, None) == -6
-    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 4, fake, 4, None, fake, 1e-10, 4, None, None) == -8
-    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 4, fake, 4, fake, None, 1e-10, 4, None, None) == -9
-    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 4, fake, 4, fake, fake, -1.0, 4, None, None) == -10
-    assert lib.elsi_gpu_x_refine(4, 2, 2, fake, 4, fake, 4, fake, fake, 1e-10, -1, None, None) == -11
-    assert lib.elsi_gpu_x_refine(0, 0, 0, None, 1, None, 1, None, None, 1e-10, 4, ctypes.byref(sw), None) == 0
+
+    def refine(n, k, kw, Ht, ldh, X, ldx, Q=None, ldq=1, dd=None, ee=None, th=fake, rs=fake, tol=1e-10, ms=4,
+               swp=None):
+        return lib.elsi_gpu_x_refine(n, k, kw, Ht, ldh, X, ldx, Q, ldq, dd, ee, None, th, rs, None, tol, ms, swp,
+                                     None)
+
+    assert refine(-1, 0, 0, fake, 1, fake, 1) == -1
+    assert refine(4, 5, 0, fake, 4, fake, 4) == -2
+    assert refine(4, 2, 3, fake, 4, fake, 4) == -3
+    assert refine(4, 2, 2, None, 4, fake, 4) == -4
+    assert refine(4, 2, 2, fake, 3, fake, 4) == -4
+    assert refine(4, 2, 2, fake, 4, fake, 3) == -6
+    assert refine(4, 2, 2, fake, 4, fake, 4, Q=fake, ldq=3, dd=fake, ee=fake) == -9
+    assert refine(4, 2, 2, fake, 4, fake, 4, Q=fake, ldq=4, dd=None, ee=fake) == -10
+    assert refine(4, 2, 2, fake, 4, fake, 4, Q=fake, ldq=4, dd=fake, ee=None) == -11
+    assert refine(4, 2, 2, fake, 4, fake, 4, th=None) == -13
+    assert refine(4, 2, 2, fake, 4, fake, 4, rs=None) == -14
+    assert refine(4, 2, 2, fake, 4, fake, 4, tol=-1.0) == -16
+    assert refine(4, 2, 2, fake, 4, fake, 4, ms=-1) == -17
+    assert refine(0, 0, 0, None, 1, None, 1, th=None, rs=None, swp=ctypes.byref(sw)) == 0
     assert sw.value == 0
+    # back-transformation stage entry
+    lib.elsi_gpu_x_backtransform.argtypes = [i, i, vp, i, vp, vp, vp, i, i, i, i, vp]
+    assert lib.elsi_gpu_x_backtransform(0, 8, fake, 1, fake, fake, fake, 1, 1, 0, 0, None) == -1
+    assert lib.elsi_gpu_x_backtransform(8, 65, fake, 8, fake, fake, fake, 8, 1, 0, 0, None) == -2
+    assert lib.elsi_gpu_x_backtransform(8, 8, fake, 8, fake, fake, fake, 8, 1, 2, 0, None) == -10
+    assert lib.elsi_gpu_x_backtransform(8, 8, fake, 8, fake, fake, fake, 8, 1, 0, 64, None) == -11
 
 
 def test_product_path_does_not_import_oracle():

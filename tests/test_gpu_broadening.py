@@ -1,0 +1,182 @@
+"""Broadening schemes (Sec. 4.6 broadening_scheme: Fermi-Dirac Eq. (17),
+Gaussian Eq. (21), Methfessel-Paxton orders 0 and 1) and a chemical potential
+shared by several problems (the k-point / spin sum of Sec. 4.5) against the
+oracle.
+
+Gates as everywhere: eigenvalues by gates.eig_excess, D within 1e-9.  The
+occupations and mu come from the same bisection on both sides, on
+eigenvalues that agree to the gate: they agree to 1e-12 in f, and mu to 1e-9
+where the electron count moves with mu (inside a spectral gap every mu gives
+the electron count, reading R7, and then the GPU's mu must reproduce it with
+the oracle's eigenvalues).  Methfessel-Paxton order 1 gives negative
+occupations above mu, which enter D with their sign.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gates import eig_excess
+from synth import generator as G
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = [O.FERMI, O.GAUSSIAN, O.MP0, O.MP1]
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _cdev(A):
+    from paper_1705_11191_amd import binding as B
+
+    return B.as_fortran(torch.tensor(np.asarray(A, dtype=np.complex128), device="cuda"))
+
+
+def _count(eps, w, scheme, mu, width, spin):
+    return sum(wl * O.occupation_value(scheme, e, mu, width, spin) for e, wl in zip(eps, w))
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("weighted", [False, True])
+def test_occupations_stage_vs_oracle(scheme, weighted):
+    from paper_1705_11191_amd import binding as B
+
+    rng = np.random.default_rng(10 * scheme + int(weighted))
+    if weighted:
+        parts = [np.sort(rng.uniform(-1.0, 1.0, m)) for m in (150, 170, 130)]
+        eps = np.concatenate(parts)
+        w = np.concatenate([np.full(len(p), wp) for p, wp in zip(parts, (0.5, 0.25, 0.25))])
+        ne = 0.5 * 60 + 0.25 * 70 + 0.25 * 50
+    else:
+        eps = np.sort(rng.uniform(-1.0, 1.0, 450))
+        w = None
+        ne = 171.0
+    width, spin = 0.03, 2.0
+    f, mu, ks, st = B.occupations(_dev(eps), ne, width, spin=spin, scheme=scheme,
+                                  weight=_dev(w) if w is not None else None)
+    fo, muo, sto = O.occupations(eps, ne, width, spin=spin, scheme=scheme, weight=w)
+    f = f.cpu().numpy()
+    assert st == sto == 0
+    assert abs(mu - muo) <= 1e-12
+    assert np.abs(f - fo).max() <= 1e-12
+    # k_s is one past the last |f| > 1e-20 of the GPU's own occupations; which
+    # of the states below 1e-13 the charge fix-up zeroes is a rounding-level
+    # decision (reading R2), so against the oracle k_s only has to cover every
+    # state the oracle occupies above 1e-12
+    last = np.nonzero(np.abs(f) > 1e-20)[0]
+    assert ks == (last[-1] + 1 if last.size else 0)
+    big = np.nonzero(np.abs(fo) > 1e-12)[0]
+    assert ks >= (big[-1] + 1 if big.size else 0)
+    assert abs(f.sum() - ne) <= 1e-11
+
+
+@pytest.mark.parametrize("system,scheme,width", [("lattice", O.GAUSSIAN, 0.01), ("lattice", O.MP0, 0.02),
+                                                  ("chain", O.GAUSSIAN, 0.02), ("chain", O.MP1, 0.02),
+                                                  ("chain", O.MP1, 0.05)])
+def test_dm_broadening_vs_oracle(system, scheme, width):
+    from paper_1705_11191_amd import binding as B
+
+    # the 1D chain of config 0 has a dense band at mu; the small lattice has a gap there
+    sp = G.make_lattice_system(300, seed=31) if system == "lattice" else G.make_config(0)
+    ref = O.dm(sp.H, sp.S, sp.n_occ, width, scheme=scheme)
+    h = B.Handle(sp.n, sp.n, sp.n_occ)
+    h.set_occupation(scheme, width)
+    D, ev, f, energy, mu, st = h.dm(_dev(sp.H), _dev(sp.S))
+    info = h.info()
+    h.close()
+    D, ev, f = D.cpu().numpy(), ev.cpu().numpy(), f.cpu().numpy()
+    print(f"[broadening] scheme {scheme} width {width}: k_s {info['k_s']} min f {ref['occ'].min():.2e} "
+          f"D err {np.abs(D - ref['D']).max():.2e}", flush=True)
+    assert st == 0
+    assert eig_excess(ev, ref["eval"], sp.S) <= 1.0
+    assert np.abs(f - ref["occ"]).max() <= 1e-12
+    if abs(mu - ref["mu"]) > 1e-9:
+        assert abs(_count(ref["eval"], np.ones(sp.n), scheme, mu, width, 1.0) - sp.n_occ) <= 1e-11
+    assert np.abs(D - ref["D"]).max() <= 1e-9
+    assert abs(energy - ref["energy"]) <= 1e-9 * max(1.0, abs(ref["energy"]))
+    if scheme == O.MP1 and width >= 0.05:
+        assert ref["occ"].min() < -1e-4 and ref["occ"].max() > 1.0   # occupations outside [0, 1] entered D
+
+
+def test_density_stage_with_negative_occupations():
+    from paper_1705_11191_amd import binding as B
+
+    rng = np.random.default_rng(12)
+    n, k = 300, 140
+    C = rng.standard_normal((n, k))
+    f = rng.uniform(-0.2, 1.0, k)
+    Cd = B.fortran_empty(n, k)
+    Cd.copy_(torch.tensor(C, device="cuda"))
+    D = B.density(Cd, _dev(f)).cpu().numpy().T
+    want = (C * f) @ C.T
+    assert np.abs(D - want).max() <= 64 * k * np.finfo(float).eps * np.abs(C).max() ** 2
+
+
+@pytest.mark.parametrize("scheme", [O.FERMI, O.MP1])
+def test_dm_batched_shared_mu_real(scheme):
+    """Three problems as the spin channels / k-points of one system with weights
+    0.5, 0.3, 0.2: one mu for all, weighted occupations, D per problem."""
+    from paper_1705_11191_amd import binding as B
+
+    sps = [G.make_lattice_system(n, seed=70 + q) for q, n in enumerate((200, 260, 300))]
+    w = [0.5, 0.3, 0.2]
+    ne = [sp.n_occ for sp in sps]
+    width = 0.01 if scheme == O.FERMI else 0.03
+    ref, mu_ref, st_ref = O.dm_shared_mu([sp.H for sp in sps], [sp.S for sp in sps], ne, w, width, scheme=scheme)
+    h = B.Handle(8, 8, 2)
+    h.set_occupation(scheme, width)
+    Ds, evals, energy, mu, status, rc = h.dm_batched([_dev(sp.H) for sp in sps], [_dev(sp.S) for sp in sps], ne,
+                                                     kweight=w)
+    h.close()
+    assert rc == 0 and status == [0, 0, 0] and st_ref == 0
+    assert all(m == mu[0] for m in mu)
+    all_eval = np.concatenate([r["eval"] for r in ref])
+    all_w = np.concatenate([np.full(len(r["eval"]), wp) for r, wp in zip(ref, w)])
+    if abs(mu[0] - mu_ref) > 1e-9:
+        assert abs(_count(all_eval, all_w, scheme, mu[0], width, 1.0) - sum(a * b for a, b in zip(w, ne))) <= 1e-11
+    charge = 0.0
+    for q, sp in enumerate(sps):
+        D = Ds[q].cpu().numpy()
+        print(f"[shared mu] problem {q}: D err {np.abs(D - ref[q]['D']).max():.2e}", flush=True)
+        assert eig_excess(evals[q].cpu().numpy(), ref[q]["eval"], sp.S) <= 1.0
+        assert np.abs(D - ref[q]["D"]).max() <= 1e-9
+        assert abs(energy[q] - ref[q]["energy"]) <= 1e-9 * max(1.0, abs(ref[q]["energy"]))
+        charge += np.trace(D @ sp.S)
+    # the weighted occupations put the whole electron count into sum_p tr(D_p S_p)
+    assert abs(charge - sum(a * b for a, b in zip(w, ne))) <= 1e-10
+
+
+def test_dm_batched_shared_mu_kpoints():
+    """Four k-points of one periodic cell (two +-k pairs, weights 1/4): complex
+    Hermitian problems sharing one mu; H(-k) = conj H(k) gives equal spectra
+    and conjugate density matrices within each pair."""
+    from paper_1705_11191_amd import binding as B
+
+    cells = (2, 3, 3)
+    kpts = [(0.125, 0.25, 0.25), (-0.125, -0.25, -0.25), (0.375, 0.25, -0.25), (-0.375, -0.25, 0.25)]
+    sps = [G.make_kpoint_system(cells, k, seed=21) for k in kpts]
+    n = sps[0].H.shape[0]
+    w = [0.25] * 4
+    ne = [sp.n_occ for sp in sps]
+    ref, mu_ref, st_ref = O.dm_shared_mu([sp.H for sp in sps], [sp.S for sp in sps], ne, w, sps[0].kT)
+    h = B.Handle(n, n, ne[0], dtype=B.COMPLEX128)
+    Ds, evals, energy, mu, status, rc = h.dm_batched([_cdev(sp.H) for sp in sps], [_cdev(sp.S) for sp in sps], ne,
+                                                     kweight=w)
+    h.close()
+    assert rc == 0 and status == [0] * 4
+    if abs(mu[0] - mu_ref) > 1e-9:
+        all_eval = np.concatenate([r["eval"] for r in ref])
+        assert abs(_count(all_eval, np.full(all_eval.size, 0.25), O.FERMI, mu[0], sps[0].kT, 1.0) - ne[0]) <= 1e-11
+    charge = 0.0
+    for q, sp in enumerate(sps):
+        D = Ds[q].cpu().numpy()
+        assert eig_excess(evals[q].cpu().numpy(), ref[q]["eval"], sp.S) <= 1.0
+        assert np.abs(D - ref[q]["D"]).max() <= 1e-9
+        assert np.abs(D - D.conj().T).max() <= 1e-12
+        charge += np.trace(D @ sp.S).real
+    assert abs(charge - ne[0]) <= 1e-10
+    assert np.abs(Ds[0].cpu().numpy() - Ds[1].cpu().numpy().conj()).max() <= 1e-9
