@@ -380,6 +380,19 @@ int elsi_gpu_x_gemm_fp32(char ta, char tb, int m, int n, int k, double alpha, co
  * *fail_col (host, may be NULL) receives the 1-based first bad pivot. */
 int elsi_gpu_x_cholesky(int n, double *S, int lds, int *fail_col, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): elsi_gpu_x_cholesky
+ * with the same kernels and results, but no hipMalloc, hipFree or other
+ * allocating call.  Its scratch (the inverses of the 64 x 64 diagonal blocks
+ * of L and the pivot flag, 8 MiB + 256 B) is a fixed device array that each
+ * GPU holds until the process ends; the caller passes only S.  Every call on
+ * one GPU shares that GPU's array, so calls that overlap on one GPU race.
+ * Errors: -1 n < 0 or n > ELSI_GPU_NOALLOC_MAX_N (checked on the host, no
+ * GPU call), -2 S NULL, -3 lds < n; 1 S not positive definite (*fail_col as
+ * elsi_gpu_x_cholesky), 5 HIP error. */
+#define ELSI_GPU_NOALLOC_MAX_N 16384
+int elsi_gpu_x_cholesky_noalloc(int n, double *S, int lds, int *fail_col, void *hip_stream);
+
 /* H <- L^-1 H L^-T, Eq. (11); H full symmetric on exit; L from Eq. (10). */
 int elsi_gpu_x_reduce(int n, double *H, int ldh, const double *L, int ldl, void *hip_stream);
 

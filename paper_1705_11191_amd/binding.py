@@ -102,6 +102,7 @@ def lib():
         L.elsi_gpu_x_dgemm.argtypes = [c, c, i, i, i, d, vp, i, vp, i, d, vp, i, vp]
         L.elsi_gpu_x_gemm_fp32.argtypes = [c, c, i, i, i, d, vp, i, vp, i, d, vp, i, i, vp]
         L.elsi_gpu_x_cholesky.argtypes = [i, vp, i, ctypes.POINTER(i), vp]
+        L.elsi_gpu_x_cholesky_noalloc.argtypes = [i, vp, i, ctypes.POINTER(i), vp]
         L.elsi_gpu_x_reduce.argtypes = [i, vp, i, vp, i, vp]
         L.elsi_gpu_x_backsub.argtypes = [i, i, vp, i, vp, i, vp]
         L.elsi_gpu_x_occupations.argtypes = [i, vp, vp, i, d, d, d, d, i, vp, ctypes.POINTER(d),
@@ -193,6 +194,19 @@ def cholesky(S: torch.Tensor) -> int:
     fail = ctypes.c_int(0)
     rc = lib().elsi_gpu_x_cholesky(n, _ptr(S), n, ctypes.byref(fail), _stream())
     _check(rc, "elsi_gpu_x_cholesky", ok=(0, 1))
+    return fail.value
+
+
+NOALLOC_MAX_N = 16384   # ELSI_GPU_NOALLOC_MAX_N
+
+
+def cholesky_noalloc(S: torch.Tensor) -> int:
+    """As cholesky, through the entry point that allocates nothing (its scratch
+    is a fixed device array; n <= NOALLOC_MAX_N)."""
+    n = S.shape[0]
+    fail = ctypes.c_int(0)
+    rc = lib().elsi_gpu_x_cholesky_noalloc(n, _ptr(S), n, ctypes.byref(fail), _stream())
+    _check(rc, "elsi_gpu_x_cholesky_noalloc", ok=(0, 1))
     return fail.value
 
 

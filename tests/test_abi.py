@@ -121,6 +121,14 @@ def test_strerror_and_argument_checks_without_gpu():
     assert lib.elsi_gpu_x_backtransform(8, 8, fake, 8, fake, fake, fake, 8, 1, 2, 0, None) == -10
     assert lib.elsi_gpu_x_backtransform(8, 8, fake, 8, fake, fake, fake, 8, 1, 0, 64, None) == -11
 
+    # the allocation-free Cholesky rejects sizes beyond its fixed scratch on
+    # the host, before any GPU call
+    lib.elsi_gpu_x_cholesky_noalloc.argtypes = [i, vp, i, ctypes.POINTER(i), vp]
+    fc = ctypes.c_int(3)
+    assert lib.elsi_gpu_x_cholesky_noalloc(16385, fake, 16385, ctypes.byref(fc), None) == -1
+    assert lib.elsi_gpu_x_cholesky_noalloc(-1, fake, 1, ctypes.byref(fc), None) == -1
+    assert lib.elsi_gpu_x_cholesky_noalloc(0, None, 1, ctypes.byref(fc), None) == 0 and fc.value == 0
+
 
 def test_product_path_does_not_import_oracle():
     # the GPU package and binding must not reach into the CPU oracle
