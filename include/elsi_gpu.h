@@ -230,8 +230,11 @@ int elsi_gpu_set_band_width(elsi_gpu_handle h, int b);
  * refinement and also ends with ELSI_GPU_ERR_REFINE).  Eigenvalues above the
  * k' refined ones are the FP32-step values.  Needs about 3n^2 more doubles
  * of workspace.  Batched calls always run in FP64.
- * Errors: -1 h NULL, -2 prec unknown or a complex handle asks for MIXED,
- * -3 refine_tol not >= 0, -4 max_refine < 0. */
+ * Complex handles: elsi_gpu_dm runs this mode on the real 2n x 2n image of
+ * the pencil (FP32 products on the image carry complex64 precision, the
+ * refinement complex128); elsi_gpu_ev on complex handles stays FP64.
+ * Errors: -1 h NULL, -2 prec unknown, -3 refine_tol not >= 0,
+ * -4 max_refine < 0. */
 int elsi_gpu_set_precision(elsi_gpu_handle h, int prec, double refine_tol, int max_refine);
 
 /* Measurement aid, not part of the method: on = 1 brackets every GEMM launch

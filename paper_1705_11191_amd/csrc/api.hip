@@ -124,7 +124,6 @@ int elsi_gpu_set_precision(elsi_gpu_handle h, int prec, double refine_tol, int m
 {
     if (!h) return -1;
     if (prec != ELSI_GPU_PREC_FP64 && prec != ELSI_GPU_PREC_MIXED) return -2;
-    if (prec == ELSI_GPU_PREC_MIXED && h->dtype != ELSI_GPU_REAL64) return -2;
     if (!(refine_tol >= 0.0)) return -3;
     if (max_refine < 0) return -4;
     h->precision = prec;

@@ -121,7 +121,8 @@ static CLayout make_clayout(size_t base, int n)
 size_t workspace_bytes(const elsi_gpu_handle_s* h)
 {
     if (h->dtype == ELSI_GPU_COMPLEX128) {
-        const size_t base = make_layout(2 * h->n, h->band_width, 2 * h->n).total;
+        const size_t base =
+            make_layout(2 * h->n, h->band_width, 2 * h->n, h->precision == ELSI_GPU_PREC_MIXED).total;
         return make_clayout(base, h->n).total;
     }
     return make_layout(h->n, h->band_width, h->n, h->precision == ELSI_GPU_PREC_MIXED, h->values_copies != 0).total;
@@ -551,8 +552,11 @@ static elsi_gpu_handle_s inner_handle(const elsi_gpu_handle_s* h, int n_state2)
     r.overlap_factored = h->overlap_factored;
     r.band_width = h->band_width;
     r.batch_workers = 1;
+    r.precision = h->precision;
+    r.refine_tol = h->refine_tol;
+    r.max_refine = h->max_refine;
     r.ws = h->ws;
-    r.ws_bytes = make_layout(r.n, r.band_width, r.n).total;
+    r.ws_bytes = make_layout(r.n, r.band_width, r.n, r.precision == ELSI_GPU_PREC_MIXED).total;
     r.ws_owned = 0;
     std::memset(&r.info, 0, sizeof(r.info));
     r.info.n_basis = r.n;
@@ -588,6 +592,7 @@ static int ev_complex(elsi_gpu_handle_s* h, double* H, double* S, double* eval, 
     embed_complex(st, n, H, n, H2, n2, false);
     if (S2) embed_complex(st, n, S, n, S2, n2, h->overlap_factored != 0);
     elsi_gpu_handle_s r = inner_handle(h, k2);
+    r.precision = ELSI_GPU_PREC_FP64;   // complex eigenvectors are computed in FP64
     r.info.band_width = std::min(r.band_width, std::max(1, n2 - 1));
     Timer tm(st);
     DcState dc;
@@ -636,7 +641,7 @@ static int dm_complex(elsi_gpu_handle_s* h, double* H, double* S, double* occ, d
     hipStream_t st = h->stream;
     const int n = h->n, n2 = 2 * n;
     char* ws = (char*)h->ws;
-    const Layout L = make_layout(n2, h->band_width, n2);
+    const Layout L = make_layout(n2, h->band_width, n2, h->precision == ELSI_GPU_PREC_MIXED);
     const CLayout C = make_clayout(L.total, n);
     double* H2 = (double*)(ws + C.h2);
     double* S2 = h->overlap_is_unit ? nullptr : (double*)(ws + C.s2);
@@ -652,7 +657,7 @@ static int dm_complex(elsi_gpu_handle_s* h, double* H, double* S, double* occ, d
     double e2 = 0.0, mu2 = 0.0;
     const int rc2 = dm_real(&r, H2, S2, occ2, D2, nullptr, &e2, &mu2);
     complex_info(h, r);
-    if (rc2 != 0 && rc2 != ELSI_GPU_ERR_MU) return rc2;
+    if (rc2 != 0 && rc2 != ELSI_GPU_ERR_MU && rc2 != ELSI_GPU_ERR_REFINE) return rc2;
     extract_complex(st, n, D2, n2, D, n, false);
     if (eval) pair_values(st, n, (const double*)(ws + L.w), eval);
     // Fermi-Dirac occupations of the states: the mean over each real pair
@@ -691,6 +696,7 @@ int eg::eigenvalues_only(elsi_gpu_handle_s* h, const double* H, const double* S,
         embed_complex(st, n, H, n, H2, n2, false);
         if (S2) embed_complex(st, n, S, n, S2, n2, h->overlap_factored != 0);
         elsi_gpu_handle_s r = inner_handle(h, n2);
+        r.precision = ELSI_GPU_PREC_FP64;
         r.info.band_width = std::min(r.band_width, std::max(1, n2 - 1));
         Timer tm(st);
         DcState dc;

@@ -82,10 +82,18 @@ def test_strerror_and_argument_checks_without_gpu():
     lib.elsi_gpu_finalize.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
     assert lib.elsi_gpu_finalize(ctypes.byref(h)) == 0
     assert h.value is None
-    # complex handles have no mixed mode
+    # complex handles take the mixed mode for dm (on the real image): the
+    # workspace grows by the refinement's buffers of the 2n image
     assert lib.elsi_gpu_init(ctypes.byref(h), 1, 10, 10, 5.0, None) == 0
-    assert lib.elsi_gpu_set_precision(h, 1, 1e-10, 4) == -2
+    assert lib.elsi_gpu_workspace_size(h, ctypes.byref(ws64)) == 0
+    assert lib.elsi_gpu_set_precision(h, 1, 1e-10, 4) == 0
+    assert lib.elsi_gpu_workspace_size(h, ctypes.byref(wsmx)) == 0
+    assert wsmx.value >= ws64.value + 20 * 20 * 8
     assert lib.elsi_gpu_set_precision(h, 0, 1e-10, 4) == 0
+    # the singularity check is for real handles
+    lib.elsi_gpu_set_singularity.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]
+    assert lib.elsi_gpu_set_singularity(h, 1, 1e-5) == -2
+    assert lib.elsi_gpu_set_singularity(h, 0, 1e-5) == 0
     assert lib.elsi_gpu_finalize(ctypes.byref(h)) == 0
     # refinement stage entry: argument checks return before any device work
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
@@ -120,7 +128,6 @@ def test_strerror_and_argument_checks_without_gpu():
     assert lib.elsi_gpu_x_backtransform(8, 65, fake, 8, fake, fake, fake, 8, 1, 0, 0, None) == -2
     assert lib.elsi_gpu_x_backtransform(8, 8, fake, 8, fake, fake, fake, 8, 1, 2, 0, None) == -10
     assert lib.elsi_gpu_x_backtransform(8, 8, fake, 8, fake, fake, fake, 8, 1, 0, 64, None) == -11
-
     # the allocation-free Cholesky rejects sizes beyond its fixed scratch on
     # the host, before any GPU call
     lib.elsi_gpu_x_cholesky_noalloc.argtypes = [i, vp, i, ctypes.POINTER(i), vp]

@@ -93,7 +93,10 @@ def test_dm_broadening_vs_oracle(system, scheme, width):
           f"D err {np.abs(D - ref['D']).max():.2e}", flush=True)
     assert st == 0
     assert eig_excess(ev, ref["eval"], sp.S) <= 1.0
-    assert np.abs(f - ref["occ"]).max() <= 1e-12
+    # f moves with the eigenvalues at up to 1.5 / (sqrt(pi) width) per Ha (the
+    # steepest slope, Methfessel-Paxton order 1), times their agreement (the
+    # 1e-10 Ha gate; measured up to 5e-13 Ha on these pencils)
+    assert np.abs(f - ref["occ"]).max() <= 1e-10
     if abs(mu - ref["mu"]) > 1e-9:
         assert abs(_count(ref["eval"], np.ones(sp.n), scheme, mu, width, 1.0) - sp.n_occ) <= 1e-11
     assert np.abs(D - ref["D"]).max() <= 1e-9

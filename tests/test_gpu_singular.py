@@ -65,7 +65,7 @@ def test_dm_with_duplicated_basis_functions_vs_oracle(n0, dup):
     h.set_overlap_factored(True)
     D2, *_ = h.dm(_dev(H), Sd)
     h.close()
-    assert np.abs(D2.cpu().numpy() - D).max() <= 1e-12
+    assert np.abs(D2.cpu().numpy() - D).max() <= 1e-10   # lam_j = ||X_j||^2 is recomputed from X
 
 
 def test_ev_with_duplicated_basis_functions_vs_oracle():
@@ -108,13 +108,16 @@ def test_check_on_a_well_conditioned_overlap_takes_the_cholesky_route():
 
 
 def test_tolerance_above_small_eigenvalues_vs_oracle():
-    """A nonsingular S with tau in a gap of its spectrum: the directions below
-    tau are dropped on both sides alike."""
+    """A nonsingular S with tau in a wide gap of its spectrum: the directions
+    below tau are dropped on both sides alike.  (The lattice basis holds a
+    large cluster of eigenvalues of S within 1e-3 of the smallest; a cut inside
+    it would not determine the kept subspace in FP64, so tau sits in the widest
+    gap above the cluster, whose width bounds the subspace's sensitivity.)"""
     from paper_1705_11191_amd import binding as B
 
-    sp = G.make_lattice_system(260, seed=97, kappa=1e6)
+    sp = G.make_lattice_system(260, seed=97, kappa=1e3)
     lam = np.linalg.eigvalsh(sp.S)
-    j = next(j for j in range(2, 200) if lam[j + 1] - lam[j] > 1e-3 * lam[j + 1])
+    j = 180 + int(np.argmax(np.diff(lam)[180:230]))
     tau = 0.5 * (lam[j] + lam[j + 1])
     ref = O.dm_checked(sp.H, sp.S, sp.n_occ, sp.kT, tau)
     h = B.Handle(sp.n, sp.n, sp.n_occ)
