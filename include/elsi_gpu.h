@@ -144,6 +144,9 @@ typedef struct elsi_gpu_info {
      * number of states of the last call (n_basis on the Cholesky route). */
     double overlap_min_eig;
     int n_nonsing;
+    /* Mixed precision: the largest weighted Newton step measured in each of
+     * the first eight refinement sweeps (0 beyond the last). */
+    double refine_hist[8];
 } elsi_gpu_info;
 
 /* Create a handle (elsi_init, Sec. 4.4).  n_state: eigenvectors returned by
@@ -222,9 +225,11 @@ int elsi_gpu_set_band_width(elsi_gpu_handle h, int b);
  * states, P = I - Z Z^T): y_l = -P (T - theta_l)^-1 P Q^T r_l, with the
  * shifted tridiagonal systems solved per state.  When the largest weighted
  * step max_l w_l ||y_l||_2 over the wanted states (w_l = f_l in dm, 1 in ev)
- * is at most refine_tol, that step is taken and one closing Rayleigh-Ritz
- * sweep ends the call with status 0 (an untaken step would be amplified by
- * L^-T in the eigenvectors c = L^-T x); otherwise x_l += Q y_l and the next
+ * is at most refine_tol, or the contraction measured over the last two
+ * steps predicts that taking it leaves less than refine_tol
+ * (10 (W_s / W_{s-1}) W_s <= refine_tol), that step is taken and one closing
+ * Rayleigh-Ritz sweep ends the call with status 0 (an untaken step would be
+ * amplified by L^-T in the eigenvectors c = L^-T x); otherwise x_l += Q y_l and the next
  * sweep starts, up to max_refine sweeps in all (default 6; then
  * ELSI_GPU_ERR_REFINE with all outputs written; max_refine = 0 skips the
  * refinement and also ends with ELSI_GPU_ERR_REFINE).  Eigenvalues above the

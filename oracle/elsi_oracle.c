@@ -747,12 +747,12 @@ void orc_tridiag_shift_solve(int n, const double *d, const double *e, double shi
     free(u0); free(u1); free(u2); free(y);
 }
 
-/* X <- X L_G^-T with G = X^T X = L_G L_G^T (CholeskyQR), twice.  Returns 0, */
-/* or 1 when a Gram matrix is not positive definite (X untouched then, or    */
-/* after the first pass).                                                    */
-static int cholesky_qr2(int n, int k, double *X, int ldx, double *G)
+/* X <- X L_G^-T with G = X^T X = L_G L_G^T (CholeskyQR), `passes` times.   */
+/* Returns 0, or 1 when a Gram matrix is not positive definite (X untouched  */
+/* then, or after the first pass).                                           */
+static int cholesky_qr(int n, int k, double *X, int ldx, double *G, int passes)
 {
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < passes; ++pass) {
 #pragma omp parallel for schedule(static)
         for (int j = 0; j < k; ++j)
             for (int i = 0; i < k; ++i) {
@@ -782,7 +782,8 @@ static int cholesky_qr2(int n, int k, double *X, int ldx, double *G)
 /* refined vectors.                                                          */
 /*                                                                           */
 /* Each sweep:                                                               */
-/*   (1) CholeskyQR twice: G = X^T X = L_G L_G^T, X <- X L_G^-T;             */
+/*   (1) CholeskyQR: G = X^T X = L_G L_G^T, X <- X L_G^-T (twice in the first */
+/*       sweep, once after a correction);                                     */
 /*   (2) Rayleigh-Ritz: A = X^T H~ X = W diag(theta) W^T (orc_gevp, S = I),  */
 /*       X <- X W;                                                           */
 /*   (3) residuals r_l = H~ x_l - theta_l x_l, res_l = ||r_l||_2.            */
@@ -804,11 +805,12 @@ static int cholesky_qr2(int n, int k, double *X, int ldx, double *G)
 /* last allowed sweep (status 3, X as that sweep's Rayleigh-Ritz left it),   */
 /* X_l += Qp y_l for every l with step_l <= 1/2 (a larger step lies outside  */
 /* the region where the linear model holds and is not taken) and the next    */
-/* sweep starts.  When the largest weighted step max_{l<kw} w_l step_l was   */
-/* <= tol (weight NULL: w_l = 1), that step is still taken and the next      */
-/* sweep, steps (1)-(3) only, closes the call with 0: the error left is then */
-/* the step's own error, of the order of the contraction rate times tol      */
-/* (the untaken step itself would be amplified by L^-T in c = L^-T x).       */
+/* sweep starts.  When the largest weighted step W_s = max_{l<kw} w_l step_l */
+/* (weight NULL: w_l = 1) is <= tol, or when 10 (W_s / W_{s-1}) W_s <= tol   */
+/* (the contraction measured over the last two steps predicts that taking    */
+/* W_s leaves less than tol), that step is still taken and the next sweep,   */
+/* steps (1)-(3) only, closes the call with 0 (the untaken step would be     */
+/* amplified by L^-T in c = L^-T x).                                         */
 /* Dependent columns (G not positive definite)                               */
 /* end the call with 3 and leave X as the last completed sweep left it.      */
 /* step (k, may be NULL) receives the last computed steps (0 without Qp).    */
@@ -846,11 +848,14 @@ int orc_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int l
         if (st) { free(G); free(I); free(Wq); free(Xs); free(R); free(Y); free(stp); return 3; }
     }
     int status = 3, finishing = 0;
+    double prev_worst = 0.0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         /* (1) orthonormalize a copy, so that a failure leaves X as it was */
         for (int j = 0; j < k; ++j)
             for (int i = 0; i < n; ++i) Xs[IDX(i, j, n)] = X[IDX(i, j, ldx)];
-        if (cholesky_qr2(n, k, Xs, n, G)) { status = 3; break; }
+        /* twice for the starting vectors; once after a correction, which leaves */
+        /* them orthonormal to O(step) */
+        if (cholesky_qr(n, k, Xs, n, G, sweep == 0 ? 2 : 1)) { status = 3; break; }
         /* (2) A = X^T (H~ X), lower triangle of H~ read */
 #pragma omp parallel for schedule(static)
         for (int j = 0; j < k; ++j)
@@ -954,7 +959,16 @@ int orc_refine(int n, int k, int kw, const double *Ht, int ldh, double *X, int l
             }
         }
         if (sweep == max_sweeps - 1) { status = 3; break; }
-        if (worst <= tol) finishing = 1;        /* take this last step, then one closing sweep */
+        /* take this last step, then one closing sweep, when it is within tol or */
+        /* when the contraction measured from the previous step predicts what it */
+        /* leaves within tol (with a safety factor of 10)                        */
+        if (worst <= tol) finishing = 1;
+        if (prev_worst > 0.0) {
+            double rate = worst / prev_worst;
+            if (rate > 1.0) rate = 1.0;
+            if (10.0 * rate * worst <= tol) finishing = 1;
+        }
+        prev_worst = worst;
         /* X_l += Qp y_l for the steps inside the linear region */
 #pragma omp parallel for schedule(static)
         for (int r = 0; r < n; ++r)

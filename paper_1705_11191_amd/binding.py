@@ -52,11 +52,13 @@ class Info(ctypes.Structure):
                 ("probe_flops", ctypes.c_double), ("probe_kernel", ctypes.c_char * 48),
                 ("refine_sweeps", ctypes.c_int), ("refine_states", ctypes.c_int),
                 ("refine_resid", ctypes.c_double), ("refine_step", ctypes.c_double),
-                ("overlap_min_eig", ctypes.c_double), ("n_nonsing", ctypes.c_int)]
+                ("overlap_min_eig", ctypes.c_double), ("n_nonsing", ctypes.c_int),
+                ("refine_hist", ctypes.c_double * 8)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "stage_ms"}
         d["probe_kernel"] = self.probe_kernel.decode()
+        d["refine_hist"] = list(self.refine_hist)
         d["stage_ms"] = {s: self.stage_ms[i] for i, s in enumerate(STAGES)}
         return d
 

@@ -104,6 +104,7 @@ struct RefineOutcome {
     int converged;
     double rmax;   // largest residual norm of the first kw states after the last sweep
     double smax;   // largest weighted step of the first kw states (-1: none computed)
+    double hist[8];   // smax of each of the first eight sweeps
 };
 size_t refine_scratch_doubles(int n, int k);
 int refine_subspace(hipStream_t st, int n, int k, int kw, const double* Ht, int ldh, const RefineBuffers& B,

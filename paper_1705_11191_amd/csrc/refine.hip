@@ -2,8 +2,8 @@
 // matrix H~ = L^-1 H L^-T (Eq. (11)), used after the steps of Fig. 1 ran
 // with FP32 matrix-core arithmetic.  The paper's solvers work in one
 // precision; this stage is this library's addition.  One sweep:
-//   (1) orthonormalize X (n x k) by CholeskyQR twice: G = X^T X = R^T R,
-//       X <- X R^-1;
+//   (1) orthonormalize X (n x k) by CholeskyQR (twice in the first sweep,
+//       once after a correction): G = X^T X = R^T R, X <- X R^-1;
 //   (2) Rayleigh-Ritz: A = X^T H~ X (k x k), A = W Theta W^T by the FP64
 //       solver of this library (S = I), X <- X W;
 //   (3) residuals r_l = H~ x_l - theta_l x_l (the pencil residual
@@ -20,11 +20,11 @@
 //       pivoting, one lane per column.
 // After each sweep x_l += Q y_l (for steps <= 1/2, inside the region where
 // the linear model holds) and the next sweep starts.  Once the largest
-// weighted step over the wanted states is <= tol, that step is still taken
-// and one closing sweep of steps (1)-(3) ends the call converged: the step
-// left untaken would be amplified by L^-T in the pencil's eigenvectors,
-// while the error after taking it is of the order of the contraction rate
-// times tol.
+// weighted step W_s over the wanted states is <= tol, or the contraction
+// measured over the last two steps predicts that taking it leaves less than
+// tol (10 (W_s / W_{s-1}) W_s <= tol), that step is still taken and one
+// closing sweep of steps (1)-(3) ends the call converged: the step left
+// untaken would be amplified by L^-T in the pencil's eigenvectors.
 #include "api_internal.h"
 
 #include <algorithm>
@@ -215,15 +215,20 @@ int refine_subspace(hipStream_t st, int n, int k, int kw, const double* Ht, int 
         if (rc) return rc > 0 ? rc : kStatusHip;
     }
     bool finishing = false;
+    double prev_smax = 0.0;
+    for (int l = 0; l < (int)(sizeof(out->hist) / sizeof(out->hist[0])); ++l) out->hist[l] = 0.0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         double* X = B.X[xi];
         double* W = B.X[(xi + 1) % 3];
         double* X2 = B.X[(xi + 2) % 3];
-        // (1) two CholeskyQR passes; each factorization is checked before X is
-        // touched, so that a failure leaves the vectors of the last completed
-        // sweep (or the starting ones) in B.X[out->x_buf]
+        // (1) CholeskyQR: twice for the starting vectors, once after a
+        // correction (which leaves them orthonormal to O(step)); each
+        // factorization is checked before X is touched, so that a failure
+        // leaves the vectors of the last completed sweep (or the starting
+        // ones) in B.X[out->x_buf]
         fill_i(st, B.dinfo, 1, 0);
-        for (int pass = 0; pass < 2; ++pass) {
+        const int passes = (sweep == 0) ? 2 : 1;
+        for (int pass = 0; pass < passes; ++pass) {
             dgemm_splitk(st, 'T', 'N', k, k, n, 1.0, X, ldb, X, ldb, 0.0, B.G, k, B.part, B.npart);
             dpotrf(st, k, B.G, k, B.Linv, B.dinfo);
             int hinfo = 0;
@@ -264,9 +269,11 @@ int refine_subspace(hipStream_t st, int n, int k, int kw, const double* Ht, int 
             out->converged = (rmax <= tol) ? 1 : 0;
             break;
         }
-        // (4) Newton correction in the basis of T
+        // (4) Newton correction in the basis of T.  P commutes with (T - theta)^-1
+        // (Z holds eigenvectors of T), so one projection after the solves gives
+        // P (T - theta)^-1 P rho; the rounding a solve adds along an eigenvector
+        // of T whose eigenvalue is near theta is removed by that projection
         pc->apply_qt(st, R, ldb, k, tmp);
-        project_out(st, n, k, pc->Z, pc->ldz, R, ldb, B.G, B.part, B.npart);
         hipLaunchKernelGGL(tri_shift_solve_kernel, dim3(ceil_div(k, 64)), dim3(64), 0, st, n, k, pc->d, pc->e,
                            B.theta, R, ldb, tmp, B.U1, B.SW);
         project_out(st, n, k, pc->Z, pc->ldz, R, ldb, B.G, B.part, B.npart);
@@ -277,11 +284,16 @@ int refine_subspace(hipStream_t st, int n, int k, int kw, const double* Ht, int 
         double smax = 0.0;
         for (int l = 0; l < kw; ++l) smax = std::max(smax, hw[l] * hs[l]);
         out->smax = smax;
+        if (sweep < (int)(sizeof(out->hist) / sizeof(out->hist[0]))) out->hist[sweep] = smax;
         if (sweep == max_sweeps - 1) break;
         // a step within tol is still taken, and one closing Rayleigh-Ritz
         // sweep follows: left untaken, it would be amplified by L^-T in the
-        // pencil's eigenvectors
+        // pencil's eigenvectors.  The same holds when the contraction measured
+        // over the last two steps predicts that taking this one leaves less
+        // than tol (safety factor 10).
         if (smax <= tol) finishing = true;
+        if (prev_smax > 0.0 && 10.0 * std::min(1.0, smax / prev_smax) * smax <= tol) finishing = true;
+        prev_smax = smax;
         pc->apply_q(st, R, ldb, k, tmp);
         masked_add_kernel<<<dim3(std::max(1, std::min(ceil_div(n, 256), 64)), k), dim3(256), 0, st>>>(
             n, B.X[xi], ldb, R, ldb, B.step, kStepCap);

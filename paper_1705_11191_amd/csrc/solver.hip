@@ -304,16 +304,22 @@ struct ReflectorPrecond : RefinePrecond {
     int n = 0, b = 0, kmax = 0;
     const double *Vall = nullptr, *Tall = nullptr, *V2 = nullptr, *tau2 = nullptr;
     double *Tq = nullptr, *q1work = nullptr;
+    // Q1's products run on the FP32 matrix cores, as in step (5) of this mode:
+    // the correction only needs its own size to a few digits
     void apply_qt(hipStream_t st, double* X, int ld, int ncol, double* tmp) override
     {
         (void)tmp;
-        apply_q1(st, n, b, ncol, Vall, Tall, X, ld, q1work, true);
+        {
+            Fp32GemmScope fp32(true);
+            apply_q1(st, n, b, ncol, Vall, Tall, X, ld, q1work, true);
+        }
         apply_q2(st, n, b, ncol, V2, tau2, kmax, X, ld, Tq, true, true);
     }
     void apply_q(hipStream_t st, double* X, int ld, int ncol, double* tmp) override
     {
         (void)tmp;
         apply_q2(st, n, b, ncol, V2, tau2, kmax, X, ld, Tq, false, true);
+        Fp32GemmScope fp32(true);
         apply_q1(st, n, b, ncol, Vall, Tall, X, ld, q1work, false);
     }
 };
@@ -371,6 +377,7 @@ static int refine_states(elsi_gpu_handle_s* h, const double* Ht, char* ws, const
     h->info.refine_states = kp;
     h->info.refine_resid = out.rmax;
     h->info.refine_step = out.smax;
+    for (int l = 0; l < 8; ++l) h->info.refine_hist[l] = out.hist[l];
     tm.mark(ELSI_GPU_ST_REFINE);
     return (rc == kStatusRefine || !out.converged) ? kStatusRefine : 0;
 }
@@ -425,6 +432,7 @@ static int ev_real(elsi_gpu_handle_s* h, double* H, double* S, double* eval, dou
     h->info.refine_states = 0;
     h->info.refine_resid = 0.0;
     h->info.refine_step = 0.0;
+    for (int l = 0; l < 8; ++l) h->info.refine_hist[l] = 0.0;
     Timer tm(st);
     DcState dc;
     rc = front_half(h, H, S, ws, L, tm, &dc);
@@ -472,6 +480,7 @@ static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, doub
     h->info.refine_states = 0;
     h->info.refine_resid = 0.0;
     h->info.refine_step = 0.0;
+    for (int l = 0; l < 8; ++l) h->info.refine_hist[l] = 0.0;
     Timer tm(st);
     DcState dc;
     rc = front_half(h, H, S, ws, L, tm, &dc);

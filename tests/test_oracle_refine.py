@@ -265,3 +265,22 @@ def test_tridiagonal_shifted_solve_is_backward_stable():
     # an exactly singular matrix gets the tiny-pivot guard: finite result
     x = O.tridiag_shift_solve(np.zeros(2), np.zeros(1), 0.0, np.array([1.0, 1.0]))
     assert np.all(np.isfinite(x))
+
+
+def test_measured_contraction_closes_the_refinement_early():
+    """The closing sweep also follows a step W_s > tol when the contraction
+    measured over the last two steps predicts that taking it leaves less than
+    tol (10 (W_s / W_{s-1}) W_s <= tol); the subspace then still meets tol."""
+    n, k = 60, 8
+    Ht = G.tight_binding_chain(n, 0.0, 1.0)
+    lam, V = _chain_closed_form(n, 0.0, 1.0)
+    rng = np.random.default_rng(24)
+    g = rng.standard_normal(n)
+    X0 = V[:, :k] + 1e-2 * (V[:, k:] @ rng.standard_normal((n - k, k)))
+    tol = 1e-12
+    X, theta, res, step, sweeps, st = O.refine(Ht, X0, k, tol=tol, max_sweeps=8, Q=np.eye(n), d=1e-5 * g,
+                                               e=np.ones(n - 1))
+    assert st == 0 and sweeps == 4
+    assert step.max() > tol                   # the last measured step itself was above tol ...
+    assert _angle(V, k, X) <= tol             # ... and taking it left the subspace within tol
+    assert np.abs(theta - lam[:k]).max() < 1e-13
