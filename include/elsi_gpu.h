@@ -436,6 +436,15 @@ int elsi_gpu_x_band_reduce(int n, int b, double *A, int lda, double *band, int l
 int elsi_gpu_x_tridiagonalize(int n, int b, double *A, int lda, double *d, double *e,
                               void *hip_stream);
 
+/* Schedule of the bulge chasing in step (2), process-wide (a test hook: both
+ * compute the same reflectors up to rounding).  0 automatic: the row-window
+ * schedule (one workgroup per block row of the band, the band in registers)
+ * whenever its grid of (n-2)/b+1 workgroups fits the device at once, else
+ * the pipelined-sweep schedule (one workgroup per sweep, blocks through
+ * device memory); 1 the same choice; 2 always the pipelined-sweep schedule.
+ * Returns -1 for another value. */
+int elsi_gpu_x_set_bulge_path(int path);
+
 /* Steps (1)+(2) on A as elsi_gpu_x_tridiagonalize (d, e receive T), then
  * X (n x ncol, ldx, device) <- Q X (trans 0: steps (4) and (5), Q2 then Q1)
  * or Q^T X (trans 1: Q1^T then Q2^T, the map the mixed mode's refinement

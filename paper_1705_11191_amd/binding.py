@@ -116,6 +116,7 @@ def lib():
         L.elsi_gpu_x_refine.argtypes = [i, i, i, vp, i, vp, i, vp, i, vp, vp, vp, vp, vp, vp, d, i,
                                         ctypes.POINTER(i), vp]
         L.elsi_gpu_x_backtransform.argtypes = [i, i, vp, i, vp, vp, vp, i, i, i, i, vp]
+        L.elsi_gpu_x_set_bulge_path.argtypes = [i]
         _lib = L
     return _lib
 
@@ -269,6 +270,12 @@ def tridiagonalize(A: torch.Tensor, b: int):
     rc = lib().elsi_gpu_x_tridiagonalize(n, b, _ptr(A), n, _ptr(d), _ptr(e), _stream())
     _check(rc, "elsi_gpu_x_tridiagonalize")
     return d, e[: n - 1]
+
+
+def set_bulge_path(path: int) -> None:
+    """Schedule of the bulge chasing, process-wide: 0 automatic, 1 row window
+    (when its grid fits the device), 2 pipelined sweeps."""
+    _check(lib().elsi_gpu_x_set_bulge_path(int(path)), "elsi_gpu_x_set_bulge_path")
 
 
 def tridiag_eig(d: torch.Tensor, e: torch.Tensor):

@@ -333,18 +333,18 @@ int elsi_gpu_x_tridiagonalize(int n, int b, double* A, int lda, double* d, doubl
     if (!e && n > 1) return -6;
     hipStream_t st = (hipStream_t)hip_stream;
     const int bb = std::min(b, std::max(1, n - 1));
-    DevBuf<double> Vall, Tall, Bd, work, Acopy, V2, tau2, ee;
+    DevBuf<double> Vall, Tall, Bd, work, Acopy, V2, tau2, ee, mbox;
     DevBuf<int> ints;
     if (!Vall.alloc((size_t)n * n) || !Tall.alloc((size_t)ceil_div(n, bb) * bb * bb) ||
         !Bd.alloc((size_t)2 * bb * n) || !work.alloc(sy2sb_workspace_doubles(n, bb)) ||
         !Acopy.alloc((size_t)n * n) || !V2.alloc((size_t)n * n) ||
         !tau2.alloc((size_t)std::max(n - 2, 1) * sb2st_kmax(n, bb)) || !ee.alloc((size_t)n) ||
-        !ints.alloc((size_t)n + 64))
+        !ints.alloc((size_t)n + 64) || !mbox.alloc(sb2st_mailbox_doubles(n, bb)))
         return ELSI_GPU_ERR_OOM;
     copy_matrix(st, n, n, A, lda, Acopy.p, n);
     mirror_lower_to_upper(st, n, Acopy.p, n);
     sy2sb(st, n, bb, Acopy.p, n, Vall.p, Tall.p, Bd.p, 2 * bb, work.p);
-    int rc = sb2st(st, n, bb, Bd.p, 2 * bb, d, ee.p, V2.p, tau2.p, ints.p + 64, ints.p);
+    int rc = sb2st(st, n, bb, Bd.p, 2 * bb, d, ee.p, V2.p, tau2.p, ints.p + 64, ints.p, mbox.p);
     if (rc) return rc;
     if (n > 1) (void)hipMemcpyAsync(e, ee.p, sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, st);
     int herr = 0;
@@ -352,6 +352,13 @@ int elsi_gpu_x_tridiagonalize(int n, int b, double* A, int lda, double* d, doubl
     rc = sync_status(st);
     if (rc) return rc;
     return herr ? ELSI_GPU_ERR_NO_CONV : 0;
+}
+
+int elsi_gpu_x_set_bulge_path(int path)
+{
+    if (path < 0 || path > 2) return -1;
+    set_bulge_path(path);
+    return 0;
 }
 
 int elsi_gpu_x_backtransform(int n, int b, const double* A, int lda, double* d, double* e, double* X, int ldx,
@@ -371,19 +378,20 @@ int elsi_gpu_x_backtransform(int n, int b, const double* A, int lda, double* d, 
     hipStream_t st = (hipStream_t)hip_stream;
     const int bb = std::min(b, std::max(1, n - 1));
     const int kmax = sb2st_kmax(n, bb);
-    DevBuf<double> Vall, Tall, Bd, work, Acopy, V2, tau2, ee, Tq, q1work;
+    DevBuf<double> Vall, Tall, Bd, work, Acopy, V2, tau2, ee, Tq, q1work, mbox;
     DevBuf<int> ints;
     if (!Vall.alloc((size_t)n * n) || !Tall.alloc((size_t)ceil_div(n, bb) * bb * bb) ||
         !Bd.alloc((size_t)2 * bb * n) || !work.alloc(sy2sb_workspace_doubles(n, bb)) ||
         !Acopy.alloc((size_t)n * n) || !V2.alloc((size_t)n * n) ||
         !tau2.alloc((size_t)std::max(n - 2, 1) * kmax) || !ee.alloc((size_t)n) ||
         !ints.alloc((size_t)n + 64) || !Tq.alloc(apply_q2_workspace_doubles(n, bb)) ||
+        !mbox.alloc(sb2st_mailbox_doubles(n, bb)) ||
         !q1work.alloc(apply_q1_workspace_doubles(n, std::max(ncol, 1))))
         return ELSI_GPU_ERR_OOM;
     copy_matrix(st, n, n, A, lda, Acopy.p, n);
     mirror_lower_to_upper(st, n, Acopy.p, n);
     sy2sb(st, n, bb, Acopy.p, n, Vall.p, Tall.p, Bd.p, 2 * bb, work.p);
-    int rc = sb2st(st, n, bb, Bd.p, 2 * bb, d, ee.p, V2.p, tau2.p, ints.p + 64, ints.p);
+    int rc = sb2st(st, n, bb, Bd.p, 2 * bb, d, ee.p, V2.p, tau2.p, ints.p + 64, ints.p, mbox.p);
     if (rc) return rc;
     if (n > 1) (void)hipMemcpyAsync(e, ee.p, sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, st);
     if (ncol > 0) {

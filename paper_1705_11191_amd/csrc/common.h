@@ -243,8 +243,12 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
 
 // Step (2): band -> tridiagonal; see sb2st.hip.
 int sb2st_kmax(int n, int b);
+size_t sb2st_mailbox_doubles(int n, int b);
 int sb2st(hipStream_t st, int n, int b, double* Bd, int ldb, double* d, double* e, double* V2, double* tau2,
-          int* progress, int* err);
+          int* progress, int* err, double* mbox);
+// 0: automatic (row window when its grid fits the device), 1: row window
+// when it fits, 2: pipelined sweeps; process-wide, for tests
+void set_bulge_path(int path);
 
 // Step (3): tridiagonal divide and conquer; see stedc.hip.
 struct MergeDescH {

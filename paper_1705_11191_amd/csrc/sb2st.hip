@@ -2,29 +2,48 @@
 // Eq. (13) and Fig. 1): T = Q2^T B Q2 by Householder bulge chasing on the
 // band (successive band reduction).
 //
-// Storage: lower band with room for the bulge, Bd(r, c) = A(c + r, c) for
-// 0 <= r < 2b (ld = 2b).  Sweep s annihilates column s below its first
-// subdiagonal.  Its task 0 reflects A(s+1:s+b, s) and updates the diagonal
-// block A(J0, J0) from both sides; task k >= 1 works on rows J_k = [s+1+kb,
-// s+(k+1)b]: it applies the previous reflector from the right to the block
-// A(J_k, J_{k-1}) (which fills it), takes a new reflector from the block's
-// first column, applies it from the left to the block and from both sides to
-// A(J_k, J_k).  The fill left in the other columns of the block is removed by
-// the following sweeps.
+// Sweep s annihilates column s below its first subdiagonal.  Its task 0
+// reflects A(s+1:s+b, s) and updates the diagonal block A(J0, J0) from both
+// sides; task k >= 1 works on rows J_k = [s+1+kb, s+(k+1)b]: it applies the
+// previous reflector from the right to the block A(J_k, J_{k-1}) (which fills
+// it), takes a new reflector from the block's first column, applies it from
+// the left to the block and from both sides to A(J_k, J_k).  The fill left in
+// the other columns of the block is removed by the following sweeps.
 //
-// Parallel schedule: one workgroup per sweep, sweeps dealt round-robin to a
+// Row-window schedule (the default).  Workgroup k owns rows J_k(s) in every
+// sweep: the off-diagonal block A(J_k, J_{k-1}) and the full symmetric
+// diagonal block A(J_k, J_k) stay in its registers for the whole chase.  From
+// sweep s to s+1 the window moves down one row.  Its top row is final for the
+// sweep and becomes the bottom row of workgroup k-1's next window; the new
+// bottom row comes from workgroup k+1.  Entries are indexed by absolute row
+// and column mod b, so the move copies no data: the leaving row's slot takes
+// the entering row, the off-diagonal slot of the leaving column takes the
+// column that leaves the diagonal block, and that diagonal slot takes the
+// entering column.  An entering row needs only its b+1 entries nearest the
+// diagonal: further out, earlier sweeps have annihilated every entry.  Task
+// (s, k) publishes its reflector as soon as it is formed (for the right
+// application in task (s, k+1)) and its top row after its two-sided update;
+// it waits for the reflector of (s, k-1) and the row of (s-1, k+1), so it
+// runs at pipeline step 2s + k.  Messages are b+1 doubles in two-slot
+// mailboxes, announced by per-workgroup counters.
+//
+// Pipelined-sweep schedule (used when the row-window grid does not fit the
+// device at once).  One workgroup per sweep, sweeps dealt round-robin to a
 // grid that is entirely resident (cooperative launch).  Task k of sweep s
 // touches only rows J_k(s); it overlaps task k+1 of sweep s-1 and nothing
-// later, so it starts once sweep s-1 reports k+2 finished tasks.
+// later, so it starts once sweep s-1 reports k+2 finished tasks.  Each task
+// loads its two blocks from the band and stores them back.
 //
-// Hand-off between workgroups: the band is only ever read and written with
-// device-scope (agent) relaxed atomic accesses, which are coherent across the
-// XCDs without writing back or invalidating their L2 caches.  A task's stores
-// complete (s_waitcnt) before the workgroup barrier, after which one lane
-// publishes the progress counter; waiting lanes poll the counter with the same
-// kind of access.  Every wait is bounded and an expired wait aborts the whole
-// grid with an error flag.
+// Hand-off between workgroups (both schedules): data shared between
+// workgroups is only read and written with device-scope (agent) coherent
+// accesses, which are coherent across the XCDs without writing back or
+// invalidating their L2 caches.  A producer's stores complete (s_waitcnt)
+// before one lane publishes the counter; waiting lanes poll the counter with
+// the same kind of access.  Every wait is bounded and an expired wait aborts
+// the whole grid with an error flag.
 #include "common.h"
+
+#include <atomic>
 
 namespace eg {
 namespace {
@@ -230,6 +249,260 @@ __global__ __launch_bounds__(SBT) void sb2st_kernel(SbArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Row-window schedule
+// ---------------------------------------------------------------------------
+struct SbWinArgs {
+    int n, b, nsweeps, kmax, ldb;
+    const double* Bd;   // the band on entry (read once)
+    double* V2;
+    double* tau2;
+    double* d;
+    double* e;
+    double* vbox;   // kmax x 2 slots x 65: reflector by absolute row mod b, then tau
+    double* rbox;   // kmax x 2 slots x 65: top row by absolute column mod b, then its diagonal entry
+    int* vflag;     // kmax: number of sweeps whose reflector is published
+    int* rflag;     // kmax: number of sweeps whose top row is published
+    int* err;
+    long long spin_limit;
+};
+
+constexpr int kBox = 65;
+
+__device__ inline bool wait_count(int* flag, int need, int* err, long long limit)
+{
+    long long spins = 0;
+    for (;;) {
+        if (ld_flag(flag) >= need) return true;
+        if (ld_flag(err)) return false;
+        if (++spins > limit) {
+            st_flag(err, 1);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Offset of A(R, C) in the band on entry (bandwidth b, lower storage
+// Bd(r, c) = A(c + r, c)), or -1 outside the band.  Branch-free, so that the
+// window's 32 loads issue back to back.
+__device__ inline long band_offset(int n, int b, int ldb, int R, int C)
+{
+    const int lo = min(R, C), dist = abs(R - C);
+    const bool in = R >= 0 && C >= 0 && R < n && C < n && dist <= b;
+    return in ? (long)lo * ldb + dist : -1;
+}
+
+// One-hot mask of column slot `slot` among the wave's slots 16q .. 16q+15
+// (0 when another wave holds it).  The mask is made opaque to the compiler so
+// that the per-slot selects below stay selects on fixed registers instead of
+// being turned into indexed vector accesses.
+__device__ __forceinline__ unsigned slot_mask(int slot, int q)
+{
+    const int j = slot - 16 * q;
+    unsigned m = __builtin_amdgcn_readfirstlane((j >= 0 && j < 16) ? (1u << j) : 0u);
+    asm volatile("" : "+s"(m));
+    return m;
+}
+
+__device__ __forceinline__ bool has(unsigned m, int j) { return (m >> j) & 1u; }
+
+// Thread (l, q) = (tid % 64, tid / 64) holds the window row in slot l, in the
+// column slots 16q .. 16q+15: ob (off-diagonal block) and dg (diagonal block,
+// both triangles).  Slots >= b stay zero.
+__global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
+{
+    __shared__ double vps[SB], vs[SB], ws[SB], rowm[SB];
+    __shared__ double red[4][SB];
+    __shared__ double sh[4];   // tau, alpha, tau of the previous reflector, diagonal entry of the new row
+    __shared__ int abort_flag;
+    const int tid = threadIdx.x;
+    const int l = tid & 63;
+    const int q = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = a.n, b = a.b;
+    const int k = blockIdx.x;
+    double ob[16], dg[16];
+    {
+        const int R0 = 1 + k * b, p0 = R0 % b;
+        const int R = (l < b) ? R0 + ((l - p0 + b) % b) : n;   // n: no row
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int c = 16 * q + j;
+            const int cc = (c - p0 + b) % b;
+            const long oo = (c < b) ? band_offset(n, b, a.ldb, R, R0 - b + cc) : -1;
+            const long od = (c < b) ? band_offset(n, b, a.ldb, R, R0 + cc) : -1;
+            const double xo = a.Bd[oo < 0 ? 0 : oo];
+            const double xd = a.Bd[od < 0 ? 0 : od];
+            ob[j] = (oo < 0) ? 0.0 : xo;
+            dg[j] = (od < 0) ? 0.0 : xd;
+        }
+    }
+    if (tid == 0) {
+        abort_flag = 0;
+        if (k == 0) a.d[0] = a.Bd[0];
+    }
+    __syncthreads();
+
+    for (int s = 0; s < a.nsweeps && k < ntasks(n, b, s); ++s) {
+        const int r0 = s + 1 + k * b;
+        const int p = r0 % b;                  // slot of the top row
+        const int pm = (p == 0) ? b - 1 : p - 1;   // slot of the row (and column) that left
+        const int rowabs = r0 + ((l >= p) ? l - p : l - p + b);
+        const bool valid = l < b && rowabs < n;
+        const bool need_row = s > 0 && k + 1 < ntasks(n, b, s - 1);
+        const bool need_v = k > 0;
+        // ---- waits: the row of (s-1, k+1) in wave 0, the reflector of (s, k-1) in wave 1
+        if (tid == 0 && need_row && !wait_count(&a.rflag[k + 1], s, a.err, a.spin_limit)) abort_flag = 1;
+        if (tid == 64 && need_v && !wait_count(&a.vflag[k - 1], s + 1, a.err, a.spin_limit)) abort_flag = 1;
+        __syncthreads();
+        if (abort_flag) return;
+        if (q == 0) {
+            const double* box = a.rbox + ((size_t)(k + 1) * 2 + ((s - 1) & 1)) * kBox;
+            rowm[l] = (need_row && l < b) ? ldc(box + l) : 0.0;
+            if (l == 0) sh[3] = need_row ? ldc(box + 64) : 0.0;
+        } else if (q == 1) {
+            const double* box = a.vbox + ((size_t)(k - 1) * 2 + (s & 1)) * kBox;
+            vps[l] = (need_v && l < b) ? ldc(box + l) : 0.0;
+            if (l == 0) sh[2] = need_v ? ldc(box + 64) : 0.0;
+        }
+        __syncthreads();
+        // ---- move the window down one row (zeros when the new row is past n)
+        if (s > 0) {
+            const double rd = sh[3];
+            const unsigned mpm = slot_mask(pm, q);
+            const double col_in = (l == pm) ? rd : rowm[l];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (has(mpm, j)) {
+                    ob[j] = dg[j];
+                    dg[j] = col_in;
+                }
+            }
+            if (l == pm) {
+                const double alpha_in = rowm[pm];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    ob[j] = has(mpm, j) ? alpha_in : 0.0;
+                    dg[j] = has(mpm, j) ? rd : rowm[16 * q + j];
+                }
+            }
+        }
+        // ---- right application of the previous reflector: ob <- ob (I - tp vp vp^T)
+        const double tp = sh[2];
+        if (need_v && tp != 0.0) {
+            double part = 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) part += ob[j] * vps[16 * q + j];
+            red[q][l] = part;
+            __syncthreads();
+            const double w = tp * (red[0][l] + red[1][l] + red[2][l] + red[3][l]);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) ob[j] -= w * vps[16 * q + j];
+        }
+        // ---- reflector of the block's first column (k >= 1) or of column s (k == 0)
+        const int hc = (k > 0) ? p : pm;
+        const int hq = hc >> 4;
+        const unsigned mhc = slot_mask(hc, q);
+        if (q == hq) {
+            double x = 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (has(mhc, j)) x = ob[j];
+            if (!valid) x = 0.0;
+            const double tail = wave_sum64((l != p) ? x * x : 0.0);
+            const double x0 = __shfl(x, p, 64);
+            double t = 0.0, den = 1.0, alpha = x0;
+            if (tail > 0.0) {
+                const double nrm = sqrt(x0 * x0 + tail);
+                alpha = (x0 >= 0.0) ? -nrm : nrm;
+                t = (alpha - x0) / alpha;
+                den = x0 - alpha;
+            }
+            const double v = (l == p) ? 1.0 : ((valid && tail > 0.0) ? x / den : 0.0);
+            vs[l] = v;
+            if (l == 0) {
+                sh[0] = t;
+                sh[1] = alpha;
+            }
+            if (k + 1 < ntasks(n, b, s)) {   // for the right application in task (s, k+1)
+                double* box = a.vbox + ((size_t)k * 2 + (s & 1)) * kBox;
+                if (l < b) stc(box + l, v);
+                if (l == 0) stc(box + 64, t);
+                __builtin_amdgcn_s_waitcnt(0);
+                if (l == 0) st_flag(&a.vflag[k], s + 1);
+            }
+        }
+        __syncthreads();
+        const double t = sh[0], alpha = sh[1];
+        const double v = vs[l];
+        // ---- left application to the off-diagonal block; column sums inside each wave
+        if (k > 0 && t != 0.0) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const double u = t * wave_sum64(v * ob[j]);
+                ob[j] -= v * u;
+            }
+        }
+        {
+            const double col_out = (l == p) ? alpha : 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (has(mhc, j)) ob[j] = col_out;
+        }
+        // ---- two-sided update of the diagonal block: dg <- H dg H
+        if (t != 0.0) {
+            double part = 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) part += dg[j] * vs[16 * q + j];
+            red[q][l] = part;
+            __syncthreads();
+            const double pi = t * (red[0][l] + red[1][l] + red[2][l] + red[3][l]);
+            const double beta = 0.5 * t * wave_sum64(pi * v);
+            const double w = pi - beta * v;
+            if (q == 0) ws[l] = w;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 16; ++j) dg[j] -= v * ws[16 * q + j] + w * vs[16 * q + j];
+        }
+        // ---- the top row, final for this sweep, to workgroup k-1
+        if (k > 0 && s + 1 < a.nsweeps && k - 1 < ntasks(n, b, s + 1)) {
+            double* box = a.rbox + ((size_t)k * 2 + (s & 1)) * kBox;
+            if (l == p) {
+                const unsigned mp = slot_mask(p, q);
+                double dpp = 0.0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    if (16 * q + j < b) stc(box + 16 * q + j, ob[j]);
+                    if (has(mp, j)) dpp = dg[j];
+                }
+                if (mp) stc(box + 64, dpp);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (tid == 0) st_flag(&a.rflag[k], s + 1);
+        }
+        // ---- outputs: the reflector for Q2, and T's entries that are final
+        if (q == 0 && valid) a.V2[cm(rowabs, s, n)] = v;
+        if (tid == 0) a.tau2[(size_t)s * a.kmax + k] = t;
+        if (k == 0) {
+            if (tid == 0) a.e[s] = alpha;
+            const int l1 = (p + 1 == b) ? 0 : p + 1;
+            const unsigned mp = slot_mask(p, q), ml1 = slot_mask(l1, q);
+            double dp = 0.0, dl1 = 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (has(mp, j)) dp = dg[j];
+                if (has(ml1, j)) dl1 = dg[j];
+            }
+            if (l == p && mp) a.d[r0] = dp;
+            if (s == a.nsweeps - 1 && l == l1) {
+                if (ml1) a.d[n - 1] = dl1;
+                if (mp) a.e[n - 2] = dp;
+            }
+        }
+    }
+}
+
 __global__ void extract_tridiag_kernel(int n, const double* Bd, int ldb, double* d, double* e)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -242,37 +515,69 @@ __global__ void extract_tridiag_kernel(int n, const double* Bd, int ldb, double*
 
 int sb2st_kmax(int n, int b) { return n >= 2 ? (n - 2) / b + 1 : 1; }
 
+size_t sb2st_mailbox_doubles(int n, int b) { return (size_t)sb2st_kmax(n, b) * 4 * kBox; }
+
+namespace {
+std::atomic<int> g_bulge_path{0};   // 0: automatic, 1: row window (if it fits), 2: pipelined sweeps
+}
+
+void set_bulge_path(int path) { g_bulge_path.store(path); }
+
 // Bd (ldb = 2b) -> (d, e); reflectors into V2 (n x n, ld n) and tau2
-// (nsweeps x kmax).  progress: n ints of scratch.  Returns 0, or 2 when a
-// wait expired (the grid was aborted).
+// (nsweeps x kmax).  progress: n ints of scratch; mbox: sb2st_mailbox_doubles.
+// Returns 0 (an expired wait sets *err and aborts the grid; the caller reports
+// it), or kStatusHip when the launch fails.
 int sb2st(hipStream_t st, int n, int b, double* Bd, int ldb, double* d, double* e, double* V2, double* tau2,
-          int* progress, int* err)
+          int* progress, int* err, double* mbox)
 {
     const int nsweeps = n - 2;
     fill_i(st, err, 1, 0);
-    if (nsweeps > 0) {
-        fill_i(st, progress, (size_t)nsweeps, 0);
-        int dev = 0, cus = 0, per_cu = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sb2st_kernel, SBT, 0);
-        int resident = std::max(1, cus * std::max(1, per_cu));
-        // sweep s starts two tasks after sweep s-1, so a workgroup that takes
-        // sweep s + grid after finishing sweep s (ntasks(0) tasks) never holds the
-        // pipeline back once grid >= ntasks(0) / 2; a few spare workgroups absorb
-        // uneven timing
-        const int need = ((n - 2) / b + 1) / 2 + 8;
-        int grid = std::min(nsweeps, std::min(std::min(resident, cus > 0 ? cus : 1), need));
-        SbArgs a;
-        a.n = n; a.b = b; a.ldb = ldb; a.nsweeps = nsweeps; a.kmax = sb2st_kmax(n, b);
-        a.Bd = Bd; a.V2 = V2; a.tau2 = tau2; a.progress = progress; a.err = err;
+    if (nsweeps <= 0) {
+        hipLaunchKernelGGL(extract_tridiag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, Bd, ldb, d, e);
+        return 0;
+    }
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    cus = std::max(cus, 1);
+    const int kmax = sb2st_kmax(n, b);
+    const int path = g_bulge_path.load();
+    int per_cu_w = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_w, sb2st_window_kernel, SBT, 0);
+    const int resident_w = cus * std::max(0, per_cu_w);
+    if (path != 2 && kmax <= resident_w) {
+        fill_i(st, progress, (size_t)2 * kmax, 0);
+        SbWinArgs a;
+        a.n = n; a.b = b; a.nsweeps = nsweeps; a.kmax = kmax; a.ldb = ldb;
+        a.Bd = Bd; a.V2 = V2; a.tau2 = tau2; a.d = d; a.e = e;
+        a.vbox = mbox; a.rbox = mbox + (size_t)kmax * 2 * kBox;
+        a.vflag = progress; a.rflag = progress + kmax; a.err = err;
         a.spin_limit = 1LL << 22;
         void* args[] = {&a};
-        const bool gated = persistent_enter(grid, resident);
-        hipError_t rc = hipLaunchCooperativeKernel((const void*)sb2st_kernel, dim3(grid), dim3(SBT), args, 0, st);
-        persistent_leave(st, gated, grid);
-        if (rc != hipSuccess) return kStatusHip;
+        const bool gated = persistent_enter(kmax, resident_w);
+        hipError_t rc = hipLaunchCooperativeKernel((const void*)sb2st_window_kernel, dim3(kmax), dim3(SBT), args, 0, st);
+        persistent_leave(st, gated, kmax);
+        return rc == hipSuccess ? 0 : kStatusHip;
     }
+    fill_i(st, progress, (size_t)nsweeps, 0);
+    int per_cu = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sb2st_kernel, SBT, 0);
+    int resident = std::max(1, cus * std::max(1, per_cu));
+    // sweep s starts two tasks after sweep s-1, so a workgroup that takes
+    // sweep s + grid after finishing sweep s (ntasks(0) tasks) never holds the
+    // pipeline back once grid >= ntasks(0) / 2; a few spare workgroups absorb
+    // uneven timing
+    const int need = ((n - 2) / b + 1) / 2 + 8;
+    int grid = std::min(nsweeps, std::min(std::min(resident, cus), need));
+    SbArgs a;
+    a.n = n; a.b = b; a.ldb = ldb; a.nsweeps = nsweeps; a.kmax = kmax;
+    a.Bd = Bd; a.V2 = V2; a.tau2 = tau2; a.progress = progress; a.err = err;
+    a.spin_limit = 1LL << 22;
+    void* args[] = {&a};
+    const bool gated = persistent_enter(grid, resident);
+    hipError_t rc = hipLaunchCooperativeKernel((const void*)sb2st_kernel, dim3(grid), dim3(SBT), args, 0, st);
+    persistent_leave(st, gated, grid);
+    if (rc != hipSuccess) return kStatusHip;
     hipLaunchKernelGGL(extract_tridiag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, Bd, ldb, d, e);
     return 0;
 }

@@ -42,7 +42,7 @@ void density_matrix(hipStream_t st, int n, int k, const double* C, int ldc, cons
 // workspace layout (all sub-buffers 256-byte aligned)
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t linv, bd, vall, tall, v2, tau2, tq2, d, e, w, z, z2, u, sywork, dcwork, q1work, f, scal, ints;
+    size_t linv, bd, vall, tall, v2, tau2, tq2, d, e, w, z, z2, u, sywork, dcwork, q1work, f, scal, ints, mbox;
     // mixed precision: the band reduction's copy of H~ (H keeps H~ for the
     // refinement), which afterwards holds the eigenvectors of T of the carried
     // states; the refinement's k' x k' blocks, per-state values and the
@@ -77,6 +77,7 @@ static Layout make_layout(int n, int b, int ncol, bool mixed = false, bool vcopy
     L.f = put(sizeof(double) * n);
     L.scal = put(sizeof(double) * 16);
     L.ints = put(sizeof(int) * ((size_t)n + 64));
+    L.mbox = put(sizeof(double) * sb2st_mailbox_doubles(n, b));
     if (mixed) {
         L.hcopy = put(sizeof(double) * nn);
         L.rg = put(sizeof(double) * nn);
@@ -251,7 +252,8 @@ static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, cons
     tm.mark(ELSI_GPU_ST_BAND);
     double* d = (double*)(ws + L.d);
     double* e = (double*)(ws + L.e);
-    int rc = sb2st(st, n, b, Bd, 2 * b, d, e, (double*)(ws + L.v2), (double*)(ws + L.tau2), progress, err);
+    int rc = sb2st(st, n, b, Bd, 2 * b, d, e, (double*)(ws + L.v2), (double*)(ws + L.tau2), progress, err,
+                   (double*)(ws + L.mbox));
     if (rc) return rc;
     tm.mark(ELSI_GPU_ST_BULGE);
     double* w = (double*)(ws + L.w);
