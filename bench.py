@@ -431,6 +431,33 @@ def complex_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def counters_q2(args):
+    """The counter passes' Q2 program: a calibration copy (--calibrate-copy),
+    then X <- Q X for a random symmetric A of order n and n/2 columns."""
+    import torch
+
+    from paper_1705_11191_amd import binding as B
+
+    n = args.counters_n
+    if args.calibrate_copy:
+        x = torch.ones(COPY_ELEMS, device="cuda", dtype=torch.float64)
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
+    g = torch.Generator(device="cuda").manual_seed(5)
+    A = torch.randn(n, n, device="cuda", dtype=torch.float64, generator=g)
+    A = A + A.T
+    X = B.fortran_empty(n, n // 2)
+    X.copy_(torch.randn(n, n // 2, device="cuda", dtype=torch.float64, generator=g))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.backtransform(A, args.band, X, trans=False)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_only": True, "stage": "q2", "n": n, "ncol": n // 2,
+                      "wall_s": time.perf_counter() - t0}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,6 +472,13 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary of --kernel from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--kernel", default="dgemm_kernel<128,128,0,true,false,false>")
+    ap.add_argument("--counters-only", action="store_true",
+                    help="one untimed FP64 step of the single workload and nothing else (no HIP events, no "
+                         "launch probe, no CPU baseline): the program the hardware-counter passes run")
+    ap.add_argument("--counters-stage", choices=["dm", "q2"], default="dm",
+                    help="with --counters-only: dm (the whole solve of the workload) or q2 (one application "
+                         "of Q = Q1 Q2 to n/2 columns, n = --counters-n, random symmetric input)")
+    ap.add_argument("--counters-n", type=int, default=16384)
     ap.add_argument("--pmc-command", action="append", default=[])
     ap.add_argument("--workload", choices=["single", "batch", "complex"], default="single",
                     help="single: the N=32768 dm solve; batch: 256 uneven problems in one batched call")
@@ -495,6 +529,9 @@ def main():
     from paper_1705_11191_amd import binding as B
     from synth import generator as G
 
+    if args.counters_only and args.counters_stage == "q2":
+        counters_q2(args)
+        return
     wl = WORKLOADS[args.config]
     n = wl["n"]
     dev = torch.device("cuda:0")
@@ -565,6 +602,13 @@ def main():
         del ws
         return ms, stage_ms, info, probe_info, status[0]
 
+    if args.counters_only:
+        # the calibration copy (--calibrate-copy) ran above; one plain step follows
+        t0 = time.perf_counter()
+        run_path(False, 1, 0, probe=False)
+        print(json.dumps({"counters_only": True, "workload": wl["name"],
+                          "wall_s": time.perf_counter() - t0}), flush=True)
+        return
     mixed_only = args.precision == "mixed"
     out = None
     ref64 = None

@@ -25,7 +25,13 @@
 // application in task (s, k+1)) and its top row after its two-sided update;
 // it waits for the reflector of (s, k-1) and the row of (s-1, k+1), so it
 // runs at pipeline step 2s + k.  Messages are b+1 doubles in two-slot
-// mailboxes, announced by per-workgroup counters.
+// mailboxes.  Each double travels as two 64-bit words, one per 32-bit half,
+// each word tagged with the sweep in its upper 32 bits: 64-bit atomic stores
+// are single-copy atomic, so a word whose tag matches holds its half of this
+// sweep's value, and a consumer wave that finds every tag current has the
+// whole message.  The producer therefore stores and moves on (no wait for its
+// stores, no counter), and the consumer's poll of the message is also its
+// load.
 //
 // Pipelined-sweep schedule (used when the row-window grid does not fit the
 // device at once).  One workgroup per sweep, sweeps dealt round-robin to a
@@ -37,10 +43,10 @@
 // Hand-off between workgroups (both schedules): data shared between
 // workgroups is only read and written with device-scope (agent) coherent
 // accesses, which are coherent across the XCDs without writing back or
-// invalidating their L2 caches.  A producer's stores complete (s_waitcnt)
-// before one lane publishes the counter; waiting lanes poll the counter with
-// the same kind of access.  Every wait is bounded and an expired wait aborts
-// the whole grid with an error flag.
+// invalidating their L2 caches.  In the pipelined-sweep schedule a producer's
+// stores complete (s_waitcnt) before one lane publishes a progress counter;
+// waiting lanes poll the counter with the same kind of access.  Every wait is
+// bounded and an expired wait aborts the whole grid with an error flag.
 #include "common.h"
 
 #include <atomic>
@@ -259,25 +265,59 @@ struct SbWinArgs {
     double* tau2;
     double* d;
     double* e;
-    double* vbox;   // kmax x 2 slots x 65: reflector by absolute row mod b, then tau
-    double* rbox;   // kmax x 2 slots x 65: top row by absolute column mod b, then its diagonal entry
-    int* vflag;     // kmax: number of sweeps whose reflector is published
-    int* rflag;     // kmax: number of sweeps whose top row is published
+    unsigned long long* vbox;   // kmax x 2 slots x kBoxWords: reflector by absolute row mod b, then tau
+    unsigned long long* rbox;   // kmax x 2 slots x kBoxWords: top row by absolute column mod b, then its diagonal
     int* err;
     long long spin_limit;
 };
 
-constexpr int kBox = 65;
+constexpr int kBoxWords = 2 * 65;   // value i in words 2i (upper half) and 2i+1 (lower half); i = 64: the extra value
 
-__device__ inline bool wait_count(int* flag, int need, int* err, long long limit)
+__device__ inline unsigned long long ld_word(const unsigned long long* p)
 {
+    return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void put_value(unsigned long long* box, int i, double x, unsigned tag)
+{
+    const unsigned long long bits = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long t = (unsigned long long)tag << 32;
+    __hip_atomic_store(box + 2 * i, t | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(box + 2 * i + 1, t | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wave polls a message until every word it needs carries `tag`: values
+// 0 .. b-1 (lane l takes value l) and the extra value (lane 0).  Returns false
+// when the grid's error flag is set or the spin limit expires (then it sets
+// the flag).
+__device__ inline bool poll_message(const unsigned long long* box, int b, unsigned tag, int* err, long long limit,
+                                    double& val, double& extra)
+{
+    const int lane = threadIdx.x & 63;
     long long spins = 0;
     for (;;) {
-        if (ld_flag(flag) >= need) return true;
-        if (ld_flag(err)) return false;
-        if (++spins > limit) {
-            st_flag(err, 1);
-            return false;
+        bool ok = true;
+        if (lane < b) {
+            const unsigned long long w0 = ld_word(box + 2 * lane), w1 = ld_word(box + 2 * lane + 1);
+            ok = (unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag;
+            val = __builtin_bit_cast(double, (w0 << 32) | (w1 & 0xffffffffull));
+        }
+        if (lane == 0) {
+            const unsigned long long w0 = ld_word(box + 128), w1 = ld_word(box + 129);
+            ok = ok && (unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag;
+            extra = __builtin_bit_cast(double, (w0 << 32) | (w1 & 0xffffffffull));
+        }
+        if (__all(ok)) return true;
+        if ((++spins & 63) == 0) {
+            int bad = 0;
+            if (lane == 0) {
+                bad = ld_flag(err);
+                if (!bad && spins > limit) {
+                    st_flag(err, 1);
+                    bad = 1;
+                }
+            }
+            if (__shfl(bad, 0, 64)) return false;
         }
         __builtin_amdgcn_s_sleep(1);
     }
@@ -351,21 +391,28 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
         const bool valid = l < b && rowabs < n;
         const bool need_row = s > 0 && k + 1 < ntasks(n, b, s - 1);
         const bool need_v = k > 0;
-        // ---- waits: the row of (s-1, k+1) in wave 0, the reflector of (s, k-1) in wave 1
-        if (tid == 0 && need_row && !wait_count(&a.rflag[k + 1], s, a.err, a.spin_limit)) abort_flag = 1;
-        if (tid == 64 && need_v && !wait_count(&a.vflag[k - 1], s + 1, a.err, a.spin_limit)) abort_flag = 1;
-        __syncthreads();
-        if (abort_flag) return;
+        // ---- messages: the row of (s-1, k+1) polled by wave 0 (tag s), the
+        // reflector of (s, k-1) by wave 1 (tag s+1)
         if (q == 0) {
-            const double* box = a.rbox + ((size_t)(k + 1) * 2 + ((s - 1) & 1)) * kBox;
-            rowm[l] = (need_row && l < b) ? ldc(box + l) : 0.0;
-            if (l == 0) sh[3] = need_row ? ldc(box + 64) : 0.0;
+            double val = 0.0, extra = 0.0;
+            if (need_row) {
+                const unsigned long long* box = a.rbox + ((size_t)(k + 1) * 2 + ((s - 1) & 1)) * kBoxWords;
+                if (!poll_message(box, b, (unsigned)s, a.err, a.spin_limit, val, extra) && l == 0) abort_flag = 1;
+            }
+            rowm[l] = (l < b) ? val : 0.0;
+            if (l == 0) sh[3] = extra;
         } else if (q == 1) {
-            const double* box = a.vbox + ((size_t)(k - 1) * 2 + (s & 1)) * kBox;
-            vps[l] = (need_v && l < b) ? ldc(box + l) : 0.0;
-            if (l == 0) sh[2] = need_v ? ldc(box + 64) : 0.0;
+            double val = 0.0, extra = 0.0;
+            if (need_v) {
+                const unsigned long long* box = a.vbox + ((size_t)(k - 1) * 2 + (s & 1)) * kBoxWords;
+                if (!poll_message(box, b, (unsigned)s + 1, a.err, a.spin_limit, val, extra) && l == 0)
+                    abort_flag = 1;
+            }
+            vps[l] = (l < b) ? val : 0.0;
+            if (l == 0) sh[2] = extra;
         }
         __syncthreads();
+        if (abort_flag) return;
         // ---- move the window down one row (zeros when the new row is past n)
         if (s > 0) {
             const double rd = sh[3];
@@ -425,11 +472,9 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
                 sh[1] = alpha;
             }
             if (k + 1 < ntasks(n, b, s)) {   // for the right application in task (s, k+1)
-                double* box = a.vbox + ((size_t)k * 2 + (s & 1)) * kBox;
-                if (l < b) stc(box + l, v);
-                if (l == 0) stc(box + 64, t);
-                __builtin_amdgcn_s_waitcnt(0);
-                if (l == 0) st_flag(&a.vflag[k], s + 1);
+                unsigned long long* box = a.vbox + ((size_t)k * 2 + (s & 1)) * kBoxWords;
+                if (l < b) put_value(box, l, v, (unsigned)s + 1);
+                if (l == 0) put_value(box, 64, t, (unsigned)s + 1);
             }
         }
         __syncthreads();
@@ -466,20 +511,17 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
         }
         // ---- the top row, final for this sweep, to workgroup k-1
         if (k > 0 && s + 1 < a.nsweeps && k - 1 < ntasks(n, b, s + 1)) {
-            double* box = a.rbox + ((size_t)k * 2 + (s & 1)) * kBox;
+            unsigned long long* box = a.rbox + ((size_t)k * 2 + (s & 1)) * kBoxWords;
             if (l == p) {
                 const unsigned mp = slot_mask(p, q);
                 double dpp = 0.0;
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
-                    if (16 * q + j < b) stc(box + 16 * q + j, ob[j]);
+                    if (16 * q + j < b) put_value(box, 16 * q + j, ob[j], (unsigned)s + 1);
                     if (has(mp, j)) dpp = dg[j];
                 }
-                if (mp) stc(box + 64, dpp);
+                if (mp) put_value(box, 64, dpp, (unsigned)s + 1);
             }
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            if (tid == 0) st_flag(&a.rflag[k], s + 1);
         }
         // ---- outputs: the reflector for Q2, and T's entries that are final
         if (q == 0 && valid) a.V2[cm(rowabs, s, n)] = v;
@@ -515,7 +557,7 @@ __global__ void extract_tridiag_kernel(int n, const double* Bd, int ldb, double*
 
 int sb2st_kmax(int n, int b) { return n >= 2 ? (n - 2) / b + 1 : 1; }
 
-size_t sb2st_mailbox_doubles(int n, int b) { return (size_t)sb2st_kmax(n, b) * 4 * kBox; }
+size_t sb2st_mailbox_doubles(int n, int b) { return (size_t)sb2st_kmax(n, b) * 4 * kBoxWords; }
 
 namespace {
 std::atomic<int> g_bulge_path{0};   // 0: automatic, 1: row window (if it fits), 2: pipelined sweeps
@@ -524,7 +566,8 @@ std::atomic<int> g_bulge_path{0};   // 0: automatic, 1: row window (if it fits),
 void set_bulge_path(int path) { g_bulge_path.store(path); }
 
 // Bd (ldb = 2b) -> (d, e); reflectors into V2 (n x n, ld n) and tau2
-// (nsweeps x kmax).  progress: n ints of scratch; mbox: sb2st_mailbox_doubles.
+// (nsweeps x kmax).  progress: n ints of scratch (pipelined-sweep schedule);
+// mbox: sb2st_mailbox_doubles (row-window schedule).
 // Returns 0 (an expired wait sets *err and aborts the grid; the caller reports
 // it), or kStatusHip when the launch fails.
 int sb2st(hipStream_t st, int n, int b, double* Bd, int ldb, double* d, double* e, double* V2, double* tau2,
@@ -546,12 +589,14 @@ int sb2st(hipStream_t st, int n, int b, double* Bd, int ldb, double* d, double* 
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_w, sb2st_window_kernel, SBT, 0);
     const int resident_w = cus * std::max(0, per_cu_w);
     if (path != 2 && kmax <= resident_w) {
-        fill_i(st, progress, (size_t)2 * kmax, 0);
+        // tag 0 everywhere: no word of a previous call can pass for a current one
+        fill_d(st, mbox, sb2st_mailbox_doubles(n, b), 0.0);
         SbWinArgs a;
         a.n = n; a.b = b; a.nsweeps = nsweeps; a.kmax = kmax; a.ldb = ldb;
         a.Bd = Bd; a.V2 = V2; a.tau2 = tau2; a.d = d; a.e = e;
-        a.vbox = mbox; a.rbox = mbox + (size_t)kmax * 2 * kBox;
-        a.vflag = progress; a.rflag = progress + kmax; a.err = err;
+        a.vbox = (unsigned long long*)mbox;
+        a.rbox = (unsigned long long*)mbox + (size_t)kmax * 2 * kBoxWords;
+        a.err = err;
         a.spin_limit = 1LL << 22;
         void* args[] = {&a};
         const bool gated = persistent_enter(kmax, resident_w);
