@@ -354,6 +354,7 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
 {
     __shared__ double vps[SB], vs[SB], ws[SB], rowm[SB];
     __shared__ double red[4][SB];
+    __shared__ double colbuf[4][16][SB + 1];   // per wave: the left application's products by column (padded)
     __shared__ double sh[4];   // tau, alpha, tau of the previous reflector, diagonal entry of the new row
     __shared__ int abort_flag;
     const int tid = threadIdx.x;
@@ -480,11 +481,25 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
         __syncthreads();
         const double t = sh[0], alpha = sh[1];
         const double v = vs[l];
-        // ---- left application to the off-diagonal block; column sums inside each wave
+        // ---- left application to the off-diagonal block.  The wave's 16 column
+        // sums go through its own LDS block: lanes 4c .. 4c+3 sum a quarter of
+        // column c each, a quad reduction completes it, and the 16 sums return
+        // as scalars.
         if (k > 0 && t != 0.0) {
+            double(*cb)[SB + 1] = colbuf[q];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) cb[j][l] = v * ob[j];
+            __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS stores are done
+            __builtin_amdgcn_wave_barrier();
+            const int c = l >> 2, r0q = (l & 3) * 16;
+            double part = 0.0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) part += cb[c][r0q + i];
+            part += __shfl_xor(part, 1, 64);
+            part += __shfl_xor(part, 2, 64);
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                const double u = t * wave_sum64(v * ob[j]);
+                const double u = t * __shfl(part, 4 * j, 64);
                 ob[j] -= v * u;
             }
         }
@@ -511,17 +526,20 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
         }
         // ---- the top row, final for this sweep, to workgroup k-1
         if (k > 0 && s + 1 < a.nsweeps && k - 1 < ntasks(n, b, s + 1)) {
+            // the row sits in lane p; lanes 0 .. 15 each take one of its 16
+            // values (a broadcast from lane p per slot) and store it, so the
+            // wave issues two stores instead of one lane issuing 32
             unsigned long long* box = a.rbox + ((size_t)k * 2 + (s & 1)) * kBoxWords;
-            if (l == p) {
-                const unsigned mp = slot_mask(p, q);
-                double dpp = 0.0;
+            const unsigned mp = slot_mask(p, q);
+            double mine = 0.0, dpp = 0.0;
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    if (16 * q + j < b) put_value(box, 16 * q + j, ob[j], (unsigned)s + 1);
-                    if (has(mp, j)) dpp = dg[j];
-                }
-                if (mp) put_value(box, 64, dpp, (unsigned)s + 1);
+            for (int j = 0; j < 16; ++j) {
+                const double x = __shfl(ob[j], p, 64);
+                if (l == j) mine = x;
+                if (has(mp, j)) dpp = dg[j];
             }
+            if (l < 16 && 16 * q + l < b) put_value(box, 16 * q + l, mine, (unsigned)s + 1);
+            if (mp && l == p) put_value(box, 64, dpp, (unsigned)s + 1);
         }
         // ---- outputs: the reflector for Q2, and T's entries that are final
         if (q == 0 && valid) a.V2[cm(rowabs, s, n)] = v;
