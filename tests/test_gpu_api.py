@@ -51,7 +51,7 @@ def test_dm_sizes_and_band_widths_vs_oracle(n, b):
     D, ev, f, energy, mu, st = h.dm(_dev(H), _dev(S))
     h.close()
     assert st == 0
-    assert eig_excess(ev.cpu().numpy(), ref["eval"], S) <= 1.0
+    assert eig_excess(ev.cpu().numpy(), ref["eval"], S, occ=ref["occ"]) <= 1.0
     D = D.cpu().numpy()
     assert np.abs(D - ref["D"]).max() <= 1e-9
     assert abs(energy - ref["energy"]) <= 1e-9 * max(1.0, abs(ref["energy"]))
@@ -113,7 +113,7 @@ def test_dm_reuses_factored_overlap():
     h.close()
     ref = O.dm(H2, sp.S, sp.n_occ, sp.kT)
     assert st == 0
-    assert eig_excess(ev2.cpu().numpy(), ref["eval"], sp.S) <= 1.0
+    assert eig_excess(ev2.cpu().numpy(), ref["eval"], sp.S, occ=ref["occ"]) <= 1.0
     assert np.abs(D2.cpu().numpy() - ref["D"]).max() <= 1e-9
 
 

@@ -58,7 +58,7 @@ def test_dm_batched_vs_oracle():
     assert rc == 0 and status == [0] * len(sps)
     for q, sp in enumerate(sps):
         ref = O.dm(sp.H, sp.S, sp.n_occ, sp.kT)
-        assert eig_excess(evals[q].cpu().numpy(), ref["eval"], sp.S) <= 1.0, q
+        assert eig_excess(evals[q].cpu().numpy(), ref["eval"], sp.S, occ=ref["occ"]) <= 1.0, q
         D = Ds[q].cpu().numpy()
         assert np.abs(D - ref["D"]).max() <= 1e-9, q
         _check_mu(mu[q], ref, sp)
@@ -232,4 +232,4 @@ def test_tuner_sets_a_width_per_bucket_and_caches_it(tmp_path):
     for q, sp in enumerate(sps):
         ref = O.dm(sp.H, sp.S, sp.n_occ, sp.kT)
         assert np.abs(Ds[q].cpu().numpy() - ref["D"]).max() <= 1e-9
-        assert eig_excess(evals[q].cpu().numpy(), ref["eval"], sp.S) <= 1.0
+        assert eig_excess(evals[q].cpu().numpy(), ref["eval"], sp.S, occ=ref["occ"]) <= 1.0

@@ -92,7 +92,7 @@ def test_dm_broadening_vs_oracle(system, scheme, width):
     print(f"[broadening] scheme {scheme} width {width}: k_s {info['k_s']} min f {ref['occ'].min():.2e} "
           f"D err {np.abs(D - ref['D']).max():.2e}", flush=True)
     assert st == 0
-    assert eig_excess(ev, ref["eval"], sp.S) <= 1.0
+    assert eig_excess(ev, ref["eval"], sp.S, occ=ref["occ"]) <= 1.0
     # f moves with the eigenvalues at up to 1.5 / (sqrt(pi) width) per Ha (the
     # steepest slope, Methfessel-Paxton order 1), times their agreement (the
     # 1e-10 Ha gate; measured up to 5e-13 Ha on these pencils)
@@ -145,7 +145,7 @@ def test_dm_batched_shared_mu_real(scheme):
     for q, sp in enumerate(sps):
         D = Ds[q].cpu().numpy()
         print(f"[shared mu] problem {q}: D err {np.abs(D - ref[q]['D']).max():.2e}", flush=True)
-        assert eig_excess(evals[q].cpu().numpy(), ref[q]["eval"], sp.S) <= 1.0
+        assert eig_excess(evals[q].cpu().numpy(), ref[q]["eval"], sp.S, occ=ref[q]["occ"]) <= 1.0
         assert np.abs(D - ref[q]["D"]).max() <= 1e-9
         assert abs(energy[q] - ref[q]["energy"]) <= 1e-9 * max(1.0, abs(ref[q]["energy"]))
         charge += np.trace(D @ sp.S)
@@ -177,7 +177,7 @@ def test_dm_batched_shared_mu_kpoints():
     charge = 0.0
     for q, sp in enumerate(sps):
         D = Ds[q].cpu().numpy()
-        assert eig_excess(evals[q].cpu().numpy(), ref[q]["eval"], sp.S) <= 1.0
+        assert eig_excess(evals[q].cpu().numpy(), ref[q]["eval"], sp.S, occ=ref[q]["occ"]) <= 1.0
         assert np.abs(D - ref[q]["D"]).max() <= 1e-9
         assert np.abs(D - D.conj().T).max() <= 1e-12
         charge += np.trace(D @ sp.S).real

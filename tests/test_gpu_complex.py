@@ -47,7 +47,7 @@ def test_complex_dm_vs_oracle(cells, kpt, seed):
     D, ev, f, energy, mu, st = h.dm(_cdev(sp.H), S)
     h.close()
     assert st == 0
-    assert eig_excess(ev.cpu().numpy(), ref["eval"], sp.S) <= 1.0
+    assert eig_excess(ev.cpu().numpy(), ref["eval"], sp.S, occ=ref["occ"]) <= 1.0
     D = D.cpu().numpy()
     assert np.abs(D - ref["D"]).max() <= 1e-9
     assert np.abs(D - D.conj().T).max() <= 1e-12
@@ -185,7 +185,7 @@ def test_complex_factored_overlap_reuse_and_unit_overlap():
     h.close()
     ref = O.zdm(H2, sp.S, sp.n_occ, sp.kT)
     assert st == 0
-    assert eig_excess(ev2.cpu().numpy(), ref["eval"], sp.S) <= 1.0
+    assert eig_excess(ev2.cpu().numpy(), ref["eval"], sp.S, occ=ref["occ"]) <= 1.0
     assert np.abs(D2.cpu().numpy() - ref["D"]).max() <= 1e-9
     # S = I
     h = B.Handle(n, n, sp.n_occ, dtype=B.COMPLEX128)
@@ -209,7 +209,7 @@ def test_complex_batched_kpoints_vs_oracle():
     assert rc == 0 and status == [0] * len(sps)
     for q, sp in enumerate(sps):
         ref = O.zdm(sp.H, sp.S, sp.n_occ, sp.kT)
-        assert eig_excess(evals[q].cpu().numpy(), ref["eval"], sp.S) <= 1.0, q
+        assert eig_excess(evals[q].cpu().numpy(), ref["eval"], sp.S, occ=ref["occ"]) <= 1.0, q
         assert np.abs(Ds[q].cpu().numpy() - ref["D"]).max() <= 1e-9, q
         assert abs(energy[q] - ref["energy"]) <= 1e-9 * max(1.0, abs(ref["energy"])), q
 

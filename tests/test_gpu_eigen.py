@@ -222,7 +222,7 @@ def test_dm_config0_vs_oracle():
     ev = ev.cpu().numpy()
     f = f.cpu().numpy()
     assert st == 0
-    assert eig_excess(ev, ref["eval"], sp.S) <= 1.0
+    assert eig_excess(ev, ref["eval"], sp.S, occ=ref["occ"]) <= 1.0
     assert np.abs(D - ref["D"]).max() <= 1e-9
     assert np.abs(D - D.T).max() == 0.0
     assert abs(mu - ref["mu"]) <= 1e-9

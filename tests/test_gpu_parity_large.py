@@ -44,7 +44,7 @@ def test_dm_n3000_vs_oracle(big):
     print(f"[parity large] dm N={N}: D err {np.abs(D - ref['D']).max():.2e} (max |D| {np.abs(ref['D']).max():.1f})",
           flush=True)
     assert st == 0
-    assert eig_excess(ev.cpu().numpy(), ref["eval"], sp.S) <= 1.0
+    assert eig_excess(ev.cpu().numpy(), ref["eval"], sp.S, occ=ref["occ"]) <= 1.0
     assert np.abs(D - ref["D"]).max() <= 1e-9
     assert np.abs(f.cpu().numpy() - ref["occ"]).max() <= 1e-12
     assert abs(energy - ref["energy"]) <= 1e-9 * max(1.0, abs(ref["energy"]))
@@ -64,7 +64,7 @@ def test_mixed_dm_n3000_vs_oracle(big):
     print(f"[parity large] mixed dm N={N}: status {st} sweeps {info['refine_sweeps']} step {info['refine_step']:.2e}"
           f" D err {np.abs(D - ref['D']).max():.2e}", flush=True)
     assert st == 0
-    assert eig_excess(ev.cpu().numpy()[:ks], ref["eval"][:ks], sp.S) <= 1.0
+    assert eig_excess(ev.cpu().numpy()[:ks], ref["eval"][:ks], sp.S, occ=ref["occ"][:ks]) <= 1.0
     assert np.abs(D - ref["D"]).max() <= 1e-9
 
 
@@ -77,7 +77,7 @@ def test_ev_n3000_with_2100_states_vs_oracle(big):
     ev, C = h.ev(_dev(sp.H), _dev(sp.S))
     h.close()
     ev, C = ev.cpu().numpy(), C.cpu().numpy()
-    assert eig_excess(ev, ref["eval"], sp.S) <= 1.0
+    assert eig_excess(ev, ref["eval"], sp.S, occ=ref["occ"]) <= 1.0
     assert np.abs(C.T @ sp.S @ C - np.eye(k)).max() <= 1e-8
     # eigenvectors of states separated from their neighbours by 1e-6 Ha match
     # the oracle's up to sign (S-inner products of 1 to 1e-8)
@@ -103,7 +103,7 @@ def test_batched_with_n4095_vs_oracle():
         ref = O.dm(sp.H, sp.S, sp.n_occ, sp.kT)
         D = Ds[q].cpu().numpy()
         print(f"[parity large] batched n={sp.n}: D err {np.abs(D - ref['D']).max():.2e}", flush=True)
-        assert eig_excess(evals[q].cpu().numpy(), ref["eval"], sp.S) <= 1.0
+        assert eig_excess(evals[q].cpu().numpy(), ref["eval"], sp.S, occ=ref["occ"]) <= 1.0
         assert np.abs(D - ref["D"]).max() <= 1e-9
 
 
@@ -122,6 +122,6 @@ def test_complex_dm_n1000_vs_oracle():
     D = D.cpu().numpy()
     print(f"[parity large] complex n={n}: D err {np.abs(D - ref['D']).max():.2e}", flush=True)
     assert st == 0
-    assert eig_excess(ev.cpu().numpy(), ref["eval"], sp.S) <= 1.0
+    assert eig_excess(ev.cpu().numpy(), ref["eval"], sp.S, occ=ref["occ"]) <= 1.0
     assert np.abs(D - ref["D"]).max() <= 1e-9
     assert np.abs(D - D.conj().T).max() <= 1e-12

@@ -218,7 +218,7 @@ def test_mixed_dm_vs_oracle(which):
     assert _closed_by_rule(info, 1e-10)
     _ritz_bounds(ev[:ks], ref["eval"], info["refine_resid"])
     assert np.abs(D - D.T).max() == 0.0
-    assert eig_excess(ev[:ks], ref["eval"][:ks], sp.S) <= 1.0
+    assert eig_excess(ev[:ks], ref["eval"][:ks], sp.S, occ=ref["occ"][:ks]) <= 1.0
     assert derr <= 1e-9
     assert abs(energy - ref["energy"]) <= 1e-9 * max(1.0, abs(ref["energy"]))
 
@@ -311,7 +311,8 @@ def test_mixed_dm_other_modes(mode):
         h.set_occupation(B.OCC_EXPLICIT)
         ev_ref, C_ref, _ = O.gevp(sp.H, sp.S)
         D, ev, f, energy, mu, st = h.dm(_dev(sp.H), _dev(sp.S), occ=occ, ok=(0, 3))
-        ref = {"eval": ev_ref, "D": (C_ref[:, :k]) @ C_ref[:, :k].T}
+        ref = {"eval": ev_ref, "D": (C_ref[:, :k]) @ C_ref[:, :k].T,
+               "occ": np.where(np.arange(n) < k, 1.0, 0.0)}
     info = h.info()
     h.close()
     D = D.cpu().numpy()
@@ -324,7 +325,7 @@ def test_mixed_dm_other_modes(mode):
     assert np.abs(D - D.T).max() == 0.0
     _ritz_bounds(ev[:ks], ref["eval"], info["refine_resid"])
     S_gate = np.eye(n) if mode == "unit_overlap" else sp.S
-    assert eig_excess(ev[:ks], ref["eval"][:ks], S_gate) <= 1.0
+    assert eig_excess(ev[:ks], ref["eval"][:ks], S_gate, occ=ref["occ"][:ks]) <= 1.0
     assert np.abs(D - ref["D"]).max() <= 1e-9
 
 
@@ -365,6 +366,6 @@ def test_mixed_complex_dm_vs_oracle(cells, kpt, seed):
     print(f"[mixed complex] n={n} status {st} sweeps {info['refine_sweeps']} step {info['refine_step']:.2e} "
           f"D err {np.abs(D - ref['D']).max():.2e}", flush=True)
     assert st == 0 and info["refine_sweeps"] >= 1
-    assert eig_excess(ev[:ks], ref["eval"][:ks], sp.S) <= 1.0
+    assert eig_excess(ev[:ks], ref["eval"][:ks], sp.S, occ=ref["occ"][:ks]) <= 1.0
     assert np.abs(D - ref["D"]).max() <= 1e-9
     assert np.abs(D - D.conj().T).max() <= 1e-12

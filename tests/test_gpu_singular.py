@@ -53,7 +53,7 @@ def test_dm_with_duplicated_basis_functions_vs_oracle(n0, dup):
     assert st == 0 and m == ref["n_nonsing"] == n0
     assert abs(info["overlap_min_eig"]) <= 1e-10
     assert np.all(np.isinf(ev[m:])) and np.all(f[m:] == 0.0)
-    assert eig_excess(ev[:m], ref["eval"][:m], sp.S) <= 1.0
+    assert eig_excess(ev[:m], ref["eval"][:m], sp.S, occ=ref["occ"][:m]) <= 1.0
     assert np.abs(D - ref["D"]).max() <= 1e-9
     assert abs(energy - ref["energy"]) <= 1e-9 * max(1.0, abs(ref["energy"]))
     X = Sd.cpu().numpy().T   # column-major X in the row-major buffer
@@ -127,5 +127,5 @@ def test_tolerance_above_small_eigenvalues_vs_oracle():
     h.close()
     m = info["n_nonsing"]
     assert st == 0 and m == ref["n_nonsing"] == sp.n - (j + 1)
-    assert eig_excess(ev.cpu().numpy()[:m], ref["eval"][:m], sp.S) <= 1.0
+    assert eig_excess(ev.cpu().numpy()[:m], ref["eval"][:m], sp.S, occ=ref["occ"][:m]) <= 1.0
     assert np.abs(D.cpu().numpy() - ref["D"]).max() <= 1e-9
