@@ -5,11 +5,23 @@
 // A pool of host worker threads, each with its own non-blocking stream and its
 // own workspace, takes problems largest first (longest-processing-time order)
 // and runs the single-problem driver on them, so that the many small kernels of
-// small problems overlap on the device.  Kernels whose workgroups wait on each
-// other pass a gate while a batch is active (together at most half of their
-// resident capacity, so all admitted ones fit on the device at once), and
-// the panel factorization of step (1) takes its per-column path, so that no two
-// waiting kernels can hold the device between them.
+// small problems overlap on the device.  The panel factorization of step (1)
+// takes its per-column path there (kernels that never wait on each other).
+//
+// Kernels whose workgroups wait on each other pass a gate while a batch is
+// active.  The runtime runs cooperative launches one at a time across all
+// streams, which would put every problem's bulge chasing in one line, so a
+// kernel with at least three workgroups per compute unit takes an ordinary
+// launch instead and the gate keeps it fully resident.  The argument: the
+// workgroups of a launch go to the XCDs in turn, so an XCD of C compute units
+// receives at most ceil(w / X) of a kernel's w workgroups (X XCDs), each using
+// at most 1/p <= 1/3 of every resource of a compute unit.  With the admitted
+// kernels' shares summing to at most half of the device and at most C / 2 of
+// them admitted, an XCD carries less than C/2 + (C/2)(1/3) = 2C/3 compute
+// units' worth of waiting workgroups, so one of its compute units is loaded to
+// at most 2/3 and takes the next one as soon as the kernels that do not wait
+// (which always finish) have left.  Every wait in those kernels is bounded
+// as well: an expired wait sets the kernel's error flag instead of hanging.
 #include "api_internal.h"
 
 #include <algorithm>
@@ -29,7 +41,9 @@ namespace {
 std::atomic<int> g_batch_depth{0};
 std::mutex g_persistent_mu;
 std::condition_variable g_persistent_cv;
-int g_persistent_used = 0;   // workgroups of admitted persistent kernels
+constexpr long long kDevice = 1LL << 30;   // the whole device, in share units
+long long g_persistent_used = 0;           // shares of the admitted kernels
+int g_persistent_kernels = 0;              // admitted kernels
 
 struct BatchDepth {
     BatchDepth() { g_batch_depth.fetch_add(1); }
@@ -104,24 +118,53 @@ int run_pool(elsi_gpu_handle_s* h, int count, const int* n, int* status, Fn fn)
 
 bool batch_mode_active() { return g_batch_depth.load(std::memory_order_relaxed) > 0; }
 
-bool persistent_enter(int workgroups, int capacity)
+namespace {
+// compute units of the current device, and per XCD
+void device_cus(int& cus, int& per_xcd)
 {
-    if (!batch_mode_active()) return false;
-    const int budget = std::max(1, capacity / 2);
+    int dev = 0, xcds = 0;
+    cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipDeviceGetAttribute(&xcds, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || xcds < 1) xcds = 1;
+    cus = std::max(1, cus);
+    per_xcd = std::max(1, cus / xcds);
+}
+}  // namespace
+
+bool persistent_plain_ok(int per_cu) { return batch_mode_active() && per_cu >= 3; }
+
+long long persistent_enter(int workgroups, int per_cu)
+{
+    if (!batch_mode_active()) return 0;
+    int cus = 1, per_xcd = 1;
+    device_cus(cus, per_xcd);
+    const long long capacity = (long long)cus * std::max(1, per_cu);
+    // a kernel with fewer than three workgroups per compute unit falls outside
+    // the residency argument above and is admitted alone
+    const long long share = per_cu >= 3
+                                ? std::max(1LL, ((long long)workgroups * kDevice + capacity - 1) / capacity)
+                                : kDevice / 2;
+    const int max_kernels = std::max(1, per_xcd / 2);
     std::unique_lock<std::mutex> lk(g_persistent_mu);
     // a kernel larger than the budget is admitted alone
-    g_persistent_cv.wait(lk, [&] { return g_persistent_used == 0 || g_persistent_used + workgroups <= budget; });
-    g_persistent_used += workgroups;
-    return true;
+    g_persistent_cv.wait(lk, [&] {
+        return g_persistent_kernels == 0 ||
+               (g_persistent_used + share <= kDevice / 2 && g_persistent_kernels < max_kernels);
+    });
+    g_persistent_used += share;
+    ++g_persistent_kernels;
+    return share;
 }
 
-void persistent_leave(hipStream_t st, bool entered, int workgroups)
+void persistent_leave(hipStream_t st, long long share)
 {
-    if (!entered) return;
+    if (share == 0) return;
     (void)hipStreamSynchronize(st);
     {
         std::lock_guard<std::mutex> lk(g_persistent_mu);
-        g_persistent_used -= workgroups;
+        g_persistent_used -= share;
+        --g_persistent_kernels;
     }
     g_persistent_cv.notify_all();
 }

@@ -115,16 +115,20 @@ __device__ inline void tri_inverse_lower64(int jb, double (*Lm)[65], double (*X)
 
 // Batched calls run several problems at once from host worker threads on
 // their own streams.  While such a call is active, kernels whose workgroups
-// wait on one another (persistent cooperative kernels) are admitted to the
-// device through a gate counted in workgroups: all admitted kernels together
-// hold at most half of the kernel's resident capacity (`capacity` workgroups
-// on the whole device), so every one of them can be fully resident at once
-// whatever the interleaving of their dispatch.  enter() blocks until the
-// workgroups fit; leave() waits for the kernel on its stream and releases
-// them.  Outside batched calls both are no-ops.
+// wait on one another are admitted to the device through a gate counted in
+// shares of the device: a kernel of w workgroups of which p fit on one compute
+// unit takes w / (p x compute units), and the admitted kernels together take
+// at most half (a kernel with p < 3 is admitted alone).  The runtime runs
+// cooperative launches one at a time across all streams, so inside a batch a
+// kernel with p >= 3 takes an ordinary launch (persistent_plain_ok); the gate
+// is what keeps every admitted one fully resident then (batched.hip gives the
+// argument).  enter() blocks until the kernel fits and returns its share;
+// leave() waits for the kernel on its stream and returns the share.  Outside
+// batched calls enter() returns 0 and both are no-ops.
 bool batch_mode_active();
-bool persistent_enter(int workgroups, int capacity);
-void persistent_leave(hipStream_t st, bool entered, int workgroups);
+long long persistent_enter(int workgroups, int per_cu);
+void persistent_leave(hipStream_t st, long long share);
+bool persistent_plain_ok(int per_cu);
 
 // Optional device timing of individual launches (off by default).  While it is
 // enabled, the GEMM launchers bracket every launch with a pair of events on the

@@ -617,9 +617,14 @@ int sb2st(hipStream_t st, int n, int b, double* Bd, int ldb, double* d, double* 
         a.err = err;
         a.spin_limit = 1LL << 22;
         void* args[] = {&a};
-        const bool gated = persistent_enter(kmax, resident_w);
-        hipError_t rc = hipLaunchCooperativeKernel((const void*)sb2st_window_kernel, dim3(kmax), dim3(SBT), args, 0, st);
-        persistent_leave(st, gated, kmax);
+        // inside a batched call an ordinary launch, kept resident by the gate
+        // (cooperative launches would run one problem's bulge chasing at a time)
+        const long long share = persistent_enter(kmax, per_cu_w);
+        const hipError_t rc =
+            persistent_plain_ok(per_cu_w)
+                ? hipLaunchKernel((const void*)sb2st_window_kernel, dim3(kmax), dim3(SBT), args, 0, st)
+                : hipLaunchCooperativeKernel((const void*)sb2st_window_kernel, dim3(kmax), dim3(SBT), args, 0, st);
+        persistent_leave(st, share);
         return rc == hipSuccess ? 0 : kStatusHip;
     }
     fill_i(st, progress, (size_t)nsweeps, 0);
@@ -637,9 +642,9 @@ int sb2st(hipStream_t st, int n, int b, double* Bd, int ldb, double* d, double* 
     a.Bd = Bd; a.V2 = V2; a.tau2 = tau2; a.progress = progress; a.err = err;
     a.spin_limit = 1LL << 22;
     void* args[] = {&a};
-    const bool gated = persistent_enter(grid, resident);
+    const long long share = persistent_enter(grid, std::max(1, per_cu));
     hipError_t rc = hipLaunchCooperativeKernel((const void*)sb2st_kernel, dim3(grid), dim3(SBT), args, 0, st);
-    persistent_leave(st, gated, grid);
+    persistent_leave(st, share);
     if (rc != hipSuccess) return kStatusHip;
     hipLaunchKernelGGL(extract_tridiag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, Bd, ldb, d, e);
     return 0;
