@@ -310,7 +310,8 @@ def batch_bench(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"lattice3d_batch{len(sizes)}_loguniform256_4096_plain_fp64_dm",
-                   "problems": len(sizes), "sum_n": sum(sizes), "workers": args.batch_workers},
+                   "problems": len(sizes), "sum_n": sum(sizes), "workers": args.batch_workers,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "band_table": ({"n_max": tuned["n_max"], "b": tuned["b"], "tune_ms": tuned["tune_ms"],
                         "cached": tuned["cached"]} if tuned else None),
         "sequential_single_calls_ms": ms_seq,
@@ -487,7 +488,10 @@ def main():
     ap.add_argument("--shared-mu", action="store_true",
                     help="complex workload: one batched call over the k-points with one chemical potential")
     ap.add_argument("--cell", default="8,8,12", help="complex workload: cell sites along x,y,z")
-    ap.add_argument("--batch-workers", type=int, default=8)
+    ap.add_argument("--batch-workers", type=int, default=16)
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="batch workload: hardware queues of the HIP runtime (GPU_MAX_HW_QUEUES, read when "
+                         "the runtime starts; worker streams beyond it share queues); 0 keeps the environment's")
     ap.add_argument("--tune", action="store_true",
                     help="batch workload: tune the band width per size bucket before the timed steps")
     ap.add_argument("--tune-cache", default=None,
@@ -503,6 +507,9 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=1,
                     help="single workload: timed steps of the FP32+refine run (after one warm-up)")
     args = ap.parse_args()
+    if args.workload == "batch" and args.hw_queues > 0:
+        # read by the HIP runtime when it starts, i.e. before torch touches the GPU
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))
     if args.workload == "complex":
         if args.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)

@@ -299,7 +299,12 @@ int elsi_gpu_dm(elsi_gpu_handle h, double *H, double *S, double *occ, double *D,
  * also covers a bad entry of a per-problem array).
  * ------------------------------------------------------------------------ */
 
-/* Worker threads of the batched calls, 1 <= workers <= 16.
+/* Worker threads of the batched calls, 1 <= workers <= 16.  Each worker's
+ * stream runs on one of the HIP runtime's hardware queues, of which there are
+ * GPU_MAX_HW_QUEUES (read from the environment when the runtime starts;
+ * 4 unless set): workers beyond that count share queues and their kernels
+ * wait for each other, so set it to at least the worker count before the
+ * process first uses the GPU.
  * Errors: -1 handle, -2 workers. */
 int elsi_gpu_set_batch_workers(elsi_gpu_handle h, int workers);
 
