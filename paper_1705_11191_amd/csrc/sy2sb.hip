@@ -567,9 +567,15 @@ __global__ __launch_bounds__(CQ_NT, 1) void panel_cholqr_kernel(int m, double* P
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         rec, (short)0, (int)(((size_t)l1o + BMAX * BMAX) * 8), 0x00020000);
 
-    // the rows stay in LDS through all three phases
-#pragma unroll 8
-    for (int r = 0; r < BMAX; ++r) St[tid][r] = (i < m) ? P[cm(i, r, ldp)] : 0.0;
+    // the rows stay in LDS through all three phases; all 64 loads of a row
+    // are issued before the first store, so that they are in flight together
+    {
+        double x[BMAX];
+#pragma unroll
+        for (int r = 0; r < BMAX; ++r) x[r] = (i < m) ? P[cm(i, r, ldp)] : 0.0;
+#pragma unroll
+        for (int r = 0; r < BMAX; ++r) St[tid][r] = x[r];
+    }
     __syncthreads();
     int arrive = 0;
 
@@ -690,34 +696,22 @@ __global__ __launch_bounds__(CQ_NT, 1) void panel_cholqr_kernel(int m, double* P
             cq_rows_solve(St, Gb, dinv);   // rows <- rows L^-T
         } else {
             if (blk == 0 && wave == 0) {
-                // R = R2 R1 = L2^T L1^T, lane c forming column c:
-                // R(r, c) = sum_k L2(k, r) L1(c, k)
-                {
-                    double l1[BMAX];
-#pragma unroll
-                    for (int k = 0; k < BMAX; ++k) l1[k] = bld(rs, l1o + lane + 64 * k);
-#pragma unroll
-                    for (int r = 0; r < BMAX; ++r) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int k = r; k < BMAX; ++k) s += Gb[k][r] * l1[k];
-                        Xb[r][lane] = s;
-                    }
-                }
                 // Q1 = rows 0..63 of the panel = the rows of wave 0
                 double a[BMAX];
 #pragma unroll
                 for (int q = 0; q < BMAX; ++q) a[q] = St[lane][q];
                 cq_signed_lu_wave(a, sgn);
 #pragma unroll
-                for (int q = 0; q < BMAX; ++q) Gb[lane][q] = a[q];
+                for (int q = 0; q < BMAX; ++q) Xb[lane][q] = a[q];
             }
             __syncthreads();
             if (blk == 0) {
+                // L below the diagonal of the top block (R goes on and above it
+                // after the barrier), and U^T for every workgroup
                 for (int e = tid; e < BMAX * BMAX; e += NT) {
                     const int r = e & 63, c = e >> 6;
-                    if (r < m) P[cm(r, c, ldp)] = (r <= c) ? sgn[r] * Xb[r][c] : Gb[r][c];
-                    bst(rs, mgo + e, (r >= c) ? Gb[c][r] : 0.0);   // U^T
+                    if (r > c && r < m) P[cm(r, c, ldp)] = Xb[r][c];
+                    bst(rs, mgo + e, (r >= c) ? Xb[c][r] : 0.0);   // U^T
                 }
             }
             if (!cq_grid_sync(counter, err, arrive, nblk, &bad)) return;
@@ -735,7 +729,49 @@ __global__ __launch_bounds__(CQ_NT, 1) void panel_cholqr_kernel(int m, double* P
             __syncthreads();
             if (tid < BMAX) dinv[tid] = 1.0 / Xb[tid][tid];
             __syncthreads();
-            if (blk > 0 || wave > 0) cq_rows_solve(St, Xb, dinv);   // V2 = Q2 U^-1 (rows 64 and on)
+            if (blk > 0 || wave > 0) {
+                cq_rows_solve(St, Xb, dinv);   // V2 = Q2 U^-1 (rows 64 and on)
+            } else {
+                // off the other workgroups' path: R = R2 R1 = L2^T L1^T into P
+                // as S R on and above the diagonal, on the matrix cores.  A =
+                // L2^T from Gb (which still holds L2 below its diagonal and the
+                // Gram matrix above it, hence the mask), B = L1^T from L1 staged
+                // in this wave's own rows of St (free once the LU has read them).
+#pragma unroll
+                for (int k0 = 0; k0 < BMAX; k0 += 16) {
+                    double l1[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) l1[k] = bld(rs, l1o + lane + 64 * (k0 + k));   // L1(lane, k)
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) St[lane][k0 + k] = l1[k];
+                }
+                cq_wave_sync();
+                const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 1   // rolled: unrolled, it pushes the kernel past its register budget
+                for (int I = 0; I < 4; ++I) {
+                    double4_t acc[4];
+#pragma unroll
+                    for (int J = 0; J < 4; ++J) acc[J] = (double4_t){0.0, 0.0, 0.0, 0.0};
+                    // tile (I, J) needs k from 16 I (L2(k, i) = 0 for k < i) to
+                    // 16 J + 15 (L1(j, k) = 0 for k > j)
+#pragma unroll
+                    for (int kk = 16 * I; kk < BMAX; kk += 4) {
+                        const int k = kk + lk, ii = 16 * I + li;
+                        const double a = (k >= ii) ? Gb[k][ii] : 0.0;
+#pragma unroll
+                        for (int J = I; J < 4; ++J)
+                            if (kk < 16 * J + 16)
+                                acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, St[16 * J + li][k], acc[J], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int J = I; J < 4; ++J)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int row = 16 * I + 4 * r + lk, col = 16 * J + li;
+                            if (row <= col && row < m) P[cm(row, col, ldp)] = sgn[row] * acc[J][r];
+                        }
+                }
+            }
         }
         __syncthreads();
     }
