@@ -669,11 +669,17 @@ __global__ __launch_bounds__(CQ_NT, 1) void panel_cholqr_kernel(int m, double* P
                     const double d = fabs(Gb[r][c] - (r == c ? 1.0 : 0.0));
                     dev = (d > dev || d != d) ? d : dev;   // a NaN counts as a large deviation
                 }
-                red[tid] = dev;
+                // largest deviation over the workgroup (a NaN wins every comparison)
+#pragma unroll
+                for (int h = 1; h < 64; h <<= 1) {
+                    const double o = __shfl_xor(dev, h, 64);
+                    dev = (o > dev || o != o) ? o : dev;
+                }
+                if (lane == 0) red[wave] = dev;
                 __syncthreads();
                 if (tid == 0) {
                     double mx = 0.0;
-                    for (int t = 0; t < NT; ++t) mx = (red[t] > mx || red[t] != red[t]) ? red[t] : mx;
+                    for (int t = 0; t < NW; ++t) mx = (red[t] > mx || red[t] != red[t]) ? red[t] : mx;
                     flag = (mx <= thr) ? 1 : 0;
                 }
                 __syncthreads();
