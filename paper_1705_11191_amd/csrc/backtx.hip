@@ -81,13 +81,29 @@ __global__ __launch_bounds__(256) void q2_build_t_kernel(int n, int b, const dou
         tau[tid] = (tid < b && s < nsweeps && k < q2_ntasks(n, b, s)) ? tau2[(size_t)s * kmax + k] : 0.0;
     }
     __syncthreads();
+    // G = V^T V above the diagonal on the matrix cores: the ten 16 x 16 tiles on
+    // and above the diagonal, each summed only over the window rows where both
+    // of its column ranges can be nonzero (reflector i lives in rows
+    // i .. i+b-1)
+    {
+        const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+        for (int t = wave; t < 10; t += 4) {
+            const int I = t < 4 ? 0 : (t < 7 ? 1 : (t < 9 ? 2 : 3));
+            const int J = t < 4 ? t : (t < 7 ? t - 3 : (t < 9 ? t - 5 : 3));
+            const int k_hi = min(2 * NB2, 16 * I + 15 + b);
+            double4_t acc = {0.0, 0.0, 0.0, 0.0};
+            for (int kk = 16 * J; kk < k_hi; kk += 4)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[kk + lk][16 * I + li], Vs[kk + lk][16 * J + li], acc, 0,
+                                                           0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * I + 4 * r + lk, j = 16 * J + li;
+                Gs[i][j] = (i < j) ? acc[r] : 0.0;
+            }
+        }
+    }
     for (int e = tid; e < NB2 * NB2; e += 256) {
         const int i = e % NB2, j = e / NB2;
-        double acc = 0.0;
-        if (i < j) {
-            for (int r = 0; r < 2 * NB2; ++r) acc += Vs[r][i] * Vs[r][j];
-        }
-        Gs[i][j] = acc;
         Ts[i][j] = (i == j) ? tau[i] : 0.0;   // tau is zero beyond the block's reflectors
     }
     __syncthreads();

@@ -245,62 +245,92 @@ __global__ __launch_bounds__(256) void dc_prep_kernel(const MergeDesc* __restric
         dsort[t] = df[q];
     }
     __syncthreads();
-    if (tid != 0) return;
-    // sequential deflation scan over the ascending poles; the pending
-    // candidate's weight and pole are carried in registers
+    // sequential deflation scan over the ascending poles by thread 0, the
+    // pending candidate's weight and pole carried in registers.  The scan
+    // reads (row, weight, pole) from LDS in chunks: waves 1.. stage chunk c+1
+    // while thread 0 scans chunk c, so that it never waits on memory.
+    constexpr int CH = 1024;
+    __shared__ double zc[2][CH], dc[2][CH];
+    __shared__ int pc[2][CH];
+    for (int t = tid; t < CH && t < ns; t += blockDim.x) {
+        zc[0][t] = zsort[t];
+        dc[0][t] = dsort[t];
+        pc[0][t] = perm[t];
+    }
+    __syncthreads();
     const double tol = 8.0 * kEps * fmax(dmax, rho);
     int K = 0, ndf = 0, nrot = 0;
     int pcand = -1;   // local row of the pending non-deflated candidate
     double zp = 0.0, dp = 0.0;
     double zs2 = 0.0;
-    for (int t = 0; t < ns; ++t) {
-        const int q = perm[t];
-        const double zq = zsort[t];
-        const double dq = dsort[t];
-        if (rho * fabs(zq) <= tol) {
-            ma.dfv[o + ndf] = dq;
-            ma.dfrow[o + ndf] = q;
-            ma.rowpos[o + q] = -1 - ndf;
-            ++ndf;
-            continue;
-        }
-        if (pcand >= 0) {
-            const double r = sqrt(zp * zp + zq * zq);
-            const double c = zq / r, s = zp / r;
-            if (fabs(c * s * (dp - dq)) <= tol) {
-                // rotate the weight of pcand onto q and deflate pcand
-                ma.rot_p[o + nrot] = pcand;
-                ma.rot_q[o + nrot] = q;
-                ma.rot_c[o + nrot] = c;
-                ma.rot_s[o + nrot] = s;
-                ++nrot;
-                const double dpn = c * c * dp + s * s * dq;
-                const double dqn = s * s * dp + c * c * dq;
-                zf[q] = r;
-                zf[pcand] = 0.0;
-                df[pcand] = dpn;
-                df[q] = dqn;
-                ma.dfv[o + ndf] = dpn;
-                ma.dfrow[o + ndf] = pcand;
-                ma.rowpos[o + pcand] = -1 - ndf;
-                ++ndf;
+    const int nch = (ns + CH - 1) / CH;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int cb = ch & 1, c0 = ch * CH;
+        if (tid == 0) {
+            const int cn = min(CH, ns - c0);
+            for (int u = 0; u < cn; ++u) {
+                const int q = pc[cb][u];
+                const double zq = zc[cb][u];
+                const double dq = dc[cb][u];
+                if (rho * fabs(zq) <= tol) {
+                    ma.dfv[o + ndf] = dq;
+                    ma.dfrow[o + ndf] = q;
+                    ma.rowpos[o + q] = -1 - ndf;
+                    ++ndf;
+                    continue;
+                }
+                if (pcand >= 0) {
+                    // |c s (dp - dq)| <= tol for the rotation (c, s) = (zq, zp) / r,
+                    // tested as |zq zp (dp - dq)| <= tol r^2 (no root or division
+                    // unless the rotation is taken)
+                    const double r2 = zp * zp + zq * zq;
+                    if (fabs(zq * zp * (dp - dq)) <= tol * r2) {
+                        // rotate the weight of pcand onto q and deflate pcand
+                        const double r = sqrt(r2);
+                        const double c = zq / r, s = zp / r;
+                        ma.rot_p[o + nrot] = pcand;
+                        ma.rot_q[o + nrot] = q;
+                        ma.rot_c[o + nrot] = c;
+                        ma.rot_s[o + nrot] = s;
+                        ++nrot;
+                        const double dpn = c * c * dp + s * s * dq;
+                        const double dqn = s * s * dp + c * c * dq;
+                        zf[q] = r;
+                        zf[pcand] = 0.0;
+                        df[pcand] = dpn;
+                        df[q] = dqn;
+                        ma.dfv[o + ndf] = dpn;
+                        ma.dfrow[o + ndf] = pcand;
+                        ma.rowpos[o + pcand] = -1 - ndf;
+                        ++ndf;
+                        pcand = q;
+                        zp = r;
+                        dp = dqn;
+                        continue;
+                    }
+                    // pcand is final
+                    ma.ds[o + K] = dp;
+                    ma.zs[o + K] = zp;
+                    ma.ndrow[o + K] = pcand;
+                    ma.rowpos[o + pcand] = K;
+                    zs2 += zp * zp;
+                    ++K;
+                }
                 pcand = q;
-                zp = r;
-                dp = dqn;
-                continue;
+                zp = zq;
+                dp = dq;
             }
-            // pcand is final
-            ma.ds[o + K] = dp;
-            ma.zs[o + K] = zp;
-            ma.ndrow[o + K] = pcand;
-            ma.rowpos[o + pcand] = K;
-            zs2 += zp * zp;
-            ++K;
+        } else if (tid >= 64 && ch + 1 < nch) {
+            const int nb = cb ^ 1, c1 = c0 + CH;
+            for (int t = tid - 64; t < CH && c1 + t < ns; t += (int)blockDim.x - 64) {
+                zc[nb][t] = zsort[c1 + t];
+                dc[nb][t] = dsort[c1 + t];
+                pc[nb][t] = perm[c1 + t];
+            }
         }
-        pcand = q;
-        zp = zq;
-        dp = dq;
+        __syncthreads();
     }
+    if (tid != 0) return;
     if (pcand >= 0) {
         ma.ds[o + K] = dp;
         ma.zs[o + K] = zp;
