@@ -215,6 +215,24 @@ void dtrsm_right_lower_t_lowerpart(hipStream_t st, int n, const double* L, int l
 void fill_d(hipStream_t st, double* p, size_t count, double v);
 void fill_i(hipStream_t st, int* p, size_t count, int v);
 void copy_matrix(hipStream_t st, int m, int n, const double* A, int lda, double* B, int ldb);
+// up to kMaxCopies independent copies B_c = A_c (m_c x n_c) in one launch
+struct CopyDesc {
+    int m, n;
+    const double* A;
+    int lda;
+    double* B;
+    int ldb;
+};
+constexpr int kMaxCopies = 8;
+struct CopyBatch {
+    int count = 0;
+    CopyDesc d[kMaxCopies];
+    void add(int m, int n, const double* A, int lda, double* B, int ldb)
+    {
+        if (m > 0 && n > 0) d[count++] = CopyDesc{m, n, A, lda, B, ldb};
+    }
+};
+void copy_matrices(hipStream_t st, const CopyBatch& cb);
 void mirror_lower_to_upper(hipStream_t st, int n, double* A, int lda);
 void symmetrize_average(hipStream_t st, int n, double* A, int lda);
 void set_identity(hipStream_t st, int n, double* A, int lda);

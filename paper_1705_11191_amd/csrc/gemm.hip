@@ -450,6 +450,43 @@ __global__ void splitk_reduce_kernel(int m, int n, int nsplit, double alpha, con
     *p = v;
 }
 
+// The same for small outputs with many partials (the panel products V^T X):
+// four threads per entry each sum every fourth partial in split order, and the
+// four sums are added in order, so that each thread's loads stay few and in
+// flight together.
+__global__ __launch_bounds__(256) void splitk_reduce_small_kernel(int m, int n, int nsplit, double alpha,
+                                                                  const double* __restrict__ part, double beta,
+                                                                  double* C, int ldc)
+{
+    __shared__ double red[4][64];
+    const int tid = threadIdx.x, o = tid & 63, g = tid >> 6;
+    const size_t mn = (size_t)m * n;
+    const size_t e = (size_t)blockIdx.x * 64 + o;
+    double s = 0.0;
+    if (e < mn) {
+        int q = g;
+        for (; q + 12 < nsplit; q += 16) {
+            const double v0 = part[(size_t)q * mn + e], v1 = part[(size_t)(q + 4) * mn + e];
+            const double v2 = part[(size_t)(q + 8) * mn + e], v3 = part[(size_t)(q + 12) * mn + e];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; q < nsplit; q += 4) s += part[(size_t)q * mn + e];
+    }
+    red[g][o] = s;
+    __syncthreads();
+    if (g == 0 && e < mn) {
+        const double t = ((red[0][o] + red[1][o]) + red[2][o]) + red[3][o];
+        const int i = (int)(e % m), j = (int)(e / m);
+        double* p = C + cm(i, j, ldc);
+        double v = alpha * t;
+        if (beta != 0.0) v += beta * (*p);
+        *p = v;
+    }
+}
+
 void tile_shape(int m, int n, int& BM, int& BN)
 {
     if (n <= 64) { BN = 64; BM = (m >= 16384) ? 128 : 64; }
@@ -714,8 +751,12 @@ void dgemm_splitk(hipStream_t st, char ta, char tb, int m, int n, int k, double 
     nsplit = (k + kper - 1) / kper;
     dispatch_shape(st, ta, tb, m, n, k, 1.0, A, lda, B, ldb, 0.0, work, m, 0, nsplit, kper, (size_t)m * n);
     const size_t mn = (size_t)m * n;
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, m, n, nsplit,
-                       alpha, work, beta, C, ldc);
+    if (mn <= 16384 && nsplit >= 8)
+        hipLaunchKernelGGL(splitk_reduce_small_kernel, dim3((unsigned)((mn + 63) / 64)), dim3(256), 0, st, m, n,
+                           nsplit, alpha, work, beta, C, ldc);
+    else
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, m, n, nsplit,
+                           alpha, work, beta, C, ldc);
 }
 
 void dgemm_tn_small(hipStream_t st, int m, int n, int k, double alpha, const double* A, int lda,

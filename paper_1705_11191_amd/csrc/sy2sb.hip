@@ -1031,19 +1031,25 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
         finish_w(m, bw, V1, T1, W1);
         if (!pair) {
             // A22 -= [V W] [W V]^T, lower tiles
-            copy_matrix(st, m, bw, V1, n, VW, m);
-            copy_matrix(st, m, bw, W1, m, VW + (size_t)m * bw, m);
-            copy_matrix(st, m, bw, W1, m, WV, m);
-            copy_matrix(st, m, bw, V1, n, WV + (size_t)m * bw, m);
+            CopyBatch cb;
+            cb.add(m, bw, V1, n, VW, m);
+            cb.add(m, bw, W1, m, VW + (size_t)m * bw, m);
+            cb.add(m, bw, W1, m, WV, m);
+            cb.add(m, bw, V1, n, WV + (size_t)m * bw, m);
+            copy_matrices(st, cb);
             dgemm(st, 'N', 'T', m, m, 2 * bw, -1.0, VW, m, WV, m, 1.0, A + cm(r0, r0, lda), lda, 1);
             ++p;
             continue;
         }
         // (a) the second panel's columns J2 = [r0, r0+b) over rows r0..: -= [V1 W1] [W1 V1]^T
-        copy_matrix(st, m, b, V1, n, VW, m);
-        copy_matrix(st, m, b, W1, m, VW + (size_t)m * b, m);
-        copy_matrix(st, b, b, W1, m, WV, b);
-        copy_matrix(st, b, b, V1, n, WV + (size_t)b * b, b);
+        {
+            CopyBatch cb;
+            cb.add(m, b, V1, n, VW, m);
+            cb.add(m, b, W1, m, VW + (size_t)m * b, m);
+            cb.add(b, b, W1, m, WV, b);
+            cb.add(b, b, V1, n, WV + (size_t)b * b, b);
+            copy_matrices(st, cb);
+        }
         dgemm(st, 'N', 'T', m, b, 2 * b, -1.0, VW, m, WV, b, 1.0, A + cm(r0, r0, lda), lda);
         // second panel
         const int r2 = r0 + b;
@@ -1057,17 +1063,25 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
         // (b) Y2 -= [V1' W1'] [W1'^T V2 ; V1'^T V2]
         dgemm_splitk(st, 'T', 'N', b, b, m2, 1.0, W1s, m, V2, n, 0.0, Gc, 2 * b, part, npart);
         dgemm_splitk(st, 'T', 'N', b, b, m2, 1.0, V1s, n, V2, n, 0.0, Gc + b, 2 * b, part, npart);
-        copy_matrix(st, m2, b, V1s, n, VW, m2);
-        copy_matrix(st, m2, b, W1s, m, VW + (size_t)m2 * b, m2);
+        {
+            CopyBatch cb;
+            cb.add(m2, b, V1s, n, VW, m2);
+            cb.add(m2, b, W1s, m, VW + (size_t)m2 * b, m2);
+            copy_matrices(st, cb);
+        }
         dgemm(st, 'N', 'N', m2, b, 2 * b, -1.0, VW, m2, Gc, 2 * b, 1.0, Y, m2);
         finish_w(m2, b, V2, T2, W2);
         // A(R2, R2) -= [V1' W1' V2 W2] [W1' V1' W2 V2]^T, lower tiles
-        copy_matrix(st, m2, b, V2, n, VW + (size_t)2 * m2 * b, m2);
-        copy_matrix(st, m2, b, W2, m2, VW + (size_t)3 * m2 * b, m2);
-        copy_matrix(st, m2, b, W1s, m, WV, m2);
-        copy_matrix(st, m2, b, V1s, n, WV + (size_t)m2 * b, m2);
-        copy_matrix(st, m2, b, W2, m2, WV + (size_t)2 * m2 * b, m2);
-        copy_matrix(st, m2, b, V2, n, WV + (size_t)3 * m2 * b, m2);
+        {
+            CopyBatch cb;
+            cb.add(m2, b, V2, n, VW + (size_t)2 * m2 * b, m2);
+            cb.add(m2, b, W2, m2, VW + (size_t)3 * m2 * b, m2);
+            cb.add(m2, b, W1s, m, WV, m2);
+            cb.add(m2, b, V1s, n, WV + (size_t)m2 * b, m2);
+            cb.add(m2, b, W2, m2, WV + (size_t)2 * m2 * b, m2);
+            cb.add(m2, b, V2, n, WV + (size_t)3 * m2 * b, m2);
+            copy_matrices(st, cb);
+        }
         dgemm(st, 'N', 'T', m2, m2, 4 * b, -1.0, VW, m2, WV, m2, 1.0, A + cm(r2, r2, lda), lda, 1);
         p += 2;
     }

@@ -28,6 +28,17 @@ __global__ void copy_matrix_kernel(int m, int n, const double* A, int lda, doubl
         if (i < m) B[cm(i, j, ldb)] = A[cm(i, j, lda)];
 }
 
+// Several independent column-major copies in one launch (blockIdx.z picks the
+// copy); the packing of the update operands takes one launch instead of one
+// per block.
+__global__ void copy_batch_kernel(CopyBatch cb)
+{
+    const CopyDesc d = cb.d[blockIdx.z];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.m) return;
+    for (int j = blockIdx.y; j < d.n; j += gridDim.y) d.B[cm(i, j, d.ldb)] = d.A[cm(i, j, d.lda)];
+}
+
 // Copy the lower triangle onto the upper one through a 32 x 32 LDS tile so
 // that both the reads and the writes are coalesced.
 __global__ void mirror_kernel(int n, double* A, int lda)
@@ -335,6 +346,18 @@ void copy_matrix(hipStream_t st, int m, int n, const double* A, int lda, double*
     if (m <= 0 || n <= 0) return;
     dim3 grid(ceil_div(m, 256), std::min(n, 65535));
     hipLaunchKernelGGL(copy_matrix_kernel, grid, dim3(256), 0, st, m, n, A, lda, B, ldb);
+}
+
+void copy_matrices(hipStream_t st, const CopyBatch& cb)
+{
+    int mmax = 0, nmax = 0;
+    for (int c = 0; c < cb.count; ++c) {
+        mmax = std::max(mmax, cb.d[c].m);
+        nmax = std::max(nmax, cb.d[c].n);
+    }
+    if (cb.count <= 0 || mmax <= 0 || nmax <= 0) return;
+    dim3 grid(ceil_div(mmax, 256), std::min(nmax, 65535), cb.count);
+    hipLaunchKernelGGL(copy_batch_kernel, grid, dim3(256), 0, st, cb);
 }
 
 void mirror_lower_to_upper(hipStream_t st, int n, double* A, int lda)
