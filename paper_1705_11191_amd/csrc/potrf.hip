@@ -46,9 +46,19 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(int jb, int j0, double* 
     __shared__ int bad;
     const int tid = threadIdx.x;
     if (tid == 0) bad = (*info != 0);
-    for (int e = tid; e < NB * NB; e += 256) {
-        int i = e % NB, c = e / NB;
-        L[i][c] = (i < jb && c < jb && i >= c) ? A[cm(j0 + i, j0 + c, lda)] : 0.0;
+    {
+        // a thread's 16 loads are all in flight before its first LDS store
+        double v[NB * NB / 256];
+#pragma unroll
+        for (int u = 0; u < NB * NB / 256; ++u) {
+            const int e = tid + 256 * u, i = e % NB, c = e / NB;
+            v[u] = (i < jb && c < jb && i >= c) ? A[cm(j0 + i, j0 + c, lda)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NB * NB / 256; ++u) {
+            const int e = tid + 256 * u;
+            L[e % NB][e / NB] = v[u];
+        }
     }
     __syncthreads();
     if (bad) return;
@@ -103,9 +113,18 @@ __global__ __launch_bounds__(256) void trtri_blocks_kernel(int n, const double* 
     const int j0 = blk * NB;
     const int jb = min(NB, n - j0);
     const int tid = threadIdx.x;
-    for (int e = tid; e < NB * NB; e += 256) {
-        int i = e % NB, c = e / NB;
-        Ls[i][c] = (i < jb && c < jb && i >= c) ? L[cm(j0 + i, j0 + c, ldl)] : 0.0;
+    {
+        double v[NB * NB / 256];
+#pragma unroll
+        for (int u = 0; u < NB * NB / 256; ++u) {
+            const int e = tid + 256 * u, i = e % NB, c = e / NB;
+            v[u] = (i < jb && c < jb && i >= c) ? L[cm(j0 + i, j0 + c, ldl)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NB * NB / 256; ++u) {
+            const int e = tid + 256 * u;
+            Ls[e % NB][e / NB] = v[u];
+        }
     }
     __syncthreads();
     tri_inverse_lower64<256>(jb, Ls, X, Y);

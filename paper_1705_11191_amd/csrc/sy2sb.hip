@@ -807,18 +807,33 @@ __global__ void panel_store_v_kernel(int m, int bw, int nr, const double* P, int
 // reflectors A, B (A first) T_AB = -T_AA G_AB T_BB; the blocks double in size
 // from 1 to 32, each level two parallel small products over 256 threads.
 __global__ __launch_bounds__(256) void build_t_kernel(int bw, const double* G, int ldg, const double* tau,
-                                                       double* T, int ldt, const int* gram_tau)
+                                                       double* T, int ldt, int* flags, int nflags)
 {
     __shared__ double Ts[BMAX][BMAX + 1];
     __shared__ double Gs[BMAX][BMAX + 1];
     __shared__ double Ys[BMAX][BMAX + 1];
     const int tid = threadIdx.x;
-    for (int e = tid; e < BMAX * BMAX; e += 256) {
-        const int r = e % BMAX, c = e / BMAX;
-        Gs[r][c] = (r < bw && c < bw) ? G[cm(r, c, ldg)] : 0.0;
-        // reflectors from the reconstruction take tau_c = 2 / v_c^T v_c, which makes
-        // each one exactly orthogonal for the stored v_c
-        Ts[r][c] = (r == c && r < bw) ? (*gram_tau ? 2.0 / G[cm(r, r, ldg)] : tau[r]) : 0.0;
+    {
+        // a thread's loads are all in flight before its first LDS store;
+        // flags[2] is the CholeskyQR2 status of the panel
+        const bool gt = flags[2] != 0;
+        double v[BMAX * BMAX / 256];
+#pragma unroll
+        for (int u = 0; u < BMAX * BMAX / 256; ++u) {
+            const int e = tid + 256 * u, r = e % BMAX, c = e / BMAX;
+            v[u] = (r < bw && c < bw) ? G[cm(r, c, ldg)] : 0.0;
+        }
+        const double td = (tid < bw && !gt) ? tau[tid] : 0.0;
+#pragma unroll
+        for (int u = 0; u < BMAX * BMAX / 256; ++u) {
+            const int e = tid + 256 * u, r = e % BMAX, c = e / BMAX;
+            Gs[r][c] = v[u];
+            Ts[r][c] = 0.0;
+        }
+        // reflectors from the reconstruction take tau_c = 2 / v_c^T v_c, which
+        // makes each one exactly orthogonal for the stored v_c
+        __syncthreads();
+        if (tid < bw) Ts[tid][tid] = gt ? 2.0 / Gs[tid][tid] : td;
     }
     __syncthreads();
     for (int sz = 1; sz < BMAX; sz *= 2) {
@@ -848,6 +863,9 @@ __global__ __launch_bounds__(256) void build_t_kernel(int bw, const double* G, i
         const int r = e % bw, c = e / bw;
         T[cm(r, c, ldt)] = Ts[r][c];
     }
+    // the panel's counters, error flags and status start at zero for the next
+    // panel (every thread has read the status above)
+    if (tid < nflags) flags[tid] = 0;
 }
 
 // Band of the reduced matrix: Bd(r, c) = A(c + r, c) for 0 <= r <= b, zero for b < r < ldb.
@@ -947,8 +965,8 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
         const int nblk = ceil_div(m, PR);
         bool coop_done = false;
         // ibuf: per-column kernel counter and error flag, CholeskyQR2 status,
-        // counter and error flag
-        fill_i(st, ibuf, 5, 0);
+        // counter and error flag; zero on entry (cleared before the first panel,
+        // and by build_t_kernel at the end of every panel)
         int* cq_status = ibuf + 2;
         // batched calls take the per-column path: its kernels never wait on each other
         if (!batch_mode_active() && bw == BMAX && nr == BMAX && m >= 2 * BMAX) {
@@ -999,7 +1017,7 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
                            lda, V, n, zpad);
         double* T = Tall + (size_t)p * b * b;
         dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, V, n, 0.0, Gv, 64, part, npart);
-        hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(256), 0, st, bw, Gv, 64, tau, T, b, cq_status);
+        hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(256), 0, st, bw, Gv, 64, tau, T, b, ibuf, 5);
     };
     // Y = A22 V (A22 = A(r0.., r0..), symmetric, lower triangle read)
     auto form_y = [&](int r0, int m, int bw, const double* V) {
@@ -1014,6 +1032,7 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
     };
 
     const int npanel = ceil_div(n, b);
+    fill_i(st, ibuf, 5, 0);
     int p = 0;
     while (p < npanel) {
         const int j = p * b;
