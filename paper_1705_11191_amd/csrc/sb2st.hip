@@ -265,13 +265,13 @@ struct SbWinArgs {
     double* tau2;
     double* d;
     double* e;
-    unsigned long long* vbox;   // kmax x 2 slots x kBoxWords: reflector by absolute row mod b, then tau
+    unsigned long long* vbox;   // kmax x 2 slots x kBoxWords: reflector by absolute row mod b, tau, alpha
     unsigned long long* rbox;   // kmax x 2 slots x kBoxWords: top row by absolute column mod b, then its diagonal
     int* err;
     long long spin_limit;
 };
 
-constexpr int kBoxWords = 2 * 65;   // value i in words 2i (upper half) and 2i+1 (lower half); i = 64: the extra value
+constexpr int kBoxWords = 2 * 66;   // value i in words 2i (upper half) and 2i+1 (lower half); i = 64, 65: extra values
 
 __device__ inline unsigned long long ld_word(const unsigned long long* p)
 {
@@ -323,6 +323,35 @@ __device__ inline bool poll_message(const unsigned long long* box, int b, unsign
     }
 }
 
+// The whole wave polls one value of a message (value i) until it carries
+// `tag`; false as for poll_message.
+__device__ inline bool poll_value(const unsigned long long* box, int i, unsigned tag, int* err, long long limit,
+                                  double& val)
+{
+    const int lane = threadIdx.x & 63;
+    long long spins = 0;
+    for (;;) {
+        const unsigned long long w0 = ld_word(box + 2 * i), w1 = ld_word(box + 2 * i + 1);
+        const bool ok = (unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag;
+        if (__all(ok)) {
+            val = __builtin_bit_cast(double, (w0 << 32) | (w1 & 0xffffffffull));
+            return true;
+        }
+        if ((++spins & 63) == 0) {
+            int bad = 0;
+            if (lane == 0) {
+                bad = ld_flag(err);
+                if (!bad && spins > limit) {
+                    st_flag(err, 1);
+                    bad = 1;
+                }
+            }
+            if (__shfl(bad, 0, 64)) return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // Offset of A(R, C) in the band on entry (bandwidth b, lower storage
 // Bd(r, c) = A(c + r, c)), or -1 outside the band.  Branch-free, so that the
 // window's 32 loads issue back to back.
@@ -355,7 +384,7 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
     __shared__ double vps[SB], vs[SB], ws[SB], rowm[SB];
     __shared__ double red[4][SB];
     __shared__ double colbuf[4][16][SB + 1];   // per wave: the left application's products by column (padded)
-    __shared__ double sh[4];   // tau, alpha, tau of the previous reflector, diagonal entry of the new row
+    __shared__ double sh[5];   // tau, alpha, tau of the previous reflector, diagonal entry and alpha of the new row
     __shared__ int abort_flag;
     const int tid = threadIdx.x;
     const int l = tid & 63;
@@ -392,16 +421,19 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
         const bool valid = l < b && rowabs < n;
         const bool need_row = s > 0 && k + 1 < ntasks(n, b, s - 1);
         const bool need_v = k > 0;
-        // ---- messages: the row of (s-1, k+1) polled by wave 0 (tag s), the
-        // reflector of (s, k-1) by wave 1 (tag s+1)
+        // ---- messages needed first: the reflector of (s, k-1) polled by wave 1
+        // (tag s+1) and, by wave 0, the alpha of (s-1, k+1) (tag s): the entry
+        // of the row entering this window in the column leaving the diagonal
+        // block.  That row's other entries are needed only by the two-sided
+        // update and are polled there, so that this task can start as soon as
+        // its neighbour below has its reflector.
         if (q == 0) {
-            double val = 0.0, extra = 0.0;
+            double alpha_in = 0.0;
             if (need_row) {
-                const unsigned long long* box = a.rbox + ((size_t)(k + 1) * 2 + ((s - 1) & 1)) * kBoxWords;
-                if (!poll_message(box, b, (unsigned)s, a.err, a.spin_limit, val, extra) && l == 0) abort_flag = 1;
+                const unsigned long long* box = a.vbox + ((size_t)(k + 1) * 2 + ((s - 1) & 1)) * kBoxWords;
+                if (!poll_value(box, 65, (unsigned)s, a.err, a.spin_limit, alpha_in) && l == 0) abort_flag = 1;
             }
-            rowm[l] = (l < b) ? val : 0.0;
-            if (l == 0) sh[3] = extra;
+            if (l == 0) sh[4] = alpha_in;
         } else if (q == 1) {
             double val = 0.0, extra = 0.0;
             if (need_v) {
@@ -414,25 +446,18 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
         }
         __syncthreads();
         if (abort_flag) return;
-        // ---- move the window down one row (zeros when the new row is past n)
+        // ---- move the window down one row: the column leaving the diagonal
+        // block joins the off-diagonal block, and the entering row's only
+        // nonzero there is alpha_in (its diagonal-block entries come later)
+        const unsigned mpm = slot_mask(pm, q);
         if (s > 0) {
-            const double rd = sh[3];
-            const unsigned mpm = slot_mask(pm, q);
-            const double col_in = (l == pm) ? rd : rowm[l];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                if (has(mpm, j)) {
-                    ob[j] = dg[j];
-                    dg[j] = col_in;
-                }
-            }
+            for (int j = 0; j < 16; ++j)
+                if (has(mpm, j)) ob[j] = dg[j];
             if (l == pm) {
-                const double alpha_in = rowm[pm];
+                const double alpha_in = sh[4];
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    ob[j] = has(mpm, j) ? alpha_in : 0.0;
-                    dg[j] = has(mpm, j) ? rd : rowm[16 * q + j];
-                }
+                for (int j = 0; j < 16; ++j) ob[j] = has(mpm, j) ? alpha_in : 0.0;
             }
         }
         // ---- right application of the previous reflector: ob <- ob (I - tp vp vp^T)
@@ -472,11 +497,15 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
                 sh[0] = t;
                 sh[1] = alpha;
             }
+            unsigned long long* box = a.vbox + ((size_t)k * 2 + (s & 1)) * kBoxWords;
             if (k + 1 < ntasks(n, b, s)) {   // for the right application in task (s, k+1)
-                unsigned long long* box = a.vbox + ((size_t)k * 2 + (s & 1)) * kBoxWords;
                 if (l < b) put_value(box, l, v, (unsigned)s + 1);
                 if (l == 0) put_value(box, 64, t, (unsigned)s + 1);
             }
+            // alpha opens task (s+1, k-1): the entry of this window's top row
+            // in the column just reflected
+            if (k > 0 && s + 1 < a.nsweeps && k - 1 < ntasks(n, b, s + 1) && l == 0)
+                put_value(box, 65, alpha, (unsigned)s + 1);
         }
         __syncthreads();
         const double t = sh[0], alpha = sh[1];
@@ -508,6 +537,30 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
 #pragma unroll
             for (int j = 0; j < 16; ++j)
                 if (has(mhc, j)) ob[j] = col_out;
+        }
+        // ---- the entering row (of (s-1, k+1), tag s) into the diagonal block:
+        // its entries as the new column, its diagonal entry in its own lane
+        if (s > 0) {
+            if (q == 0) {
+                double val = 0.0, extra = 0.0;
+                if (need_row) {
+                    const unsigned long long* box = a.rbox + ((size_t)(k + 1) * 2 + ((s - 1) & 1)) * kBoxWords;
+                    if (!poll_message(box, b, (unsigned)s, a.err, a.spin_limit, val, extra) && l == 0) abort_flag = 1;
+                }
+                rowm[l] = (l < b) ? val : 0.0;
+                if (l == 0) sh[3] = extra;
+            }
+            __syncthreads();
+            if (abort_flag) return;
+            const double rd = sh[3];
+            const double col_in = (l == pm) ? rd : rowm[l];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (has(mpm, j)) dg[j] = col_in;
+            if (l == pm) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) dg[j] = has(mpm, j) ? rd : rowm[16 * q + j];
+            }
         }
         // ---- two-sided update of the diagonal block: dg <- H dg H
         if (t != 0.0) {
