@@ -323,6 +323,41 @@ __device__ inline bool poll_message(const unsigned long long* box, int b, unsign
     }
 }
 
+// One wave polls 16 values of a message (values i0 .. i0+15 below b, lane l
+// taking value i0 + l % 16; 0 for the others) and the extra value 64 (every
+// lane) until all carry `tag`; false as for poll_message.
+__device__ inline bool poll_part(const unsigned long long* box, int i0, int b, unsigned tag, int* err, long long limit,
+                                 double& val, double& extra)
+{
+    const int lane = threadIdx.x & 63;
+    const int i = i0 + (lane & 15);
+    const bool mine = i < b;
+    long long spins = 0;
+    for (;;) {
+        const unsigned long long w0 = mine ? ld_word(box + 2 * i) : 0, w1 = mine ? ld_word(box + 2 * i + 1) : 0;
+        const unsigned long long x0 = ld_word(box + 128), x1 = ld_word(box + 129);
+        const bool ok = (!mine || ((unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag)) &&
+                        (unsigned)(x0 >> 32) == tag && (unsigned)(x1 >> 32) == tag;
+        if (__all(ok)) {
+            val = mine ? __builtin_bit_cast(double, (w0 << 32) | (w1 & 0xffffffffull)) : 0.0;
+            extra = __builtin_bit_cast(double, (x0 << 32) | (x1 & 0xffffffffull));
+            return true;
+        }
+        if ((++spins & 63) == 0) {
+            int bad = 0;
+            if (lane == 0) {
+                bad = ld_flag(err);
+                if (!bad && spins > limit) {
+                    st_flag(err, 1);
+                    bad = 1;
+                }
+            }
+            if (__shfl(bad, 0, 64)) return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // The whole wave polls one value of a message (value i) until it carries
 // `tag`; false as for poll_message.
 __device__ inline bool poll_value(const unsigned long long* box, int i, unsigned tag, int* err, long long limit,
@@ -384,7 +419,7 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
     __shared__ double vps[SB], vs[SB], ws[SB], rowm[SB];
     __shared__ double red[4][SB];
     __shared__ double colbuf[4][16][SB + 1];   // per wave: the left application's products by column (padded)
-    __shared__ double sh[5];   // tau, alpha, tau of the previous reflector, diagonal entry and alpha of the new row
+    __shared__ double sh[4];   // tau, alpha, -, diagonal entry of the entering row
     __shared__ int abort_flag;
     const int tid = threadIdx.x;
     const int l = tid & 63;
@@ -421,56 +456,57 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
         const bool valid = l < b && rowabs < n;
         const bool need_row = s > 0 && k + 1 < ntasks(n, b, s - 1);
         const bool need_v = k > 0;
-        // ---- messages needed first: the reflector of (s, k-1) polled by wave 1
-        // (tag s+1) and, by wave 0, the alpha of (s-1, k+1) (tag s): the entry
-        // of the row entering this window in the column leaving the diagonal
-        // block.  That row's other entries are needed only by the two-sided
-        // update and are polled there, so that this task can start as soon as
-        // its neighbour below has its reflector.
-        if (q == 0) {
-            double alpha_in = 0.0;
-            if (need_row) {
-                const unsigned long long* box = a.vbox + ((size_t)(k + 1) * 2 + ((s - 1) & 1)) * kBoxWords;
-                if (!poll_value(box, 65, (unsigned)s, a.err, a.spin_limit, alpha_in) && l == 0) abort_flag = 1;
-            }
-            if (l == 0) sh[4] = alpha_in;
-        } else if (q == 1) {
-            double val = 0.0, extra = 0.0;
-            if (need_v) {
-                const unsigned long long* box = a.vbox + ((size_t)(k - 1) * 2 + (s & 1)) * kBoxWords;
-                if (!poll_message(box, b, (unsigned)s + 1, a.err, a.spin_limit, val, extra) && l == 0)
-                    abort_flag = 1;
-            }
-            vps[l] = (l < b) ? val : 0.0;
-            if (l == 0) sh[2] = extra;
+        // ---- messages needed first, each wave polling what it uses itself (no
+        // workgroup barrier before the right application): the reflector of
+        // (s, k-1) (tag s+1), every wave its 16 entries and tau, and the alpha
+        // of (s-1, k+1) (tag s), the entering row's entry in the column leaving
+        // the diagonal block, by the wave holding that column.  The entering
+        // row's other entries are needed only by the two-sided update and are
+        // polled there.
+        const unsigned mpm = slot_mask(pm, q);
+        bool fail = false;
+        double tp = 0.0;
+        if (need_v) {
+            const unsigned long long* box = a.vbox + ((size_t)(k - 1) * 2 + (s & 1)) * kBoxWords;
+            double val = 0.0;
+            fail = !poll_part(box, 16 * q, b, (unsigned)s + 1, a.err, a.spin_limit, val, tp);
+            if (l < 16) vps[16 * q + l] = val;
+            __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS stores are done
+            __builtin_amdgcn_wave_barrier();
         }
-        __syncthreads();
-        if (abort_flag) return;
+        double alpha_in = 0.0;
+        if (need_row && mpm)
+            fail = !poll_value(a.vbox + ((size_t)(k + 1) * 2 + ((s - 1) & 1)) * kBoxWords, 65, (unsigned)s, a.err,
+                               a.spin_limit, alpha_in) || fail;
+        if (fail && l == 0) abort_flag = 1;
         // ---- move the window down one row: the column leaving the diagonal
         // block joins the off-diagonal block, and the entering row's only
         // nonzero there is alpha_in (its diagonal-block entries come later)
-        const unsigned mpm = slot_mask(pm, q);
         if (s > 0) {
 #pragma unroll
             for (int j = 0; j < 16; ++j)
                 if (has(mpm, j)) ob[j] = dg[j];
             if (l == pm) {
-                const double alpha_in = sh[4];
 #pragma unroll
                 for (int j = 0; j < 16; ++j) ob[j] = has(mpm, j) ? alpha_in : 0.0;
             }
         }
         // ---- right application of the previous reflector: ob <- ob (I - tp vp vp^T)
-        const double tp = sh[2];
-        if (need_v && tp != 0.0) {
+        // (the barrier also settles a failed poll in every wave)
+        {
             double part = 0.0;
+            if (need_v) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j) part += ob[j] * vps[16 * q + j];
+                for (int j = 0; j < 16; ++j) part += ob[j] * vps[16 * q + j];
+            }
             red[q][l] = part;
             __syncthreads();
-            const double w = tp * (red[0][l] + red[1][l] + red[2][l] + red[3][l]);
+            if (abort_flag) return;
+            if (need_v && tp != 0.0) {
+                const double w = tp * (red[0][l] + red[1][l] + red[2][l] + red[3][l]);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) ob[j] -= w * vps[16 * q + j];
+                for (int j = 0; j < 16; ++j) ob[j] -= w * vps[16 * q + j];
+            }
         }
         // ---- reflector of the block's first column (k >= 1) or of column s (k == 0)
         const int hc = (k > 0) ? p : pm;
