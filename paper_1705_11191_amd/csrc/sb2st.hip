@@ -286,12 +286,10 @@ __device__ inline void put_value(unsigned long long* box, int i, double x, unsig
     __hip_atomic_store(box + 2 * i + 1, t | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One wave polls a message until every word it needs carries `tag`: values
-// 0 .. b-1 (lane l takes value l) and the extra value (lane 0).  Returns false
-// when the grid's error flag is set or the spin limit expires (then it sets
-// the flag).
-__device__ inline bool poll_message(const unsigned long long* box, int b, unsigned tag, int* err, long long limit,
-                                    double& val, double& extra)
+// One wave polls values 0 .. b-1 of a message (lane l taking value l) until
+// they carry `tag`.
+__device__ inline bool poll_row(const unsigned long long* box, int b, unsigned tag, int* err, long long limit,
+                                double& val)
 {
     const int lane = threadIdx.x & 63;
     long long spins = 0;
@@ -301,11 +299,6 @@ __device__ inline bool poll_message(const unsigned long long* box, int b, unsign
             const unsigned long long w0 = ld_word(box + 2 * lane), w1 = ld_word(box + 2 * lane + 1);
             ok = (unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag;
             val = __builtin_bit_cast(double, (w0 << 32) | (w1 & 0xffffffffull));
-        }
-        if (lane == 0) {
-            const unsigned long long w0 = ld_word(box + 128), w1 = ld_word(box + 129);
-            ok = ok && (unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag;
-            extra = __builtin_bit_cast(double, (w0 << 32) | (w1 & 0xffffffffull));
         }
         if (__all(ok)) return true;
         if ((++spins & 63) == 0) {
@@ -324,10 +317,12 @@ __device__ inline bool poll_message(const unsigned long long* box, int b, unsign
 }
 
 // One wave polls 16 values of a message (values i0 .. i0+15 below b, lane l
-// taking value i0 + l % 16; 0 for the others) and the extra value 64 (every
-// lane) until all carry `tag`; false as for poll_message.
-__device__ inline bool poll_part(const unsigned long long* box, int i0, int b, unsigned tag, int* err, long long limit,
-                                 double& val, double& extra)
+// taking value i0 + l % 16; 0 for the others) and, when `with_extra` (uniform),
+// the extra value 64 (every lane) until all carry `tag`.  Every poll returns
+// false when the grid's error flag is set or its spin limit expires (then it
+// sets the flag).
+__device__ inline bool poll_part(const unsigned long long* box, int i0, int b, bool with_extra, unsigned tag,
+                                 int* err, long long limit, double& val, double& extra)
 {
     const int lane = threadIdx.x & 63;
     const int i = i0 + (lane & 15);
@@ -335,12 +330,12 @@ __device__ inline bool poll_part(const unsigned long long* box, int i0, int b, u
     long long spins = 0;
     for (;;) {
         const unsigned long long w0 = mine ? ld_word(box + 2 * i) : 0, w1 = mine ? ld_word(box + 2 * i + 1) : 0;
-        const unsigned long long x0 = ld_word(box + 128), x1 = ld_word(box + 129);
+        const unsigned long long x0 = with_extra ? ld_word(box + 128) : 0, x1 = with_extra ? ld_word(box + 129) : 0;
         const bool ok = (!mine || ((unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag)) &&
-                        (unsigned)(x0 >> 32) == tag && (unsigned)(x1 >> 32) == tag;
+                        (!with_extra || ((unsigned)(x0 >> 32) == tag && (unsigned)(x1 >> 32) == tag));
         if (__all(ok)) {
             val = mine ? __builtin_bit_cast(double, (w0 << 32) | (w1 & 0xffffffffull)) : 0.0;
-            extra = __builtin_bit_cast(double, (x0 << 32) | (x1 & 0xffffffffull));
+            extra = with_extra ? __builtin_bit_cast(double, (x0 << 32) | (x1 & 0xffffffffull)) : 0.0;
             return true;
         }
         if ((++spins & 63) == 0) {
@@ -359,7 +354,7 @@ __device__ inline bool poll_part(const unsigned long long* box, int i0, int b, u
 }
 
 // The whole wave polls one value of a message (value i) until it carries
-// `tag`; false as for poll_message.
+// `tag`.
 __device__ inline bool poll_value(const unsigned long long* box, int i, unsigned tag, int* err, long long limit,
                                   double& val)
 {
@@ -397,6 +392,16 @@ __device__ inline long band_offset(int n, int b, int ldb, int R, int C)
     return in ? (long)lo * ldb + dist : -1;
 }
 
+// Value of v in lane `lane` (wave-uniform) in every lane, through two scalar
+// register reads rather than a cross-lane permute through the LDS unit.
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    const unsigned long long w = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)w, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(w >> 32), lane);
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+
 // One-hot mask of column slot `slot` among the wave's slots 16q .. 16q+15
 // (0 when another wave holds it).  The mask is made opaque to the compiler so
 // that the per-slot selects below stay selects on fixed registers instead of
@@ -419,7 +424,7 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
     __shared__ double vps[SB], vs[SB], ws[SB], rowm[SB];
     __shared__ double red[4][SB];
     __shared__ double colbuf[4][16][SB + 1];   // per wave: the left application's products by column (padded)
-    __shared__ double sh[4];   // tau, alpha, -, diagonal entry of the entering row
+    __shared__ double sh[2];   // tau, alpha
     __shared__ int abort_flag;
     const int tid = threadIdx.x;
     const int l = tid & 63;
@@ -469,7 +474,7 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
         if (need_v) {
             const unsigned long long* box = a.vbox + ((size_t)(k - 1) * 2 + (s & 1)) * kBoxWords;
             double val = 0.0;
-            fail = !poll_part(box, 16 * q, b, (unsigned)s + 1, a.err, a.spin_limit, val, tp);
+            fail = !poll_part(box, 16 * q, b, true, (unsigned)s + 1, a.err, a.spin_limit, val, tp);
             if (l < 16) vps[16 * q + l] = val;
             __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS stores are done
             __builtin_amdgcn_wave_barrier();
@@ -519,7 +524,7 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
                 if (has(mhc, j)) x = ob[j];
             if (!valid) x = 0.0;
             const double tail = wave_sum64((l != p) ? x * x : 0.0);
-            const double x0 = __shfl(x, p, 64);
+            const double x0 = lane_value(x, p);
             double t = 0.0, den = 1.0, alpha = x0;
             if (tail > 0.0) {
                 const double nrm = sqrt(x0 * x0 + tail);
@@ -564,7 +569,7 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
             part += __shfl_xor(part, 2, 64);
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                const double u = t * __shfl(part, 4 * j, 64);
+                const double u = t * lane_value(part, 4 * j);
                 ob[j] -= v * u;
             }
         }
@@ -574,21 +579,39 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
             for (int j = 0; j < 16; ++j)
                 if (has(mhc, j)) ob[j] = col_out;
         }
+        // ---- the top row's entries left of the diagonal block are final now:
+        // to workgroup k-1 for task (s+1, k-1) (its diagonal entry follows the
+        // two-sided update).  The row sits in lane p; lanes 0 .. 15 each take
+        // one of the wave's 16 values by a scalar read and store it.
+        const bool row_out = k > 0 && s + 1 < a.nsweeps && k - 1 < ntasks(n, b, s + 1);
+        unsigned long long* rbx = a.rbox + ((size_t)k * 2 + (s & 1)) * kBoxWords;
+        if (row_out) {
+            double mine = 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const double x = lane_value(ob[j], p);
+                if (l == j) mine = x;
+            }
+            if (l < 16 && 16 * q + l < b) put_value(rbx, 16 * q + l, mine, (unsigned)s + 1);
+        }
         // ---- the entering row (of (s-1, k+1), tag s) into the diagonal block:
-        // its entries as the new column, its diagonal entry in its own lane
+        // its entries as the new column and as its own lane's row; its
+        // diagonal entry, published later, only by the wave holding that slot
         if (s > 0) {
+            // wave 0 polls the entries; after the barrier the wave holding the
+            // leaving slot polls the diagonal entry, the last value its sender
+            // publishes, while the others go on
+            const unsigned long long* box = a.rbox + ((size_t)(k + 1) * 2 + ((s - 1) & 1)) * kBoxWords;
             if (q == 0) {
-                double val = 0.0, extra = 0.0;
-                if (need_row) {
-                    const unsigned long long* box = a.rbox + ((size_t)(k + 1) * 2 + ((s - 1) & 1)) * kBoxWords;
-                    if (!poll_message(box, b, (unsigned)s, a.err, a.spin_limit, val, extra) && l == 0) abort_flag = 1;
-                }
+                double val = 0.0;
+                if (need_row && !poll_row(box, b, (unsigned)s, a.err, a.spin_limit, val) && l == 0) abort_flag = 1;
                 rowm[l] = (l < b) ? val : 0.0;
-                if (l == 0) sh[3] = extra;
             }
             __syncthreads();
             if (abort_flag) return;
-            const double rd = sh[3];
+            double rd = 0.0;
+            if (mpm && need_row && !poll_value(box, 64, (unsigned)s, a.err, a.spin_limit, rd) && l == 0)
+                abort_flag = 1;
             const double col_in = (l == pm) ? rd : rowm[l];
 #pragma unroll
             for (int j = 0; j < 16; ++j)
@@ -613,22 +636,14 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
 #pragma unroll
             for (int j = 0; j < 16; ++j) dg[j] -= v * ws[16 * q + j] + w * vs[16 * q + j];
         }
-        // ---- the top row, final for this sweep, to workgroup k-1
-        if (k > 0 && s + 1 < a.nsweeps && k - 1 < ntasks(n, b, s + 1)) {
-            // the row sits in lane p; lanes 0 .. 15 each take one of its 16
-            // values (a broadcast from lane p per slot) and store it, so the
-            // wave issues two stores instead of one lane issuing 32
-            unsigned long long* box = a.rbox + ((size_t)k * 2 + (s & 1)) * kBoxWords;
+        // ---- the top row's diagonal entry, final now, to workgroup k-1
+        if (row_out) {
             const unsigned mp = slot_mask(p, q);
-            double mine = 0.0, dpp = 0.0;
+            double dpp = 0.0;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const double x = __shfl(ob[j], p, 64);
-                if (l == j) mine = x;
+            for (int j = 0; j < 16; ++j)
                 if (has(mp, j)) dpp = dg[j];
-            }
-            if (l < 16 && 16 * q + l < b) put_value(box, 16 * q + l, mine, (unsigned)s + 1);
-            if (mp && l == p) put_value(box, 64, dpp, (unsigned)s + 1);
+            if (mp && l == p) put_value(rbx, 64, dpp, (unsigned)s + 1);
         }
         // ---- outputs: the reflector for Q2, and T's entries that are final
         if (q == 0 && valid) a.V2[cm(rowabs, s, n)] = v;
