@@ -621,7 +621,15 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
                 for (int j = 0; j < 16; ++j) dg[j] = has(mpm, j) ? rd : rowm[16 * q + j];
             }
         }
-        // ---- two-sided update of the diagonal block: dg <- H dg H
+        // ---- two-sided update of the diagonal block: dg <- H dg H.  The top
+        // row's diagonal entry goes to workgroup k-1 as soon as it is known:
+        // with v_p = 1 it is dg_pp - (w_p + w_p), the value the update below
+        // leaves there.
+        const unsigned mp = slot_mask(p, q);
+        double dpp = 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (has(mp, j)) dpp = dg[j];
         if (t != 0.0) {
             double part = 0.0;
 #pragma unroll
@@ -631,19 +639,13 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
             const double pi = t * (red[0][l] + red[1][l] + red[2][l] + red[3][l]);
             const double beta = 0.5 * t * wave_sum64(pi * v);
             const double w = pi - beta * v;
+            if (row_out && mp && l == p) put_value(rbx, 64, dpp - (v * w + w * v), (unsigned)s + 1);
             if (q == 0) ws[l] = w;
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < 16; ++j) dg[j] -= v * ws[16 * q + j] + w * vs[16 * q + j];
-        }
-        // ---- the top row's diagonal entry, final now, to workgroup k-1
-        if (row_out) {
-            const unsigned mp = slot_mask(p, q);
-            double dpp = 0.0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (has(mp, j)) dpp = dg[j];
-            if (mp && l == p) put_value(rbx, 64, dpp, (unsigned)s + 1);
+        } else if (row_out && mp && l == p) {
+            put_value(rbx, 64, dpp, (unsigned)s + 1);
         }
         // ---- outputs: the reflector for Q2, and T's entries that are final
         if (q == 0 && valid) a.V2[cm(rowabs, s, n)] = v;
@@ -651,7 +653,7 @@ __global__ __launch_bounds__(256) void sb2st_window_kernel(SbWinArgs a)
         if (k == 0) {
             if (tid == 0) a.e[s] = alpha;
             const int l1 = (p + 1 == b) ? 0 : p + 1;
-            const unsigned mp = slot_mask(p, q), ml1 = slot_mask(l1, q);
+            const unsigned ml1 = slot_mask(l1, q);
             double dp = 0.0, dl1 = 0.0;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
