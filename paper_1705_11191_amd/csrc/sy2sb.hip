@@ -539,6 +539,46 @@ __device__ void cq_rows_solve(double (*__restrict__ St)[LP], const double (*__re
     }
 }
 
+// The wave's 64 rows of St <- St (I - F^T) with F = L - I for a lower
+// triangular L in LDS whose strict upper triangle is zero: X L^-T to first
+// order in F.  Column block J takes the products over columns 0 .. 16J+15 of
+// the rows as they were; blocks are formed last to first so that no block
+// reads a column already replaced.
+// (Not inlined: inlined into the panel kernel, it pushes the kernel's other
+// phases past their register budget.)
+__device__ __attribute__((noinline)) void cq_rows_first_order(double (*__restrict__ St)[LP],
+                                                              const double (*__restrict__ L)[LP])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int r0 = 64 * wave;
+#pragma unroll 1
+    for (int J = 3; J >= 0; --J) {
+        const int o = 16 * J;
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            const int ra = r0 + 32 * h;
+            double4_t acc[2];
+#pragma unroll
+            for (int R = 0; R < 2; ++R)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[R][r] = St[ra + 16 * R + 4 * r + lk][o + li];
+            for (int kk = 0; kk < o + 16; kk += 4) {
+                const int kq = kk + lk, c = o + li;
+                const double f = (kq <= c) ? L[c][kq] - ((kq == c) ? 1.0 : 0.0) : 0.0;   // F(c, kq)
+#pragma unroll
+                for (int R = 0; R < 2; ++R)
+                    acc[R] = __builtin_amdgcn_mfma_f64_16x16x4f64(-St[ra + 16 * R + li][kq], f, acc[R], 0, 0, 0);
+            }
+#pragma unroll
+            for (int R = 0; R < 2; ++R)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) St[ra + 16 * R + 4 * r + lk][o + li] = acc[R][r];
+        }
+        cq_wave_sync();
+    }
+}
+
 // One thread per panel row (CQ_NT rows per workgroup, m >= 64, 64 columns).
 // rec holds nblk partial Gram records, the summed record, U^T and the
 // first-pass factor L1 (written and read by workgroup 0 only).
@@ -685,21 +725,36 @@ __global__ __launch_bounds__(CQ_NT, 1) void panel_cholqr_kernel(int m, double* P
                 __syncthreads();
                 if (!flag) return;
             }
-            if (wave == 0) {
-                const bool ok = cq_cholesky_wave(Gb, colv);
-                if (lane == 0) flag = ok ? 1 : 0;
-            }
-            __syncthreads();
-            if (!flag) return;
-            if (tid < BMAX) dinv[tid] = 1.0 / Gb[tid][tid];
-            if (ph == 0 && blk == 0) {
+            if (ph == 1 && thr <= 1e-9) {
+                // The second pass starts from columns orthonormal to thr: G =
+                // I + E with |E_ij| <= thr, so chol(G) = I + F with F the lower
+                // triangle of E and half its diagonal, and L^-T = I - F^T, both
+                // up to terms of order 64 thr^2, far below the rounding of
+                // entries of order one.  No factorization or substitution chain.
                 for (int e = tid; e < BMAX * BMAX; e += NT) {
                     const int r = e & 63, c = e >> 6;
-                    bst(rs, l1o + e, (r >= c) ? Gb[r][c] : 0.0);
+                    const double g = Gb[r][c];
+                    Gb[r][c] = (r > c) ? g : ((r == c) ? 1.0 + 0.5 * (g - 1.0) : 0.0);
                 }
+                __syncthreads();
+                cq_rows_first_order(St, Gb);   // rows <- rows (I - F^T)
+            } else {
+                if (wave == 0) {
+                    const bool ok = cq_cholesky_wave(Gb, colv);
+                    if (lane == 0) flag = ok ? 1 : 0;
+                }
+                __syncthreads();
+                if (!flag) return;
+                if (tid < BMAX) dinv[tid] = 1.0 / Gb[tid][tid];
+                if (ph == 0 && blk == 0) {
+                    for (int e = tid; e < BMAX * BMAX; e += NT) {
+                        const int r = e & 63, c = e >> 6;
+                        bst(rs, l1o + e, (r >= c) ? Gb[r][c] : 0.0);
+                    }
+                }
+                __syncthreads();
+                cq_rows_solve(St, Gb, dinv);   // rows <- rows L^-T
             }
-            __syncthreads();
-            cq_rows_solve(St, Gb, dinv);   // rows <- rows L^-T
         } else {
             if (blk == 0 && wave == 0) {
                 // Q1 = rows 0..63 of the panel = the rows of wave 0
