@@ -46,6 +46,12 @@ int elsi_gpu_init(elsi_gpu_handle* h, int dtype, int n_basis, int n_state, doubl
     p->stream = (hipStream_t)hip_stream;
     std::memset(&p->info, 0, sizeof(p->info));
     p->info.n_basis = n_basis;
+    // second stream and events for full -> band; without them the solve runs
+    // on the one stream
+    if (hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking) != hipSuccess) p->aux_stream = nullptr;
+    for (auto& ev : p->aux_ev)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+    (void)hipGetLastError();
     *h = p;
     return 0;
 }
@@ -156,6 +162,12 @@ int elsi_gpu_get_info(elsi_gpu_handle h, elsi_gpu_info* out)
 int elsi_gpu_finalize(elsi_gpu_handle* h)
 {
     if (!h || !*h) return -1;
+    if ((*h)->aux_stream) {
+        (void)hipStreamSynchronize((*h)->aux_stream);
+        (void)hipStreamDestroy((*h)->aux_stream);
+    }
+    for (auto ev : (*h)->aux_ev)
+        if (ev) (void)hipEventDestroy(ev);
     release_workspace(*h);
     delete *h;
     *h = nullptr;

@@ -147,6 +147,11 @@ struct elsi_gpu_handle_s {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     int ws_owned = 0;
+    // second stream and events of full -> band (created by elsi_gpu_init,
+    // released by elsi_gpu_finalize; batch workers and inner handles borrow
+    // or leave them null)
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t aux_ev[2] = {nullptr, nullptr};
     elsi_gpu_info info;
 };
 

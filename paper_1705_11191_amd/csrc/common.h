@@ -260,8 +260,14 @@ void explicit_occupations(hipStream_t st, int n, int n_state, const double* eps,
 
 // Step (1): full (n x n, full symmetric) -> band; see sy2sb.hip.
 size_t sy2sb_workspace_doubles(int n, int b);
+// A second stream and two events for full -> band: when given, each panel's
+// Gram matrix V^T V and T factor run on st2 while st forms Y = A22 V.
+struct Sy2sbAux {
+    hipStream_t st2;
+    hipEvent_t ev_v, ev_t;
+};
 void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, double* Tall, double* Bd,
-           int ldbd, double* work);
+           int ldbd, double* work, const Sy2sbAux* aux = nullptr);
 
 // Step (2): band -> tridiagonal; see sb2st.hip.
 int sb2st_kmax(int n, int b);

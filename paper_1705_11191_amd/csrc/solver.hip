@@ -246,8 +246,12 @@ static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, cons
         copy_matrix(st, n, n, H, n, A, n);
     }
     {
+        // outside batched calls (whose workers keep one stream each) the panel
+        // T factors run on the handle's second stream
+        Sy2sbAux aux{nullptr, nullptr, nullptr};
+        if (!batch_mode_active()) aux = Sy2sbAux{h->aux_stream, h->aux_ev[0], h->aux_ev[1]};
         Fp32GemmScope fp32(mixed);
-        sy2sb(st, n, b, A, n, Vall, Tall, Bd, 2 * b, (double*)(ws + L.sywork));
+        sy2sb(st, n, b, A, n, Vall, Tall, Bd, 2 * b, (double*)(ws + L.sywork), &aux);
     }
     tm.mark(ELSI_GPU_ST_BAND);
     double* d = (double*)(ws + L.d);
@@ -569,6 +573,9 @@ static elsi_gpu_handle_s inner_handle(const elsi_gpu_handle_s* h, int n_state2)
     r.ws = h->ws;
     r.ws_bytes = make_layout(r.n, r.band_width, r.n, r.precision == ELSI_GPU_PREC_MIXED).total;
     r.ws_owned = 0;
+    r.aux_stream = h->aux_stream;   // borrowed: the outer handle releases them
+    r.aux_ev[0] = h->aux_ev[0];
+    r.aux_ev[1] = h->aux_ev[1];
     std::memset(&r.info, 0, sizeof(r.info));
     r.info.n_basis = r.n;
     return r;

@@ -972,6 +972,7 @@ size_t sy2sb_workspace_doubles(int n, int b)
     w += 2 * 64 * 64;                // correction coefficients of a pair (2b x b)
     w += (size_t)8 * n * 64;         // split-K partials
     w += 64;                         // barrier counter and error flag
+    w += (size_t)128 * 64 * 64;      // split-K partials of V^T V on the second stream
     return w;
 }
 
@@ -991,7 +992,7 @@ size_t sy2sb_workspace_doubles(int n, int b)
 //       in between;
 // and A(R2, R2) -= [V1' W1' V2 W2] [W1' V1' W2 V2]^T applies both panels.
 void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, double* Tall, double* Bd,
-           int ldbd, double* work)
+           int ldbd, double* work, const Sy2sbAux* aux)
 {
     const int nblk_max = ceil_div(n, PR);
     double* Y = work;
@@ -1011,6 +1012,12 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
     double* part = Gc + 2 * 64 * 64;
     int* ibuf = (int*)(part + (size_t)8 * n * 64);
     const size_t npart = (size_t)8 * n * 64;
+    double* part2 = part + npart + 64;
+    const size_t npart2 = (size_t)128 * 64 * 64;
+    // each panel's V^T V and T factor on a second stream, beside Y = A22 V
+    // (which needs only V); the W formation waits for T
+    const bool fork = aux && aux->st2 && aux->ev_v && aux->ev_t;
+    hipStream_t sv = fork ? aux->st2 : st;
 
     // QR of panel p (columns j .. j+bw-1, rows j+b ..): V into Vall, T into Tall.
     auto factor_panel = [&](int p, int m, int bw, int nr) {
@@ -1071,8 +1078,14 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
         hipLaunchKernelGGL(panel_store_v_kernel, dim3(ceil_div(m + zpad, 256), bw), dim3(256), 0, st, m, bw, nr, P,
                            lda, V, n, zpad);
         double* T = Tall + (size_t)p * b * b;
-        dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, V, n, 0.0, Gv, 64, part, npart);
-        hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(256), 0, st, bw, Gv, 64, tau, T, b, ibuf, 5);
+        if (fork) {
+            (void)hipEventRecord(aux->ev_v, st);
+            (void)hipStreamWaitEvent(sv, aux->ev_v, 0);
+        }
+        dgemm_splitk(sv, 'T', 'N', bw, bw, m, 1.0, V, n, V, n, 0.0, Gv, 64, fork ? part2 : part,
+                     fork ? npart2 : npart);
+        hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(256), 0, sv, bw, Gv, 64, tau, T, b, ibuf, 5);
+        if (fork) (void)hipEventRecord(aux->ev_t, sv);
     };
     // Y = A22 V (A22 = A(r0.., r0..), symmetric, lower triangle read)
     auto form_y = [&](int r0, int m, int bw, const double* V) {
@@ -1080,6 +1093,7 @@ void sy2sb(hipStream_t st, int n, int b, double* A, int lda, double* Vall, doubl
     };
     // W = X - 1/2 V (T^T (V^T X)) with X = Y T
     auto finish_w = [&](int m, int bw, const double* V, const double* T, double* W) {
+        if (fork) (void)hipStreamWaitEvent(st, aux->ev_t, 0);   // T, and the panel's flags cleared
         dgemm(st, 'N', 'N', m, bw, bw, 1.0, Y, m, T, b, 0.0, W, m);
         dgemm_splitk(st, 'T', 'N', bw, bw, m, 1.0, V, n, W, m, 0.0, Z, 64, part, npart);
         dgemm(st, 'T', 'N', bw, bw, bw, 1.0, T, b, Z, 64, 0.0, U, 64);
