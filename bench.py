@@ -97,9 +97,10 @@ def _traffic_file(kernel: str, workload: str) -> str:
     return os.path.join(PROFILES, f"{tag}_{workload}_hbm_traffic.md")
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when there is none or the GEMM source changed since it was taken."""
+def load_traffic(kernel: str, workload: str, launches: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None
+    when there is none, the GEMM source changed since it was taken, or the solve
+    now launches the kernel a different number of times (another mix of shapes)."""
     path = _traffic_file(kernel, workload)
     if not os.path.exists(path):
         return None
@@ -107,7 +108,8 @@ def load_traffic(kernel: str, workload: str):
         for line in fh:
             if line.startswith("traffic_json:"):
                 rec = json.loads(line.split(":", 1)[1])
-                if rec.get("kernel") == kernel and rec.get("gemm_src_sha256") == _sha256(GEMM_SRC):
+                if (rec.get("kernel") == kernel and rec.get("gemm_src_sha256") == _sha256(GEMM_SRC)
+                        and rec.get("launches") == launches):
                     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     return None
 
@@ -633,7 +635,7 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": load_traffic(kname, wl["name"]),
+            "traffic": load_traffic(kname, wl["name"], pinfo["probe_launches"]),
             "kernel": kname,
             "launches_per_step": pinfo["probe_launches"],
             "avg_launch_ms": pinfo["probe_ms"] / launches,

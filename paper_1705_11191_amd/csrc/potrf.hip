@@ -14,7 +14,8 @@ namespace eg {
 namespace {
 
 constexpr int NB = 64;     // diagonal block
-constexpr int NBO = 1024;   // outer panel
+constexpr int NBO = 2048;   // outer panel
+constexpr int NBM = 256;    // middle panel: inside an outer panel the updates take K = 256 rather than 64
 
 __device__ inline double lane_value(double v, int l)
 {
@@ -153,20 +154,28 @@ void dpotrf(hipStream_t st, int n, double* A, int lda, double* Linv, int* info)
 {
     for (int J0 = 0; J0 < n; J0 += NBO) {
         const int JB = std::min(NBO, n - J0);
-        for (int j0 = J0; j0 < J0 + JB; j0 += NB) {
-            const int jb = std::min(NB, J0 + JB - j0);
-            double* Lj = Linv + (size_t)(j0 / NB) * NB * NB;
-            hipLaunchKernelGGL(potf2_inv_kernel, dim3(1), dim3(256), 0, st, jb, j0, A, lda, Lj, info);
-            const int r0 = j0 + jb;
-            if (r0 >= n) break;
-            double* P = A + cm(r0, j0, lda);
-            // panel rows below the block: P <- P L_jj^-T
-            dgemm(st, 'N', 'T', n - r0, jb, jb, 1.0, P, lda, Lj, NB, 0.0, P, lda);
-            // update the rest of this outer panel (columns r0 .. J0+JB-1)
-            const int wc = J0 + JB - r0;
-            if (wc > 0)
-                dgemm(st, 'N', 'T', n - r0, wc, jb, -1.0, P, lda, A + cm(r0, j0, lda), lda, 1.0,
-                      A + cm(r0, r0, lda), lda, 1);
+        for (int M0 = J0; M0 < J0 + JB; M0 += NBM) {
+            const int MB = std::min(NBM, J0 + JB - M0);
+            for (int j0 = M0; j0 < M0 + MB; j0 += NB) {
+                const int jb = std::min(NB, M0 + MB - j0);
+                double* Lj = Linv + (size_t)(j0 / NB) * NB * NB;
+                hipLaunchKernelGGL(potf2_inv_kernel, dim3(1), dim3(256), 0, st, jb, j0, A, lda, Lj, info);
+                const int r0 = j0 + jb;
+                if (r0 >= n) break;
+                double* P = A + cm(r0, j0, lda);
+                // panel rows below the block: P <- P L_jj^-T
+                dgemm(st, 'N', 'T', n - r0, jb, jb, 1.0, P, lda, Lj, NB, 0.0, P, lda);
+                // update the rest of this middle panel (columns r0 .. M0+MB-1)
+                const int wc = M0 + MB - r0;
+                if (wc > 0)
+                    dgemm(st, 'N', 'T', n - r0, wc, jb, -1.0, P, lda, A + cm(r0, j0, lda), lda, 1.0,
+                          A + cm(r0, r0, lda), lda, 1);
+            }
+            // update the rest of this outer panel (columns M0+MB .. J0+JB-1), K = MB
+            const int m0 = M0 + MB, mc = J0 + JB - m0;
+            if (mc > 0 && m0 < n)
+                dgemm(st, 'N', 'T', n - m0, mc, MB, -1.0, A + cm(m0, M0, lda), lda, A + cm(m0, M0, lda), lda, 1.0,
+                      A + cm(m0, m0, lda), lda, 1);
         }
         const int t0 = J0 + JB;
         if (t0 < n) {
@@ -186,14 +195,20 @@ void dtrsm_left_lower_n(hipStream_t st, int n, int ncol, const double* L, int ld
 {
     for (int I0 = 0; I0 < n; I0 += NBO) {
         const int IB = std::min(NBO, n - I0);
-        for (int i0 = I0; i0 < I0 + IB; i0 += NB) {
-            const int ib = std::min(NB, I0 + IB - i0);
-            const double* Li = Linv + (size_t)(i0 / NB) * NB * NB;
-            dgemm(st, 'N', 'N', ib, ncol, ib, 1.0, Li, NB, B + i0, ldb, 0.0, B + i0, ldb);
-            const int r0 = i0 + ib, rn = I0 + IB - r0;
-            if (rn > 0)
-                dgemm(st, 'N', 'N', rn, ncol, ib, -1.0, L + cm(r0, i0, ldl), ldl, B + i0, ldb, 1.0,
-                      B + r0, ldb);
+        for (int M0 = I0; M0 < I0 + IB; M0 += NBM) {
+            const int MB = std::min(NBM, I0 + IB - M0);
+            for (int i0 = M0; i0 < M0 + MB; i0 += NB) {
+                const int ib = std::min(NB, M0 + MB - i0);
+                const double* Li = Linv + (size_t)(i0 / NB) * NB * NB;
+                dgemm(st, 'N', 'N', ib, ncol, ib, 1.0, Li, NB, B + i0, ldb, 0.0, B + i0, ldb);
+                const int r0 = i0 + ib, rn = M0 + MB - r0;
+                if (rn > 0)
+                    dgemm(st, 'N', 'N', rn, ncol, ib, -1.0, L + cm(r0, i0, ldl), ldl, B + i0, ldb, 1.0,
+                          B + r0, ldb);
+            }
+            const int m0 = M0 + MB, mn = I0 + IB - m0;
+            if (mn > 0)
+                dgemm(st, 'N', 'N', mn, ncol, MB, -1.0, L + cm(m0, M0, ldl), ldl, B + M0, ldb, 1.0, B + m0, ldb);
         }
         const int t0 = I0 + IB;
         if (t0 < n)
@@ -211,15 +226,22 @@ void dtrsm_right_lower_t_lowerpart(hipStream_t st, int n, const double* L, int l
 {
     for (int J0 = 0; J0 < n; J0 += NBO) {
         const int JB = std::min(NBO, n - J0);
-        for (int j0 = J0; j0 < J0 + JB; j0 += NB) {
-            const int jb = std::min(NB, J0 + JB - j0);
-            const double* Lj = Linv + (size_t)(j0 / NB) * NB * NB;
-            double* Bj = B + cm(j0, j0, ldb);
-            dgemm(st, 'N', 'T', n - j0, jb, jb, 1.0, Bj, ldb, Lj, NB, 0.0, Bj, ldb);
-            const int c0 = j0 + jb, cn = J0 + JB - c0;
-            if (cn > 0)
-                dgemm(st, 'N', 'T', n - c0, cn, jb, -1.0, B + cm(c0, j0, ldb), ldb, L + cm(c0, j0, ldl), ldl,
-                      1.0, B + cm(c0, c0, ldb), ldb, 1);
+        for (int M0 = J0; M0 < J0 + JB; M0 += NBM) {
+            const int MB = std::min(NBM, J0 + JB - M0);
+            for (int j0 = M0; j0 < M0 + MB; j0 += NB) {
+                const int jb = std::min(NB, M0 + MB - j0);
+                const double* Lj = Linv + (size_t)(j0 / NB) * NB * NB;
+                double* Bj = B + cm(j0, j0, ldb);
+                dgemm(st, 'N', 'T', n - j0, jb, jb, 1.0, Bj, ldb, Lj, NB, 0.0, Bj, ldb);
+                const int c0 = j0 + jb, cn = M0 + MB - c0;
+                if (cn > 0)
+                    dgemm(st, 'N', 'T', n - c0, cn, jb, -1.0, B + cm(c0, j0, ldb), ldb, L + cm(c0, j0, ldl), ldl,
+                          1.0, B + cm(c0, c0, ldb), ldb, 1);
+            }
+            const int m0 = M0 + MB, mc = J0 + JB - m0;
+            if (mc > 0)
+                dgemm(st, 'N', 'T', n - m0, mc, MB, -1.0, B + cm(m0, M0, ldb), ldb, L + cm(m0, M0, ldl), ldl, 1.0,
+                      B + cm(m0, m0, ldb), ldb, 1);
         }
         const int t0 = J0 + JB;
         if (t0 < n)
@@ -259,16 +281,24 @@ void dtrsm_left_lower_t(hipStream_t st, int n, int ncol, const double* L, int ld
     for (int ob = nouter - 1; ob >= 0; --ob) {
         const int I0 = ob * NBO;
         const int IB = std::min(NBO, n - I0);
-        const int ninner = ceil_div(IB, NB);
-        for (int q = ninner - 1; q >= 0; --q) {
-            const int i0 = I0 + q * NB;
-            const int ib = std::min(NB, I0 + IB - i0);
-            const double* Li = Linv + (size_t)(i0 / NB) * NB * NB;
-            dgemm(st, 'T', 'N', ib, ncol, ib, 1.0, Li, NB, B + i0, ldb, 0.0, B + i0, ldb);
-            const int rn = i0 - I0;   // rows of this outer block above the inner block
-            if (rn > 0)
-                dgemm(st, 'T', 'N', rn, ncol, ib, -1.0, L + cm(i0, I0, ldl), ldl, B + i0, ldb, 1.0,
-                      B + I0, ldb);
+        const int nmid = ceil_div(IB, NBM);
+        for (int mb = nmid - 1; mb >= 0; --mb) {
+            const int M0 = I0 + mb * NBM;
+            const int MB = std::min(NBM, I0 + IB - M0);
+            const int ninner = ceil_div(MB, NB);
+            for (int q = ninner - 1; q >= 0; --q) {
+                const int i0 = M0 + q * NB;
+                const int ib = std::min(NB, M0 + MB - i0);
+                const double* Li = Linv + (size_t)(i0 / NB) * NB * NB;
+                dgemm(st, 'T', 'N', ib, ncol, ib, 1.0, Li, NB, B + i0, ldb, 0.0, B + i0, ldb);
+                const int rn = i0 - M0;   // rows of this middle block above the inner block
+                if (rn > 0)
+                    dgemm(st, 'T', 'N', rn, ncol, ib, -1.0, L + cm(i0, M0, ldl), ldl, B + i0, ldb, 1.0,
+                          B + M0, ldb);
+            }
+            const int mn = M0 - I0;       // rows of this outer block above the middle block
+            if (mn > 0)
+                dgemm(st, 'T', 'N', mn, ncol, MB, -1.0, L + cm(M0, I0, ldl), ldl, B + M0, ldb, 1.0, B + I0, ldb);
         }
         if (I0 > 0)
             dgemm(st, 'T', 'N', I0, ncol, IB, -1.0, L + cm(I0, 0, ldl), ldl, B + I0, ldb, 1.0, B, ldb);

@@ -77,7 +77,7 @@ def test_dgemm_symmetric_lower(m, n):
     assert np.abs(got - ref).max() <= tol
 
 
-@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 130, 257, 300, 513])
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 130, 257, 300, 513, 1300])
 def test_cholesky_vs_oracle(n):
     from paper_1705_11191_amd import binding as B
 
