@@ -386,6 +386,12 @@ size_t apply_q2_workspace_doubles(int n, int b)
     return (size_t)ngroups * kmax * NB2 * NB2;
 }
 
+void build_q2_t(hipStream_t st, int n, int b, const double* V2, const double* tau2, int kmax, double* Tq)
+{
+    if (n <= 2) return;
+    hipLaunchKernelGGL(q2_build_t_kernel, dim3(ceil_div(n - 2, b), kmax), dim3(256), 0, st, n, b, V2, tau2, kmax, Tq);
+}
+
 // X (n x ncol) <- Q2 X, or Q2^T X (trans); Tq: apply_q2_workspace_doubles(n, b)
 // doubles, rebuilt from the reflectors unless tq_ready says a previous call on
 // the same reflectors left it there.  slab: columns per workgroup (0 picks
@@ -395,8 +401,7 @@ void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const do
 {
     if (n <= 2 || ncol <= 0) return;
     const int ngroups = ceil_div(n - 2, b);
-    if (!tq_ready)
-        hipLaunchKernelGGL(q2_build_t_kernel, dim3(ngroups, kmax), dim3(256), 0, st, n, b, V2, tau2, kmax, Tq);
+    if (!tq_ready) build_q2_t(st, n, b, V2, tau2, kmax, Tq);
     const int qw = slab > 0 ? slab : q2_slab_width(ncol);
     const int nslab = ceil_div(ncol, qw);
     const int tmax = (ngroups - 1) + kmax;   // last step: g = 0 with its last block

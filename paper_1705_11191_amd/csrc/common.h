@@ -292,6 +292,10 @@ struct DcState {
     std::vector<MergeDescH> last;
     const MergeDescH* last_dev = nullptr;   // the last merge's descriptor on the device
     void* work = nullptr;                   // the solver's scratch (merge bookkeeping)
+    // Q2's block T factors were launched beside this solve (on another stream):
+    // the stream that applies Q2 waits on q2t_ev (if set) and skips the build
+    bool q2t_built = false;
+    hipEvent_t q2t_ev = nullptr;
 };
 size_t stedc_workspace_bytes(int n);
 int stedc_values(hipStream_t st, int n, const double* d, const double* e, double* w, double* Z, double* Z2,
@@ -302,6 +306,9 @@ int stedc(hipStream_t st, int n, const double* d, const double* e, double* w, do
 
 // Steps (4) and (5): back-transformations; see backtx.hip.
 size_t apply_q2_workspace_doubles(int n, int b);
+// The block T factors of Q2 (apply_q2_workspace_doubles(n, b) doubles at Tq),
+// built from the bulge-chasing reflectors alone; apply_q2 with tq_ready uses them.
+void build_q2_t(hipStream_t st, int n, int b, const double* V2, const double* tau2, int kmax, double* Tq);
 void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const double* tau2, int kmax,
               double* X, int ldx, double* Tq, bool trans = false, bool tq_ready = false, int slab = 0);
 int q2_slab_width(int ncol);

@@ -200,8 +200,10 @@ struct Timer {
 // reduction (Eq. (11)), full -> band and band -> tridiagonal (Eq. (13)), and
 // the tridiagonal eigenpairs (divide and conquer).  On success w holds all
 // eigenvalues ascending and Z the eigenvectors of T (first ncol columns).
+// vectors: back_half follows, so Q2's block T factors are built on the
+// handle's second stream while the tridiagonal problem is solved.
 static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, const Layout& L, Timer& tm,
-                      DcState* dc)
+                      DcState* dc, bool vectors)
 {
     hipStream_t st = h->stream;
     const int n = h->n, b = std::min(h->band_width, std::max(1, n - 1));
@@ -260,10 +262,31 @@ static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, cons
                    (double*)(ws + L.mbox));
     if (rc) return rc;
     tm.mark(ELSI_GPU_ST_BULGE);
+    // the T factors need only the reflectors of step (2); outside batched calls
+    // (whose workers keep one stream each) they run beside the tridiagonal solve
+    bool q2t_built = false;
+    hipEvent_t q2t_ev = nullptr;
+    if (vectors && !batch_mode_active() && h->aux_stream && h->aux_ev[0] && h->aux_ev[1] &&
+        hipEventRecord(h->aux_ev[0], st) == hipSuccess &&
+        hipStreamWaitEvent(h->aux_stream, h->aux_ev[0], 0) == hipSuccess) {
+        build_q2_t(h->aux_stream, n, b, (double*)(ws + L.v2), (double*)(ws + L.tau2), sb2st_kmax(n, b),
+                   (double*)(ws + L.tq2));
+        if (hipEventRecord(h->aux_ev[1], h->aux_stream) == hipSuccess)
+            q2t_ev = h->aux_ev[1];
+        else if (hipStreamSynchronize(h->aux_stream) != hipSuccess)
+            return kStatusHip;
+        q2t_built = true;
+    }
     double* w = (double*)(ws + L.w);
     rc = stedc_values(st, n, d, e, w, (double*)(ws + L.z), (double*)(ws + L.z2), (double*)(ws + L.u), n,
                       ws + L.dcwork, err2, dc);
-    if (rc) return rc;
+    if (rc) {
+        // no back half follows: keep later work on the stream behind the reads of the reflectors
+        if (q2t_ev) (void)hipStreamWaitEvent(st, q2t_ev, 0);
+        return rc;
+    }
+    dc->q2t_built = q2t_built;
+    dc->q2t_ev = q2t_ev;
     tm.mark(ELSI_GPU_ST_TRIDIAG);
     return 0;
 }
@@ -292,8 +315,11 @@ static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L
     stedc_vectors(st, *dc, k);   // top merge of step (3) restricted to the k wanted columns
     if (zsave) copy_matrix(st, n, k, X, n, zsave, n);
     tm.mark(ELSI_GPU_ST_TRIDIAG);
+    if (dc->q2t_ev) (void)hipStreamWaitEvent(st, dc->q2t_ev, 0);
     apply_q2(st, n, b, k, (double*)(ws + L.v2), (double*)(ws + L.tau2), sb2st_kmax(n, b), X, n,
-             (double*)(ws + L.tq2));
+             (double*)(ws + L.tq2), false, dc->q2t_built);
+    dc->q2t_built = false;
+    dc->q2t_ev = nullptr;
     tm.mark(ELSI_GPU_ST_BACK_Q2);
     {
         Fp32GemmScope fp32(h->precision == ELSI_GPU_PREC_MIXED);
@@ -441,7 +467,7 @@ static int ev_real(elsi_gpu_handle_s* h, double* H, double* S, double* eval, dou
     for (int l = 0; l < 8; ++l) h->info.refine_hist[l] = 0.0;
     Timer tm(st);
     DcState dc;
-    rc = front_half(h, H, S, ws, L, tm, &dc);
+    rc = front_half(h, H, S, ws, L, tm, &dc, true);
     if (rc) { tm.finish(&h->info); return rc; }
     int rstat = 0;
     if (mixed) {
@@ -489,7 +515,7 @@ static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, doub
     for (int l = 0; l < 8; ++l) h->info.refine_hist[l] = 0.0;
     Timer tm(st);
     DcState dc;
-    rc = front_half(h, H, S, ws, L, tm, &dc);
+    rc = front_half(h, H, S, ws, L, tm, &dc, true);
     if (rc) { tm.finish(&h->info); return rc; }
     double* w = (double*)(ws + L.w);
     double* f = occ ? occ : (double*)(ws + L.f);
@@ -614,7 +640,7 @@ static int ev_complex(elsi_gpu_handle_s* h, double* H, double* S, double* eval, 
     r.info.band_width = std::min(r.band_width, std::max(1, n2 - 1));
     Timer tm(st);
     DcState dc;
-    rc = front_half(&r, H2, S2, ws, L, tm, &dc);
+    rc = front_half(&r, H2, S2, ws, L, tm, &dc, true);
     if (rc) {
         tm.finish(&r.info);
         complex_info(h, r);
@@ -718,7 +744,7 @@ int eg::eigenvalues_only(elsi_gpu_handle_s* h, const double* H, const double* S,
         r.info.band_width = std::min(r.band_width, std::max(1, n2 - 1));
         Timer tm(st);
         DcState dc;
-        rc = front_half(&r, H2, S2, ws, L, tm, &dc);
+        rc = front_half(&r, H2, S2, ws, L, tm, &dc, false);
         tm.finish(&r.info);
         complex_info(h, r);
         if (rc) return rc;
@@ -735,7 +761,7 @@ int eg::eigenvalues_only(elsi_gpu_handle_s* h, const double* H, const double* S,
     h->info.band_width = std::min(h->band_width, std::max(1, n - 1));
     Timer tm(st);
     DcState dc;
-    rc = front_half(h, Hc, Sc, ws, L, tm, &dc);
+    rc = front_half(h, Hc, Sc, ws, L, tm, &dc, false);
     tm.finish(&h->info);
     if (rc) return rc;
     (void)hipMemcpyAsync(eval, ws + L.w, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
