@@ -426,6 +426,14 @@ void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const do
 // so that every application is a product with K = Q1G b.
 constexpr int Q1G = kQ1Group;
 
+// panels with at least two rows below them carry reflectors (full width b)
+static int q1_panels(int n, int b)
+{
+    int nvalid = 0;
+    while (n - (nvalid + 1) * b >= 2) ++nvalid;
+    return nvalid;
+}
+
 size_t apply_q1_workspace_doubles(int n, int ncol)
 {
     const size_t w = (size_t)Q1G * 64;
@@ -434,10 +442,59 @@ size_t apply_q1_workspace_doubles(int n, int ncol)
     return 2 * w * c + 8 * w * c + 2 * w * w + w * 64;
 }
 
+size_t q1_tfactor_doubles(int n, int b)
+{
+    const size_t w = (size_t)Q1G * 64;
+    return (size_t)std::max(1, ceil_div(q1_panels(n, b), Q1G)) * w * w;
+}
+
+// T' of group g (two panels or more) into Tg (ld Q1G*64), block column by
+// block column; Gg (Q1G*64 square) and tmp (Q1G*64 x 64) are scratch, part
+// the split-K partials of the Gram matrix V'^T V'.
+static void q1_group_t(hipStream_t st, int n, int b, int g, int nvalid, const double* Vall, const double* Tall,
+                       double* Tg, double* Gg, double* tmp, double* part, size_t npart)
+{
+    const int wmax = Q1G * 64;
+    const int p0 = g * Q1G;
+    const int np = std::min(Q1G, nvalid - p0);
+    const int w = np * b;
+    const int j0 = p0 * b;
+    const int r0 = j0 + b;
+    const int m = n - r0;
+    const double* V = Vall + cm(r0, j0, n);
+    const double* T = Tall + (size_t)p0 * b * b;
+    dgemm_splitk(st, 'T', 'N', w, w, m, 1.0, V, n, V, n, 0.0, Gg, wmax, part, npart);
+    fill_d(st, Tg, (size_t)wmax * w, 0.0);
+    for (int q = 0; q < np; ++q)
+        copy_matrix(st, b, b, T + (size_t)q * b * b, b, Tg + cm(q * b, q * b, wmax), wmax);
+    for (int q = 1; q < np; ++q) {
+        const int c = q * b;
+        dgemm(st, 'N', 'N', c, b, b, 1.0, Gg + cm(0, c, wmax), wmax, T + (size_t)q * b * b, b, 0.0, tmp, wmax);
+        dgemm(st, 'N', 'N', c, b, c, -1.0, Tg, wmax, tmp, wmax, 0.0, Tg + cm(0, c, wmax), wmax);
+    }
+}
+
+void build_q1_t(hipStream_t st, int n, int b, int ncol, const double* Vall, const double* Tall, double* Tq1,
+                double* work)
+{
+    // the scratch apply_q1 uses for its own T' with ncol columns
+    const int wmax = Q1G * 64;
+    const size_t c = (size_t)std::max(ncol, 1);
+    double* part = work + 2 * (size_t)wmax * c;
+    const size_t npart = (size_t)8 * wmax * c;
+    double* Gg = part + npart + (size_t)wmax * wmax;
+    double* tmp = Gg + (size_t)wmax * wmax;
+    const int nvalid = q1_panels(n, b);
+    const int ngroups = ceil_div(nvalid, Q1G);
+    for (int g = 0; g < ngroups; ++g)
+        if (std::min(Q1G, nvalid - g * Q1G) >= 2)
+            q1_group_t(st, n, b, g, nvalid, Vall, Tall, Tq1 + (size_t)g * wmax * wmax, Gg, tmp, part, npart);
+}
+
 // X (n x ncol) <- Q1 X with the panel reflectors of step (1), or Q1^T X
 // (trans: the groups first to last, each with its T'^T).
 void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const double* Tall, double* X, int ldx,
-              double* work, bool trans)
+              double* work, bool trans, const double* Tq1)
 {
     if (ncol <= 0) return;
     const int wmax = Q1G * 64;
@@ -448,9 +505,7 @@ void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const 
     double* Tg = part + npart;                       // wmax x wmax
     double* Gg = Tg + (size_t)wmax * wmax;           // wmax x wmax
     double* tmp = Gg + (size_t)wmax * wmax;          // wmax x 64
-    // panels with at least two rows below them carry reflectors (full width b)
-    int nvalid = 0;
-    while (n - (nvalid + 1) * b >= 2) ++nvalid;
+    const int nvalid = q1_panels(n, b);
     const int ngroups = ceil_div(nvalid, Q1G);
     const char tt = trans ? 'T' : 'N';
     for (int gi = 0; gi < ngroups; ++gi) {
@@ -469,18 +524,14 @@ void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const 
             dgemm(st, 'N', 'N', m, ncol, b, -1.0, V, n, W2, wmax, 1.0, X + r0, ldx);
             continue;
         }
-        // T' of the group
-        dgemm_splitk(st, 'T', 'N', w, w, m, 1.0, V, n, V, n, 0.0, Gg, wmax, part, npart);
-        fill_d(st, Tg, (size_t)wmax * w, 0.0);
-        for (int q = 0; q < np; ++q)
-            copy_matrix(st, b, b, T + (size_t)q * b * b, b, Tg + cm(q * b, q * b, wmax), wmax);
-        for (int q = 1; q < np; ++q) {
-            const int c = q * b;
-            dgemm(st, 'N', 'N', c, b, b, 1.0, Gg + cm(0, c, wmax), wmax, T + (size_t)q * b * b, b, 0.0, tmp, wmax);
-            dgemm(st, 'N', 'N', c, b, c, -1.0, Tg, wmax, tmp, wmax, 0.0, Tg + cm(0, c, wmax), wmax);
-        }
+        // T' of the group: built beforehand, or here
+        const double* Tp = Tg;
+        if (Tq1)
+            Tp = Tq1 + (size_t)g * wmax * wmax;
+        else
+            q1_group_t(st, n, b, g, nvalid, Vall, Tall, Tg, Gg, tmp, part, npart);
         dgemm_splitk(st, 'T', 'N', w, ncol, m, 1.0, V, n, X + r0, ldx, 0.0, W, wmax, part, npart);
-        dgemm(st, tt, 'N', w, ncol, w, 1.0, Tg, wmax, W, wmax, 0.0, W2, wmax);
+        dgemm(st, tt, 'N', w, ncol, w, 1.0, Tp, wmax, W, wmax, 0.0, W2, wmax);
         dgemm(st, 'N', 'N', m, ncol, w, -1.0, V, n, W2, wmax, 1.0, X + r0, ldx);
     }
 }

@@ -296,6 +296,7 @@ struct DcState {
     // the stream that applies Q2 waits on q2t_ev (if set) and skips the build
     bool q2t_built = false;
     hipEvent_t q2t_ev = nullptr;
+    const double* q1t = nullptr;   // Q1's group T' factors, built on the same stream before q2t_ev
 };
 size_t stedc_workspace_bytes(int n);
 int stedc_values(hipStream_t st, int n, const double* d, const double* e, double* w, double* Z, double* Z2,
@@ -313,7 +314,13 @@ void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const do
               double* X, int ldx, double* Tq, bool trans = false, bool tq_ready = false, int slab = 0);
 int q2_slab_width(int ncol);
 size_t apply_q1_workspace_doubles(int n, int ncol);
+// The group T' factors of Q1 (q1_tfactor_doubles(n, b) doubles at Tq1), built
+// from the panel reflectors alone, with the scratch of an apply_q1 workspace
+// for ncol columns; apply_q1 given Tq1 uses them instead of building its own.
+size_t q1_tfactor_doubles(int n, int b);
+void build_q1_t(hipStream_t st, int n, int b, int ncol, const double* Vall, const double* Tall, double* Tq1,
+                double* work);
 void apply_q1(hipStream_t st, int n, int b, int ncol, const double* Vall, const double* Tall, double* X,
-              int ldx, double* work, bool trans = false);
+              int ldx, double* work, bool trans = false, const double* Tq1 = nullptr);
 
 }  // namespace eg

@@ -42,7 +42,8 @@ void density_matrix(hipStream_t st, int n, int k, const double* C, int ldc, cons
 // workspace layout (all sub-buffers 256-byte aligned)
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t linv, bd, vall, tall, v2, tau2, tq2, d, e, w, z, z2, u, sywork, dcwork, q1work, f, scal, ints, mbox;
+    size_t linv, bd, vall, tall, v2, tau2, tq2, tq1, d, e, w, z, z2, u, sywork, dcwork, q1work, f, scal, ints, mbox;
+    int q1ncol;   // columns the Q1 workspace is sized for
     // mixed precision: the band reduction's copy of H~ (H keeps H~ for the
     // refinement), which afterwards holds the eigenvectors of T of the carried
     // states; the refinement's k' x k' blocks, per-state values and the
@@ -65,6 +66,7 @@ static Layout make_layout(int n, int b, int ncol, bool mixed = false, bool vcopy
     L.v2 = put(sizeof(double) * nn);
     L.tau2 = put(sizeof(double) * (size_t)std::max(n - 2, 1) * sb2st_kmax(n, b));
     L.tq2 = put(sizeof(double) * apply_q2_workspace_doubles(n, b));
+    L.tq1 = put(sizeof(double) * q1_tfactor_doubles(n, b));
     L.d = put(sizeof(double) * n);
     L.e = put(sizeof(double) * n);
     L.w = put(sizeof(double) * n);
@@ -74,6 +76,7 @@ static Layout make_layout(int n, int b, int ncol, bool mixed = false, bool vcopy
     L.sywork = put(sizeof(double) * sy2sb_workspace_doubles(n, b));
     L.dcwork = put(stedc_workspace_bytes(n));
     L.q1work = put(sizeof(double) * apply_q1_workspace_doubles(n, ncol));
+    L.q1ncol = ncol;
     L.f = put(sizeof(double) * n);
     L.scal = put(sizeof(double) * 16);
     L.ints = put(sizeof(int) * ((size_t)n + 64));
@@ -262,8 +265,9 @@ static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, cons
                    (double*)(ws + L.mbox));
     if (rc) return rc;
     tm.mark(ELSI_GPU_ST_BULGE);
-    // the T factors need only the reflectors of step (2); outside batched calls
-    // (whose workers keep one stream each) they run beside the tridiagonal solve
+    // the T factors of Q2 need only the reflectors of step (2), the group T'
+    // factors of Q1 only those of step (1); outside batched calls (whose workers
+    // keep one stream each) both are built beside the tridiagonal solve
     bool q2t_built = false;
     hipEvent_t q2t_ev = nullptr;
     if (vectors && !batch_mode_active() && h->aux_stream && h->aux_ev[0] && h->aux_ev[1] &&
@@ -271,6 +275,7 @@ static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, cons
         hipStreamWaitEvent(h->aux_stream, h->aux_ev[0], 0) == hipSuccess) {
         build_q2_t(h->aux_stream, n, b, (double*)(ws + L.v2), (double*)(ws + L.tau2), sb2st_kmax(n, b),
                    (double*)(ws + L.tq2));
+        build_q1_t(h->aux_stream, n, b, L.q1ncol, Vall, Tall, (double*)(ws + L.tq1), (double*)(ws + L.q1work));
         if (hipEventRecord(h->aux_ev[1], h->aux_stream) == hipSuccess)
             q2t_ev = h->aux_ev[1];
         else if (hipStreamSynchronize(h->aux_stream) != hipSuccess)
@@ -287,6 +292,7 @@ static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, cons
     }
     dc->q2t_built = q2t_built;
     dc->q2t_ev = q2t_ev;
+    dc->q1t = q2t_built ? (const double*)(ws + L.tq1) : nullptr;
     tm.mark(ELSI_GPU_ST_TRIDIAG);
     return 0;
 }
@@ -323,7 +329,8 @@ static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L
     tm.mark(ELSI_GPU_ST_BACK_Q2);
     {
         Fp32GemmScope fp32(h->precision == ELSI_GPU_PREC_MIXED);
-        apply_q1(st, n, b, k, (double*)(ws + L.vall), (double*)(ws + L.tall), X, n, (double*)(ws + L.q1work));
+        apply_q1(st, n, b, k, (double*)(ws + L.vall), (double*)(ws + L.tall), X, n, (double*)(ws + L.q1work), false,
+                 dc->q1t);
     }
     tm.mark(ELSI_GPU_ST_BACK_Q1);
     if (backsub) back_substitute(h, S, ws, L, tm, k);
@@ -335,6 +342,7 @@ static void back_half(elsi_gpu_handle_s* h, double* S, char* ws, const Layout& L
 struct ReflectorPrecond : RefinePrecond {
     int n = 0, b = 0, kmax = 0;
     const double *Vall = nullptr, *Tall = nullptr, *V2 = nullptr, *tau2 = nullptr;
+    const double* Tq1 = nullptr;   // Q1's group T' factors when built beforehand
     double *Tq = nullptr, *q1work = nullptr;
     // Q1's products run on the FP32 matrix cores, as in step (5) of this mode:
     // the correction only needs its own size to a few digits
@@ -343,7 +351,7 @@ struct ReflectorPrecond : RefinePrecond {
         (void)tmp;
         {
             Fp32GemmScope fp32(true);
-            apply_q1(st, n, b, ncol, Vall, Tall, X, ld, q1work, true);
+            apply_q1(st, n, b, ncol, Vall, Tall, X, ld, q1work, true, Tq1);
         }
         apply_q2(st, n, b, ncol, V2, tau2, kmax, X, ld, Tq, true, true);
     }
@@ -352,7 +360,7 @@ struct ReflectorPrecond : RefinePrecond {
         (void)tmp;
         apply_q2(st, n, b, ncol, V2, tau2, kmax, X, ld, Tq, false, true);
         Fp32GemmScope fp32(true);
-        apply_q1(st, n, b, ncol, Vall, Tall, X, ld, q1work, false);
+        apply_q1(st, n, b, ncol, Vall, Tall, X, ld, q1work, false, Tq1);
     }
 };
 
@@ -360,10 +368,11 @@ struct ReflectorPrecond : RefinePrecond {
 // H), with the Newton correction through the reduced-precision factorization;
 // the eigenvectors of T of the k' states are in hcopy.  On return Z holds the
 // refined vectors and w[0 .. k') their Ritz values.  kw leading states decide
-// convergence, each step weighted by weight[l] (device; NULL: 1).  Returns 0,
-// kStatusRefine (outputs usable, tolerance not reached) or an error.
+// convergence, each step weighted by weight[l] (device; NULL: 1).  q1t: Q1's
+// group T' factors when the front half built them (NULL: built per application).
+// Returns 0, kStatusRefine (outputs usable, tolerance not reached) or an error.
 static int refine_states(elsi_gpu_handle_s* h, const double* Ht, char* ws, const Layout& L, Timer& tm, int kp,
-                         int kw, const double* weight)
+                         int kw, const double* weight, const double* q1t)
 {
     hipStream_t st = h->stream;
     const int n = h->n, b = std::min(h->band_width, std::max(1, n - 1));
@@ -393,6 +402,7 @@ static int refine_states(elsi_gpu_handle_s* h, const double* Ht, char* ws, const
     pc.tau2 = (const double*)(ws + L.tau2);
     pc.Tq = (double*)(ws + L.tq2);
     pc.q1work = (double*)(ws + L.q1work);
+    pc.Tq1 = q1t;
     pc.Z = (const double*)(ws + L.hcopy);
     pc.ldz = n;
     pc.d = (const double*)(ws + L.d);
@@ -473,7 +483,7 @@ static int ev_real(elsi_gpu_handle_s* h, double* H, double* S, double* eval, dou
     if (mixed) {
         const int kp = refine_columns(n, k);
         back_half(h, S, ws, L, tm, kp, &dc, false, (double*)(ws + L.hcopy));
-        rstat = refine_states(h, H, ws, L, tm, kp, k, nullptr);
+        rstat = refine_states(h, H, ws, L, tm, kp, k, nullptr, dc.q1t);
         if (rstat && rstat != kStatusRefine) { tm.finish(&h->info); return rstat; }
         back_substitute(h, S, ws, L, tm, k);
     } else {
@@ -543,7 +553,7 @@ static int dm_real(elsi_gpu_handle_s* h, double* H, double* S, double* occ, doub
         // the refined eigenvalues
         const int kp = refine_columns(n, ks);
         back_half(h, S, ws, L, tm, kp, &dc, false, (double*)(ws + L.hcopy));
-        rstat = refine_states(h, H, ws, L, tm, kp, ks, f);   // each state weighted by its occupation
+        rstat = refine_states(h, H, ws, L, tm, kp, ks, f, dc.q1t);   // each state weighted by its occupation
         if (rstat && rstat != kStatusRefine) { tm.finish(&h->info); return rstat; }
         if ((rc = occupy())) return rc;
         ks = std::min(ks, kp);
