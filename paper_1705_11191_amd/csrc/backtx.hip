@@ -375,9 +375,18 @@ __global__ __launch_bounds__(256, 2) void q2_apply_step_kernel(int n, int b, int
 
 }  // namespace
 
-// columns of X per workgroup: wide slabs amortize the loads of V and T, narrow
-// ones keep enough workgroups in flight when X has few columns
-int q2_slab_width(int ncol) { return ncol >= 8192 ? 512 : (ncol >= 2048 ? 256 : 128); }
+// Columns of X per workgroup: wide slabs amortize the loads of V and T, narrow
+// ones keep enough workgroups in flight.  The width follows the column count,
+// halved while the busiest step (about half of the row groups active) would
+// have fewer than about 1024 workgroups: N = 8,192 with 2,050 columns takes
+// 128 (Q2 18.3 -> 16.6 ms against 256), N = 32,768 with 8,194 columns 512.
+int q2_slab_width(int n, int b, int ncol)
+{
+    int w = ncol >= 8192 ? 512 : (ncol >= 2048 ? 256 : 128);
+    const long long busy = std::max(1, ceil_div(std::max(n - 2, 1), b) / 2);
+    while (w > 128 && busy * ceil_div(ncol, w) < 1024) w /= 2;
+    return w;
+}
 
 size_t apply_q2_workspace_doubles(int n, int b)
 {
@@ -395,14 +404,14 @@ void build_q2_t(hipStream_t st, int n, int b, const double* V2, const double* ta
 // X (n x ncol) <- Q2 X, or Q2^T X (trans); Tq: apply_q2_workspace_doubles(n, b)
 // doubles, rebuilt from the reflectors unless tq_ready says a previous call on
 // the same reflectors left it there.  slab: columns per workgroup (0 picks
-// q2_slab_width(ncol); otherwise 128, 256 or 512).
+// q2_slab_width(n, b, ncol); otherwise 128, 256 or 512).
 void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const double* tau2, int kmax, double* X,
               int ldx, double* Tq, bool trans, bool tq_ready, int slab)
 {
     if (n <= 2 || ncol <= 0) return;
     const int ngroups = ceil_div(n - 2, b);
     if (!tq_ready) build_q2_t(st, n, b, V2, tau2, kmax, Tq);
-    const int qw = slab > 0 ? slab : q2_slab_width(ncol);
+    const int qw = slab > 0 ? slab : q2_slab_width(n, b, ncol);
     const int nslab = ceil_div(ncol, qw);
     const int tmax = (ngroups - 1) + kmax;   // last step: g = 0 with its last block
     for (int s = 0; s < tmax; ++s) {

@@ -312,7 +312,7 @@ size_t apply_q2_workspace_doubles(int n, int b);
 void build_q2_t(hipStream_t st, int n, int b, const double* V2, const double* tau2, int kmax, double* Tq);
 void apply_q2(hipStream_t st, int n, int b, int ncol, const double* V2, const double* tau2, int kmax,
               double* X, int ldx, double* Tq, bool trans = false, bool tq_ready = false, int slab = 0);
-int q2_slab_width(int ncol);
+int q2_slab_width(int n, int b, int ncol);
 size_t apply_q1_workspace_doubles(int n, int ncol);
 // The group T' factors of Q1 (q1_tfactor_doubles(n, b) doubles at Tq1), built
 // from the panel reflectors alone, with the scratch of an apply_q1 workspace

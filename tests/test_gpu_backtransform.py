@@ -5,7 +5,7 @@ Q = Q1 Q2 is formed explicitly by applying it to the identity; that Q must be
 orthogonal and must tridiagonalize the input (Q^T A Q = T with the returned d
 and e), which pins it without reference to the kernels.  Every other
 application -- each Q2 column-slab width (128, 256 and 512 columns per
-workgroup, the last taken automatically at >= 8192 columns), and the
+workgroup, each chosen explicitly, and the automatic choice), and the
 transposed products Q^T X the mixed mode's refinement uses -- must then equal
 NumPy's product with that explicit Q.  Tolerances: products of an orthogonal
 matrix with unit-scale columns, 32 n eps.

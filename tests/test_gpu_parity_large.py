@@ -1,6 +1,6 @@
 """Element-wise oracle parity at sizes that take the size branches of the
-kernels: N = 3000 (several 1024-wide outer panels, 47 band panels; ev with
-2100 states runs the Q2 back-transformation with 256-column slabs), a batch
+kernels: N = 3000 (an outer panel of 2048 and a ragged one, 47 band panels;
+ev with 2100 states, more than 2048 columns in the back-transformations), a batch
 holding an n = 4095 problem (the largest of the benchmark batch), and a
 complex pencil of n = 1000.  The oracle needs 10-30 s for each on the host
 cores; its results are computed once per module.  Gates as everywhere:
