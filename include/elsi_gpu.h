@@ -153,8 +153,8 @@ typedef struct elsi_gpu_info {
  * elsi_gpu_ev (1..n_basis); n_electron: electron count for elsi_gpu_dm;
  * hip_stream: the hipStream_t the calls run on (NULL = default stream); the
  * handle also creates a second stream and two events of its own, on which the
- * panel T factors of full -> band, and the block T factors of the bulge-chasing
- * reflectors (beside the tridiagonal solve), run beside the stream's work (the
+ * panel T factors of full -> band, and the block T factors of both
+ * back-transformations (beside the tridiagonal solve), run beside the stream's work (the
  * calls still return with everything ordered after their work on hip_stream), and
  * elsi_gpu_finalize releases them.  Defaults: Fermi-Dirac, width 0.01 Ha, occ_accuracy 1e-13,
  * mu_max_steps 100, spin factor 1, band width 64.
