@@ -183,6 +183,29 @@ def test_standard_ev_overlap_is_unit(n):
 
 
 
+@pytest.mark.parametrize("kind", ["rank40", "blockdiag", "diagonal"])
+def test_standard_ev_panels_that_cholesky_qr_cannot_factor(kind):
+    """Rank-deficient panels defeat CholeskyQR2, and inside a solve (not only in
+    the stage entry) those panels take the per-column Householder fallback.
+    The spectrum and the eigenpairs must come out as for any other matrix."""
+    from paper_1705_11191_amd import binding as B
+
+    n = 700
+    A = _panel_kind_matrix(kind, n, 9)
+    print(f"[ev panels] kind={kind} n={n}", flush=True)
+    h = B.Handle(n, n, n / 4)
+    h.set_overlap_is_unit(True)
+    ev, C = h.ev(_dev(A), None)
+    h.close()
+    ev = ev.cpu().numpy()
+    C = C.cpu().numpy()
+    ref = np.linalg.eigvalsh(A)
+    scale = np.abs(ref).max()
+    assert np.abs(ev - ref).max() <= 64 * n * EPS * scale
+    assert np.abs(A @ C - C * ev).max() <= 64 * n * EPS * scale
+    assert np.abs(C.T @ C - np.eye(n)).max() <= 64 * n * EPS
+
+
 @pytest.mark.parametrize("b", [64, 32])
 def test_ev_config0_vs_oracle(b):
     from paper_1705_11191_amd import binding as B
