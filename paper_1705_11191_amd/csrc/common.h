@@ -77,7 +77,7 @@ __device__ __forceinline__ double wave_sum_dpp(double v)
 // X_BA = -X_BB (L_BA X_AA); Y is LDS scratch.  Only the lower triangle of L is
 // read.
 template <int NT>
-__device__ inline void tri_inverse_lower64(int jb, double (*Lm)[65], double (*X)[65], double (*Y)[65])
+__device__ __forceinline__ void tri_inverse_lower64(int jb, double (*Lm)[65], double (*X)[65], double (*Y)[65])
 {
     const int tid = threadIdx.x;
     for (int e = tid; e < 64 * 64; e += NT) {
@@ -85,6 +85,10 @@ __device__ inline void tri_inverse_lower64(int jb, double (*Lm)[65], double (*X)
         X[r][c] = (r == c && r < jb) ? 1.0 / Lm[r][r] : 0.0;
     }
     __syncthreads();
+    // each dot product's LDS operands are loaded into registers before its
+    // multiply-adds, so that the loads are in flight together (the sums keep
+    // their order: entries a .. sz-1, and 0 .. bb)
+#pragma unroll
     for (int lg = 0; lg < 6; ++lg) {
         const int sz = 1 << lg;
         const int nout = 32 << lg;   // (64 / 2sz) pairs of sz x sz blocks
@@ -92,8 +96,16 @@ __device__ inline void tri_inverse_lower64(int jb, double (*Lm)[65], double (*X)
             const int pr = e >> (2 * lg), rem = e & (sz * sz - 1);
             const int bb = rem & (sz - 1), a = rem >> lg;
             const int p0 = pr << (lg + 1), pb = p0 + sz;
+            double lv[32], xv[32];
+#pragma unroll
+            for (int ii = 0; ii < (1 << lg); ++ii) {
+                lv[ii] = Lm[pb + bb][p0 + ii];
+                xv[ii] = X[p0 + ii][p0 + a];
+            }
             double y = 0.0;
-            for (int ii = a; ii < sz; ++ii) y += Lm[pb + bb][p0 + ii] * X[p0 + ii][p0 + a];
+#pragma unroll
+            for (int ii = 0; ii < (1 << lg); ++ii)
+                if (ii >= a) y += lv[ii] * xv[ii];
             Y[pb + bb][p0 + a] = y;
         }
         __syncthreads();
@@ -101,8 +113,16 @@ __device__ inline void tri_inverse_lower64(int jb, double (*Lm)[65], double (*X)
             const int pr = e >> (2 * lg), rem = e & (sz * sz - 1);
             const int bb = rem & (sz - 1), a = rem >> lg;
             const int p0 = pr << (lg + 1), pb = p0 + sz;
+            double xv[32], yv[32];
+#pragma unroll
+            for (int jj = 0; jj < (1 << lg); ++jj) {
+                xv[jj] = X[pb + bb][pb + jj];
+                yv[jj] = Y[pb + jj][p0 + a];
+            }
             double t = 0.0;
-            for (int jj = 0; jj <= bb; ++jj) t += X[pb + bb][pb + jj] * Y[pb + jj][p0 + a];
+#pragma unroll
+            for (int jj = 0; jj < (1 << lg); ++jj)
+                if (jj <= bb) t += xv[jj] * yv[jj];
             X[pb + bb][p0 + a] = -t;
         }
         __syncthreads();

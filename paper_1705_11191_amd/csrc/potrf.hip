@@ -82,8 +82,13 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(int jb, int j0, double* 
             if (lane >= c) g[c] = l;
             col[lane] = (lane > c) ? l : 0.0;
             wave_lds_sync();
+            // the column into registers first, so that its LDS reads are all in
+            // flight together instead of one round trip per pair of entries
+            double cv[NB];
 #pragma unroll
-            for (int q = c + 1; q < NB; ++q) g[q] -= l * col[q];   // only q <= r is kept
+            for (int q = c + 1; q < NB; ++q) cv[q] = col[q];
+#pragma unroll
+            for (int q = c + 1; q < NB; ++q) g[q] -= l * cv[q];   // only q <= r is kept
             wave_lds_sync();
         }
         if (!fail) {
