@@ -891,15 +891,28 @@ __global__ __launch_bounds__(256) void build_t_kernel(int bw, const double* G, i
         if (tid < bw) Ts[tid][tid] = gt ? 2.0 / Gs[tid][tid] : td;
     }
     __syncthreads();
-    for (int sz = 1; sz < BMAX; sz *= 2) {
+    // each dot product's LDS operands are loaded into registers before its
+    // multiply-adds, so that the loads are in flight together (the sums keep
+    // their order: entries 0 .. bb, and a .. sz-1)
+#pragma unroll
+    for (int lg = 0; lg < 6; ++lg) {
+        const int sz = 1 << lg;
         const int nout = (BMAX / (2 * sz)) * sz * sz;   // entries of all off-diagonal blocks
         // Y = G_AB T_BB (row a of A, column b of B)
         for (int e = tid; e < nout; e += 256) {
             const int pr = e / (sz * sz), rem = e % (sz * sz);
             const int a = rem % sz, bb = rem / sz;
             const int p0 = pr * 2 * sz, pb = p0 + sz;
+            double gv[32], tv[32];
+#pragma unroll
+            for (int jj = 0; jj < (1 << lg); ++jj) {
+                gv[jj] = Gs[p0 + a][pb + jj];
+                tv[jj] = Ts[pb + jj][pb + bb];
+            }
             double y = 0.0;
-            for (int jj = 0; jj <= bb; ++jj) y += Gs[p0 + a][pb + jj] * Ts[pb + jj][pb + bb];
+#pragma unroll
+            for (int jj = 0; jj < (1 << lg); ++jj)
+                if (jj <= bb) y += gv[jj] * tv[jj];
             Ys[p0 + a][pb + bb] = y;
         }
         __syncthreads();
@@ -908,8 +921,16 @@ __global__ __launch_bounds__(256) void build_t_kernel(int bw, const double* G, i
             const int pr = e / (sz * sz), rem = e % (sz * sz);
             const int a = rem % sz, bb = rem / sz;
             const int p0 = pr * 2 * sz, pb = p0 + sz;
+            double tv[32], yv[32];
+#pragma unroll
+            for (int ii = 0; ii < (1 << lg); ++ii) {
+                tv[ii] = Ts[p0 + a][p0 + ii];
+                yv[ii] = Ys[p0 + ii][pb + bb];
+            }
             double t = 0.0;
-            for (int ii = a; ii < sz; ++ii) t += Ts[p0 + a][p0 + ii] * Ys[p0 + ii][pb + bb];
+#pragma unroll
+            for (int ii = 0; ii < (1 << lg); ++ii)
+                if (ii >= a) t += tv[ii] * yv[ii];
             Ts[p0 + a][pb + bb] = -t;
         }
         __syncthreads();
