@@ -51,3 +51,33 @@ def test_tuner_buckets_and_samples():
     assert s == sorted(s) and s[0] < 105 and s[-1] > 134
     assert tune._sample([3, 4], 8) == [3, 4]
     assert tune._sample([], 8) == []
+
+
+def test_traffic_summary_round_trip_and_staleness(tmp_path, monkeypatch):
+    """The HBM traffic figure is read back from the counter summary only while
+    the GEMM source and the kernel's launch count per solve are those it was
+    taken with; each counter is scaled by the calibration copy's reading."""
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    src = tmp_path / "gemm.hip"
+    src.write_text("kernel source A")
+    monkeypatch.setattr(bench, "GEMM_SRC", str(src))
+    kern = "dgemm_kernel<128,128,0,true,false,false>"
+    full = "void eg::(anonymous namespace)::dgemm_kernel<128, 128, 0, true, false, false>(int, int)"
+    known_kib = bench.COPY_ELEMS * 8 / 1024
+
+    def csv_file(name, counter, copy_kib, vals):
+        rows = ["Counter_Name,Kernel_Name,Counter_Value", f'{counter},"void eg::neg_kernel(double*)",{copy_kib}']
+        rows += [f'{counter},"{full}",{v}' for v in vals]
+        path = tmp_path / name
+        path.write_text("\n".join(rows) + "\n")
+        return str(path)
+
+    fetch = csv_file("f.csv", "FETCH_SIZE", known_kib / 2, [100.0, 300.0])   # reads back half: factor 2
+    write = csv_file("w.csv", "WRITE_SIZE", known_kib, [40.0, 60.0])         # factor 1
+    bench.summarize_pmc(fetch, write, kern, "wl", ["the two counter passes"])
+    want = 200.0 * 1024 * 2 + 50.0 * 1024
+    assert math.isclose(bench.load_traffic(kern, "wl", 2), want)
+    assert bench.load_traffic(kern, "wl", 3) is None   # another mix of products
+    assert bench.load_traffic(kern, "other", 2) is None
+    src.write_text("kernel source B")
+    assert bench.load_traffic(kern, "wl", 2) is None   # the GEMM changed since
