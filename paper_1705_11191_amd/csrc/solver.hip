@@ -203,8 +203,9 @@ struct Timer {
 // reduction (Eq. (11)), full -> band and band -> tridiagonal (Eq. (13)), and
 // the tridiagonal eigenpairs (divide and conquer).  On success w holds all
 // eigenvalues ascending and Z the eigenvectors of T (first ncol columns).
-// vectors: back_half follows, so Q2's block T factors are built on the
-// handle's second stream while the tridiagonal problem is solved.
+// vectors: back_half follows, so the block T factors of Q2 and the group T'
+// factors of Q1 are built on the handle's second stream while the tridiagonal
+// problem is solved.
 static int front_half(elsi_gpu_handle_s* h, double* H, double* S, char* ws, const Layout& L, Timer& tm,
                       DcState* dc, bool vectors)
 {
